@@ -1,0 +1,46 @@
+"""Plain FP64 CPU oracle for PCG map-making (Naess & Louis, arXiv:1309.7473).
+
+TEST INFRASTRUCTURE ONLY.  This package is the independent checker of the GPU
+library: only the test suite, the smoke check and the benchmark's CPU-baseline
+leg may import it.  It shares no code with the GPU path and imports nothing
+from it; its inputs come from the seeded generator package `synth`.
+
+Everything is float64 NumPy/SciPy, written for clarity over speed:
+
+* operators.py - pointing P and its transpose, the stationary per-detector
+  noise filter N^-1, A = P^T N^-1 P and b = P^T N^-1 d (eq. 1-2), the binned
+  blocks and the active-pixel mask (eq. 3-5, 7);
+* precon.py    - binned and Jacobi preconditioners (eq. 3-5) and the circulant
+  ("constant correlation") preconditioner with Gaussian regularisation and
+  polarisation blocks (eq. 7-13 and the Regularization / Polarization
+  sections);
+* pcg.py       - preconditioned conjugate gradients and the CG error A-norm
+  estimate quoted in the Results section;
+* dense.py     - dense A by probing unit vectors (eq. 6) and a direct solve.
+
+Readings of points the paper leaves open are listed in the design doc; functions
+cite the equation or section they follow.  Parity unpinned: none of the
+functions here (every one has a pin in tests/test_oracle_*.py).
+"""
+
+from .operators import (  # noqa: F401
+    OracleScan,
+    pointing,
+    pointing_T,
+    inv_noise,
+    detector_weights,
+    hits,
+    binned_blocks,
+    active_mask,
+    apply_A,
+    rhs,
+)
+from .precon import (  # noqa: F401
+    BinnedPrecon,
+    CirculantPrecon,
+    reference_pixel,
+    sym_sqrt,
+    gaussian_taper,
+)
+from .pcg import pcg, anorm_estimate  # noqa: F401
+from .dense import dense_operator, dense_solve  # noqa: F401

@@ -1,0 +1,42 @@
+"""The benchmark workloads as seeded synthetic scans.
+
+Workloads (sizes as in the project's benchmark definitions):
+
+1. intensity only, 8 detectors on a cross-scan line x 2^14 samples at 100 Hz,
+   64 x 64 map, white (sigma = 1) + 1/f (f_knee = 1 Hz, index -3) noise,
+   no scan-angle drift;
+2. I,Q,U, 256 detectors on a hexagonal focal plane 0.5 deg (60 px) across,
+   2^20 samples at 400 Hz, 512 x 512 map, linear scan-angle drift of at most
+   +-10 deg in total, psi_d ~ U[0, pi), sigma_d log-normal with 10 % scatter,
+   f_knee,d ~ U(0.5, 3) Hz, index -3;
+3. the pattern of 2 at 1024 detectors x 2^21 samples on a 1024 x 1024 map;
+5. the shape of 2 (scan ids 0..7 train, 1000.. held out).
+
+`make_config(cid, scan_id, **overrides)` draws one scan; overrides shrink a
+workload for tests (e.g. ndet, nsamp, ny, nx) while keeping its recipe.
+Seeds are numpy SeedSequence([cid, scan_id]) with spawned children for the
+sky, focal plane, detector angles, noise parameters, drift and noise draws.
+"""
+
+from .scan import raster_scan
+
+CONFIG_DEFS = {
+    1: dict(ncomp=1, ndet=8, nsamp=2**14, fsample=100.0, ny=64, nx=64,
+            layout="line", sigma=1.0, sigma_scatter=0.0, fknee=(1.0, 1.0),
+            alpha=-3.0, drift_deg=0.0),
+    2: dict(ncomp=3, ndet=256, nsamp=2**20, fsample=400.0, ny=512, nx=512,
+            layout="hex", hex_diameter_px=60.0, sigma=1.0, sigma_scatter=0.1,
+            fknee=(0.5, 3.0), alpha=-3.0, drift_deg=10.0),
+    3: dict(ncomp=3, ndet=1024, nsamp=2**21, fsample=400.0, ny=1024, nx=1024,
+            layout="hex", hex_diameter_px=60.0, sigma=1.0, sigma_scatter=0.1,
+            fknee=(0.5, 3.0), alpha=-3.0, drift_deg=10.0),
+    5: dict(ncomp=3, ndet=256, nsamp=2**20, fsample=400.0, ny=512, nx=512,
+            layout="hex", hex_diameter_px=60.0, sigma=1.0, sigma_scatter=0.1,
+            fknee=(0.5, 3.0), alpha=-3.0, drift_deg=10.0),
+}
+
+
+def make_config(cid, scan_id=0, **overrides):
+    spec = dict(CONFIG_DEFS[cid])
+    spec.update(overrides)
+    return raster_scan(seed=(cid, scan_id), **spec)
