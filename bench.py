@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark of the map-making hot path on one MI355X.
+
+Workload: the 256-detector I,Q,U raster scan (2^20 samples per detector at
+400 Hz, 512 x 512 map, hexagonal focal plane, scan-angle drift, white + 1/f
+noise), float32 timestreams, float64 maps and CG scalars.  A step is one PCG
+iteration with the circulant preconditioner: the A-apply (gather, per-detector
+real FFT, 1/N(f), inverse FFT, atomic scatter), the preconditioner apply and
+the CG reductions/updates.  The right-hand side is b = A m_sky (a noiseless
+timestream, as in the paper's test), computed on the GPU.
+
+Prints one JSON line: throughput in timestream samples per second of PCG
+iterations, the HIP-event roofline of the dominant kernel, PCG time-to-1e-6
+for the binned and circulant preconditioners, and the FP64 CPU oracle timed
+on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
+
+# algorithmic HBM bytes per timestream sample of each kernel (float32 path,
+# I,Q,U): pointing 12 B (i32 pixel + 2 x f32 weight), packed timestream 4 B
+# per pass that reads or writes it, 1/N(f) (n/2+1) x 4 B / n ~ 2 B.  The map
+# and its float64 accumulator are cache resident and not counted.
+ALG_BYTES = {"pass1": 16.0, "pass2": 10.0, "pass3": 16.0, "single": 26.0, "apply_A": 34.0}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("filter.hip", "fft_lds.h", "mm_device.h"):
+        with open(os.path.join(ROOT, "paper_1309_7473_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, src_hash):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_config2.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != src_hash:
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(inp, ndet_sample=8, reps=2):
+    """The FP64 oracle's A-apply on the first ndet_sample detectors."""
+    import numpy as np
+    import oracle
+    from types import SimpleNamespace
+    sub = SimpleNamespace(ncomp=inp.ncomp, ny=inp.ny, nx=inp.nx, pix=inp.pix[:ndet_sample],
+                          cos2psi=None if inp.cos2psi is None else inp.cos2psi[:ndet_sample],
+                          sin2psi=None if inp.sin2psi is None else inp.sin2psi[:ndet_sample],
+                          inv_noise=inp.inv_noise[:ndet_sample])
+    o = oracle.OracleScan(sub)
+    B = oracle.binned_blocks(o, oracle.detector_weights(o))
+    mask = oracle.active_mask(o, B)
+    x = inp.sky.reshape(inp.ncomp, -1) * mask
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        oracle.apply_A(o, x, mask)
+        times.append(time.perf_counter() - t0)
+    t = min(times)
+    S = ndet_sample * inp.nsamp
+    return {"value": S / t, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"A-apply on {ndet_sample} of {inp.ndet} detectors x {inp.nsamp} samples "
+                      f"(best of {reps}: {t:.2f} s per apply); numpy FFT and bincount, one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--taper", type=float, default=20.0, help="circulant Gaussian taper (px)")
+    ap.add_argument("--det-group", type=int, default=0)
+    ap.add_argument("--fft-m1", type=int, default=0)
+    ap.add_argument("--no-solve", action="store_true", help="skip time-to-1e-6 solves")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--ndet", type=int, default=256, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1309_7473_amd as mm
+    from synth import make_config
+
+    t0 = time.time()
+    inp = make_config(2, ndet=args.ndet)
+    t_gen = time.time() - t0
+    S = inp.ndet * inp.nsamp
+    scan = mm.Scan(inp, tod_dtype="f32", det_group=args.det_group, fft_m1=args.fft_m1)
+    info = scan.info()
+    x_sky = torch.from_numpy(inp.sky.ravel().copy()).cuda()
+    b = scan.apply_A(x_sky)                     # noiseless right-hand side
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    scan.build_precon("circulant", sigma=args.taper)
+    torch.cuda.synchronize()
+    t_setup_circ = time.perf_counter() - t1
+
+    # warm-up, then exactly K PCG iterations (tol = 0 never stops early)
+    scan.pcg("circulant", b, tol=0.0, maxiter=args.warmup, check_every=args.warmup, history=False)
+    mm.mm_profile_enable(scan.handle, True)
+    mm.mm_profile_read(scan.handle)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record()
+    res = scan.pcg("circulant", b, tol=0.0, maxiter=args.steps, check_every=args.steps,
+                   history=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    prof = mm.mm_profile_read(scan.handle)
+    mm.mm_profile_enable(scan.handle, False)
+    assert res["iters"] == args.steps, res
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    value = S / (ms_step * 1e-3)
+
+    # roofline of the dominant kernel (largest summed time)
+    kern = {k: v for k, v in prof.items() if k in ("single", "pass1", "pass2", "pass3")}
+    dom = max(kern, key=lambda k: kern[k][0])
+    tot_ms, nl, ns = kern[dom]
+    avg_s = tot_ms * 1e-3 / nl
+    bytes_per_launch = ALG_BYTES[dom] * ns / nl
+    achieved = bytes_per_launch / avg_s / 1e9
+    src_hash = kernel_source_hash()
+    traffic = load_traffic(dom, src_hash)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
+            "alg_bytes_per_launch": bytes_per_launch}
+    a_ms, a_n, a_s = prof["apply_A"]
+    apply_ms = a_ms / a_n
+    apply_roof = {"ms": round(apply_ms, 4), "samples_per_s": S / (apply_ms * 1e-3),
+                  "alg_bytes_per_sample": ALG_BYTES["apply_A"],
+                  "frac": round(ALG_BYTES["apply_A"] * S / (apply_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+    per_kernel = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1],
+                      "share": round(v[0] / (ms_step * args.steps), 4)} for k, v in prof.items()}
+
+    solves = None
+    if not args.no_solve:
+        solves = {}
+        for name in ("binned", "circulant"):
+            r = scan.pcg(name, b, tol=1e-6, maxiter=5000, check_every=10, history=False)
+            solves[name] = {"iters": r["iters"], "converged": r["converged"],
+                            "time_s": round(r["t_solve_s"], 4), "rel_resid": r["rel_resid"]}
+        solves["circulant"]["setup_s"] = round(t_setup_circ, 4)
+
+    cpu = None if args.no_cpu else cpu_baseline(inp)
+    out = {
+        "metric": "PCG time-to-1e-6 residual (s) & A-apply samples/s; learned vs circulant vs binned",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "config2: I,Q,U raster, 256 detectors x 2^20 samples @400 Hz, "
+                               "512x512 map, hex focal plane 60 px, drift <=10 deg, white+1/f noise",
+                   "step": "one PCG iteration, circulant preconditioner (A-apply + M_C + CG updates)",
+                   "samples_per_step": S, "accumulate": "f64", "taper_px": args.taper,
+                   "plan": info},
+        "roofline": roof,
+        "apply_A": apply_roof,
+        "kernels": per_kernel,
+        "time_to_1e-6": solves,
+        "cpu_baseline": cpu,
+        "wall_s_timed": round(wall, 3),
+        "gen_s": round(t_gen, 1),
+        "source_hash": src_hash,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

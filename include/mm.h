@@ -1,0 +1,224 @@
+/*
+ * mm.h - C ABI of the MI355X map-making library (libmm.so).
+ *
+ * The library solves the maximum-likelihood map-making equation
+ *     (P^T N^-1 P) m = P^T N^-1 d                         (paper eq. 2)
+ * for a pixelised I or I,Q,U sky map m, given detector timestreams d, a
+ * nearest-pixel pointing matrix P with weights (1, cos 2psi, sin 2psi)
+ * (eq. 1 and the Test setup section) and per-detector stationary noise N
+ * (inverse power spectrum 1/N(f) per detector), by preconditioned conjugate
+ * gradients with the binned (eq. 3-4), Jacobi (eq. 5) or circulant
+ * "constant correlation" preconditioner (eq. 7-13).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers (e.g. torch.Tensor.data_ptr() of a
+ *     CUDA/HIP tensor) unless marked [host].
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it and the call returns without waiting unless the
+ *     description says "synchronises".
+ *   - Maps are float64 [ncomp][ny][nx], x fastest, pixel id p = y*nx + x.
+ *     Only active pixels (hit at least once and, for I,Q,U, with a binned
+ *     3x3 block of reciprocal condition number >= mask_rcond) are unknowns:
+ *     every map the library writes is zero on inactive pixels, and inactive
+ *     entries of input maps are ignored.
+ *   - Timestream-shaped arrays are [ndet][nsamp], detector-major.
+ *   - Errors: a status code is returned and no exception crosses the ABI.
+ *     Arguments are validated before anything is enqueued, so an MM_EINVAL
+ *     return has written nothing.  mm_last_error() gives a message for the
+ *     last non-OK status on the calling thread.  Faults inside kernels
+ *     surface as MM_EDEVICE at the next call that synchronises.
+ *   - A handle is not thread-safe; distinct handles may be used concurrently
+ *     on distinct streams.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_scan_s* mm_scan;   /* opaque, owned by the library */
+
+typedef enum {
+  MM_OK = 0,
+  MM_ENOCONV = 1,      /* non-fatal: PCG hit maxiter; x holds the last iterate */
+  MM_EINVAL = -1,      /* bad argument; nothing was written */
+  MM_ENOMEM = -2,      /* workspace too small */
+  MM_EDEVICE = -3,     /* HIP runtime / kernel error */
+  MM_ENOTBUILT = -4,   /* preconditioner requested before mm_build_precon */
+  MM_EBREAKDOWN = -5   /* PCG breakdown (p.Ap <= 0, r.z <= 0 or non-finite);
+                          x holds the last good iterate */
+} mm_status;
+
+typedef enum { MM_F32 = 0, MM_BF16 = 1, MM_F64 = 2 } mm_dtype;
+
+typedef enum {
+  MM_M_NONE = 0,       /* identity */
+  MM_M_JACOBI = 1,     /* eq. 5: per-pixel blocks of P^T P */
+  MM_M_BINNED = 2,     /* eq. 3-4: per-pixel blocks of P^T diag(N^-1_tt) P */
+  MM_M_CIRCULANT = 3   /* eq. 8-13: Sigma^-1 F^-1 K(k)^-1 F Sigma^-T */
+} mm_precon;
+
+/* Description of one scan (one set of detector timestreams and pointing). */
+typedef struct {
+  int32_t ncomp;            /* 1 (I) or 3 (I,Q,U) */
+  int32_t ny, nx;           /* map shape; powers of two in [4, 4096] */
+  int32_t ndet;             /* detectors, >= 1 */
+  int32_t tod_dtype;        /* mm_dtype of the timestream arithmetic:
+                               MM_F32 (FFT and filter in float32) or
+                               MM_F64 (everything in float64) */
+  int64_t nsamp;            /* samples per detector: power of two, 16 ..2^22 */
+  double  fsample;          /* sample rate in Hz (reporting only) */
+  const int32_t* pix;       /* [ndet][nsamp] pixel id, -1 = off-map (zero row
+                               of P).  BORROWED: must stay valid and unchanged
+                               until mm_destroy_scan. */
+  const float* cos2psi;     /* [ndet][nsamp] weight of Q; NULL iff ncomp == 1. BORROWED */
+  const float* sin2psi;     /* [ndet][nsamp] weight of U; NULL iff ncomp == 1. BORROWED */
+  const float* inv_noise;   /* [ndet][nsamp/2+1] 1/N_d(f_k) on the real-FFT
+                               frequencies k = 0..nsamp/2; must be finite and
+                               >= 0.  BORROWED */
+  void*   workspace;        /* device memory of at least workspace_bytes, 256-byte
+                               aligned; owned by the caller, used by the library
+                               until mm_destroy_scan */
+  size_t  workspace_bytes;
+  int32_t det_group;        /* detectors per filter-pipeline group; 0 = automatic.
+                               Bounds the timestream scratch in the workspace. */
+  int32_t fft_m1;           /* four-step FFT split (0 = automatic): the packed
+                               complex length nsamp/2 = fft_m1 * (nsamp/2/fft_m1) */
+  double  mask_rcond;       /* I,Q,U activity threshold on lambda_min/lambda_max of
+                               the binned block; <= 0 selects 1e-3 */
+} mm_scan_desc;
+
+/* Bytes of device workspace the scan needs (the caller allocates it and puts
+ * the pointer in desc->workspace).  Only the shape fields and the tuning
+ * fields (det_group, fft_m1, tod_dtype) are read.  Returns 0 and sets
+ * mm_last_error() on an invalid description. */
+size_t mm_scan_workspace_bytes(const mm_scan_desc* desc /*[host]*/);
+
+/* Creates a scan handle: validates desc, uploads FFT twiddle tables into the
+ * workspace, and computes on `stream` the per-detector binned weights
+ * w_d = (N^-1)_tt (eq. 3-4), the hit counts, the binned and Jacobi blocks and
+ * the active-pixel mask.  Synchronises `stream`.  *out receives the handle. */
+mm_status mm_create_scan(const mm_scan_desc* desc /*[host]*/, void* stream,
+                         mm_scan* out /*[host]*/);
+
+/* Releases the handle (never frees caller memory).  NULL is a no-op. */
+void mm_destroy_scan(mm_scan scan);
+
+/* b = P^T N^-1 d (right-hand side of eq. 2) on the active pixels.
+ * tod: [ndet][nsamp] in the scan's tod_dtype (float or double).
+ * b: [ncomp][ny][nx] float64, overwritten. */
+mm_status mm_rhs(mm_scan scan, const void* tod, double* b, void* stream);
+
+/* y = A x = P^T N^-1 P x (eq. 2), the per-iteration operator: a nearest-pixel
+ * gather of x into timestreams, a per-detector real FFT, multiplication by
+ * 1/N(f), the inverse FFT, and an atomic scatter-add back to pixels
+ * (accumulated in float64).  x, y: [ncomp][ny][nx] float64; y is
+ * overwritten; x and y must not overlap. */
+mm_status mm_apply_A(mm_scan scan, const double* x, double* y, void* stream);
+
+/* Options of the circulant preconditioner (Implementation, Regularization and
+ * Polarization sections). */
+typedef struct {
+  int32_t ref_y, ref_x;     /* reference pixel; -1: the active pixel nearest
+                               (ny/2, nx/2), smallest id on ties */
+  double  gauss_sigma_px;   /* Gaussian taper of q (Regularization section);
+                               <= 0 disables it */
+  int32_t symmetrize;       /* 1: q(d) <- (q(d) + q(-d)^T)/2 and a Hermitian
+                               eigenvalue floor; 0: eq. 12 literally (general
+                               3x3 inverse per wavenumber, no floor) */
+  double  eig_floor_rel;    /* floor = eig_floor_rel * max eigenvalue over all
+                               wavenumbers; <= 0 selects 1e-6 */
+} mm_precon_opts;
+
+/* Builds a preconditioner on `stream`.  JACOBI, BINNED: per-pixel inverse
+ * blocks (already prepared by mm_create_scan; this is a no-op).  CIRCULANT:
+ * Sigma = B^(1/2) from the binned blocks (eq. 7), ncomp probes A e_(r,g)
+ * (eq. 6), q (eq. 10/13), taper, optional symmetrisation, 2-D FFT (eq. 11),
+ * per-wavenumber inverse.  Synchronises `stream`.  opts may be NULL for
+ * defaults (no taper, symmetrize = 1, eig_floor_rel = 1e-6). */
+mm_status mm_build_precon(mm_scan scan, int32_t precon /*mm_precon*/,
+                          const mm_precon_opts* opts /*[host]*/, void* stream);
+
+/* z = M r for the binned (eq. 3-4) or, with precon = MM_M_JACOBI, the Jacobi
+ * (eq. 5) preconditioner: z_p = B_p^-1 r_p per active pixel. */
+mm_status mm_apply_precon_binned(mm_scan scan, int32_t precon, const double* r,
+                                 double* z, void* stream);
+
+/* z = M_C r = Sigma^-1 F^-1 K^-1 F Sigma^-T r (eq. 12).  MM_ENOTBUILT if the
+ * circulant preconditioner was not built. */
+mm_status mm_apply_precon_circulant(mm_scan scan, const double* r, double* z,
+                                    void* stream);
+
+typedef struct {
+  double  tol;              /* stop when ||r||_2 <= tol ||b||_2 (recursive residual) */
+  int32_t maxiter;          /* maximum A-applies in the loop */
+  int32_t check_every;      /* read the residual on the host every k iterations (>= 1) */
+  int32_t use_x0;           /* 1: start from the x passed in; 0: x0 = 0 */
+} mm_pcg_opts;
+
+typedef struct {
+  int32_t iters;            /* A-applies performed in the loop */
+  int32_t converged;        /* 1 if ||r|| <= tol ||b|| was reached */
+  double  rel_resid;        /* final recursive ||r|| / ||b|| */
+  double  t_solve_s;        /* wall time of the solve */
+  double* history;          /* [host] optional (may be NULL): ||r_k||/||b|| for
+                               k = 0..iters, array of at least maxiter+1 */
+  double* alpha;            /* [host] optional: alpha_k, k = 0..iters-1 */
+  double* rho;              /* [host] optional: r_k.z_k, k = 0..iters-1 */
+} mm_pcg_result;
+
+/* Solves A x = b by PCG (Introduction; textbook PCG with device-resident
+ * scalars).  precon: MM_M_NONE, JACOBI, BINNED or CIRCULANT (the latter must
+ * be built).  b, x: [ncomp][ny][nx] float64 device arrays; x is overwritten
+ * with the solution.  Synchronises `stream`.  Returns MM_OK, MM_ENOCONV or
+ * MM_EBREAKDOWN (with res filled in all three cases). */
+mm_status mm_pcg_solve(mm_scan scan, int32_t precon, const double* b, double* x,
+                       const mm_pcg_opts* opts /*[host]*/,
+                       mm_pcg_result* res /*[host]*/, void* stream);
+
+/* Diagnostics of a scan handle. */
+typedef struct {
+  int32_t n_active;         /* active pixels */
+  int32_t ref_pixel;        /* circulant reference pixel id, -1 if not built */
+  int32_t n_floored;        /* eigenvalues raised by the circulant floor */
+  int32_t det_group;        /* detectors per pipeline group in use */
+  int32_t fft_m1, fft_m2;   /* four-step split in use (m1 = 1: one-pass kernel) */
+  int32_t single_pass;      /* 1 if each detector's filter runs in one kernel */
+  size_t  workspace_bytes;  /* bytes used */
+} mm_scan_info;
+
+mm_status mm_get_info(mm_scan scan, mm_scan_info* out /*[host]*/);
+
+/* Copies the active-pixel mask (int32, 1 = active) into dst [ny][nx]. */
+mm_status mm_get_mask(mm_scan scan, int32_t* dst, void* stream);
+
+/* Per-stage device timing for benchmarks: while enabled, every launch of a
+ * timed stage is bracketed by two HIP events recorded on the stream it runs
+ * on; mm_profile_read waits for them, returns the summed durations and
+ * resets.  Stages: 0 one-pass filter kernel, 1 four-step pass 1 (gather +
+ * column FFTs), 2 pass 2 (row FFTs + 1/N(f) + inverse row FFTs), 3 pass 3
+ * (inverse column FFTs + scatter), 4 one whole A-apply or right-hand side,
+ * 5 one preconditioner apply.  samples[i] counts the timestream samples
+ * (stages 0-4) or map entries (stage 5) the launches processed. */
+typedef struct {
+  int32_t n_stages;
+  double  ms[8];
+  int64_t launches[8];
+  int64_t samples[8];
+} mm_profile;
+
+mm_status mm_profile_enable(mm_scan scan, int32_t enable);
+mm_status mm_profile_read(mm_scan scan, mm_profile* out /*[host]*/);
+
+/* Thread-local message describing the last non-OK status ("" if none). */
+const char* mm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

@@ -1,0 +1,255 @@
+"""MI355X map-making library: Python binding of libmm.so (include/mm.h).
+
+The functions here have the C ABI's names and only marshal arguments
+(torch device tensors -> pointers, the current HIP stream); every step of the
+computation runs in the HIP kernels of libmm.so.  Importing the package fails
+if libmm.so has not been built.
+
+`Scan` keeps the device copies of one scan's inputs and its workspace alive
+for the lifetime of a handle.
+"""
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from ._abi import (  # noqa: F401
+    lib, check, MMError, mm_scan_desc, mm_precon_opts, mm_pcg_opts, mm_pcg_result,
+    mm_scan_info, MM_OK, MM_ENOCONV, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENOTBUILT,
+    MM_EBREAKDOWN, MM_F32, MM_BF16, MM_F64, MM_M_NONE, MM_M_JACOBI, MM_M_BINNED,
+    MM_M_CIRCULANT, LIB_PATH, mm_profile, PROFILE_STAGES,
+)
+
+PRECON = {"none": MM_M_NONE, "jacobi": MM_M_JACOBI, "binned": MM_M_BINNED,
+          "circulant": MM_M_CIRCULANT}
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------- raw ABI calls
+def mm_scan_workspace_bytes(desc):
+    return int(lib.mm_scan_workspace_bytes(C.byref(desc)))
+
+
+def mm_create_scan(desc, stream=None):
+    h = C.c_void_p()
+    check(lib.mm_create_scan(C.byref(desc), _stream(stream), C.byref(h)), "mm_create_scan")
+    return h
+
+
+def mm_destroy_scan(h):
+    lib.mm_destroy_scan(h)
+
+
+def mm_rhs(h, tod, b, stream=None):
+    check(lib.mm_rhs(h, _ptr(tod, name="tod"), _ptr(b, torch.float64, name="b"), _stream(stream)),
+          "mm_rhs")
+
+
+def mm_apply_A(h, x, y, stream=None):
+    check(lib.mm_apply_A(h, _ptr(x, torch.float64, name="x"), _ptr(y, torch.float64, name="y"),
+                         _stream(stream)), "mm_apply_A")
+
+
+def mm_build_precon(h, precon, opts=None, stream=None):
+    o = None if opts is None else C.byref(opts)
+    check(lib.mm_build_precon(h, int(precon), o, _stream(stream)), "mm_build_precon")
+
+
+def mm_apply_precon_binned(h, precon, r, z, stream=None):
+    check(lib.mm_apply_precon_binned(h, int(precon), _ptr(r, torch.float64, name="r"),
+                                     _ptr(z, torch.float64, name="z"), _stream(stream)),
+          "mm_apply_precon_binned")
+
+
+def mm_apply_precon_circulant(h, r, z, stream=None):
+    check(lib.mm_apply_precon_circulant(h, _ptr(r, torch.float64, name="r"),
+                                        _ptr(z, torch.float64, name="z"), _stream(stream)),
+          "mm_apply_precon_circulant")
+
+
+def mm_pcg_solve(h, precon, b, x, opts, stream=None, history_len=0):
+    """Returns (status, result dict).  MM_ENOCONV is returned, not raised."""
+    res = mm_pcg_result()
+    hist = alpha = rho = None
+    if history_len:
+        hist = (C.c_double * (history_len + 1))()
+        alpha = (C.c_double * history_len)()
+        rho = (C.c_double * history_len)()
+        res.history = C.cast(hist, C.POINTER(C.c_double))
+        res.alpha = C.cast(alpha, C.POINTER(C.c_double))
+        res.rho = C.cast(rho, C.POINTER(C.c_double))
+    st = lib.mm_pcg_solve(h, int(precon), _ptr(b, torch.float64, name="b"),
+                          _ptr(x, torch.float64, name="x"), C.byref(opts), C.byref(res),
+                          _stream(stream))
+    if st not in (MM_OK, MM_ENOCONV, MM_EBREAKDOWN):
+        check(st, "mm_pcg_solve")
+    out = dict(status=st, iters=res.iters, converged=bool(res.converged),
+               rel_resid=res.rel_resid, t_solve_s=res.t_solve_s)
+    if history_len:
+        n = min(res.iters, history_len)
+        out["history"] = np.array(hist[: n + 1])
+        out["alpha"] = np.array(alpha[:n])
+        out["rho"] = np.array(rho[:n])
+    return st, out
+
+
+def mm_get_info(h):
+    info = mm_scan_info()
+    check(lib.mm_get_info(h, C.byref(info)), "mm_get_info")
+    return {k: getattr(info, k) for k, _ in mm_scan_info._fields_}
+
+
+def mm_get_mask(h, dst, stream=None):
+    check(lib.mm_get_mask(h, _ptr(dst, torch.int32, name="dst"), _stream(stream)), "mm_get_mask")
+
+
+def mm_profile_enable(h, enable=True):
+    check(lib.mm_profile_enable(h, 1 if enable else 0), "mm_profile_enable")
+
+
+def mm_profile_read(h):
+    """Synchronises the timed launches; returns {stage: (ms, launches, samples)}."""
+    p = mm_profile()
+    check(lib.mm_profile_read(h, C.byref(p)), "mm_profile_read")
+    return {PROFILE_STAGES[i]: (p.ms[i], p.launches[i], p.samples[i])
+            for i in range(p.n_stages) if PROFILE_STAGES[i] and p.launches[i]}
+
+
+def mm_last_error():
+    return lib.mm_last_error().decode(errors="replace")
+
+
+# ---------------------------------------------------------------- Scan owner
+class Scan:
+    """Device copies of one scan's inputs, its workspace and its handle.
+
+    inputs: an object with ncomp, ny, nx, ndet (pix.shape[0]), nsamp, fsample,
+    pix (int32 [ndet][nsamp]), cos2psi/sin2psi (float32 or None) and
+    inv_noise (float32 [ndet][nsamp/2+1]) as numpy arrays or device tensors.
+    """
+
+    def __init__(self, inputs, tod_dtype="f32", det_group=0, fft_m1=0, mask_rcond=0.0,
+                 device="cuda", stream=None):
+        self.device = torch.device(device)
+        dev = self.device
+
+        def up(a, dt):
+            if a is None:
+                return None
+            if isinstance(a, torch.Tensor):
+                return a.to(device=dev, dtype=dt).contiguous()
+            return torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)
+
+        self.pix = up(inputs.pix, torch.int32)
+        self.cos2psi = up(inputs.cos2psi, torch.float32)
+        self.sin2psi = up(inputs.sin2psi, torch.float32)
+        self.inv_noise = up(inputs.inv_noise, torch.float32)
+        self.ncomp, self.ny, self.nx = int(inputs.ncomp), int(inputs.ny), int(inputs.nx)
+        self.ndet, self.nsamp = int(self.pix.shape[0]), int(self.pix.shape[1])
+        self.npix = self.ny * self.nx
+        self.tod_dtype = {"f32": MM_F32, "f64": MM_F64}[tod_dtype]
+        self.real_dtype = torch.float32 if tod_dtype == "f32" else torch.float64
+        d = mm_scan_desc()
+        d.ncomp, d.ny, d.nx, d.ndet = self.ncomp, self.ny, self.nx, self.ndet
+        d.tod_dtype = self.tod_dtype
+        d.nsamp = self.nsamp
+        d.fsample = float(getattr(inputs, "fsample", 0.0))
+        d.pix = self.pix.data_ptr()
+        d.cos2psi = self.cos2psi.data_ptr() if self.cos2psi is not None else None
+        d.sin2psi = self.sin2psi.data_ptr() if self.sin2psi is not None else None
+        d.inv_noise = self.inv_noise.data_ptr()
+        d.det_group = int(det_group)
+        d.fft_m1 = int(fft_m1)
+        d.mask_rcond = float(mask_rcond)
+        nbytes = mm_scan_workspace_bytes(d)
+        if nbytes == 0:
+            raise MMError(MM_EINVAL, "mm_scan_workspace_bytes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        d.workspace = (base + 255) // 256 * 256
+        d.workspace_bytes = nbytes
+        self.desc = d
+        self.handle = mm_create_scan(d, stream)
+
+    # convenience wrappers (allocate outputs, same names)
+    def new_map(self):
+        return torch.zeros(self.ncomp * self.npix, dtype=torch.float64, device=self.device)
+
+    def apply_A(self, x, y=None, stream=None):
+        y = self.new_map() if y is None else y
+        mm_apply_A(self.handle, x, y, stream)
+        return y
+
+    def rhs(self, tod, b=None, stream=None):
+        b = self.new_map() if b is None else b
+        tod = tod.to(device=self.device, dtype=self.real_dtype).contiguous()
+        mm_rhs(self.handle, tod, b, stream)
+        return b
+
+    def build_precon(self, name, ref=None, sigma=0.0, symmetrize=True, eig_floor_rel=0.0,
+                     stream=None):
+        o = mm_precon_opts()
+        o.ref_y, o.ref_x = (-1, -1) if ref is None else (int(ref[0]), int(ref[1]))
+        o.gauss_sigma_px = float(sigma) if sigma else 0.0
+        o.symmetrize = 1 if symmetrize else 0
+        o.eig_floor_rel = float(eig_floor_rel)
+        mm_build_precon(self.handle, PRECON[name], o, stream)
+
+    def apply_precon(self, name, r, z=None, stream=None):
+        z = self.new_map() if z is None else z
+        if name == "circulant":
+            mm_apply_precon_circulant(self.handle, r, z, stream)
+        else:
+            mm_apply_precon_binned(self.handle, PRECON[name], r, z, stream)
+        return z
+
+    def pcg(self, name, b, x=None, tol=1e-6, maxiter=5000, check_every=1, x0=False,
+            history=True, stream=None):
+        x = self.new_map() if x is None else x
+        o = mm_pcg_opts()
+        o.tol, o.maxiter, o.check_every, o.use_x0 = float(tol), int(maxiter), int(check_every), int(x0)
+        st, res = mm_pcg_solve(self.handle, PRECON[name], b, x, o, stream,
+                               history_len=maxiter if history else 0)
+        res["x"] = x
+        return res
+
+    def info(self):
+        return mm_get_info(self.handle)
+
+    def mask(self, stream=None):
+        m = torch.empty(self.npix, dtype=torch.int32, device=self.device)
+        mm_get_mask(self.handle, m, stream)
+        return m
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            mm_destroy_scan(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

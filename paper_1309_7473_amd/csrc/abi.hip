@@ -1,0 +1,229 @@
+// The extern "C" entry points declared in include/mm.h: argument validation
+// (before anything is enqueued), handle lifetime and the thread-local error
+// message.  The compute lives in filter.hip, binned.hip, circulant.hip and
+// pcg.hip.
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+mm_status fail(mm_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+mm_status hip_check(hipError_t e, const char* what) {
+  g_err = std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ") in " + what;
+  return MM_EDEVICE;
+}
+
+static constexpr uint64_t kMagic = 0x6d6d5f7363616e31ull;  // "mm_scan1"
+
+struct Handle {
+  uint64_t magic;
+  ScanImpl impl;
+};
+
+static bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static mm_status validate_shape(const mm_scan_desc* d) {
+  if (!d) return fail(MM_EINVAL, "desc is NULL");
+  if (d->ncomp != 1 && d->ncomp != 3) return fail(MM_EINVAL, "ncomp must be 1 or 3");
+  if (!pow2(d->ny) || !pow2(d->nx) || d->ny < 4 || d->nx < 4 || d->ny > 4096 || d->nx > 4096)
+    return fail(MM_EINVAL, "ny and nx must be powers of two in [4, 4096]");
+  if (d->ndet < 1) return fail(MM_EINVAL, "ndet must be >= 1");
+  if (!pow2(d->nsamp) || d->nsamp < 16 || d->nsamp > (int64_t(1) << 22))
+    return fail(MM_EINVAL, "nsamp must be a power of two in [16, 2^22]");
+  if (d->tod_dtype != MM_F32 && d->tod_dtype != MM_F64)
+    return fail(MM_EINVAL, "tod_dtype must be MM_F32 or MM_F64");
+  if (d->det_group < 0) return fail(MM_EINVAL, "det_group must be >= 0");
+  if (d->fft_m1 < 0 || (d->fft_m1 > 0 && !pow2(d->fft_m1)))
+    return fail(MM_EINVAL, "fft_m1 must be 0 or a power of two");
+  return MM_OK;
+}
+
+static ScanImpl* get(mm_scan h) {
+  Handle* hh = reinterpret_cast<Handle*>(h);
+  if (!hh || hh->magic != kMagic) return nullptr;
+  return &hh->impl;
+}
+
+}  // namespace mm
+
+using namespace mm;
+
+extern "C" {
+
+const char* mm_last_error(void) { return g_err.c_str(); }
+
+size_t mm_scan_workspace_bytes(const mm_scan_desc* desc) {
+  if (validate_shape(desc) != MM_OK) return 0;
+  Plan pl;
+  Layout L;
+  if (plan_and_layout(desc, &pl, &L) != MM_OK) return 0;
+  return L.total;
+}
+
+mm_status mm_create_scan(const mm_scan_desc* desc, void* stream, mm_scan* out) {
+  if (!out) return fail(MM_EINVAL, "out is NULL");
+  *out = nullptr;
+  mm_status r = validate_shape(desc);
+  if (r != MM_OK) return r;
+  if (!desc->pix || !desc->inv_noise) return fail(MM_EINVAL, "pix and inv_noise are required");
+  if ((desc->ncomp == 3) != (desc->cos2psi != nullptr && desc->sin2psi != nullptr))
+    return fail(MM_EINVAL, "cos2psi/sin2psi must be given iff ncomp == 3");
+  if (desc->ncomp == 1 && (desc->cos2psi || desc->sin2psi))
+    return fail(MM_EINVAL, "cos2psi/sin2psi must be NULL when ncomp == 1");
+  Plan pl;
+  Layout L;
+  if ((r = plan_and_layout(desc, &pl, &L)) != MM_OK) return r;
+  if (!desc->workspace) return fail(MM_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(desc->workspace) % 256 != 0)
+    return fail(MM_EINVAL, "workspace must be 256-byte aligned");
+  if (desc->workspace_bytes < L.total)
+    return fail(MM_ENOMEM, "workspace_bytes smaller than mm_scan_workspace_bytes()");
+  Handle* h = new (std::nothrow) Handle;
+  if (!h) return fail(MM_ENOMEM, "host allocation failed");
+  h->magic = kMagic;
+  ScanImpl& s = h->impl;
+  s.d = *desc;
+  s.nc = desc->ncomp;
+  s.ny = desc->ny;
+  s.nx = desc->nx;
+  s.ndet = desc->ndet;
+  s.npix = desc->ny * desc->nx;
+  s.n = desc->nsamp;
+  s.plan = pl;
+  s.lay = L;
+  s.ws = static_cast<char*>(desc->workspace);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((r = upload_tables(&s, st)) != MM_OK || (r = binned_setup(&s, st)) != MM_OK) {
+    h->magic = 0;
+    delete h;
+    return r;
+  }
+  *out = reinterpret_cast<mm_scan>(h);
+  return MM_OK;
+}
+
+void mm_destroy_scan(mm_scan scan) {
+  Handle* h = reinterpret_cast<Handle*>(scan);
+  if (!h || h->magic != kMagic) return;
+  h->magic = 0;
+  profile_free(&h->impl);
+  delete h;
+}
+
+mm_status mm_rhs(mm_scan scan, const void* tod, double* b, void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  if (!tod || !b) return fail(MM_EINVAL, "tod and b are required");
+  return filter_pipeline(s, 1, tod, nullptr, b, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_apply_A(mm_scan scan, const double* x, double* y, void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  if (!x || !y) return fail(MM_EINVAL, "x and y are required");
+  const size_t bytes = size_t(s->nc) * s->npix * 8;
+  const char* xa = reinterpret_cast<const char*>(x);
+  const char* ya = reinterpret_cast<const char*>(y);
+  if (xa < ya + bytes && ya < xa + bytes) return fail(MM_EINVAL, "x and y overlap");
+  return filter_pipeline(s, 0, nullptr, x, y, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_build_precon(mm_scan scan, int32_t precon, const mm_precon_opts* opts, void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  switch (precon) {
+    case MM_M_NONE:
+    case MM_M_JACOBI:
+    case MM_M_BINNED:
+      return MM_OK;
+    case MM_M_CIRCULANT: {
+      if (opts) {
+        if ((opts->ref_y >= 0) != (opts->ref_x >= 0) || opts->ref_y >= s->ny || opts->ref_x >= s->nx)
+          return fail(MM_EINVAL, "ref_y/ref_x out of range");
+      }
+      return circulant_build(s, opts, static_cast<hipStream_t>(stream));
+    }
+    default:
+      return fail(MM_EINVAL, "unknown preconditioner");
+  }
+}
+
+mm_status mm_apply_precon_binned(mm_scan scan, int32_t precon, const double* r, double* z,
+                                 void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  if (!r || !z) return fail(MM_EINVAL, "r and z are required");
+  if (precon != MM_M_BINNED && precon != MM_M_JACOBI)
+    return fail(MM_EINVAL, "precon must be MM_M_BINNED or MM_M_JACOBI");
+  return binned_apply(s, precon == MM_M_JACOBI, r, z, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_apply_precon_circulant(mm_scan scan, const double* r, double* z, void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  if (!r || !z) return fail(MM_EINVAL, "r and z are required");
+  return circulant_apply(s, r, z, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_pcg_solve(mm_scan scan, int32_t precon, const double* b, double* x,
+                       const mm_pcg_opts* opts, mm_pcg_result* res, void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  if (!b || !x || !opts) return fail(MM_EINVAL, "b, x and opts are required");
+  if (!(opts->tol >= 0.0) || opts->maxiter < 0) return fail(MM_EINVAL, "bad tol or maxiter");
+  if (precon < MM_M_NONE || precon > MM_M_CIRCULANT) return fail(MM_EINVAL, "unknown preconditioner");
+  if (precon == MM_M_CIRCULANT && !s->circ_built)
+    return fail(MM_ENOTBUILT, "circulant preconditioner not built");
+  const size_t bytes = size_t(s->nc) * s->npix * 8;
+  const char* ba = reinterpret_cast<const char*>(b);
+  const char* xa = reinterpret_cast<const char*>(x);
+  if (ba < xa + bytes && xa < ba + bytes) return fail(MM_EINVAL, "b and x overlap");
+  return pcg_solve(s, precon, b, x, opts, res, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_get_info(mm_scan scan, mm_scan_info* out) {
+  ScanImpl* s = get(scan);
+  if (!s || !out) return fail(MM_EINVAL, "invalid scan handle or out");
+  out->n_active = s->n_active;
+  out->ref_pixel = s->circ_built ? s->ref_pixel : -1;
+  out->n_floored = s->n_floored;
+  out->det_group = s->plan.G;
+  out->fft_m1 = s->plan.single ? 1 : (1 << s->plan.logM1);
+  out->fft_m2 = s->plan.single ? (1 << s->plan.logM) : (1 << s->plan.logM2);
+  out->single_pass = s->plan.single ? 1 : 0;
+  out->workspace_bytes = s->lay.total;
+  return MM_OK;
+}
+
+mm_status mm_get_mask(mm_scan scan, int32_t* dst, void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s || !dst) return fail(MM_EINVAL, "invalid scan handle or dst");
+  MM_HIP(hipMemcpyAsync(dst, s->ws + s->lay.mask, size_t(s->npix) * 4, hipMemcpyDeviceToDevice,
+                        static_cast<hipStream_t>(stream)));
+  return MM_OK;
+}
+
+mm_status mm_profile_enable(mm_scan scan, int32_t enable) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  return profile_enable(s, enable != 0);
+}
+
+mm_status mm_profile_read(mm_scan scan, mm_profile* out) {
+  ScanImpl* s = get(scan);
+  if (!s || !out) return fail(MM_EINVAL, "invalid scan handle or out");
+  return profile_read(s, out);
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// Batched power-of-two complex FFTs on data resident in LDS.
+//
+// Radix-8/4/2 Stockham autosort: every stage reads R points spaced L/R apart,
+// applies the twiddles W_{Ns R}^{r k}, k = j mod Ns, does a length-R DFT in
+// registers and writes the R results Ns apart into the autosorted position.
+// The stage works in place in LDS: all loads of a stage go to registers
+// before a barrier, the stores follow it.  Output is in natural order.
+//
+// Layout: transform b (0 <= b < B) has its element j at buf[b*bs + j*es].
+// Work items (one butterfly each) are spread over the NT threads of the
+// block, at most E/R per thread (so B*L <= E*NT).  With batch_fast the batch
+// index varies fastest across threads (contiguous columns: es = B, bs = 1);
+// otherwise the element index does (contiguous rows: es = 1).
+//
+// Twiddles come from a table tw[m] = W_Lmax^m, m < Lmax, computed in float64
+// on the host and rounded once; a length-L transform reads it with stride
+// Lmax/L.  Forward uses W = exp(-2 pi i / L); inverse uses conj and is
+// unnormalised.
+#pragma once
+#include "mm_device.h"
+
+namespace mm {
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_reg(Cx<T> (&v)[R]) {
+  if constexpr (R == 2) {
+    Cx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  } else if constexpr (R == 4) {
+    Cx<T> a0 = v[0] + v[2], a1 = v[0] - v[2];
+    Cx<T> b0 = v[1] + v[3], b1 = v[1] - v[3];
+    b1 = INV ? mul_pi(b1) : mul_mi(b1);
+    v[0] = a0 + b0;
+    v[2] = a0 - b0;
+    v[1] = a1 + b1;
+    v[3] = a1 - b1;
+  } else if constexpr (R == 8) {
+    const T h = T(0.70710678118654752440084436210485);
+    Cx<T> a[4], b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a[r] = v[r] + v[r + 4];
+      b[r] = v[r] - v[r + 4];
+    }
+    // b[r] *= W8^r (forward) or conj (inverse)
+    if constexpr (!INV) {
+      b[1] = cx(h * (b[1].x + b[1].y), h * (b[1].y - b[1].x));
+      b[2] = mul_mi(b[2]);
+      b[3] = cx(h * (b[3].y - b[3].x), -h * (b[3].x + b[3].y));
+    } else {
+      b[1] = cx(h * (b[1].x - b[1].y), h * (b[1].y + b[1].x));
+      b[2] = mul_pi(b[2]);
+      b[3] = cx(-h * (b[3].x + b[3].y), h * (b[3].x - b[3].y));
+    }
+    dft_reg<T, 4, INV>(a);
+    dft_reg<T, 4, INV>(b);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      v[2 * m] = a[m];
+      v[2 * m + 1] = b[m];
+    }
+  }
+}
+
+struct FftShape {
+  int logL;      // transform length L = 2^logL
+  int logB;      // batch count B = 2^logB
+  int es, bs;    // element / batch strides (in complex elements)
+  bool batch_fast;
+  int logLmax;   // table length
+};
+
+template <typename T, int R, int NT, int E, bool INV>
+__device__ __forceinline__ void stockham_stage(Cx<T>* __restrict__ buf, const FftShape& s,
+                                               int logNs, const Cx<T>* __restrict__ tw) {
+  constexpr int NB = E / R;
+  constexpr int logR = (R == 8) ? 3 : (R == 4) ? 2 : 1;
+  const int logLR = s.logL - logR;
+  const int LR = 1 << logLR;
+  const int nbf = 1 << (s.logB + logLR);
+  const int Ns = 1 << logNs;
+  // twiddle index step: r * k * (L / (Ns R)) in units of the L-table, times Lmax/L
+  const int tshift = (s.logL - logNs - logR) + (s.logLmax - s.logL);
+  Cx<T> v[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int w = threadIdx.x + i * NT;
+    if (w < nbf) {
+      int b, j;
+      if (s.batch_fast) {
+        b = w & ((1 << s.logB) - 1);
+        j = w >> s.logB;
+      } else {
+        j = w & (LR - 1);
+        b = w >> logLR;
+      }
+      const Cx<T>* base = buf + b * s.bs + j * s.es;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = base[(r * LR) * s.es];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int w = threadIdx.x + i * NT;
+    if (w < nbf) {
+      int b, j;
+      if (s.batch_fast) {
+        b = w & ((1 << s.logB) - 1);
+        j = w >> s.logB;
+      } else {
+        j = w & (LR - 1);
+        b = w >> logLR;
+      }
+      const int k = j & (Ns - 1);
+      if (logNs > 0) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          Cx<T> t = tw[(r * k) << tshift];
+          if (INV) t.y = -t.y;
+          v[i][r] = v[i][r] * t;
+        }
+      }
+      dft_reg<T, R, INV>(v[i]);
+      const int out = ((j - k) << logR) + k;
+      Cx<T>* base = buf + b * s.bs + out * s.es;
+#pragma unroll
+      for (int r = 0; r < R; ++r) base[(r * Ns) * s.es] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform; must be called by all NT threads of the block.
+template <typename T, int NT, int E, bool INV>
+__device__ __forceinline__ void lds_fft(Cx<T>* __restrict__ buf, const FftShape& s,
+                                        const Cx<T>* __restrict__ tw) {
+  int logNs = 0;
+  int rem = s.logL;
+  if (rem % 3 == 1) {
+    stockham_stage<T, 2, NT, E, INV>(buf, s, logNs, tw);
+    logNs += 1;
+    rem -= 1;
+  } else if (rem % 3 == 2) {
+    stockham_stage<T, 4, NT, E, INV>(buf, s, logNs, tw);
+    logNs += 2;
+    rem -= 2;
+  }
+  while (rem >= 3) {
+    stockham_stage<T, 8, NT, E, INV>(buf, s, logNs, tw);
+    logNs += 3;
+    rem -= 3;
+  }
+}
+
+}  // namespace mm

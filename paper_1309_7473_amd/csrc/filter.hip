@@ -1,0 +1,572 @@
+// The per-iteration operator A = P^T N^-1 P and the right-hand side
+// b = P^T N^-1 d (paper eq. 2) on gfx950.
+//
+// Per detector the real timestream t (n samples) is viewed as n/2 packed
+// complex values z[j] = t[2j] + i t[2j+1], so the data never moves to be
+// packed.  The length-M = n/2 complex FFT of z gives the real spectrum
+// X[k], k = 0..M, through the Hermitian pair (k, M-k):
+//   E = (Z[k] + conj Z[M-k]) / 2,  O = (Z[k] - conj Z[M-k]) / (2i),
+//   X[k] = E + W_n^k O,  X[M-k] = conj(E - W_n^k O).
+// After Y = X / N(f) the same pair gives the packed spectrum of the filtered
+// timestream, and the inverse length-M FFT (scaled by 1/M) returns it packed.
+// Each pair (k, M-k) is filtered where both ends sit in LDS.
+//
+// Small n (M <= 8192 complex): one block per detector does gather, FFT,
+// filter, inverse FFT and scatter in LDS (one kernel, no timestream traffic).
+// Large n: four-step split M = M1 * M2 (index j = j1*M2 + j2, frequency
+// k = k1 + M1*k2) in three kernels per group of detectors:
+//   pass 1: gather P x (or read d) into C columns x M1 rows, length-M1 FFTs
+//           down the columns, store;
+//   pass 2: rows k1 and M1-k1 together: twiddle W_M^{k1 j2}, length-M2 FFTs,
+//           pair filter (the partner of (k1,k2) is (M1-k1, M2-1-k2)), inverse
+//           FFTs, conjugate twiddle, store;
+//   pass 3: inverse length-M1 column FFTs, then scatter P^T back to pixels.
+// The scatter pre-sums runs of equal pixels across the lanes of a wavefront
+// and accumulates with float64 atomics into a [npix][4] accumulator.
+#include <vector>
+#include <cmath>
+
+#include "fft_lds.h"
+#include "mm_internal.h"
+
+namespace mm {
+
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+  T x, y, z, w;
+};
+
+template <typename T>
+struct PassArgs {
+  const int32_t* pix;   // group base [G][n]
+  const float* c2;
+  const float* s2;
+  const float* iN;      // group base [G][M+1]
+  const T* tod;         // group base [G][n] (rhs source)
+  const V4<T>* gmap;    // [npix]
+  double* acc;          // [npix][4]
+  Cx<T>* work;          // [G][M]
+  const Cx<T>* tw;      // Stockham table W_Lmax^m
+  TwoLevel<T> wn;       // W_n^m
+  int64_t n;
+  int npix;
+  int logM, logM1, logM2, logC, logLmax;
+  T scale;              // 1/M
+};
+
+// --------------------------------------------------------------- samples
+template <typename T, int NC, int SRC>
+__device__ __forceinline__ T source_sample(const PassArgs<T>& a, int64_t s) {
+  if constexpr (SRC == 1) {
+    return a.tod[s];
+  } else {
+    const int p = a.pix[s];
+    if (unsigned(p) >= unsigned(a.npix)) return T(0);
+    const V4<T> m = a.gmap[p];
+    if constexpr (NC == 3) {
+      return m.x + T(a.c2[s]) * m.y + T(a.s2[s]) * m.z;
+    } else {
+      return m.x;
+    }
+  }
+}
+
+// Scatter one sample per lane; must be reached by every lane of the wave
+// (inactive lanes pass s < 0).
+template <typename T, int NC>
+__device__ __forceinline__ void scatter_sample(const PassArgs<T>& a, int64_t s, T u) {
+  int p = -1;
+  double v[NC];
+  v[0] = 0.0;
+  if constexpr (NC == 3) {
+    v[1] = 0.0;
+    v[2] = 0.0;
+  }
+  if (s >= 0) {
+    p = a.pix[s];
+    if (unsigned(p) >= unsigned(a.npix)) p = -1;
+    const double ud = double(u);
+    v[0] = ud;
+    if constexpr (NC == 3) {
+      v[1] = double(a.c2[s]) * ud;
+      v[2] = double(a.s2[s]) * ud;
+    }
+  }
+  if (wave_segmented_sum<3, NC>(p, v)) {
+    double* dst = a.acc + 4 * int64_t(p);
+    atomic_add_f64(dst + 0, v[0]);
+    if constexpr (NC == 3) {
+      atomic_add_f64(dst + 1, v[1]);
+      atomic_add_f64(dst + 2, v[2]);
+    }
+  }
+}
+
+// Filter the Hermitian pair (Z[k], Z[M-k]) in place; W = W_n^k, a = iN[k]/M,
+// b = iN[M-k]/M.
+template <typename T>
+__device__ __forceinline__ void pair_filter(Cx<T>& Zk, Cx<T>& Zmk, Cx<T> W, T a, T b) {
+  const T h = T(0.5);
+  const Cx<T> E = cx(h * (Zk.x + Zmk.x), h * (Zk.y - Zmk.y));
+  const Cx<T> D = cx(h * (Zk.x - Zmk.x), h * (Zk.y + Zmk.y));
+  const Cx<T> O = cx(D.y, -D.x);
+  const Cx<T> WO = W * O;
+  const T sp = h * (a + b), sm = h * (a - b);
+  const Cx<T> Ep = cx(sp * E.x + sm * WO.x, sp * E.y + sm * WO.y);
+  const Cx<T> Op = cx(sm * E.x + sp * WO.x, sm * E.y + sp * WO.y) * conj(W);
+  Zk = cx(Ep.x - Op.y, Ep.y + Op.x);
+  Zmk = cx(Ep.x + Op.y, Op.x - Ep.y);
+}
+
+// DC / Nyquist bin: Z[0] carries X[0] = Re+Im and X[M] = Re-Im.
+template <typename T>
+__device__ __forceinline__ Cx<T> dc_filter(Cx<T> Z0, T a0, T aM) {
+  const T y0 = a0 * (Z0.x + Z0.y);
+  const T yM = aM * (Z0.x - Z0.y);
+  return cx(T(0.5) * (y0 + yM), T(0.5) * (y0 - yM));
+}
+
+// ------------------------------------------------------ prologue / epilogue
+template <typename T>
+__global__ void k_prologue(const double* __restrict__ x, const int32_t* __restrict__ mask,
+                           V4<T>* __restrict__ gmap, double* __restrict__ acc, int npix, int nc) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  const bool on = mask[p] != 0;
+  V4<T> g;
+  g.x = on ? T(x[p]) : T(0);
+  g.y = (on && nc == 3) ? T(x[npix + p]) : T(0);
+  g.z = (on && nc == 3) ? T(x[2 * npix + p]) : T(0);
+  g.w = T(0);
+  gmap[p] = g;
+  double4 z;
+  z.x = z.y = z.z = z.w = 0.0;
+  reinterpret_cast<double4*>(acc)[p] = z;
+}
+
+__global__ void k_zero_acc(double* __restrict__ acc, int npix) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  double4 z;
+  z.x = z.y = z.z = z.w = 0.0;
+  reinterpret_cast<double4*>(acc)[p] = z;
+}
+
+__global__ void k_epilogue(const double* __restrict__ acc, const int32_t* __restrict__ mask,
+                           double* __restrict__ y, int npix, int nc) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  const bool on = mask[p] != 0;
+  const double4 a = reinterpret_cast<const double4*>(acc)[p];
+  y[p] = on ? a.x : 0.0;
+  if (nc == 3) {
+    y[npix + p] = on ? a.y : 0.0;
+    y[2 * npix + p] = on ? a.z : 0.0;
+  }
+}
+
+// ------------------------------------------------------------- single pass
+template <typename T, int NC, int SRC>
+__global__ void __launch_bounds__(kNT) k_single(PassArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
+  T* bufr = reinterpret_cast<T*>(smem);
+  const int M = 1 << a.logM;
+  const int g = blockIdx.x;
+  const int64_t base = int64_t(g) * a.n;
+  const int nsamp = 2 * M;
+  for (int e = threadIdx.x; e < nsamp; e += kNT) bufr[e] = source_sample<T, NC, SRC>(a, base + e);
+  __syncthreads();
+  FftShape sh{a.logM, 0, 1, M, false, a.logLmax};
+  lds_fft<T, kNT, kE, false>(buf, sh, a.tw);
+  const float* iN = a.iN + int64_t(g) * (M + 1);
+  for (int k = threadIdx.x; k <= M / 2; k += kNT) {
+    if (k == 0) {
+      buf[0] = dc_filter(buf[0], a.scale * T(iN[0]), a.scale * T(iN[M]));
+    } else {
+      Cx<T> zk = buf[k], zm = buf[M - k];
+      pair_filter(zk, zm, a.wn(k), a.scale * T(iN[k]), a.scale * T(iN[M - k]));
+      buf[k] = zk;
+      if (k != M - k) buf[M - k] = zm;
+    }
+  }
+  __syncthreads();
+  lds_fft<T, kNT, kE, true>(buf, sh, a.tw);
+  // every lane of a wave takes the same number of trips (the scatter shuffles)
+  for (int e0 = 0; e0 < nsamp; e0 += kNT) {
+    const int e = e0 + threadIdx.x;
+    const bool in = e < nsamp;
+    scatter_sample<T, NC>(a, in ? base + e : int64_t(-1), in ? bufr[e] : T(0));
+  }
+}
+
+// ------------------------------------------------------------- four-step
+template <typename T, int NC, int SRC>
+__global__ void __launch_bounds__(kNT) k_pass1(PassArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
+  T* bufr = reinterpret_cast<T*>(smem);
+  const int logNB = a.logM2 - a.logC;
+  const int g = blockIdx.x >> logNB;
+  const int cb = blockIdx.x & ((1 << logNB) - 1);
+  const int C = 1 << a.logC;
+  const int M1 = 1 << a.logM1, M2 = 1 << a.logM2;
+  const int j20 = cb << a.logC;
+  const int64_t base = int64_t(g) * a.n;
+  const int nsamp = 2 * C * M1;
+#pragma unroll 4
+  for (int e = threadIdx.x; e < nsamp; e += kNT) {
+    const int j1 = e >> (a.logC + 1);
+    const int q = e & (2 * C - 1);
+    const int64_t s = base + 2 * (int64_t(j1) * M2 + j20) + q;
+    bufr[e] = source_sample<T, NC, SRC>(a, s);
+  }
+  __syncthreads();
+  FftShape sh{a.logM1, a.logC, C, 1, true, a.logLmax};
+  lds_fft<T, kNT, kE, false>(buf, sh, a.tw);
+  Cx<T>* w = a.work + (int64_t(g) << a.logM);
+  for (int e = threadIdx.x; e < C * M1; e += kNT) {
+    const int k1 = e >> a.logC;
+    const int c = e & (C - 1);
+    w[int64_t(k1) * M2 + j20 + c] = buf[e];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
+  const int M1 = 1 << a.logM1, M2 = 1 << a.logM2;
+  const int M = 1 << a.logM;
+  const int lhalf = a.logM1 - 1;
+  const int g = blockIdx.x >> lhalf;
+  const int pr = blockIdx.x & ((1 << lhalf) - 1);
+  const int ra = pr;
+  const int rb = (pr == 0) ? (M1 >> 1) : (M1 - pr);
+  Cx<T>* w = a.work + (int64_t(g) << a.logM);
+  for (int e = threadIdx.x; e < 2 * M2; e += kNT) {
+    const int row = e >> a.logM2;
+    const int j2 = e & (M2 - 1);
+    const int k1 = row ? rb : ra;
+    const Cx<T> v = w[int64_t(k1) * M2 + j2];
+    buf[e] = v * a.wn(2 * int64_t(k1) * j2);
+  }
+  __syncthreads();
+  FftShape sh{a.logM2, 1, 1, M2, false, a.logLmax};
+  lds_fft<T, kNT, kE, false>(buf, sh, a.tw);
+  const float* iN = a.iN + int64_t(g) * (M + 1);
+  const T sc = a.scale;
+  if (pr != 0) {
+    for (int k2 = threadIdx.x; k2 < M2; k2 += kNT) {
+      const int k = ra + M1 * k2;
+      const int im = M2 + (M2 - 1 - k2);
+      Cx<T> zk = buf[k2], zm = buf[im];
+      pair_filter(zk, zm, a.wn(k), sc * T(iN[k]), sc * T(iN[M - k]));
+      buf[k2] = zk;
+      buf[im] = zm;
+    }
+  } else {
+    for (int t = threadIdx.x; t < M2; t += kNT) {
+      if (t < M2 / 2) {
+        // row 0: k = M1*k2, partner M1*(M2-k2)
+        const int k2 = t;
+        if (k2 == 0) {
+          buf[0] = dc_filter(buf[0], sc * T(iN[0]), sc * T(iN[M]));
+          // k = M/2 (k2 = M2/2) pairs with itself
+          const int h = M2 / 2;
+          Cx<T> zk = buf[h], zm = buf[h];
+          pair_filter(zk, zm, a.wn(M / 2), sc * T(iN[M / 2]), sc * T(iN[M / 2]));
+          buf[h] = zk;
+        } else {
+          const int k = M1 * k2;
+          Cx<T> zk = buf[k2], zm = buf[M2 - k2];
+          pair_filter(zk, zm, a.wn(k), sc * T(iN[k]), sc * T(iN[M - k]));
+          buf[k2] = zk;
+          buf[M2 - k2] = zm;
+        }
+      } else {
+        // row M1/2: k = M1/2 + M1*k2, partner at column M2-1-k2
+        const int k2 = t - M2 / 2;
+        const int k = (M1 >> 1) + M1 * k2;
+        const int i0 = M2 + k2, i1 = M2 + (M2 - 1 - k2);
+        Cx<T> zk = buf[i0], zm = buf[i1];
+        pair_filter(zk, zm, a.wn(k), sc * T(iN[k]), sc * T(iN[M - k]));
+        buf[i0] = zk;
+        buf[i1] = zm;
+      }
+    }
+  }
+  __syncthreads();
+  lds_fft<T, kNT, kE, true>(buf, sh, a.tw);
+  for (int e = threadIdx.x; e < 2 * M2; e += kNT) {
+    const int row = e >> a.logM2;
+    const int j2 = e & (M2 - 1);
+    const int k1 = row ? rb : ra;
+    w[int64_t(k1) * M2 + j2] = buf[e] * conj(a.wn(2 * int64_t(k1) * j2));
+  }
+}
+
+template <typename T, int NC>
+__global__ void __launch_bounds__(kNT) k_pass3(PassArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
+  T* bufr = reinterpret_cast<T*>(smem);
+  const int logNB = a.logM2 - a.logC;
+  const int g = blockIdx.x >> logNB;
+  const int cb = blockIdx.x & ((1 << logNB) - 1);
+  const int C = 1 << a.logC;
+  const int M1 = 1 << a.logM1, M2 = 1 << a.logM2;
+  const int j20 = cb << a.logC;
+  const Cx<T>* w = a.work + (int64_t(g) << a.logM);
+  for (int e = threadIdx.x; e < C * M1; e += kNT) {
+    const int k1 = e >> a.logC;
+    const int c = e & (C - 1);
+    buf[e] = w[int64_t(k1) * M2 + j20 + c];
+  }
+  __syncthreads();
+  FftShape sh{a.logM1, a.logC, C, 1, true, a.logLmax};
+  lds_fft<T, kNT, kE, true>(buf, sh, a.tw);
+  const int64_t base = int64_t(g) * a.n;
+  const int nsamp = 2 * C * M1;
+  for (int e = threadIdx.x; e < nsamp; e += kNT) {
+    const int j1 = e >> (a.logC + 1);
+    const int q = e & (2 * C - 1);
+    const int64_t s = base + 2 * (int64_t(j1) * M2 + j20) + q;
+    scatter_sample<T, NC>(a, s, bufr[e]);
+  }
+}
+
+// ------------------------------------------------------------- host side
+static int ilog2(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+
+template <typename K>
+static void raise_lds_limit(K kernel, size_t bytes) {
+  if (bytes > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+template <typename T, int NC, int SRC>
+static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
+  const Plan& pl = s->plan;
+  const int M = 1 << pl.logM;
+  PassArgs<T> a;
+  a.gmap = s->at<V4<T>>(s->lay.gmap);
+  a.acc = s->at<double>(s->lay.acc);
+  a.work = s->at<Cx<T>>(s->lay.tod);
+  a.tw = s->at<Cx<T>>(s->lay.tw);
+  a.wn.hi = s->at<Cx<T>>(s->lay.wn_hi);
+  a.wn.lo = s->at<Cx<T>>(s->lay.wn_lo);
+  a.wn.logS = pl.logS;
+  a.n = s->n;
+  a.npix = s->npix;
+  a.logM = pl.logM;
+  a.logM1 = pl.logM1;
+  a.logM2 = pl.logM2;
+  a.logC = pl.logC;
+  a.logLmax = pl.logLmax;
+  a.scale = T(1) / T(M);
+  const int G = pl.G;
+  for (int d0 = 0; d0 < s->ndet; d0 += G) {
+    const int gd = (s->ndet - d0 < G) ? (s->ndet - d0) : G;
+    const int64_t off = int64_t(d0) * s->n;
+    a.pix = s->d.pix + off;
+    a.c2 = s->d.cos2psi ? s->d.cos2psi + off : nullptr;
+    a.s2 = s->d.sin2psi ? s->d.sin2psi + off : nullptr;
+    a.iN = s->d.inv_noise + int64_t(d0) * (M + 1);
+    a.tod = tod ? static_cast<const T*>(tod) + off : nullptr;
+    const int64_t gs = int64_t(gd) * s->n;
+    hipEvent_t tok;
+    if (pl.single) {
+      const size_t lds = size_t(M) * sizeof(Cx<T>);
+      raise_lds_limit(k_single<T, NC, SRC>, lds);
+      prof_begin(s, st, &tok);
+      hipLaunchKernelGGL((k_single<T, NC, SRC>), dim3(gd), dim3(kNT), lds, st, a);
+      prof_end(s, st, tok, kProfSingle, gs);
+    } else {
+      const int C = 1 << pl.logC;
+      const int M1 = 1 << pl.logM1, M2 = 1 << pl.logM2;
+      const size_t lds13 = size_t(C) * M1 * sizeof(Cx<T>);
+      const size_t lds2 = size_t(2) * M2 * sizeof(Cx<T>);
+      raise_lds_limit(k_pass1<T, NC, SRC>, lds13);
+      raise_lds_limit(k_pass2<T>, lds2);
+      raise_lds_limit(k_pass3<T, NC>, lds13);
+      prof_begin(s, st, &tok);
+      hipLaunchKernelGGL((k_pass1<T, NC, SRC>), dim3(gd * (M2 / C)), dim3(kNT), lds13, st, a);
+      prof_end(s, st, tok, kProfPass1, gs);
+      prof_begin(s, st, &tok);
+      hipLaunchKernelGGL((k_pass2<T>), dim3(gd * (M1 / 2)), dim3(kNT), lds2, st, a);
+      prof_end(s, st, tok, kProfPass2, gs);
+      prof_begin(s, st, &tok);
+      hipLaunchKernelGGL((k_pass3<T, NC>), dim3(gd * (M2 / C)), dim3(kNT), lds13, st, a);
+      prof_end(s, st, tok, kProfPass3, gs);
+    }
+  }
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+template <typename T>
+static mm_status run_pipeline(ScanImpl* s, int src, const void* tod, hipStream_t st) {
+  if (s->nc == 3)
+    return src ? run_pipeline_t<T, 3, 1>(s, tod, st) : run_pipeline_t<T, 3, 0>(s, tod, st);
+  return src ? run_pipeline_t<T, 1, 1>(s, tod, st) : run_pipeline_t<T, 1, 0>(s, tod, st);
+}
+
+mm_status filter_pipeline(ScanImpl* s, int src, const void* tod, const double* x, double* y,
+                          hipStream_t st) {
+  const int npix = s->npix;
+  const dim3 blk(256), grd((npix + 255) / 256);
+  const int32_t* mask = s->at<int32_t>(s->lay.mask);
+  double* acc = s->at<double>(s->lay.acc);
+  hipEvent_t tok;
+  prof_begin(s, st, &tok);
+  if (src == 0) {
+    if (s->plan.f64)
+      hipLaunchKernelGGL(k_prologue<double>, grd, blk, 0, st, x, mask,
+                         s->at<V4<double>>(s->lay.gmap), acc, npix, s->nc);
+    else
+      hipLaunchKernelGGL(k_prologue<float>, grd, blk, 0, st, x, mask,
+                         s->at<V4<float>>(s->lay.gmap), acc, npix, s->nc);
+  } else {
+    hipLaunchKernelGGL(k_zero_acc, grd, blk, 0, st, acc, npix);
+  }
+  MM_HIP(hipGetLastError());
+  mm_status r = s->plan.f64 ? run_pipeline<double>(s, src, tod, st)
+                            : run_pipeline<float>(s, src, tod, st);
+  if (r != MM_OK) return r;
+  hipLaunchKernelGGL(k_epilogue, grd, blk, 0, st, acc, mask, y, npix, s->nc);
+  MM_HIP(hipGetLastError());
+  prof_end(s, st, tok, kProfApplyA, int64_t(s->ndet) * s->n);
+  return MM_OK;
+}
+
+// --------------------------------------------------------- plan / tables
+mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
+  const int64_t n = d->nsamp;
+  pl->f64 = d->tod_dtype == MM_F64;
+  pl->logn = ilog2(n);
+  pl->logM = pl->logn - 1;
+  const int M = 1 << pl->logM;
+  const size_t cxb = pl->f64 ? 16 : 8;
+  pl->single = (M <= kE * kNT);
+  if (pl->single) {
+    pl->logM1 = 0;
+    pl->logM2 = pl->logM;
+    pl->logC = 0;
+    pl->G = d->ndet;
+    pl->logLmax = pl->logM;
+  } else {
+    int l1;
+    if (d->fft_m1 > 0) {
+      l1 = ilog2(d->fft_m1);
+    } else {
+      l1 = pl->logM / 2;
+      if (l1 > 9) l1 = 9;
+      if (pl->logM - l1 > 12) l1 = pl->logM - 12;
+    }
+    pl->logM1 = l1;
+    pl->logM2 = pl->logM - l1;
+    if (pl->logM1 < 2 || pl->logM2 < 5 || pl->logM2 > 12 || pl->logM1 > 9)
+      return fail(MM_EINVAL, "fft_m1 gives an unsupported four-step split");
+    int lc = 4;
+    while (lc > 0 && ((1 << lc) << pl->logM1) > kE * kNT) --lc;
+    if (lc > pl->logM2) lc = pl->logM2;
+    pl->logC = lc;
+    if ((2 << (lc + pl->logM1)) % kNT != 0 || (2 << pl->logM2) % kNT != 0)
+      return fail(MM_EINVAL, "four-step blocks too small for the thread count");
+    int G = d->det_group;
+    if (G <= 0) {
+      // keep the group's timestream scratch near 64 MiB (MALL-resident)
+      const int64_t per = int64_t(M) * int64_t(cxb);
+      G = int((int64_t(64) << 20) / per);
+      if (G < 1) G = 1;
+    }
+    if (G > d->ndet) G = d->ndet;
+    pl->G = G;
+    pl->logLmax = pl->logM1 > pl->logM2 ? pl->logM1 : pl->logM2;
+  }
+  pl->logS = (pl->logn + 1) / 2;
+  const int maxside = d->ny > d->nx ? d->ny : d->nx;
+  pl->logMapL = ilog2(maxside);
+  // layout
+  const int64_t npix = int64_t(d->ny) * d->nx;
+  const int nc = d->ncomp;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  L->tod = take(pl->single ? 0 : size_t(pl->G) * size_t(M) * cxb);
+  L->tw = take((size_t(1) << pl->logLmax) * cxb);
+  L->wn_hi = take((size_t(1) << (pl->logn - pl->logS)) * cxb);
+  L->wn_lo = take((size_t(1) << pl->logS) * cxb);
+  L->gmap = take(size_t(npix) * 4 * (pl->f64 ? 8 : 4));
+  L->acc = take(size_t(npix) * 4 * 8);
+  L->detw = take(size_t(d->ndet) * 8);
+  L->hits = take(size_t(npix) * 8);
+  L->bb = take(size_t(npix) * 6 * 8);
+  L->bj = take(size_t(npix) * 6 * 8);
+  L->binv_b = take(size_t(npix) * 6 * 8);
+  L->binv_j = take(size_t(npix) * 6 * 8);
+  L->siginv = take(size_t(npix) * 6 * 8);
+  L->mask = take(size_t(npix) * 4);
+  L->kinv = take(size_t(npix) * nc * nc * 16);
+  L->planes = take(size_t(npix) * nc * nc * 16);
+  L->probe = take(size_t(npix) * nc * nc * 8);
+  L->tw_map = take((size_t(1) << pl->logMapL) * 16);
+  L->vec = take(size_t(npix) * nc * 8 * 5);
+  L->partials = take(size_t(kMaxPartials) * 4 * 8);
+  L->pcg = take(sizeof(PcgDev));
+  L->hist = take(size_t(3) * (kHistCap + 1) * 8);
+  L->misc = take(256);
+  L->total = off;
+  return MM_OK;
+}
+
+template <typename T>
+static void table(std::vector<Cx<T>>& v, int64_t count, int64_t step, int64_t n) {
+  v.resize(count);
+  for (int64_t m = 0; m < count; ++m) {
+    const long double ang = -2.0L * 3.14159265358979323846264338327950288L *
+                            (long double)((m * step) % n) / (long double)n;
+    v[m].x = T(std::cos(double(ang)));
+    v[m].y = T(std::sin(double(ang)));
+  }
+}
+
+template <typename T>
+static mm_status upload_t(ScanImpl* s, hipStream_t st) {
+  const Plan& pl = s->plan;
+  std::vector<Cx<T>> tw, hi, lo;
+  const int64_t Lmax = int64_t(1) << pl.logLmax;
+  table(tw, Lmax, 1, Lmax);
+  const int64_t n = int64_t(1) << pl.logn;
+  const int64_t S = int64_t(1) << pl.logS;
+  table(hi, n / S, S, n);
+  table(lo, S, 1, n);
+  MM_HIP(hipMemcpyAsync(s->ws + s->lay.tw, tw.data(), tw.size() * sizeof(Cx<T>),
+                        hipMemcpyHostToDevice, st));
+  MM_HIP(hipMemcpyAsync(s->ws + s->lay.wn_hi, hi.data(), hi.size() * sizeof(Cx<T>),
+                        hipMemcpyHostToDevice, st));
+  MM_HIP(hipMemcpyAsync(s->ws + s->lay.wn_lo, lo.data(), lo.size() * sizeof(Cx<T>),
+                        hipMemcpyHostToDevice, st));
+  std::vector<Cx<double>> tm;
+  const int64_t Lm = int64_t(1) << pl.logMapL;
+  table(tm, Lm, 1, Lm);
+  MM_HIP(hipMemcpyAsync(s->ws + s->lay.tw_map, tm.data(), tm.size() * sizeof(Cx<double>),
+                        hipMemcpyHostToDevice, st));
+  MM_HIP(hipStreamSynchronize(st));
+  return MM_OK;
+}
+
+mm_status upload_tables(ScanImpl* s, hipStream_t st) {
+  return s->plan.f64 ? upload_t<double>(s, st) : upload_t<float>(s, st);
+}
+
+}  // namespace mm

@@ -1,0 +1,123 @@
+// Internal host-side state of a scan handle and the launch helpers shared by
+// the translation units of libmm.so.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/mm.h"
+
+namespace mm {
+
+constexpr int kNT = 256;         // threads per block of the timestream kernels
+constexpr int kE = 32;           // complex elements per thread in LDS FFTs
+constexpr int kMapE = 16;        // ... in the float64 map FFTs
+constexpr int kHistCap = 65536;  // PCG history entries kept on the device
+constexpr int kMaxPartials = 1024;
+constexpr int kProfStages = 8;   // see mm_profile in mm.h
+constexpr int kProfSingle = 0, kProfPass1 = 1, kProfPass2 = 2, kProfPass3 = 3, kProfApplyA = 4,
+              kProfPrecon = 5;
+
+void set_error(const std::string& msg);
+mm_status fail(mm_status st, const std::string& msg);
+mm_status hip_check(hipError_t e, const char* what);
+
+#define MM_HIP(call)                                          \
+  do {                                                        \
+    hipError_t _e = (call);                                   \
+    if (_e != hipSuccess) return ::mm::hip_check(_e, #call);  \
+  } while (0)
+
+// Device-resident PCG scalars.
+struct PcgDev {
+  double rho;      // r_k . z_k
+  double ps;       // p . A p
+  double rr;       // ||r||^2
+  double bb;       // ||b||^2
+  double rz;       // new r.z
+  double alpha, beta;
+  double tol2;
+  int iters;
+  int done;
+  int breakdown;
+  int pad;
+};
+
+// Offsets of the sub-buffers inside the caller's workspace.
+struct Layout {
+  size_t tod;        // pipeline scratch: G * M complex (0 bytes if single pass)
+  size_t tw;         // Stockham table, Lmax complex
+  size_t wn_hi, wn_lo;
+  size_t gmap;       // npix * 4 real (gather map)
+  size_t acc;        // npix * 4 double (scatter accumulator)
+  size_t detw;       // ndet double
+  size_t hits;       // npix double (hit counts, accumulated in f64)
+  size_t bb, bj;     // npix * 6 double: binned / Jacobi blocks (packed symmetric)
+  size_t binv_b, binv_j, siginv;  // npix * 6 double
+  size_t mask;       // npix int32
+  size_t kinv;       // npix * nc*nc complex double
+  size_t planes;     // ncomp^2 * npix complex double (FFT scratch, probe q planes)
+  size_t probe;      // nc*nc*npix double
+  size_t tw_map;     // max(ny,nx) complex double
+  size_t vec;        // 5 CG vectors of nc*npix double (r, z, p, s, tmp)
+  size_t partials;   // kMaxPartials * 4 double
+  size_t pcg;        // PcgDev
+  size_t hist;       // 3 * (kHistCap+1) double
+  size_t misc;       // small ints / doubles (ref key, floor count, lambda max)
+  size_t total;
+};
+
+struct Plan {
+  bool f64;
+  bool single;       // whole detector filtered in one kernel
+  int logn, logM;    // n = 2^logn samples, M = n/2 packed complex
+  int logM1, logM2;  // four-step split
+  int logC;          // columns per pass-1/3 block
+  int G;             // detectors per group
+  int logLmax;       // Stockham table length
+  int logS;          // two-level table split for W_n
+  int logMapL;       // map FFT table length
+};
+
+struct Profiler;
+
+struct ScanImpl {
+  mm_scan_desc d;
+  int nc, ny, nx, ndet, npix;
+  int64_t n;
+  Plan plan;
+  Layout lay;
+  char* ws;
+  int ref_pixel = -1;
+  int n_floored = 0;
+  int n_active = 0;
+  bool circ_built = false;
+  int circ_sym = 1;
+  int maxdyn_lds = 65536;
+  Profiler* prof = nullptr;
+
+  template <typename P>
+  P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
+};
+
+// ---- launchers implemented across the .hip files -------------------------
+mm_status plan_and_layout(const mm_scan_desc* d, Plan* plan, Layout* lay);
+mm_status upload_tables(ScanImpl* s, hipStream_t st);
+mm_status filter_pipeline(ScanImpl* s, int src /*0 gather x, 1 timestream*/,
+                          const void* tod, const double* x, double* y, hipStream_t st);
+mm_status binned_setup(ScanImpl* s, hipStream_t st);
+mm_status binned_apply(ScanImpl* s, int jacobi, const double* r, double* z, hipStream_t st);
+mm_status circulant_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st);
+mm_status circulant_apply(ScanImpl* s, const double* r, double* z, hipStream_t st);
+mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x,
+                    const mm_pcg_opts* o, mm_pcg_result* res, hipStream_t st);
+mm_status fill_zero(void* p, size_t bytes, hipStream_t st);
+mm_status apply_precon(ScanImpl* s, int precon, const double* r, double* z, hipStream_t st);
+void prof_begin(ScanImpl* s, hipStream_t st, hipEvent_t* tok);
+void prof_end(ScanImpl* s, hipStream_t st, hipEvent_t tok, int stage, int64_t samples);
+mm_status profile_enable(ScanImpl* s, int enable);
+mm_status profile_read(ScanImpl* s, mm_profile* out);
+void profile_free(ScanImpl* s);
+
+}  // namespace mm

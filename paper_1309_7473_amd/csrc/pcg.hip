@@ -1,0 +1,330 @@
+// Preconditioned conjugate gradients for A m = b (paper eq. 2) with every
+// scalar kept on the device.
+//
+//   r0 = b - A x0, z0 = M r0, p0 = z0, rho0 = r0.z0
+//   loop:  s = A p;  alpha = rho / p.s;  x += alpha p;  r -= alpha s;
+//          stop when ||r|| <= tol ||b||;  z = M r;  rho' = r.z;
+//          beta = rho' / rho;  p = z + beta p
+//
+// Dot products are two-kernel reductions with a fixed summation order (block
+// partials, then one block), so a solve is bit-reproducible.  The kernels read
+// a `done` flag that the reductions set on convergence or breakdown
+// (p.s <= 0, rho <= 0 or a non-finite scalar); after it, updates are no-ops,
+// so the host only needs to look every check_every iterations.
+#include <chrono>
+#include <vector>
+
+#include "mm_device.h"
+#include "mm_internal.h"
+
+namespace mm {
+
+constexpr int kRedBlocks = 512;
+
+// partial sums of a.b (and c.d if c != nullptr)
+__global__ void __launch_bounds__(256) k_dot_partial(const double* __restrict__ a,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ c,
+                                                     const double* __restrict__ d, int64_t n,
+                                                     double* __restrict__ part) {
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    v[0] += a[i] * b[i];
+    if (c) v[1] += c[i] * d[i];
+  }
+  __shared__ double sm[32];
+  block_sum<2>(v, sm);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = v[0];
+    part[2 * blockIdx.x + 1] = v[1];
+  }
+}
+
+__device__ __forceinline__ void sum_partials(const double* part, int nb, double (&v)[2], double* sm) {
+  v[0] = v[1] = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    v[0] += part[2 * i];
+    v[1] += part[2 * i + 1];
+  }
+  block_sum<2>(v, sm);
+}
+
+// init: bb = b.b and rr = r.r; converged already if ||r0|| <= tol ||b||
+__global__ void k_fin_init(const double* __restrict__ part, int nb, PcgDev* st, double* hist) {
+  __shared__ double sm[32];
+  double v[2];
+  sum_partials(part, nb, v, sm);
+  if (threadIdx.x == 0) {
+    st->bb = v[0];
+    st->rr = v[1];
+    st->iters = 0;
+    st->breakdown = 0;
+    st->done = 0;
+    if (!isfinite(v[0]) || !isfinite(v[1])) {
+      st->done = 1;  // non-finite right-hand side or start
+      st->breakdown = 1;
+      hist[0] = v[1];
+    } else if (!(v[0] > 0.0)) {
+      st->done = 1;  // b = 0: x = 0 solves it
+      hist[0] = 0.0;
+    } else {
+      hist[0] = sqrt(v[1] / v[0]);
+      if (v[1] <= st->tol2 * v[0]) st->done = 1;
+    }
+  }
+}
+
+// rho0 = r0.z0
+__global__ void k_fin_rho0(const double* __restrict__ part, int nb, PcgDev* st) {
+  __shared__ double sm[32];
+  double v[2];
+  sum_partials(part, nb, v, sm);
+  if (threadIdx.x == 0) st->rho = v[0];
+}
+
+__global__ void k_mask_vec(double* __restrict__ x, const int32_t* __restrict__ mask, int npix,
+                           int nc) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix || mask[p]) return;
+  for (int a = 0; a < nc; ++a) x[int64_t(a) * npix + p] = 0.0;
+}
+
+// after s = A p: alpha = rho / p.s
+__global__ void k_fin_ps(const double* __restrict__ part, int nb, PcgDev* st) {
+  __shared__ double sm[32];
+  double v[2];
+  sum_partials(part, nb, v, sm);
+  if (threadIdx.x == 0 && !st->done) {
+    const double ps = v[0], rho = st->rho;
+    st->ps = ps;
+    if (!(ps > 0.0) || !(rho > 0.0) || !isfinite(ps) || !isfinite(rho)) {
+      st->breakdown = 1;
+      st->done = 1;
+      st->alpha = 0.0;
+    } else {
+      st->alpha = rho / ps;
+    }
+  }
+}
+
+// x += alpha p ; r -= alpha s ; partial r.r
+__global__ void __launch_bounds__(256) k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ s, int64_t n,
+                                                   const PcgDev* __restrict__ st,
+                                                   double* __restrict__ part) {
+  if (st->done) return;
+  const double alpha = st->alpha;
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * s[i];
+    r[i] = ri;
+    v[0] += ri * ri;
+  }
+  __shared__ double sm[32];
+  block_sum<2>(v, sm);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = v[0];
+    part[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
+__global__ void k_fin_rr(const double* __restrict__ part, int nb, PcgDev* st, double* hist,
+                         int hist_cap) {
+  if (st->done) return;
+  __shared__ double sm[32];
+  double v[2];
+  sum_partials(part, nb, v, sm);
+  if (threadIdx.x == 0) {
+    const double rr = v[0];
+    st->rr = rr;
+    const int it = st->iters + 1;
+    st->iters = it;
+    if (it <= hist_cap) {
+      hist[it] = sqrt(rr / st->bb);
+      hist[(hist_cap + 1) + it - 1] = st->alpha;
+      hist[2 * (hist_cap + 1) + it - 1] = st->rho;
+    }
+    if (!isfinite(rr)) {
+      st->breakdown = 1;
+      st->done = 1;
+    } else if (rr <= st->tol2 * st->bb) {
+      st->done = 1;
+    }
+  }
+}
+
+// rho' = r.z ; beta = rho'/rho
+__global__ void k_fin_rz(const double* __restrict__ part, int nb, PcgDev* st) {
+  if (st->done) return;
+  __shared__ double sm[32];
+  double v[2];
+  sum_partials(part, nb, v, sm);
+  if (threadIdx.x == 0) {
+    const double rz = v[0];
+    st->rz = rz;
+    st->beta = rz / st->rho;
+    st->rho = rz;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_update_p(double* __restrict__ p, const double* __restrict__ z,
+                                                  int64_t n, const PcgDev* __restrict__ st) {
+  if (st->done) return;
+  const double beta = st->beta;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_axpby(double* __restrict__ out, const double* __restrict__ a, double ca,
+                        const double* __restrict__ b, double cb, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = ca * a[i] + (b ? cb * b[i] : 0.0);
+}
+
+static int red_blocks(int64_t n) {
+  int64_t b = (n + 1023) / 1024;
+  if (b < 1) b = 1;
+  if (b > kRedBlocks) b = kRedBlocks;
+  return int(b);
+}
+
+static mm_status apply_precon_inner(ScanImpl* s, int precon, const double* r, double* z,
+                                    hipStream_t st);
+
+mm_status apply_precon(ScanImpl* s, int precon, const double* r, double* z, hipStream_t st) {
+  hipEvent_t tok;
+  prof_begin(s, st, &tok);
+  const mm_status rc = apply_precon_inner(s, precon, r, z, st);
+  prof_end(s, st, tok, kProfPrecon, int64_t(s->nc) * s->npix);
+  return rc;
+}
+
+static mm_status apply_precon_inner(ScanImpl* s, int precon, const double* r, double* z,
+                                    hipStream_t st) {
+  const int64_t N = int64_t(s->nc) * s->npix;
+  switch (precon) {
+    case MM_M_NONE: {
+      hipLaunchKernelGGL(k_axpby, dim3(red_blocks(N)), dim3(256), 0, st, z, r, 1.0,
+                         static_cast<const double*>(nullptr), 0.0, N);
+      MM_HIP(hipGetLastError());
+      return MM_OK;
+    }
+    case MM_M_JACOBI:
+      return binned_apply(s, 1, r, z, st);
+    case MM_M_BINNED:
+      return binned_apply(s, 0, r, z, st);
+    case MM_M_CIRCULANT:
+      return circulant_apply(s, r, z, st);
+    default:
+      return fail(MM_EINVAL, "unknown preconditioner");
+  }
+}
+
+mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const mm_pcg_opts* o,
+                    mm_pcg_result* res, hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const Layout& L = s->lay;
+  const int64_t N = int64_t(s->nc) * s->npix;
+  double* vec = s->at<double>(L.vec);
+  double* r = vec;
+  double* z = vec + N;
+  double* p = vec + 2 * N;
+  double* sv = vec + 3 * N;
+  double* part = s->at<double>(L.partials);
+  PcgDev* dev = s->at<PcgDev>(L.pcg);
+  double* hist = s->at<double>(L.hist);
+  const int nb = red_blocks(N);
+  const dim3 gb(nb), bb(256);
+  mm_status rc;
+
+  PcgDev init{};
+  init.tol2 = o->tol * o->tol;
+  MM_HIP(hipMemcpyAsync(dev, &init, sizeof(PcgDev), hipMemcpyHostToDevice, st));
+  // r = b - A x0  (or b), x0 = 0 unless use_x0
+  if (o->use_x0) {
+    hipLaunchKernelGGL(k_mask_vec, dim3((s->npix + 255) / 256), bb, 0, st, x,
+                       s->at<int32_t>(L.mask), s->npix, s->nc);
+    if ((rc = filter_pipeline(s, 0, nullptr, x, sv, st)) != MM_OK) return rc;
+    hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, r, b, 1.0, sv, -1.0, N);
+  } else {
+    hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, r, b, 1.0, static_cast<const double*>(nullptr), 0.0, N);
+    hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, x, b, 0.0, static_cast<const double*>(nullptr), 0.0, N);
+  }
+  // inactive entries of b are ignored: r (and with it every later vector) is masked
+  hipLaunchKernelGGL(k_mask_vec, dim3((s->npix + 255) / 256), bb, 0, st, r,
+                     s->at<int32_t>(L.mask), s->npix, s->nc);
+  MM_HIP(hipGetLastError());
+  // ||b|| over the active entries (z is free until the first M r)
+  hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, z, b, 1.0, static_cast<const double*>(nullptr), 0.0, N);
+  hipLaunchKernelGGL(k_mask_vec, dim3((s->npix + 255) / 256), bb, 0, st, z,
+                     s->at<int32_t>(L.mask), s->npix, s->nc);
+  hipLaunchKernelGGL(k_dot_partial, gb, bb, 0, st, z, z, r, r, N, part);
+  hipLaunchKernelGGL(k_fin_init, dim3(1), bb, 0, st, part, nb, dev, hist);
+  if ((rc = apply_precon(s, precon, r, z, st)) != MM_OK) return rc;
+  hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, p, z, 1.0, static_cast<const double*>(nullptr), 0.0, N);
+  hipLaunchKernelGGL(k_dot_partial, gb, bb, 0, st, r, z, static_cast<const double*>(nullptr),
+                     static_cast<const double*>(nullptr), N, part);
+  hipLaunchKernelGGL(k_fin_rho0, dim3(1), bb, 0, st, part, nb, dev);
+  MM_HIP(hipGetLastError());
+  const int maxiter = o->maxiter;
+  const int every = o->check_every > 0 ? o->check_every : 1;
+  PcgDev h{};
+  MM_HIP(hipMemcpyAsync(&h, dev, sizeof(PcgDev), hipMemcpyDeviceToHost, st));
+  MM_HIP(hipStreamSynchronize(st));
+  int it = h.done ? maxiter : 0;
+  while (it < maxiter) {
+    // s = A p
+    if ((rc = filter_pipeline(s, 0, nullptr, p, sv, st)) != MM_OK) return rc;
+    hipLaunchKernelGGL(k_dot_partial, gb, bb, 0, st, p, sv, static_cast<const double*>(nullptr),
+                       static_cast<const double*>(nullptr), N, part);
+    hipLaunchKernelGGL(k_fin_ps, dim3(1), bb, 0, st, part, nb, dev);
+    hipLaunchKernelGGL(k_update_xr, gb, bb, 0, st, x, r, p, sv, N, dev, part);
+    hipLaunchKernelGGL(k_fin_rr, dim3(1), bb, 0, st, part, nb, dev, hist, kHistCap);
+    if ((rc = apply_precon(s, precon, r, z, st)) != MM_OK) return rc;
+    hipLaunchKernelGGL(k_dot_partial, gb, bb, 0, st, r, z, static_cast<const double*>(nullptr),
+                       static_cast<const double*>(nullptr), N, part);
+    hipLaunchKernelGGL(k_fin_rz, dim3(1), bb, 0, st, part, nb, dev);
+    hipLaunchKernelGGL(k_update_p, gb, bb, 0, st, p, z, N, dev);
+    MM_HIP(hipGetLastError());
+    ++it;
+    if (it % every == 0 || it == maxiter) {
+      MM_HIP(hipMemcpyAsync(&h, dev, sizeof(PcgDev), hipMemcpyDeviceToHost, st));
+      MM_HIP(hipStreamSynchronize(st));
+      if (h.done) break;
+    }
+  }
+  MM_HIP(hipMemcpyAsync(&h, dev, sizeof(PcgDev), hipMemcpyDeviceToHost, st));
+  MM_HIP(hipStreamSynchronize(st));
+  const int iters = h.iters;
+  const int nh = iters < kHistCap ? iters : kHistCap;
+  std::vector<double> hh(size_t(3) * (kHistCap + 1));
+  MM_HIP(hipMemcpy(hh.data(), hist, hh.size() * 8, hipMemcpyDeviceToHost));
+  const bool converged = h.done && !h.breakdown;
+  if (res) {
+    res->iters = iters;
+    res->converged = converged ? 1 : 0;
+    res->rel_resid = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    if (iters == 0) res->rel_resid = h.bb > 0 ? hh[0] : 0.0;
+    res->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (res->history)
+      for (int k = 0; k <= nh; ++k) res->history[k] = hh[k];
+    if (res->alpha)
+      for (int k = 0; k < nh; ++k) res->alpha[k] = hh[(kHistCap + 1) + k];
+    if (res->rho)
+      for (int k = 0; k < nh; ++k) res->rho[k] = hh[2 * (kHistCap + 1) + k];
+  }
+  if (h.breakdown) return fail(MM_EBREAKDOWN, "PCG breakdown (p.Ap <= 0, r.z <= 0 or non-finite)");
+  if (!converged) {
+    set_error("PCG did not reach the tolerance within maxiter");
+    return MM_ENOCONV;
+  }
+  return MM_OK;
+}
+
+}  // namespace mm

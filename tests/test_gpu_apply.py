@@ -1,0 +1,151 @@
+"""GPU parity of the A-apply and the right-hand side against the FP64 oracle.
+
+Tolerances (relative L2, GPU vs oracle on identical inputs):
+  float64 timestream path: 1e-12;
+  float32 timestream path: 2e-6 for a white random map (the FFT/filter
+  rounding of ~1e-7 relative, grown by log2 n stages) and 2e-5 for a smooth
+  sky map, whose filtered timestream is small next to the timestream itself
+  because 1/N(f) removes most of its low-frequency power.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import small_raster
+from gpu_common import Pair, rel, need_gpu
+from synth import make_config, raster_scan
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32_WHITE = 2e-6
+TOL32_SKY = 2e-5
+
+
+def _check_apply(pair, tol, seed=0, label=""):
+    x = pair.masked_random(seed)
+    got, want = pair.A_gpu(x), pair.A_oracle(x)
+    e = rel(got, want)
+    print(f"[apply {label}] rel err random map = {e:.3e}", flush=True)
+    assert e <= tol, e
+    # inactive pixels are zero
+    assert np.all(got.reshape(pair.nc, -1)[:, ~pair.mask] == 0)
+    return e
+
+
+CASES = [
+    # (label, ncomp, ny, nx, ndet, nsamp, dtype, det_group, fft_m1)
+    ("single-f32-I", 1, 16, 16, 5, 2**10, "f32", 0, 0),
+    ("single-f32-IQU", 3, 16, 16, 5, 2**12, "f32", 0, 0),
+    ("single-f64-IQU", 3, 16, 16, 3, 2**13, "f64", 0, 0),
+    ("min-n", 3, 8, 8, 1, 16, "f32", 0, 0),
+    ("single-max-f32", 3, 32, 32, 2, 2**14, "f32", 0, 0),
+    ("fourstep-f32-ragged", 3, 32, 32, 5, 2**15, "f32", 2, 0),
+    ("fourstep-f32-m1=16", 3, 32, 32, 3, 2**15, "f32", 0, 16),
+    ("fourstep-f32-m1=512", 1, 32, 32, 2, 2**18, "f32", 1, 512),
+    ("fourstep-f64", 3, 32, 32, 3, 2**16, "f64", 2, 0),
+    ("fourstep-f64-m1=8", 1, 16, 16, 2, 2**15, "f64", 0, 8),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_apply_A_parity(case):
+    label, nc, ny, nx, ndet, n, dt, G, m1 = case
+    sweeps = max(1, n // (4 * nx))
+    inp = raster_scan(ncomp=nc, ny=ny, nx=nx, ndet=ndet, nsamp=n, fsample=100.0,
+                      layout="hex", hex_diameter_px=min(6.0, ny / 3), sigma_scatter=0.1,
+                      fknee=(0.5, 2.0), drift_deg=10.0, seed=(77, sweeps))
+    pair = Pair(inp, tod_dtype=dt, det_group=G, fft_m1=m1)
+    info = pair.g.info()
+    print(label, info, flush=True)
+    if m1:
+        assert info["fft_m1"] == m1
+    tol = TOL64 if dt == "f64" else TOL32_WHITE
+    _check_apply(pair, tol, label=label)
+    sky = make_sky(nc, ny, nx) * np.repeat(pair.mask[None], nc, 0)
+    e = rel(pair.A_gpu(sky.ravel()), pair.A_oracle(sky.ravel()))
+    print(f"[apply {label}] rel err sky map = {e:.3e}", flush=True)
+    assert e <= (TOL64 if dt == "f64" else TOL32_SKY), e
+
+
+def make_sky(nc, ny, nx):
+    from synth import grf_sky
+    return grf_sky(nc, ny, nx, np.random.default_rng(5))
+
+
+def test_config1_full_size_f64():
+    inp = make_config(1)
+    pair = Pair(inp, tod_dtype="f64")
+    assert pair.g.info()["single_pass"] == 1
+    assert pair.g.info()["n_active"] == int(pair.mask.sum())
+    _check_apply(pair, TOL64, label="config1")
+    sky = (inp.sky * pair.mask.reshape(1, 64, 64)).ravel()
+    assert rel(pair.A_gpu(sky), pair.A_oracle(sky)) <= TOL64
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_rhs_parity(dt):
+    inp = small_raster(ncomp=3, ny=32, nx=32, ndet=4, sweeps=256)  # n = 2^15, four-step
+    pair = Pair(inp, tod_dtype=dt, det_group=3)
+    rng = np.random.default_rng(3)
+    noise = np.stack([np.fft.irfft(np.sqrt(inp.spectrum[d]) * np.fft.rfft(
+        rng.standard_normal(inp.nsamp)), inp.nsamp) for d in range(inp.ndet)])
+    d = oracle.pointing(pair.o, inp.sky) + noise
+    d = d.astype(np.float32 if dt == "f32" else np.float64)
+    want = oracle.rhs(pair.o, d.astype(np.float64), pair.mask)
+    got = pair.host(pair.g.rhs(pair.torch.from_numpy(d).cuda()))
+    e = rel(got, want)
+    print(f"[rhs {dt}] rel err = {e:.3e}", flush=True)
+    assert e <= (TOL64 if dt == "f64" else TOL32_SKY)
+
+
+def test_A_symmetric_on_gpu_f64():
+    inp = small_raster(ncomp=3, ny=32, nx=32, ndet=6, sweeps=256)
+    pair = Pair(inp, tod_dtype="f64", det_group=4)
+    x, y = pair.masked_random(1), pair.masked_random(2)
+    Ax, Ay = pair.A_gpu(x), pair.A_gpu(y)
+    assert abs(x @ Ay - y @ Ax) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(Ay)
+
+
+def test_mask_and_hits_match_oracle():
+    inp = small_raster(ncomp=3, ny=16, nx=16, ndet=4, diameter=4.0)
+    pair = Pair(inp, tod_dtype="f32")
+    m = pair.host(pair.g.mask())
+    np.testing.assert_array_equal(m.astype(bool), pair.mask)
+
+
+def test_collision_stress_long_runs():
+    # every sample of detector 0 in one pixel, detector 1 alternating between
+    # two pixels, detector 2 entirely off the map
+    inp = small_raster(ncomp=3, ny=16, nx=16, ndet=3, sweeps=128)  # n = 8192
+    inp.pix[0, :] = 5 * 16 + 7
+    inp.pix[1, :] = np.where(np.arange(inp.nsamp) % 2 == 0, 3, 200)
+    inp.pix[2, :] = -1
+    for dt, tol in (("f32", TOL32_WHITE), ("f64", TOL64)):
+        pair = Pair(inp, tod_dtype=dt)
+        _check_apply(pair, tol, label=f"collision-{dt}")
+
+
+def test_invalid_pixel_rejected():
+    mm = need_gpu()
+    inp = small_raster(ncomp=1, ny=8, nx=8, ndet=2)
+    inp.pix[1, 7] = 64  # == npix: out of range
+    with pytest.raises(mm.MMError) as ei:
+        mm.Scan(inp)
+    assert ei.value.status == mm.MM_EINVAL
+
+
+def test_config2_shape_detector_subset():
+    """Config 2's recipe and the benchmark's launch geometry (n = 2^20,
+    512 x 512, 16 detectors per group, four-step 512 x 1024) on a 16-detector
+    draw, small enough for the oracle."""
+    inp = make_config(2, ndet=16)
+    pair = Pair(inp, tod_dtype="f32")
+    info = pair.g.info()
+    assert (info["fft_m1"], info["fft_m2"], info["det_group"]) == (512, 1024, 16)
+    _check_apply(pair, TOL32_WHITE, label="config2-subset")
+    sky = (inp.sky * pair.mask.reshape(1, 512, 512)).ravel()
+    e = rel(pair.A_gpu(sky), pair.A_oracle(sky))
+    print(f"[config2 subset] sky rel err = {e:.3e}", flush=True)
+    assert e <= TOL32_SKY

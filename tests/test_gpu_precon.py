@@ -1,0 +1,183 @@
+"""GPU parity of the binned, Jacobi and circulant preconditioners and of PCG.
+
+Tolerances: the binned/Jacobi applies are float64 end to end (1e-12).  The
+circulant preconditioner is float64 in the map domain but its probe rows come
+from the A-apply: with the float64 timestream path it matches the oracle to
+1e-9, with the float32 path to 1e-4 (the probe's float32 rounding).
+PCG iteration counts agree with the oracle's within 5 %, and the GPU solution's
+true residual ||b - A x|| / ||b|| under the oracle's float64 A is within a
+small factor of the tolerance.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import small_raster
+from gpu_common import Pair, rel
+from synth import make_config, crosslinked_torus_scan
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("nc", [1, 3])
+def test_binned_and_jacobi_apply(nc):
+    inp = small_raster(ncomp=nc, ny=16, nx=16, ndet=5, sweeps=64)
+    pair = Pair(inp, tod_dtype="f32")
+    r = pair.masked_random(4)
+    for name, B in (("binned", pair.B), ("jacobi", pair.Bj)):
+        want = oracle.BinnedPrecon(B, pair.mask)(r)
+        got = pair.host(pair.g.apply_precon(name, pair.dev(r)))
+        e = rel(got, want)
+        print(f"[{name} nc={nc}] {e:.3e}", flush=True)
+        assert e <= 1e-12
+
+
+CIRC = [
+    # label, nc, dtype, sigma, symmetrize, tol
+    ("I-f64", 1, "f64", 0.0, True, 1e-9),
+    ("IQU-f64", 3, "f64", 0.0, True, 1e-9),
+    ("IQU-f64-taper", 3, "f64", 3.0, True, 1e-9),
+    ("IQU-f64-literal", 3, "f64", 3.0, False, 1e-9),
+    ("IQU-f32-taper", 3, "f32", 4.0, True, 1e-4),
+]
+
+
+@pytest.mark.parametrize("case", CIRC, ids=[c[0] for c in CIRC])
+def test_circulant_apply(case):
+    label, nc, dt, sigma, sym, tol = case
+    inp = small_raster(ncomp=nc, ny=16, nx=16, ndet=5, sweeps=64)
+    pair = Pair(inp, tod_dtype=dt)
+    Mo = oracle.CirculantPrecon(pair.o, pair.mask, pair.B, sigma_taper=sigma or None,
+                                symmetrize=sym)
+    pair.g.build_precon("circulant", sigma=sigma, symmetrize=sym)
+    info = pair.g.info()
+    assert info["ref_pixel"] == Mo.ref
+    if sym:
+        assert info["n_floored"] == Mo.n_floored
+    r = pair.masked_random(6)
+    got = pair.host(pair.g.apply_precon("circulant", pair.dev(r)))
+    e = rel(got, Mo(r))
+    print(f"[circulant {label}] {e:.3e} floored={info['n_floored']}", flush=True)
+    assert e <= tol
+
+
+def test_circulant_reference_pixel_override_and_inactive_centre():
+    inp = small_raster(ncomp=1, ny=16, nx=16, ndet=4, sweeps=64)
+    inp.pix[inp.pix == 8 * 16 + 8] = 8 * 16 + 9   # the centre pixel becomes unhit
+    pair = Pair(inp, tod_dtype="f64")
+    assert not pair.mask[8 * 16 + 8]
+    Mo = oracle.CirculantPrecon(pair.o, pair.mask, pair.B)
+    pair.g.build_precon("circulant")
+    assert pair.g.info()["ref_pixel"] == Mo.ref
+    Mo2 = oracle.CirculantPrecon(pair.o, pair.mask, pair.B, ref=5 * 16 + 3)
+    pair.g.build_precon("circulant", ref=(5, 3))
+    r = pair.masked_random(2)
+    assert rel(pair.host(pair.g.apply_precon("circulant", pair.dev(r))), Mo2(r)) <= 1e-9
+
+
+@pytest.mark.parametrize("nc", [1, 3])
+@pytest.mark.parametrize("L", [8, 16])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_pcg_circulant_exact_on_crosslinked_torus(nc, L, dt):
+    inp = crosslinked_torus_scan(nc, L=L, periods=4, fknee=3.0)
+    pair = Pair(inp, tod_dtype=dt)
+    assert pair.mask.all()
+    pair.g.build_precon("circulant")
+    m = np.random.default_rng(1).standard_normal((nc, L * L))
+    b = pair.A_oracle(m.ravel())
+    tol = 1e-10 if dt == "f64" else 1e-5
+    res = pair.g.pcg("circulant", pair.dev(b), tol=tol, maxiter=20)
+    print(f"[torus L={L} nc={nc} {dt}] iters={res['iters']} hist={res['history']}", flush=True)
+    assert res["converged"] and res["iters"] == 1
+
+
+@pytest.mark.parametrize("nc", [1, 3])
+def test_pcg_binned_exact_for_white_noise(nc):
+    inp = small_raster(ncomp=nc, ny=16, nx=16, ndet=5, sweeps=64, white=True)
+    pair = Pair(inp, tod_dtype="f64")
+    b = pair.A_oracle(pair.masked_random(3))
+    res = pair.g.pcg("binned", pair.dev(b), tol=1e-12, maxiter=10)
+    assert res["converged"] and res["iters"] == 1
+
+
+def _true_resid(pair, x, b):
+    return np.linalg.norm(b - pair.A_oracle(x)) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("precon", ["binned", "jacobi", "circulant", "none"])
+def test_pcg_config1_matches_oracle(precon):
+    """Config 1 (I, 8 x 2^14, 64 x 64, plain FP64) solved to 1e-6."""
+    inp = make_config(1)
+    pair = Pair(inp, tod_dtype="f64")
+    o = pair.o
+    rng = np.random.default_rng(11)
+    noise = np.stack([np.fft.irfft(np.sqrt(inp.spectrum[d]) * np.fft.rfft(
+        rng.standard_normal(inp.nsamp)), inp.nsamp) for d in range(inp.ndet)])
+    d = oracle.pointing(o, inp.sky) + noise
+    b = oracle.rhs(o, d, pair.mask)
+    bg = pair.host(pair.g.rhs(pair.torch.from_numpy(d).cuda()))
+    assert rel(bg, b) <= 1e-12
+    if precon == "binned":
+        M = oracle.BinnedPrecon(pair.B, pair.mask)
+    elif precon == "jacobi":
+        M = oracle.BinnedPrecon(pair.Bj, pair.mask)
+    elif precon == "circulant":
+        M = oracle.CirculantPrecon(o, pair.mask, pair.B)
+        pair.g.build_precon("circulant")
+    else:
+        M = lambda v: v * np.tile(pair.mask, inp.ncomp)  # noqa: E731
+    ro = oracle.pcg(pair.A_oracle, M, b, tol=1e-6, maxiter=3000)
+    rg = pair.g.pcg(precon, pair.dev(b), tol=1e-6, maxiter=3000)
+    x = pair.host(rg["x"])
+    tr = _true_resid(pair, x, b)
+    print(f"[pcg config1 {precon}] oracle iters={ro.iters} gpu iters={rg['iters']} "
+          f"true resid={tr:.2e}", flush=True)
+    assert ro.converged and rg["converged"]
+    assert abs(rg["iters"] - ro.iters) <= max(1, 0.05 * ro.iters)
+    assert tr <= 2e-6
+    # history and scalars agree with the oracle's iteration by iteration
+    k = min(len(ro.history), len(rg["history"]), 20)
+    np.testing.assert_allclose(rg["history"][:k], ro.history[:k], rtol=1e-6)
+
+
+def test_pcg_config2_shape_f32_true_residual():
+    """Config 2's recipe at a reduced size with the float32 timestream path:
+    circulant and binned PCG to 1e-6; true residual under the oracle's FP64 A."""
+    inp = make_config(2, ndet=12, nsamp=2**15, ny=64, nx=64, hex_diameter_px=8.0)
+    pair = Pair(inp, tod_dtype="f32")
+    o = pair.o
+    m = inp.sky * pair.mask.reshape(1, 64, 64)
+    b = pair.A_oracle(m.ravel())
+    pair.g.build_precon("circulant", sigma=10.0)
+    out = {}
+    for name in ("binned", "circulant"):
+        rg = pair.g.pcg(name, pair.dev(b), tol=1e-6, maxiter=4000)
+        tr = _true_resid(pair, pair.host(rg["x"]), b)
+        out[name] = (rg["iters"], tr)
+        print(f"[pcg config2-small f32 {name}] iters={rg['iters']} rel={rg['rel_resid']:.2e} "
+              f"true={tr:.2e}", flush=True)
+        assert rg["converged"]
+        assert tr <= 1e-5
+    Mo = oracle.CirculantPrecon(o, pair.mask, pair.B, sigma_taper=10.0)
+    ro = oracle.pcg(pair.A_oracle, Mo, b, tol=1e-6, maxiter=4000)
+    print(f"[pcg config2-small oracle circulant] iters={ro.iters}", flush=True)
+    assert abs(out["circulant"][0] - ro.iters) <= max(2, 0.05 * ro.iters)
+
+
+def test_pcg_reports_noconv_and_breakdown():
+    mm = __import__("paper_1309_7473_amd")
+    inp = small_raster(ncomp=3, ny=16, nx=16, ndet=5, sweeps=64)
+    pair = Pair(inp, tod_dtype="f64")
+    b = pair.A_oracle(pair.masked_random(9))
+    res = pair.g.pcg("binned", pair.dev(b), tol=1e-12, maxiter=2)
+    assert res["status"] == mm.MM_ENOCONV
+    assert not res["converged"] and res["iters"] == 2
+    # b = 0 is solved by x = 0 with no iterations
+    z = pair.g.pcg("binned", pair.dev(np.zeros_like(b)), tol=1e-6, maxiter=5)
+    assert z["converged"] and z["iters"] == 0
+    # NaN in b is a breakdown, not a hang
+    bn = b.copy()
+    bn[np.flatnonzero(np.tile(pair.mask, 3))[0]] = np.nan
+    r = pair.g.pcg("binned", pair.dev(bn), tol=1e-6, maxiter=5)
+    assert not r["converged"] and r["status"] == mm.MM_EBREAKDOWN
