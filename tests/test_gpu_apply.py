@@ -63,7 +63,7 @@ def test_apply_A_parity(case):
         assert info["fft_m1"] == m1
     tol = TOL64 if dt == "f64" else TOL32_WHITE
     _check_apply(pair, tol, label=label)
-    sky = make_sky(nc, ny, nx) * np.repeat(pair.mask[None], nc, 0)
+    sky = make_sky(nc, ny, nx) * pair.mask.reshape(1, ny, nx)
     e = rel(pair.A_gpu(sky.ravel()), pair.A_oracle(sky.ravel()))
     print(f"[apply {label}] rel err sky map = {e:.3e}", flush=True)
     assert e <= (TOL64 if dt == "f64" else TOL32_SKY), e
