@@ -31,9 +31,14 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 
 # algorithmic HBM bytes per timestream sample of each kernel (float32 path,
 # I,Q,U): pointing 12 B (i32 pixel + 2 x f32 weight), packed timestream 4 B
-# per pass that reads or writes it, 1/N(f) (n/2+1) x 4 B / n ~ 2 B.  The map
-# and its float64 accumulator are cache resident and not counted.
-ALG_BYTES = {"pass1": 16.0, "pass2": 10.0, "pass3": 16.0, "single": 26.0, "apply_A": 34.0}
+# per pass that reads or writes it, 1/N(f) (n/2+1) x 4 B / n ~ 2 B; the
+# pixel-major index of the gather form of P^T is 12 B (i32 sample index +
+# 2 x f32 weight) and reads the filtered timestream (4 B).  The map and its
+# float64 accumulator are cache resident and not counted.  apply_A is the
+# whole operator's minimum: pointing twice, the timestream written and read
+# once, 1/N(f) once (34 B).
+ALG_BYTES = {"pass1": 16.0, "pass2": 10.0, "pass3": 16.0, "pass3_csr": 8.0, "reduce": 16.0,
+             "single": 26.0, "apply_A": 34.0}
 
 
 def kernel_source_hash():
@@ -141,11 +146,12 @@ def main():
     value = S / (ms_step * 1e-3)
 
     # roofline of the dominant kernel (largest summed time)
-    kern = {k: v for k, v in prof.items() if k in ("single", "pass1", "pass2", "pass3")}
+    kern = {k: v for k, v in prof.items() if k in ("single", "pass1", "pass2", "pass3", "reduce")}
     dom = max(kern, key=lambda k: kern[k][0])
     tot_ms, nl, ns = kern[dom]
     avg_s = tot_ms * 1e-3 / nl
-    bytes_per_launch = ALG_BYTES[dom] * ns / nl
+    key = "pass3_csr" if (dom == "pass3" and info["csr"]) else dom
+    bytes_per_launch = ALG_BYTES[key] * ns / nl
     achieved = bytes_per_launch / avg_s / 1e9
     src_hash = kernel_source_hash()
     traffic = load_traffic(dom, src_hash)

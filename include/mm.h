@@ -90,7 +90,16 @@ typedef struct {
                                complex length nsamp/2 = fft_m1 * (nsamp/2/fft_m1) */
   double  mask_rcond;       /* I,Q,U activity threshold on lambda_min/lambda_max of
                                the binned block; <= 0 selects 1e-3 */
+  int32_t scatter;          /* how P^T reaches the pixels in the multi-kernel
+                               (four-step) pipeline: MM_SCATTER_AUTO = per-pixel
+                               gather through a pixel-major index built at
+                               creation (no atomics; 12 B/sample of workspace for
+                               I,Q,U, 4 B for I); MM_SCATTER_ATOMIC = float64
+                               atomic scatter (no index).  The one-kernel path
+                               always scatters atomically. */
 } mm_scan_desc;
+
+enum { MM_SCATTER_AUTO = 0, MM_SCATTER_ATOMIC = 1 };
 
 /* Bytes of device workspace the scan needs (the caller allocates it and puts
  * the pointer in desc->workspace).  Only the shape fields and the tuning
@@ -188,6 +197,7 @@ typedef struct {
   int32_t det_group;        /* detectors per pipeline group in use */
   int32_t fft_m1, fft_m2;   /* four-step split in use (m1 = 1: one-pass kernel) */
   int32_t single_pass;      /* 1 if each detector's filter runs in one kernel */
+  int32_t csr;              /* 1 if P^T runs as a per-pixel gather */
   size_t  workspace_bytes;  /* bytes used */
 } mm_scan_info;
 
@@ -201,9 +211,10 @@ mm_status mm_get_mask(mm_scan scan, int32_t* dst, void* stream);
  * on; mm_profile_read waits for them, returns the summed durations and
  * resets.  Stages: 0 one-pass filter kernel, 1 four-step pass 1 (gather +
  * column FFTs), 2 pass 2 (row FFTs + 1/N(f) + inverse row FFTs), 3 pass 3
- * (inverse column FFTs + scatter), 4 one whole A-apply or right-hand side,
- * 5 one preconditioner apply.  samples[i] counts the timestream samples
- * (stages 0-4) or map entries (stage 5) the launches processed. */
+ * (inverse column FFTs, + atomic scatter without the pixel index), 4 one
+ * whole A-apply or right-hand side, 5 one preconditioner apply, 6 the
+ * per-pixel gather of P^T.  samples[i] counts the timestream samples
+ * (stages 0-4, 6) or map entries (stage 5) the launches processed. */
 typedef struct {
   int32_t n_stages;
   double  ms[8];

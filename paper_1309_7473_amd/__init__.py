@@ -18,7 +18,7 @@ from ._abi import (  # noqa: F401
     lib, check, MMError, mm_scan_desc, mm_precon_opts, mm_pcg_opts, mm_pcg_result,
     mm_scan_info, MM_OK, MM_ENOCONV, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENOTBUILT,
     MM_EBREAKDOWN, MM_F32, MM_BF16, MM_F64, MM_M_NONE, MM_M_JACOBI, MM_M_BINNED,
-    MM_M_CIRCULANT, LIB_PATH, mm_profile, PROFILE_STAGES,
+    MM_M_CIRCULANT, LIB_PATH, mm_profile, PROFILE_STAGES, MM_SCATTER_AUTO, MM_SCATTER_ATOMIC,
 )
 
 PRECON = {"none": MM_M_NONE, "jacobi": MM_M_JACOBI, "binned": MM_M_BINNED,
@@ -151,7 +151,7 @@ class Scan:
     """
 
     def __init__(self, inputs, tod_dtype="f32", det_group=0, fft_m1=0, mask_rcond=0.0,
-                 device="cuda", stream=None):
+                 scatter="auto", device="cuda", stream=None):
         self.device = torch.device(device)
         dev = self.device
 
@@ -183,6 +183,7 @@ class Scan:
         d.det_group = int(det_group)
         d.fft_m1 = int(fft_m1)
         d.mask_rcond = float(mask_rcond)
+        d.scatter = {"auto": MM_SCATTER_AUTO, "atomic": MM_SCATTER_ATOMIC}[scatter]
         nbytes = mm_scan_workspace_bytes(d)
         if nbytes == 0:
             raise MMError(MM_EINVAL, "mm_scan_workspace_bytes")

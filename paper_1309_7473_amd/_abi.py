@@ -25,6 +25,7 @@ class mm_scan_desc(C.Structure):
         ("pix", C.c_void_p), ("cos2psi", C.c_void_p), ("sin2psi", C.c_void_p),
         ("inv_noise", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("det_group", C.c_int32), ("fft_m1", C.c_int32), ("mask_rcond", C.c_double),
+        ("scatter", C.c_int32),
     ]
 
 
@@ -47,7 +48,7 @@ class mm_pcg_result(C.Structure):
 class mm_scan_info(C.Structure):
     _fields_ = [("n_active", C.c_int32), ("ref_pixel", C.c_int32), ("n_floored", C.c_int32),
                 ("det_group", C.c_int32), ("fft_m1", C.c_int32), ("fft_m2", C.c_int32),
-                ("single_pass", C.c_int32), ("workspace_bytes", C.c_size_t)]
+                ("single_pass", C.c_int32), ("csr", C.c_int32), ("workspace_bytes", C.c_size_t)]
 
 
 class mm_profile(C.Structure):
@@ -55,7 +56,8 @@ class mm_profile(C.Structure):
                 ("samples", C.c_int64 * 8)]
 
 
-PROFILE_STAGES = ["single", "pass1", "pass2", "pass3", "apply_A", "precon", "", ""]
+PROFILE_STAGES = ["single", "pass1", "pass2", "pass3", "apply_A", "precon", "reduce", ""]
+MM_SCATTER_AUTO, MM_SCATTER_ATOMIC = 0, 1
 
 
 # name -> (restype, argtypes)

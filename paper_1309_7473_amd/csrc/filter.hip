@@ -48,6 +48,10 @@ struct PassArgs {
   Cx<T>* work;          // [G][M]
   const Cx<T>* tw;      // Stockham table W_Lmax^m
   TwoLevel<T> wn;       // W_n^m
+  const int32_t* csr_off;  // group [npix+1]
+  const int32_t* csr_idx;  // group entries
+  const float2* csr_w;     // group entries (I,Q,U weights)
+  const int32_t* mask;
   int64_t n;
   int npix;
   int logM, logM1, logM2, logC, logLmax;
@@ -306,7 +310,9 @@ __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T> a) {
   }
 }
 
-template <typename T, int NC>
+// CSR = true: store the filtered, packed timestream back in place (the block
+// owns exactly the addresses it loaded); the per-pixel reduce applies P^T.
+template <typename T, int NC, bool CSR>
 __global__ void __launch_bounds__(kNT) k_pass3(PassArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
@@ -326,6 +332,15 @@ __global__ void __launch_bounds__(kNT) k_pass3(PassArgs<T> a) {
   __syncthreads();
   FftShape sh{a.logM1, a.logC, C, 1, true, a.logLmax};
   lds_fft<T, kNT, kE, true>(buf, sh, a.tw);
+  if constexpr (CSR) {
+    Cx<T>* wo = a.work + (int64_t(g) << a.logM);
+    for (int e = threadIdx.x; e < C * M1; e += kNT) {
+      const int k1 = e >> a.logC;
+      const int c = e & (C - 1);
+      wo[int64_t(k1) * M2 + j20 + c] = buf[e];
+    }
+    return;
+  }
   const int64_t base = int64_t(g) * a.n;
   const int nsamp = 2 * C * M1;
   for (int e = threadIdx.x; e < nsamp; e += kNT) {
@@ -333,6 +348,47 @@ __global__ void __launch_bounds__(kNT) k_pass3(PassArgs<T> a) {
     const int q = e & (2 * C - 1);
     const int64_t s = base + 2 * (int64_t(j1) * M2 + j20) + q;
     scatter_sample<T, NC>(a, s, bufr[e]);
+  }
+}
+
+// P^T for one detector group as a per-pixel gather: 16 lanes per pixel walk
+// its CSR entries, each lane summing a fixed stride of them, then a fixed
+// xor-tree; acc[p] += (sum u, sum c u, sum s u).  No atomics.
+template <typename T, int NC>
+__global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T> a) {
+  constexpr int LPP = 16;
+  const int sub = threadIdx.x / LPP;
+  const int l = threadIdx.x % LPP;
+  const int p = blockIdx.x * (256 / LPP) + sub;
+  if (p >= a.npix) return;            // whole 16-lane groups leave together
+  if (!a.mask[p]) return;
+  const T* u = reinterpret_cast<const T*>(a.work);
+  const int b = a.csr_off[p], e = a.csr_off[p + 1];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int k = b + l; k < e; k += LPP) {
+    const double uu = double(u[a.csr_idx[k]]);
+    s0 += uu;
+    if constexpr (NC == 3) {
+      const float2 cs = a.csr_w[k];
+      s1 += double(cs.x) * uu;
+      s2 += double(cs.y) * uu;
+    }
+  }
+#pragma unroll
+  for (int off = LPP / 2; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off, LPP);
+    if constexpr (NC == 3) {
+      s1 += __shfl_xor(s1, off, LPP);
+      s2 += __shfl_xor(s2, off, LPP);
+    }
+  }
+  if (l == 0) {
+    double* d = a.acc + 4 * int64_t(p);
+    d[0] += s0;
+    if constexpr (NC == 3) {
+      d[1] += s1;
+      d[2] += s2;
+    }
   }
 }
 
@@ -370,6 +426,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
   a.logC = pl.logC;
   a.logLmax = pl.logLmax;
   a.scale = T(1) / T(M);
+  a.mask = s->at<int32_t>(s->lay.mask);
   const int G = pl.G;
   for (int d0 = 0; d0 < s->ndet; d0 += G) {
     const int gd = (s->ndet - d0 < G) ? (s->ndet - d0) : G;
@@ -379,6 +436,12 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
     a.s2 = s->d.sin2psi ? s->d.sin2psi + off : nullptr;
     a.iN = s->d.inv_noise + int64_t(d0) * (M + 1);
     a.tod = tod ? static_cast<const T*>(tod) + off : nullptr;
+    if (pl.csr) {
+      const int gi = d0 / G;
+      a.csr_off = s->at<int32_t>(s->lay.csr_off) + int64_t(gi) * (s->npix + 1);
+      a.csr_idx = s->at<int32_t>(s->lay.csr_idx) + int64_t(gi) * G * s->n;
+      a.csr_w = s->nc == 3 ? s->at<float2>(s->lay.csr_w) + int64_t(gi) * G * s->n : nullptr;
+    }
     const int64_t gs = int64_t(gd) * s->n;
     hipEvent_t tok;
     if (pl.single) {
@@ -394,7 +457,8 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const size_t lds2 = size_t(2) * M2 * sizeof(Cx<T>);
       raise_lds_limit(k_pass1<T, NC, SRC>, lds13);
       raise_lds_limit(k_pass2<T>, lds2);
-      raise_lds_limit(k_pass3<T, NC>, lds13);
+      raise_lds_limit(k_pass3<T, NC, false>, lds13);
+      raise_lds_limit(k_pass3<T, NC, true>, lds13);
       prof_begin(s, st, &tok);
       hipLaunchKernelGGL((k_pass1<T, NC, SRC>), dim3(gd * (M2 / C)), dim3(kNT), lds13, st, a);
       prof_end(s, st, tok, kProfPass1, gs);
@@ -402,8 +466,16 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       hipLaunchKernelGGL((k_pass2<T>), dim3(gd * (M1 / 2)), dim3(kNT), lds2, st, a);
       prof_end(s, st, tok, kProfPass2, gs);
       prof_begin(s, st, &tok);
-      hipLaunchKernelGGL((k_pass3<T, NC>), dim3(gd * (M2 / C)), dim3(kNT), lds13, st, a);
+      if (pl.csr)
+        hipLaunchKernelGGL((k_pass3<T, NC, true>), dim3(gd * (M2 / C)), dim3(kNT), lds13, st, a);
+      else
+        hipLaunchKernelGGL((k_pass3<T, NC, false>), dim3(gd * (M2 / C)), dim3(kNT), lds13, st, a);
       prof_end(s, st, tok, kProfPass3, gs);
+      if (pl.csr) {
+        prof_begin(s, st, &tok);
+        hipLaunchKernelGGL((k_csr_reduce<T, NC>), dim3((s->npix + 15) / 16), dim3(256), 0, st, a);
+        prof_end(s, st, tok, kProfReduce, gs);
+      }
     }
   }
   MM_HIP(hipGetLastError());
@@ -454,6 +526,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   const int M = 1 << pl->logM;
   const size_t cxb = pl->f64 ? 16 : 8;
   pl->single = (M <= kE * kNT);
+  pl->csr = !pl->single && d->scatter != MM_SCATTER_ATOMIC;
   if (pl->single) {
     pl->logM1 = 0;
     pl->logM2 = pl->logM;
@@ -487,6 +560,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
       if (G < 1) G = 1;
     }
     if (G > d->ndet) G = d->ndet;
+    while (G > 1 && int64_t(G) * n > (int64_t(1) << 31) - 1) --G;
     pl->G = G;
     pl->logLmax = pl->logM1 > pl->logM2 ? pl->logM1 : pl->logM2;
   }
@@ -525,6 +599,12 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->pcg = take(sizeof(PcgDev));
   L->hist = take(size_t(3) * (kHistCap + 1) * 8);
   L->misc = take(256);
+  const int ngroups = pl->single ? 0 : (d->ndet + pl->G - 1) / pl->G;
+  const size_t csr_n = pl->csr ? size_t(ngroups) * pl->G * size_t(n) : 0;
+  L->csr_cnt = take(pl->csr ? size_t(ngroups) * npix * 4 : 0);
+  L->csr_off = take(pl->csr ? size_t(ngroups) * (npix + 1) * 4 : 0);
+  L->csr_idx = take(csr_n * 4);
+  L->csr_w = take(nc == 3 ? csr_n * 8 : 0);
   L->total = off;
   return MM_OK;
 }

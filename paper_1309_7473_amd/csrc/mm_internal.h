@@ -17,7 +17,7 @@ constexpr int kHistCap = 65536;  // PCG history entries kept on the device
 constexpr int kMaxPartials = 1024;
 constexpr int kProfStages = 8;   // see mm_profile in mm.h
 constexpr int kProfSingle = 0, kProfPass1 = 1, kProfPass2 = 2, kProfPass3 = 3, kProfApplyA = 4,
-              kProfPrecon = 5;
+              kProfPrecon = 5, kProfReduce = 6;
 
 void set_error(const std::string& msg);
 mm_status fail(mm_status st, const std::string& msg);
@@ -65,12 +65,17 @@ struct Layout {
   size_t pcg;        // PcgDev
   size_t hist;       // 3 * (kHistCap+1) double
   size_t misc;       // small ints / doubles (ref key, floor count, lambda max)
+  size_t csr_cnt;    // ngroups * npix int32 (counts, then fill cursors)
+  size_t csr_off;    // ngroups * (npix+1) int32
+  size_t csr_idx;    // ngroups * G * n int32 (group-relative sample index)
+  size_t csr_w;      // ngroups * G * n float2 (cos 2psi, sin 2psi)
   size_t total;
 };
 
 struct Plan {
   bool f64;
   bool single;       // whole detector filtered in one kernel
+  bool csr;          // P^T by per-pixel gather (else atomic scatter)
   int logn, logM;    // n = 2^logn samples, M = n/2 packed complex
   int logM1, logM2;  // four-step split
   int logC;          // columns per pass-1/3 block
@@ -107,6 +112,7 @@ mm_status upload_tables(ScanImpl* s, hipStream_t st);
 mm_status filter_pipeline(ScanImpl* s, int src /*0 gather x, 1 timestream*/,
                           const void* tod, const double* x, double* y, hipStream_t st);
 mm_status binned_setup(ScanImpl* s, hipStream_t st);
+mm_status csr_setup(ScanImpl* s, hipStream_t st);
 mm_status binned_apply(ScanImpl* s, int jacobi, const double* r, double* z, hipStream_t st);
 mm_status circulant_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st);
 mm_status circulant_apply(ScanImpl* s, const double* r, double* z, hipStream_t st);

@@ -53,14 +53,25 @@ def test_workspace_query_and_plan(mm):
     nb = mm.mm_scan_workspace_bytes(d)
     assert nb > 0 and nb % 256 == 0
     # grows with detector-group size (timestream scratch) for a four-step plan
-    d2 = _desc(mm, det_group=1)
-    d3 = _desc(mm, det_group=4)
+    d2 = _desc(mm, det_group=1, scatter=mm.MM_SCATTER_ATOMIC)
+    d3 = _desc(mm, det_group=4, scatter=mm.MM_SCATTER_ATOMIC)
     assert mm.mm_scan_workspace_bytes(d3) - mm.mm_scan_workspace_bytes(d2) == 3 * (1 << 15) * 8
+
+
+def test_pixel_index_workspace(mm):
+    # the pixel-major index costs 12 B per sample for I,Q,U and 4 B for I
+    a = mm.mm_scan_workspace_bytes(_desc(mm, scatter=mm.MM_SCATTER_ATOMIC))
+    b = mm.mm_scan_workspace_bytes(_desc(mm))
+    S = 4 * (1 << 16)
+    assert 12 * S <= b - a <= 12 * S + 2 * 4 * (64 * 64 + 1) + 3 * 256
+    a1 = mm.mm_scan_workspace_bytes(_desc(mm, ncomp=1, scatter=mm.MM_SCATTER_ATOMIC))
+    b1 = mm.mm_scan_workspace_bytes(_desc(mm, ncomp=1))
+    assert 4 * S <= b1 - a1 <= 4 * S + 2 * 4 * (64 * 64 + 1) + 3 * 256
 
 
 @pytest.mark.parametrize("field,value", [
     ("ncomp", 2), ("ny", 48), ("nx", 2), ("ndet", 0), ("nsamp", 1000), ("nsamp", 8),
-    ("nsamp", 1 << 23), ("tod_dtype", 7), ("fft_m1", 3), ("det_group", -1),
+    ("nsamp", 1 << 23), ("tod_dtype", 7), ("fft_m1", 3), ("det_group", -1), ("scatter", 5),
 ])
 def test_invalid_descriptions_rejected(mm, field, value):
     d = _desc(mm, **{field: value})

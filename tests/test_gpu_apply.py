@@ -49,16 +49,20 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("scatter", ["auto", "atomic"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_apply_A_parity(case):
+def test_apply_A_parity(case, scatter):
     label, nc, ny, nx, ndet, n, dt, G, m1 = case
+    if scatter == "atomic" and not label.startswith("fourstep"):
+        pytest.skip("the one-kernel path has only the atomic scatter")
     sweeps = max(1, n // (4 * nx))
     inp = raster_scan(ncomp=nc, ny=ny, nx=nx, ndet=ndet, nsamp=n, fsample=100.0,
                       layout="hex", hex_diameter_px=min(6.0, ny / 3), sigma_scatter=0.1,
                       fknee=(0.5, 2.0), drift_deg=10.0, seed=(77, sweeps))
-    pair = Pair(inp, tod_dtype=dt, det_group=G, fft_m1=m1)
+    pair = Pair(inp, tod_dtype=dt, det_group=G, fft_m1=m1, scatter=scatter)
     info = pair.g.info()
     print(label, info, flush=True)
+    assert info["csr"] == (1 if (label.startswith("fourstep") and scatter == "auto") else 0)
     if m1:
         assert info["fft_m1"] == m1
     tol = TOL64 if dt == "f64" else TOL32_WHITE
@@ -125,6 +129,24 @@ def test_collision_stress_long_runs():
     for dt, tol in (("f32", TOL32_WHITE), ("f64", TOL64)):
         pair = Pair(inp, tod_dtype=dt)
         _check_apply(pair, tol, label=f"collision-{dt}")
+    # the same on the four-step pipeline with the pixel-major gather
+    inp2 = small_raster(ncomp=3, ny=16, nx=16, ndet=3, sweeps=512)  # n = 2^15
+    inp2.pix[0, :] = 5 * 16 + 7
+    inp2.pix[1, :] = np.where(np.arange(inp2.nsamp) % 2 == 0, 3, 200)
+    inp2.pix[2, :] = -1
+    for scatter in ("auto", "atomic"):
+        pair = Pair(inp2, tod_dtype="f64", det_group=2, scatter=scatter)
+        _check_apply(pair, TOL64, label=f"collision-fourstep-{scatter}")
+
+
+def test_apply_A_bitwise_repeatable():
+    inp = small_raster(ncomp=3, ny=32, nx=32, ndet=5, sweeps=256)
+    pair = Pair(inp, tod_dtype="f32", det_group=2)
+    assert pair.g.info()["csr"] == 1
+    x = pair.dev(pair.masked_random(8))
+    y1 = pair.host(pair.g.apply_A(x))
+    y2 = pair.host(pair.g.apply_A(x))
+    assert np.array_equal(y1, y2)
 
 
 def test_invalid_pixel_rejected():
