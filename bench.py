@@ -64,6 +64,91 @@ def load_traffic(kernel, src_hash):
     return None if k is None else k.get("bytes_per_launch")
 
 
+KERNEL_KEYS = (("k_pass1", "pass1"), ("k_pass2", "pass2"), ("k_pass3", "pass3"),
+               ("k_csr_reduce", "reduce"), ("k_single", "single"))
+COPY_BYTES = 512 * 2**20
+
+
+def kernel_key(name):
+    for pat, key in KERNEL_KEYS:
+        if pat in name:
+            return key
+    return None
+
+
+def summarize(trace_dir, fetch_dir, write_dir, bench_log, out_dir):
+    """Writes the kernel-time summary (from rocprofv3 --kernel-trace --stats) and
+    the calibrated HBM traffic per launch (from two --pmc runs, FETCH_SIZE and
+    WRITE_SIZE, each with a plain 512 MiB device copy as the calibration)."""
+    import csv
+    import glob
+
+    def one(pattern):
+        f = glob.glob(os.path.join(pattern, "**", "*.csv"), recursive=True)
+        return f
+
+    stats = [f for f in one(trace_dir) if f.endswith("kernel_stats.csv")]
+    rows = list(csv.DictReader(open(stats[0]))) if stats else []
+    with open(bench_log) as fh:
+        line = [l for l in fh if l.startswith("{")][-1]
+    bench = json.loads(line)
+
+    def counters(d, name):
+        f = [x for x in one(d) if x.endswith("counter_collection.csv")][0]
+        per = {}
+        copy = []
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != name:
+                continue
+            v = float(r["Counter_Value"]) * 1024.0
+            if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 65536:
+                copy.append(v)
+            k = kernel_key(r["Kernel_Name"])
+            if k:
+                per.setdefault(k, []).append(v)
+        return per, copy
+
+    fetch, cf = counters(fetch_dir, "FETCH_SIZE")
+    write, cw = counters(write_dir, "WRITE_SIZE")
+    f_fac = COPY_BYTES / max(cf) if cf else None
+    w_fac = COPY_BYTES / max(cw) if cw else None
+    kern = {}
+    for k in sorted(set(fetch) | set(write)):
+        rd = sum(fetch.get(k, [0])) / max(1, len(fetch.get(k, []))) * (f_fac or 1.0)
+        wr = sum(write.get(k, [0])) / max(1, len(write.get(k, []))) * (w_fac or 1.0)
+        kern[k] = {"read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
+                   "bytes_per_launch": rd + wr}
+    traffic = {"workload": bench["config"]["workload"], "plan": bench["config"]["plan"],
+               "source_hash": bench["source_hash"], "fetch_scale": f_fac, "write_scale": w_fac,
+               "calibration": f"plain device copy of {COPY_BYTES} bytes read + written",
+               "kernels": kern}
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, "hbm_traffic_config2.json"), "w") as fh:
+        json.dump(traffic, fh, indent=1)
+    lines = ["# Kernel times, config-2 PCG iterations (rocprofv3 --kernel-trace --stats)", "",
+             "Command (repo root, GPU box):", "",
+             "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- "
+             "python3 bench.py --steps 10 --warmup 2 --no-solve --no-cpu", "",
+             f"Kernel source hash {bench['source_hash']}; plan {json.dumps(bench['config']['plan'])}", "",
+             "| kernel | calls | avg us | total % |", "|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r.get("Percentage", 0)))[:16]:
+        name = r["Name"][:70].replace("|", "/")
+        lines.append(f"| {name} | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    lines += ["", "HBM traffic per launch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, same "
+              "command plus --calibrate-copy; FETCH scaled x%.3g and WRITE x%.3g so that a "
+              "plain copy of 512 MiB reads and writes 512 MiB):" % (f_fac or 0, w_fac or 0), "",
+              "| kernel | read MB/launch | write MB/launch |", "|---|---|---|"]
+    for k, v in kern.items():
+        lines.append(f"| {k} | {v['read_bytes_per_launch']/1e6:.1f} | "
+                     f"{v['write_bytes_per_launch']/1e6:.1f} |")
+    lines += ["", "Bench line of the traced run: " + json.dumps(
+        {k: bench[k] for k in ("value", "ms_per_step", "roofline", "apply_A")})]
+    with open(os.path.join(out_dir, "config2_pcg_kernels.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote", out_dir)
+
+
 def cpu_baseline(inp, ndet_sample=8, reps=2):
     """The FP64 oracle's A-apply on the first ndet_sample detectors."""
     import numpy as np
@@ -100,7 +185,14 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip time-to-1e-6 solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ndet", type=int, default=256, help=argparse.SUPPRESS)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--summarize", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "LOG", "OUT"),
+                    help="summarise rocprofv3 outputs into OUT and exit")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(*args.summarize)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -176,6 +268,13 @@ def main():
                             "time_s": round(r["t_solve_s"], 4), "rel_resid": r["rel_resid"]}
         solves["circulant"]["setup_s"] = round(t_setup_circ, 4)
 
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cpu = None if args.no_cpu else cpu_baseline(inp)
     out = {
         "metric": "PCG time-to-1e-6 residual (s) & A-apply samples/s; learned vs circulant vs binned",

@@ -90,6 +90,8 @@ typedef struct {
                                complex length nsamp/2 = fft_m1 * (nsamp/2/fft_m1) */
   double  mask_rcond;       /* I,Q,U activity threshold on lambda_min/lambda_max of
                                the binned block; <= 0 selects 1e-3 */
+  int32_t fft_cols;         /* columns per pass-1/3 block of the four-step FFT
+                               (power of two, 0 = automatic) */
   int32_t scatter;          /* how P^T reaches the pixels in the multi-kernel
                                (four-step) pipeline: MM_SCATTER_AUTO = per-pixel
                                gather through a pixel-major index built at
@@ -196,6 +198,7 @@ typedef struct {
   int32_t n_floored;        /* eigenvalues raised by the circulant floor */
   int32_t det_group;        /* detectors per pipeline group in use */
   int32_t fft_m1, fft_m2;   /* four-step split in use (m1 = 1: one-pass kernel) */
+  int32_t fft_cols;         /* columns per pass-1/3 block (0: one-pass kernel) */
   int32_t single_pass;      /* 1 if each detector's filter runs in one kernel */
   int32_t csr;              /* 1 if P^T runs as a per-pixel gather */
   size_t  workspace_bytes;  /* bytes used */

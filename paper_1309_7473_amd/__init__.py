@@ -150,8 +150,8 @@ class Scan:
     inv_noise (float32 [ndet][nsamp/2+1]) as numpy arrays or device tensors.
     """
 
-    def __init__(self, inputs, tod_dtype="f32", det_group=0, fft_m1=0, mask_rcond=0.0,
-                 scatter="auto", device="cuda", stream=None):
+    def __init__(self, inputs, tod_dtype="f32", det_group=0, fft_m1=0, fft_cols=0,
+                 mask_rcond=0.0, scatter="auto", device="cuda", stream=None):
         self.device = torch.device(device)
         dev = self.device
 
@@ -182,6 +182,7 @@ class Scan:
         d.inv_noise = self.inv_noise.data_ptr()
         d.det_group = int(det_group)
         d.fft_m1 = int(fft_m1)
+        d.fft_cols = int(fft_cols)
         d.mask_rcond = float(mask_rcond)
         d.scatter = {"auto": MM_SCATTER_AUTO, "atomic": MM_SCATTER_ATOMIC}[scatter]
         nbytes = mm_scan_workspace_bytes(d)

@@ -25,7 +25,7 @@ class mm_scan_desc(C.Structure):
         ("pix", C.c_void_p), ("cos2psi", C.c_void_p), ("sin2psi", C.c_void_p),
         ("inv_noise", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("det_group", C.c_int32), ("fft_m1", C.c_int32), ("mask_rcond", C.c_double),
-        ("scatter", C.c_int32),
+        ("fft_cols", C.c_int32), ("scatter", C.c_int32),
     ]
 
 
@@ -48,7 +48,7 @@ class mm_pcg_result(C.Structure):
 class mm_scan_info(C.Structure):
     _fields_ = [("n_active", C.c_int32), ("ref_pixel", C.c_int32), ("n_floored", C.c_int32),
                 ("det_group", C.c_int32), ("fft_m1", C.c_int32), ("fft_m2", C.c_int32),
-                ("single_pass", C.c_int32), ("csr", C.c_int32), ("workspace_bytes", C.c_size_t)]
+                ("fft_cols", C.c_int32), ("single_pass", C.c_int32), ("csr", C.c_int32), ("workspace_bytes", C.c_size_t)]
 
 
 class mm_profile(C.Structure):

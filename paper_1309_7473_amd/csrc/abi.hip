@@ -46,6 +46,8 @@ static mm_status validate_shape(const mm_scan_desc* d) {
   if (d->det_group < 0) return fail(MM_EINVAL, "det_group must be >= 0");
   if (d->fft_m1 < 0 || (d->fft_m1 > 0 && !pow2(d->fft_m1)))
     return fail(MM_EINVAL, "fft_m1 must be 0 or a power of two");
+  if (d->fft_cols < 0 || (d->fft_cols > 0 && !pow2(d->fft_cols)))
+    return fail(MM_EINVAL, "fft_cols must be 0 or a power of two");
   if (d->scatter != MM_SCATTER_AUTO && d->scatter != MM_SCATTER_ATOMIC)
     return fail(MM_EINVAL, "scatter must be MM_SCATTER_AUTO or MM_SCATTER_ATOMIC");
   return MM_OK;
@@ -107,6 +109,7 @@ mm_status mm_create_scan(const mm_scan_desc* desc, void* stream, mm_scan* out) {
   s.ws = static_cast<char*>(desc->workspace);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((r = upload_tables(&s, st)) != MM_OK || (r = binned_setup(&s, st)) != MM_OK ||
+      (r = permute_inverse_spectrum(&s, st)) != MM_OK ||
       (pl.csr && (r = csr_setup(&s, st)) != MM_OK)) {
     h->magic = 0;
     delete h;
@@ -204,6 +207,7 @@ mm_status mm_get_info(mm_scan scan, mm_scan_info* out) {
   out->det_group = s->plan.G;
   out->fft_m1 = s->plan.single ? 1 : (1 << s->plan.logM1);
   out->fft_m2 = s->plan.single ? (1 << s->plan.logM) : (1 << s->plan.logM2);
+  out->fft_cols = s->plan.single ? 0 : (1 << s->plan.logC);
   out->single_pass = s->plan.single ? 1 : 0;
   out->csr = s->plan.csr ? 1 : 0;
   out->workspace_bytes = s->lay.total;

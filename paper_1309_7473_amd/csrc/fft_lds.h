@@ -14,8 +14,9 @@
 //
 // Twiddles come from a table tw[m] = W_Lmax^m, m < Lmax, computed in float64
 // on the host and rounded once; a length-L transform reads it with stride
-// Lmax/L.  Forward uses W = exp(-2 pi i / L); inverse uses conj and is
-// unnormalised.
+// Lmax/L.  A radix-8 butterfly reads W and W^4 and forms the other powers by
+// complex products (at most three roundings more than the table).  Forward
+// uses W = exp(-2 pi i / L); inverse uses conj and is unnormalised.
 #pragma once
 #include "mm_device.h"
 
@@ -71,7 +72,19 @@ struct FftShape {
   int logLmax;   // table length
 };
 
-template <typename T, int R, int NT, int E, bool INV>
+// Padded LDS addressing: element i lives at i + (i >> PAD) (PAD = 0: none).
+// One pad slot per 2^PAD elements spreads the stride-R stores of the early
+// stages of contiguous transforms over the LDS banks.
+template <int PAD>
+__device__ __forceinline__ int lds_at(int i) {
+  if constexpr (PAD == 0) {
+    return i;
+  } else {
+    return i + (i >> PAD);
+  }
+}
+
+template <typename T, int R, int NT, int E, bool INV, int PAD>
 __device__ __forceinline__ void stockham_stage(Cx<T>* __restrict__ buf, const FftShape& s,
                                                int logNs, const Cx<T>* __restrict__ tw) {
   constexpr int NB = E / R;
@@ -95,9 +108,9 @@ __device__ __forceinline__ void stockham_stage(Cx<T>* __restrict__ buf, const Ff
         j = w & (LR - 1);
         b = w >> logLR;
       }
-      const Cx<T>* base = buf + b * s.bs + j * s.es;
+      const int base = b * s.bs + j * s.es;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = base[(r * LR) * s.es];
+      for (int r = 0; r < R; ++r) v[i][r] = buf[lds_at<PAD>(base + (r * LR) * s.es)];
     }
   }
   __syncthreads();
@@ -115,43 +128,59 @@ __device__ __forceinline__ void stockham_stage(Cx<T>* __restrict__ buf, const Ff
       }
       const int k = j & (Ns - 1);
       if (logNs > 0) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          Cx<T> t = tw[(r * k) << tshift];
-          if (INV) t.y = -t.y;
-          v[i][r] = v[i][r] * t;
+        // W^r for r < R from two table reads (W and W^4) and products
+        Cx<T> w[R];
+        w[1] = tw[k << tshift];
+        if (INV) w[1].y = -w[1].y;
+        if constexpr (R >= 4) w[2] = w[1] * w[1];
+        if constexpr (R >= 4) w[3] = w[2] * w[1];
+        if constexpr (R == 8) {
+          w[4] = tw[(4 * k) << tshift];
+          if (INV) w[4].y = -w[4].y;
+          w[5] = w[4] * w[1];
+          w[6] = w[4] * w[2];
+          w[7] = w[4] * w[3];
         }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[i][r] = v[i][r] * w[r];
       }
       dft_reg<T, R, INV>(v[i]);
       const int out = ((j - k) << logR) + k;
-      Cx<T>* base = buf + b * s.bs + out * s.es;
+      const int base = b * s.bs + out * s.es;
 #pragma unroll
-      for (int r = 0; r < R; ++r) base[(r * Ns) * s.es] = v[i][r];
+      for (int r = 0; r < R; ++r) buf[lds_at<PAD>(base + (r * Ns) * s.es)] = v[i][r];
     }
   }
   __syncthreads();
 }
 
-// Full transform; must be called by all NT threads of the block.
-template <typename T, int NT, int E, bool INV>
+// Full transform; must be called by all NT threads of the block.  The
+// radix-2/4 stage (if log2 L is not a multiple of 3) runs first, or last with
+// SMALL_LAST: for contiguous transforms (es = 1) the stride of the stores of
+// the stages that follow the first one is then R * Ns >= 64 elements apart
+// only in whole 64-element runs.
+template <typename T, int NT, int E, bool INV, int PAD = 0, bool SMALL_LAST = false>
 __device__ __forceinline__ void lds_fft(Cx<T>* __restrict__ buf, const FftShape& s,
                                         const Cx<T>* __restrict__ tw) {
   int logNs = 0;
   int rem = s.logL;
-  if (rem % 3 == 1) {
-    stockham_stage<T, 2, NT, E, INV>(buf, s, logNs, tw);
-    logNs += 1;
-    rem -= 1;
-  } else if (rem % 3 == 2) {
-    stockham_stage<T, 4, NT, E, INV>(buf, s, logNs, tw);
-    logNs += 2;
-    rem -= 2;
-  }
+  const int small = rem % 3;
+  auto small_stage = [&]() {
+    if (small == 1) {
+      stockham_stage<T, 2, NT, E, INV, PAD>(buf, s, logNs, tw);
+    } else if (small == 2) {
+      stockham_stage<T, 4, NT, E, INV, PAD>(buf, s, logNs, tw);
+    }
+    logNs += small;
+  };
+  if (!SMALL_LAST && small) small_stage();
+  rem -= small;
   while (rem >= 3) {
-    stockham_stage<T, 8, NT, E, INV>(buf, s, logNs, tw);
+    stockham_stage<T, 8, NT, E, INV, PAD>(buf, s, logNs, tw);
     logNs += 3;
     rem -= 3;
   }
+  if (SMALL_LAST && small) small_stage();
 }
 
 }  // namespace mm

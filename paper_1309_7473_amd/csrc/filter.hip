@@ -52,6 +52,8 @@ struct PassArgs {
   const int32_t* csr_idx;  // group entries
   const float2* csr_w;     // group entries (I,Q,U weights)
   const int32_t* mask;
+  const float* iNt;        // group base [G][M+1], four-step order
+  const Cx<T>* tw2;        // W_{2 M2}^k2, k2 < M2
   int64_t n;
   int npix;
   int logM, logM1, logM2, logC, logLmax;
@@ -205,136 +207,237 @@ __global__ void __launch_bounds__(kNT) k_single(PassArgs<T> a) {
 }
 
 // ------------------------------------------------------------- four-step
+constexpr int kNT13 = 1024;  // threads per pass-1/3 block
+constexpr int kE13 = 8;      // complex elements per thread (C * M1 <= 8192)
+constexpr int kPad2 = 3;     // pass-2 LDS padding: one slot per 8 elements
+
+// Four consecutive samples s..s+3 (s a multiple of 4) with 16-byte loads.
 template <typename T, int NC, int SRC>
-__global__ void __launch_bounds__(kNT) k_pass1(PassArgs<T> a) {
+__device__ __forceinline__ void source4(const PassArgs<T>& a, int64_t s, T (&v)[4]) {
+  if constexpr (SRC == 1) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 t = *reinterpret_cast<const float4*>(a.tod + s);
+      v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else {
+      const double2 t0 = *reinterpret_cast<const double2*>(a.tod + s);
+      const double2 t1 = *reinterpret_cast<const double2*>(a.tod + s + 2);
+      v[0] = t0.x; v[1] = t0.y; v[2] = t1.x; v[3] = t1.y;
+    }
+  } else {
+    const int4 p4 = *reinterpret_cast<const int4*>(a.pix + s);
+    const int pp[4] = {p4.x, p4.y, p4.z, p4.w};
+    float cc[4] = {0.f, 0.f, 0.f, 0.f}, ss[4] = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (NC == 3) {
+      const float4 c4 = *reinterpret_cast<const float4*>(a.c2 + s);
+      const float4 s4 = *reinterpret_cast<const float4*>(a.s2 + s);
+      cc[0] = c4.x; cc[1] = c4.y; cc[2] = c4.z; cc[3] = c4.w;
+      ss[0] = s4.x; ss[1] = s4.y; ss[2] = s4.z; ss[3] = s4.w;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = pp[i];
+      if (unsigned(p) < unsigned(a.npix)) {
+        const V4<T> m = a.gmap[p];
+        v[i] = (NC == 3) ? m.x + T(cc[i]) * m.y + T(ss[i]) * m.z : m.x;
+      } else {
+        v[i] = T(0);
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(T* dst, const T (&v)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+    reinterpret_cast<double2*>(dst)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2*>(dst)[1] = make_double2(v[2], v[3]);
+  }
+}
+
+// Copies the length-L Stockham twiddles (W_L^m = W_Lmax^(m Lmax/L)) to LDS.
+template <typename T, int NT>
+__device__ __forceinline__ void stage_twiddles(Cx<T>* stw, const Cx<T>* tw, int logL, int logLmax) {
+  for (int m = threadIdx.x; m < (1 << logL); m += NT) stw[m] = tw[m << (logLmax - logL)];
+}
+
+// Blocks are dealt to the 8 XCDs round-robin (block i runs on XCD i mod 8).
+// For pass 1/3 the column blocks of a detector are renumbered so that XCD x
+// handles the x-th eighth of them: its samples then sit in one eighth of each
+// sweep, and the map pixels they touch stay in that XCD's L2.
+__device__ __forceinline__ void col_block(int logNB, int* g, int* cb) {
+  const int bid = blockIdx.x;
+  if (logNB >= 3) {
+    const int x = bid & 7, slot = bid >> 3;              // XCD, slot on it
+    const int per = 1 << (logNB - 3);                      // column blocks per XCD
+    *g = slot >> (logNB - 3);
+    *cb = x * per + (slot & (per - 1));
+  } else {
+    *g = bid >> logNB;
+    *cb = bid & ((1 << logNB) - 1);
+  }
+}
+
+template <typename T, int NC, int SRC>
+__global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
   T* bufr = reinterpret_cast<T*>(smem);
   const int logNB = a.logM2 - a.logC;
-  const int g = blockIdx.x >> logNB;
-  const int cb = blockIdx.x & ((1 << logNB) - 1);
+  int g, cb;
+  col_block(logNB, &g, &cb);
   const int C = 1 << a.logC;
   const int M1 = 1 << a.logM1, M2 = 1 << a.logM2;
+  Cx<T>* stw = buf + C * M1;
   const int j20 = cb << a.logC;
   const int64_t base = int64_t(g) * a.n;
-  const int nsamp = 2 * C * M1;
+  stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
+  const int nq = (C * M1) >> 1;  // groups of 4 samples
 #pragma unroll 4
-  for (int e = threadIdx.x; e < nsamp; e += kNT) {
+  for (int e4 = threadIdx.x; e4 < nq; e4 += kNT13) {
+    const int e = e4 << 2;
     const int j1 = e >> (a.logC + 1);
     const int q = e & (2 * C - 1);
     const int64_t s = base + 2 * (int64_t(j1) * M2 + j20) + q;
-    bufr[e] = source_sample<T, NC, SRC>(a, s);
+    T v[4];
+    source4<T, NC, SRC>(a, s, v);
+    store4(bufr + e, v);
   }
   __syncthreads();
-  FftShape sh{a.logM1, a.logC, C, 1, true, a.logLmax};
-  lds_fft<T, kNT, kE, false>(buf, sh, a.tw);
+  FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
+  lds_fft<T, kNT13, kE13, false>(buf, sh, stw);
   Cx<T>* w = a.work + (int64_t(g) << a.logM);
-  for (int e = threadIdx.x; e < C * M1; e += kNT) {
+  for (int e = threadIdx.x; e < C * M1; e += kNT13) {
     const int k1 = e >> a.logC;
     const int c = e & (C - 1);
     w[int64_t(k1) * M2 + j20 + c] = buf[e];
   }
 }
 
-template <typename T>
+// Rows k1 = ra and rb = M1 - ra (or 0 and M1/2) of one detector.  The
+// four-step twiddle W_M^(k1 j2) = A[j2 >> 6] * B[j2 & 63] comes from two
+// small per-row LDS tables; W_n^k = W_n^k1 * W_2M2^k2; 1/N(f) is read from
+// its copy in four-step order (row k1 contiguous).
+template <typename T, int E>
 __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
   const int M1 = 1 << a.logM1, M2 = 1 << a.logM2;
   const int M = 1 << a.logM;
+  Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
+  Cx<T>* stw = buf + lds_at<kPad2>(2 * M2);   // length-M2 Stockham twiddles
+  const int logJL = a.logM2 < 6 ? a.logM2 : 6;
+  const int JL = 1 << logJL, JH = M2 >> logJL;
+  Cx<T>* tA = stw + M2;      // [2][JH]
+  Cx<T>* tB = tA + 2 * JH;   // [2][JL]
   const int lhalf = a.logM1 - 1;
   const int g = blockIdx.x >> lhalf;
   const int pr = blockIdx.x & ((1 << lhalf) - 1);
   const int ra = pr;
   const int rb = (pr == 0) ? (M1 >> 1) : (M1 - pr);
+  stage_twiddles<T, kNT>(stw, a.tw, a.logM2, a.logLmax);
+  for (int t = threadIdx.x; t < 2 * JH; t += kNT) {
+    const int r = t >= JH, jh = t - r * JH;
+    tA[t] = a.wn(2 * int64_t(r ? rb : ra) * (int64_t(jh) << logJL));
+  }
+  for (int t = threadIdx.x; t < 2 * JL; t += kNT) {
+    const int r = t >= JL, jl = t - r * JL;
+    tB[t] = a.wn(2 * int64_t(r ? rb : ra) * jl);
+  }
+  __syncthreads();
   Cx<T>* w = a.work + (int64_t(g) << a.logM);
   for (int e = threadIdx.x; e < 2 * M2; e += kNT) {
     const int row = e >> a.logM2;
     const int j2 = e & (M2 - 1);
     const int k1 = row ? rb : ra;
     const Cx<T> v = w[int64_t(k1) * M2 + j2];
-    buf[e] = v * a.wn(2 * int64_t(k1) * j2);
+    buf[lds_at<kPad2>(e)] = v * (tA[row * JH + (j2 >> logJL)] * tB[row * JL + (j2 & (JL - 1))]);
   }
   __syncthreads();
-  FftShape sh{a.logM2, 1, 1, M2, false, a.logLmax};
-  lds_fft<T, kNT, kE, false>(buf, sh, a.tw);
-  const float* iN = a.iN + int64_t(g) * (M + 1);
+  FftShape sh{a.logM2, 1, 1, M2, false, a.logM2};
+  lds_fft<T, kNT, E, false, kPad2, true>(buf, sh, stw);
+  const float* iN = a.iNt + int64_t(g) * (M + 1);  // [k1][k2] order, then iN[M]
   const T sc = a.scale;
   if (pr != 0) {
+    const Cx<T> wa = a.wn(ra);
+    const float* ia = iN + int64_t(ra) * M2;
+    const float* ib = iN + int64_t(rb) * M2;
     for (int k2 = threadIdx.x; k2 < M2; k2 += kNT) {
-      const int k = ra + M1 * k2;
       const int im = M2 + (M2 - 1 - k2);
-      Cx<T> zk = buf[k2], zm = buf[im];
-      pair_filter(zk, zm, a.wn(k), sc * T(iN[k]), sc * T(iN[M - k]));
-      buf[k2] = zk;
-      buf[im] = zm;
+      Cx<T> zk = buf[lds_at<kPad2>(k2)], zm = buf[lds_at<kPad2>(im)];
+      pair_filter(zk, zm, wa * a.tw2[k2], sc * T(ia[k2]), sc * T(ib[M2 - 1 - k2]));
+      buf[lds_at<kPad2>(k2)] = zk;
+      buf[lds_at<kPad2>(im)] = zm;
     }
   } else {
+    const Cx<T> wh = a.wn(M1 >> 1);
+    const float* ih = iN + int64_t(M1 >> 1) * M2;
     for (int t = threadIdx.x; t < M2; t += kNT) {
       if (t < M2 / 2) {
         // row 0: k = M1*k2, partner M1*(M2-k2)
         const int k2 = t;
         if (k2 == 0) {
-          buf[0] = dc_filter(buf[0], sc * T(iN[0]), sc * T(iN[M]));
+          buf[lds_at<kPad2>(0)] = dc_filter(buf[lds_at<kPad2>(0)], sc * T(iN[0]), sc * T(iN[M]));
           // k = M/2 (k2 = M2/2) pairs with itself
           const int h = M2 / 2;
-          Cx<T> zk = buf[h], zm = buf[h];
-          pair_filter(zk, zm, a.wn(M / 2), sc * T(iN[M / 2]), sc * T(iN[M / 2]));
-          buf[h] = zk;
+          Cx<T> zk = buf[lds_at<kPad2>(h)], zm = buf[lds_at<kPad2>(h)];
+          pair_filter(zk, zm, a.tw2[h], sc * T(iN[h]), sc * T(iN[h]));
+          buf[lds_at<kPad2>(h)] = zk;
         } else {
-          const int k = M1 * k2;
-          Cx<T> zk = buf[k2], zm = buf[M2 - k2];
-          pair_filter(zk, zm, a.wn(k), sc * T(iN[k]), sc * T(iN[M - k]));
-          buf[k2] = zk;
-          buf[M2 - k2] = zm;
+          Cx<T> zk = buf[lds_at<kPad2>(k2)], zm = buf[lds_at<kPad2>(M2 - k2)];
+          pair_filter(zk, zm, a.tw2[k2], sc * T(iN[k2]), sc * T(iN[M2 - k2]));
+          buf[lds_at<kPad2>(k2)] = zk;
+          buf[lds_at<kPad2>(M2 - k2)] = zm;
         }
       } else {
         // row M1/2: k = M1/2 + M1*k2, partner at column M2-1-k2
         const int k2 = t - M2 / 2;
-        const int k = (M1 >> 1) + M1 * k2;
         const int i0 = M2 + k2, i1 = M2 + (M2 - 1 - k2);
-        Cx<T> zk = buf[i0], zm = buf[i1];
-        pair_filter(zk, zm, a.wn(k), sc * T(iN[k]), sc * T(iN[M - k]));
-        buf[i0] = zk;
-        buf[i1] = zm;
+        Cx<T> zk = buf[lds_at<kPad2>(i0)], zm = buf[lds_at<kPad2>(i1)];
+        pair_filter(zk, zm, wh * a.tw2[k2], sc * T(ih[k2]), sc * T(ih[M2 - 1 - k2]));
+        buf[lds_at<kPad2>(i0)] = zk;
+        buf[lds_at<kPad2>(i1)] = zm;
       }
     }
   }
   __syncthreads();
-  lds_fft<T, kNT, kE, true>(buf, sh, a.tw);
+  lds_fft<T, kNT, E, true, kPad2, true>(buf, sh, stw);
   for (int e = threadIdx.x; e < 2 * M2; e += kNT) {
     const int row = e >> a.logM2;
     const int j2 = e & (M2 - 1);
     const int k1 = row ? rb : ra;
-    w[int64_t(k1) * M2 + j2] = buf[e] * conj(a.wn(2 * int64_t(k1) * j2));
+    w[int64_t(k1) * M2 + j2] =
+        buf[lds_at<kPad2>(e)] * conj(tA[row * JH + (j2 >> logJL)] * tB[row * JL + (j2 & (JL - 1))]);
   }
 }
 
 // CSR = true: store the filtered, packed timestream back in place (the block
 // owns exactly the addresses it loaded); the per-pixel reduce applies P^T.
 template <typename T, int NC, bool CSR>
-__global__ void __launch_bounds__(kNT) k_pass3(PassArgs<T> a) {
+__global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
   T* bufr = reinterpret_cast<T*>(smem);
   const int logNB = a.logM2 - a.logC;
-  const int g = blockIdx.x >> logNB;
-  const int cb = blockIdx.x & ((1 << logNB) - 1);
+  int g, cb;
+  col_block(logNB, &g, &cb);
   const int C = 1 << a.logC;
   const int M1 = 1 << a.logM1, M2 = 1 << a.logM2;
+  Cx<T>* stw = buf + C * M1;
   const int j20 = cb << a.logC;
+  stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
   const Cx<T>* w = a.work + (int64_t(g) << a.logM);
-  for (int e = threadIdx.x; e < C * M1; e += kNT) {
+  for (int e = threadIdx.x; e < C * M1; e += kNT13) {
     const int k1 = e >> a.logC;
     const int c = e & (C - 1);
     buf[e] = w[int64_t(k1) * M2 + j20 + c];
   }
   __syncthreads();
-  FftShape sh{a.logM1, a.logC, C, 1, true, a.logLmax};
-  lds_fft<T, kNT, kE, true>(buf, sh, a.tw);
+  FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
+  lds_fft<T, kNT13, kE13, true>(buf, sh, stw);
   if constexpr (CSR) {
     Cx<T>* wo = a.work + (int64_t(g) << a.logM);
-    for (int e = threadIdx.x; e < C * M1; e += kNT) {
+    for (int e = threadIdx.x; e < C * M1; e += kNT13) {
       const int k1 = e >> a.logC;
       const int c = e & (C - 1);
       wo[int64_t(k1) * M2 + j20 + c] = buf[e];
@@ -343,7 +446,7 @@ __global__ void __launch_bounds__(kNT) k_pass3(PassArgs<T> a) {
   }
   const int64_t base = int64_t(g) * a.n;
   const int nsamp = 2 * C * M1;
-  for (int e = threadIdx.x; e < nsamp; e += kNT) {
+  for (int e = threadIdx.x; e < nsamp; e += kNT13) {
     const int j1 = e >> (a.logC + 1);
     const int q = e & (2 * C - 1);
     const int64_t s = base + 2 * (int64_t(j1) * M2 + j20) + q;
@@ -365,6 +468,7 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T> a) {
   const T* u = reinterpret_cast<const T*>(a.work);
   const int b = a.csr_off[p], e = a.csr_off[p + 1];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
   for (int k = b + l; k < e; k += LPP) {
     const double uu = double(u[a.csr_idx[k]]);
     s0 += uu;
@@ -427,6 +531,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
   a.logLmax = pl.logLmax;
   a.scale = T(1) / T(M);
   a.mask = s->at<int32_t>(s->lay.mask);
+  a.tw2 = s->at<Cx<T>>(s->lay.tw2);
   const int G = pl.G;
   for (int d0 = 0; d0 < s->ndet; d0 += G) {
     const int gd = (s->ndet - d0 < G) ? (s->ndet - d0) : G;
@@ -435,6 +540,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
     a.c2 = s->d.cos2psi ? s->d.cos2psi + off : nullptr;
     a.s2 = s->d.sin2psi ? s->d.sin2psi + off : nullptr;
     a.iN = s->d.inv_noise + int64_t(d0) * (M + 1);
+    a.iNt = pl.single ? nullptr : s->at<float>(s->lay.int_) + int64_t(d0) * (M + 1);
     a.tod = tod ? static_cast<const T*>(tod) + off : nullptr;
     if (pl.csr) {
       const int gi = d0 / G;
@@ -453,23 +559,34 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
     } else {
       const int C = 1 << pl.logC;
       const int M1 = 1 << pl.logM1, M2 = 1 << pl.logM2;
-      const size_t lds13 = size_t(C) * M1 * sizeof(Cx<T>);
-      const size_t lds2 = size_t(2) * M2 * sizeof(Cx<T>);
+      const size_t lds13 = (size_t(C) * M1 + M1) * sizeof(Cx<T>);
+      const int JL = M2 < 64 ? M2 : 64;
+      const size_t lds2 =
+          (size_t(2) * M2 + (size_t(2) * M2 >> kPad2) + M2 + 2 * (M2 / JL) + 2 * JL) * sizeof(Cx<T>);
       raise_lds_limit(k_pass1<T, NC, SRC>, lds13);
-      raise_lds_limit(k_pass2<T>, lds2);
       raise_lds_limit(k_pass3<T, NC, false>, lds13);
       raise_lds_limit(k_pass3<T, NC, true>, lds13);
       prof_begin(s, st, &tok);
-      hipLaunchKernelGGL((k_pass1<T, NC, SRC>), dim3(gd * (M2 / C)), dim3(kNT), lds13, st, a);
+      hipLaunchKernelGGL((k_pass1<T, NC, SRC>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
       prof_end(s, st, tok, kProfPass1, gs);
       prof_begin(s, st, &tok);
-      hipLaunchKernelGGL((k_pass2<T>), dim3(gd * (M1 / 2)), dim3(kNT), lds2, st, a);
+      const dim3 g2(gd * (M1 / 2));
+      if (M2 <= 1024) {
+        raise_lds_limit(k_pass2<T, 8>, lds2);
+        hipLaunchKernelGGL((k_pass2<T, 8>), g2, dim3(kNT), lds2, st, a);
+      } else if (M2 <= 2048) {
+        raise_lds_limit(k_pass2<T, 16>, lds2);
+        hipLaunchKernelGGL((k_pass2<T, 16>), g2, dim3(kNT), lds2, st, a);
+      } else {
+        raise_lds_limit(k_pass2<T, 32>, lds2);
+        hipLaunchKernelGGL((k_pass2<T, 32>), g2, dim3(kNT), lds2, st, a);
+      }
       prof_end(s, st, tok, kProfPass2, gs);
       prof_begin(s, st, &tok);
       if (pl.csr)
-        hipLaunchKernelGGL((k_pass3<T, NC, true>), dim3(gd * (M2 / C)), dim3(kNT), lds13, st, a);
+        hipLaunchKernelGGL((k_pass3<T, NC, true>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
       else
-        hipLaunchKernelGGL((k_pass3<T, NC, false>), dim3(gd * (M2 / C)), dim3(kNT), lds13, st, a);
+        hipLaunchKernelGGL((k_pass3<T, NC, false>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
       prof_end(s, st, tok, kProfPass3, gs);
       if (pl.csr) {
         prof_begin(s, st, &tok);
@@ -517,6 +634,33 @@ mm_status filter_pipeline(ScanImpl* s, int src, const void* tod, const double* x
   return MM_OK;
 }
 
+// 1/N(f) of every detector in four-step order: out[k1*M2 + k2] = iN[k1 + M1*k2]
+// for k < M, out[M] = iN[M].
+__global__ void k_permute_iN(const float* __restrict__ iN, float* __restrict__ out, int logM1,
+                             int logM2) {
+  const int d = blockIdx.y;
+  const int64_t M = int64_t(1) << (logM1 + logM2);
+  const float* src = iN + d * (M + 1);
+  float* dst = out + d * (M + 1);
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k <= M;
+       k += int64_t(gridDim.x) * blockDim.x) {
+    if (k == M) {
+      dst[M] = src[M];
+    } else {
+      const int64_t k1 = k & ((int64_t(1) << logM1) - 1), k2 = k >> logM1;
+      dst[(k1 << logM2) + k2] = src[k];
+    }
+  }
+}
+
+mm_status permute_inverse_spectrum(ScanImpl* s, hipStream_t st) {
+  if (s->plan.single) return MM_OK;
+  hipLaunchKernelGGL(k_permute_iN, dim3(64, s->ndet), dim3(256), 0, st, s->d.inv_noise,
+                     s->at<float>(s->lay.int_), s->plan.logM1, s->plan.logM2);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
 // --------------------------------------------------------- plan / tables
 mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   const int64_t n = d->nsamp;
@@ -546,17 +690,18 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     pl->logM2 = pl->logM - l1;
     if (pl->logM1 < 2 || pl->logM2 < 5 || pl->logM2 > 12 || pl->logM1 > 9)
       return fail(MM_EINVAL, "fft_m1 gives an unsupported four-step split");
-    int lc = 4;
+    int lc = d->fft_cols > 0 ? ilog2(d->fft_cols) : 4;
     while (lc > 0 && ((1 << lc) << pl->logM1) > kE * kNT) --lc;
     if (lc > pl->logM2) lc = pl->logM2;
+    if (lc < 1) return fail(MM_EINVAL, "fft_cols leaves fewer than two columns per block");
     pl->logC = lc;
     if ((2 << (lc + pl->logM1)) % kNT != 0 || (2 << pl->logM2) % kNT != 0)
       return fail(MM_EINVAL, "four-step blocks too small for the thread count");
     int G = d->det_group;
     if (G <= 0) {
-      // keep the group's timestream scratch near 64 MiB (MALL-resident)
+      // about 256 MiB of timestream scratch per group (large launches)
       const int64_t per = int64_t(M) * int64_t(cxb);
-      G = int((int64_t(64) << 20) / per);
+      G = int((int64_t(256) << 20) / per);
       if (G < 1) G = 1;
     }
     if (G > d->ndet) G = d->ndet;
@@ -578,6 +723,8 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   };
   L->tod = take(pl->single ? 0 : size_t(pl->G) * size_t(M) * cxb);
   L->tw = take((size_t(1) << pl->logLmax) * cxb);
+  L->tw2 = take(pl->single ? 0 : (size_t(1) << pl->logM2) * cxb);
+  L->int_ = take(pl->single ? 0 : size_t(d->ndet) * size_t(M + 1) * 4);
   L->wn_hi = take((size_t(1) << (pl->logn - pl->logS)) * cxb);
   L->wn_lo = take((size_t(1) << pl->logS) * cxb);
   L->gmap = take(size_t(npix) * 4 * (pl->f64 ? 8 : 4));
@@ -632,6 +779,13 @@ static mm_status upload_t(ScanImpl* s, hipStream_t st) {
   table(lo, S, 1, n);
   MM_HIP(hipMemcpyAsync(s->ws + s->lay.tw, tw.data(), tw.size() * sizeof(Cx<T>),
                         hipMemcpyHostToDevice, st));
+  std::vector<Cx<T>> t2;
+  if (!pl.single) {
+    const int64_t M2 = int64_t(1) << pl.logM2;
+    table(t2, M2, 1, 2 * M2);
+    MM_HIP(hipMemcpyAsync(s->ws + s->lay.tw2, t2.data(), t2.size() * sizeof(Cx<T>),
+                          hipMemcpyHostToDevice, st));
+  }
   MM_HIP(hipMemcpyAsync(s->ws + s->lay.wn_hi, hi.data(), hi.size() * sizeof(Cx<T>),
                         hipMemcpyHostToDevice, st));
   MM_HIP(hipMemcpyAsync(s->ws + s->lay.wn_lo, lo.data(), lo.size() * sizeof(Cx<T>),

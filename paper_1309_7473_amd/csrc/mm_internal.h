@@ -48,6 +48,8 @@ struct PcgDev {
 struct Layout {
   size_t tod;        // pipeline scratch: G * M complex (0 bytes if single pass)
   size_t tw;         // Stockham table, Lmax complex
+  size_t tw2;        // W_{2 M2}^k2 table, M2 complex (four-step)
+  size_t int_;       // ndet * (M+1) float: 1/N(f) in four-step order
   size_t wn_hi, wn_lo;
   size_t gmap;       // npix * 4 real (gather map)
   size_t acc;        // npix * 4 double (scatter accumulator)
@@ -113,6 +115,7 @@ mm_status filter_pipeline(ScanImpl* s, int src /*0 gather x, 1 timestream*/,
                           const void* tod, const double* x, double* y, hipStream_t st);
 mm_status binned_setup(ScanImpl* s, hipStream_t st);
 mm_status csr_setup(ScanImpl* s, hipStream_t st);
+mm_status permute_inverse_spectrum(ScanImpl* s, hipStream_t st);
 mm_status binned_apply(ScanImpl* s, int jacobi, const double* r, double* z, hipStream_t st);
 mm_status circulant_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st);
 mm_status circulant_apply(ScanImpl* s, const double* r, double* z, hipStream_t st);

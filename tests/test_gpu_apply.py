@@ -165,7 +165,7 @@ def test_config2_shape_detector_subset():
     inp = make_config(2, ndet=16)
     pair = Pair(inp, tod_dtype="f32")
     info = pair.g.info()
-    assert (info["fft_m1"], info["fft_m2"], info["det_group"]) == (512, 1024, 16)
+    assert (info["fft_m1"], info["fft_m2"], info["fft_cols"], info["det_group"]) == (512, 1024, 16, 16)
     _check_apply(pair, TOL32_WHITE, label="config2-subset")
     sky = (inp.sky * pair.mask.reshape(1, 512, 512)).ravel()
     e = rel(pair.A_gpu(sky), pair.A_oracle(sky))
