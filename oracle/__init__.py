@@ -16,7 +16,10 @@ Everything is float64 NumPy/SciPy, written for clarity over speed:
   sections);
 * pcg.py       - preconditioned conjugate gradients and the CG error A-norm
   estimate quoted in the Results section;
-* dense.py     - dense A by probing unit vectors (eq. 6) and a direct solve.
+* dense.py     - dense A by probing unit vectors (eq. 6) and a direct solve;
+* learned.py   - the learned linear symmetric correction M_L = M_C +
+  Sigma^-1 H^T H Sigma^-T (not in the paper): convolutions, adjoints, loss,
+  gradients, Adam and training pairs.
 
 Readings of points the paper leaves open are listed in the design doc; functions
 cite the equation or section they follow.  Parity unpinned: none of the
