@@ -41,6 +41,7 @@ extern "C" {
 #endif
 
 typedef struct mm_scan_s* mm_scan;   /* opaque, owned by the library */
+typedef struct mm_learned_s* mm_learned;  /* opaque learned correction */
 
 typedef enum {
   MM_OK = 0,
@@ -59,7 +60,8 @@ typedef enum {
   MM_M_NONE = 0,       /* identity */
   MM_M_JACOBI = 1,     /* eq. 5: per-pixel blocks of P^T P */
   MM_M_BINNED = 2,     /* eq. 3-4: per-pixel blocks of P^T diag(N^-1_tt) P */
-  MM_M_CIRCULANT = 3   /* eq. 8-13: Sigma^-1 F^-1 K(k)^-1 F Sigma^-T */
+  MM_M_CIRCULANT = 3,  /* eq. 8-13: Sigma^-1 F^-1 K(k)^-1 F Sigma^-T */
+  MM_M_LEARNED = 4     /* M_C + Sigma^-1 H^T H Sigma^-T (mm_learned_attach) */
 } mm_precon;
 
 /* Description of one scan (one set of detector timestreams and pointing). */
@@ -169,6 +171,9 @@ typedef struct {
   int32_t maxiter;          /* maximum A-applies in the loop */
   int32_t check_every;      /* read the residual on the host every k iterations (>= 1) */
   int32_t use_x0;           /* 1: start from the x passed in; 0: x0 = 0 */
+  int32_t snap_every;       /* > 0: copy the iterate x_k into snapshots[k/snap_every - 1] */
+  int32_t max_snaps;        /*      for k = snap_every, 2 snap_every, ... up to max_snaps */
+  double* snapshots;        /* device [max_snaps][ncomp][ny][nx] float64, or NULL */
 } mm_pcg_opts;
 
 typedef struct {
@@ -183,13 +188,65 @@ typedef struct {
 } mm_pcg_result;
 
 /* Solves A x = b by PCG (Introduction; textbook PCG with device-resident
- * scalars).  precon: MM_M_NONE, JACOBI, BINNED or CIRCULANT (the latter must
- * be built).  b, x: [ncomp][ny][nx] float64 device arrays; x is overwritten
+ * scalars).  precon: MM_M_NONE, JACOBI, BINNED, CIRCULANT (built) or LEARNED
+ * (circulant built and a learned correction attached).  b, x: [ncomp][ny][nx] float64 device arrays; x is overwritten
  * with the solution.  Synchronises `stream`.  Returns MM_OK, MM_ENOCONV or
  * MM_EBREAKDOWN (with res filled in all three cases). */
 mm_status mm_pcg_solve(mm_scan scan, int32_t precon, const double* b, double* x,
                        const mm_pcg_opts* opts /*[host]*/,
                        mm_pcg_result* res /*[host]*/, void* stream);
+
+/* ---- Learned correction to the circulant preconditioner (not in the paper):
+ * M_L r = M_C r + Sigma^-1 H^T H Sigma^-T r, H = C2 o C1 with C1 (ncomp -> 16
+ * channels) and C2 (16 -> 16) 5x5 same-padded correlations without bias,
+ * H^T their exact adjoints (weights tied, so M_L is symmetric and M_L - M_C
+ * positive semi-definite).  Convolutions run on bf16 MFMA with float32
+ * accumulation; the float32 master weights are trained with Adam on
+ * whitened pairs (r_w, t, ||e_w||^2) built by mm_learned_make_pair, loss
+ * mean ||H^T H r_w - t||^2 / ||e_w||^2.  Weights: w1 [16][ncomp][5][5],
+ * w2 [16][16][5][5] float32, row-major.  Images are [ncomp][ny][nx] float32. */
+typedef struct {
+  int32_t  epochs, batch;   /* batch <= the batch given to mm_learned_create */
+  double   lr, beta1, beta2, eps;
+  uint64_t seed;            /* pair shuffling */
+  int32_t  shuffle, drop_last;
+} mm_train_opts;
+
+/* Device workspace for a learned correction on ny x nx maps with training
+ * batches of up to `batch` pairs (activations, gradients, Adam state). */
+size_t mm_learned_workspace_bytes(int32_t ncomp, int32_t ny, int32_t nx, int32_t batch);
+mm_status mm_learned_create(int32_t ncomp, int32_t ny, int32_t nx, int32_t batch, void* workspace,
+                            size_t workspace_bytes, const float* w1 /*[host]*/,
+                            const float* w2 /*[host]*/, void* stream, mm_learned* out /*[host]*/);
+void mm_learned_destroy(mm_learned learned);
+mm_status mm_learned_get(mm_learned learned, float* w1 /*[host]*/, float* w2 /*[host]*/);
+/* Attaches (or with NULL detaches) a learned correction of the scan's map
+ * shape; MM_M_LEARNED then needs the circulant preconditioner built. */
+mm_status mm_learned_attach(mm_scan scan, mm_learned learned);
+/* One training pair from a converged x_f and an iterate x_k (device float64
+ * maps): e = x_f - x_k, r = A e, r_w = Sigma^-T r, t = Sigma e - Sigma M_C r,
+ * e2 = ||Sigma e||^2 (one float).  Needs the circulant preconditioner. */
+mm_status mm_learned_make_pair(mm_scan scan, const double* x_f, const double* x_k, float* r_w,
+                               float* t, float* e2, void* stream);
+/* Adam epochs over npairs device pairs; loss_history [host, epochs] optional.
+ * Synchronises. */
+mm_status mm_learned_train(mm_learned learned, const float* r_w, const float* t, const float* e2,
+                           int64_t npairs, const mm_train_opts* opts /*[host]*/,
+                           double* loss_history /*[host]*/, void* stream);
+/* Mean loss over npairs pairs (no update).  Synchronises. */
+mm_status mm_learned_loss(mm_learned learned, const float* r_w, const float* t, const float* e2,
+                          int64_t npairs, double* loss /*[host]*/, void* stream);
+/* H^T H of B images x (device) into y, and optionally the intermediate
+ * activations a1 = C1 x, a2 = C2 a1, a3 = C2^T a2 ([B][16][ny][nx]). */
+mm_status mm_learned_forward(mm_learned learned, const float* x, int32_t B, float* y, float* a1,
+                             float* a2, float* a3, void* stream);
+/* Loss and weight gradients of B pairs without updating the weights;
+ * g1, g2 [host] in the weight layouts.  Synchronises. */
+mm_status mm_learned_grad(mm_learned learned, const float* r_w, const float* t, const float* e2,
+                          int32_t B, double* loss /*[host]*/, float* g1 /*[host]*/,
+                          float* g2 /*[host]*/, void* stream);
+/* z = M_L r (circulant built, learned correction attached). */
+mm_status mm_apply_precon_learned(mm_scan scan, const double* r, double* z, void* stream);
 
 /* Diagnostics of a scan handle. */
 typedef struct {

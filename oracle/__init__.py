@@ -21,7 +21,7 @@ Everything is float64 NumPy/SciPy, written for clarity over speed:
   Sigma^-1 H^T H Sigma^-T (not in the paper): convolutions, adjoints, loss,
   gradients, Adam and training pairs.
 
-Readings of points the paper leaves open are listed in the design doc; functions
+Each module states the readings it takes where the paper is silent; functions
 cite the equation or section they follow.  Parity unpinned: none of the
 functions here (every one has a pin in tests/test_oracle_*.py).
 """

@@ -18,11 +18,12 @@ from ._abi import (  # noqa: F401
     lib, check, MMError, mm_scan_desc, mm_precon_opts, mm_pcg_opts, mm_pcg_result,
     mm_scan_info, MM_OK, MM_ENOCONV, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENOTBUILT,
     MM_EBREAKDOWN, MM_F32, MM_BF16, MM_F64, MM_M_NONE, MM_M_JACOBI, MM_M_BINNED,
-    MM_M_CIRCULANT, LIB_PATH, mm_profile, PROFILE_STAGES, MM_SCATTER_AUTO, MM_SCATTER_ATOMIC,
+    MM_M_CIRCULANT, MM_M_LEARNED, LIB_PATH, mm_profile, PROFILE_STAGES, MM_SCATTER_AUTO,
+    MM_SCATTER_ATOMIC, mm_train_opts,
 )
 
 PRECON = {"none": MM_M_NONE, "jacobi": MM_M_JACOBI, "binned": MM_M_BINNED,
-          "circulant": MM_M_CIRCULANT}
+          "circulant": MM_M_CIRCULANT, "learned": MM_M_LEARNED}
 
 
 def _stream(stream):
@@ -137,6 +138,92 @@ def mm_profile_read(h):
             for i in range(p.n_stages) if PROFILE_STAGES[i] and p.launches[i]}
 
 
+def mm_learned_workspace_bytes(ncomp, ny, nx, batch):
+    return int(lib.mm_learned_workspace_bytes(ncomp, ny, nx, batch))
+
+
+def _host_f32(a, n, name):
+    a = np.ascontiguousarray(a, dtype=np.float32).ravel()
+    if a.size != n:
+        raise ValueError(f"{name} must have {n} elements")
+    return a
+
+
+def mm_learned_create(ncomp, ny, nx, batch, workspace, w1, w2, stream=None):
+    w1 = _host_f32(w1, 16 * ncomp * 25, "w1")
+    w2 = _host_f32(w2, 16 * 16 * 25, "w2")
+    h = C.c_void_p()
+    check(lib.mm_learned_create(ncomp, ny, nx, batch, _ptr(workspace, torch.uint8, name="workspace"),
+                                workspace.numel(), w1.ctypes.data_as(C.c_void_p),
+                                w2.ctypes.data_as(C.c_void_p), _stream(stream), C.byref(h)),
+          "mm_learned_create")
+    return h
+
+
+def mm_learned_destroy(h):
+    lib.mm_learned_destroy(h)
+
+
+def mm_learned_get(h, ncomp):
+    w1 = np.empty(16 * ncomp * 25, np.float32)
+    w2 = np.empty(16 * 16 * 25, np.float32)
+    check(lib.mm_learned_get(h, w1.ctypes.data_as(C.c_void_p), w2.ctypes.data_as(C.c_void_p)),
+          "mm_learned_get")
+    return w1.reshape(16, ncomp, 5, 5), w2.reshape(16, 16, 5, 5)
+
+
+def mm_learned_attach(scan_h, h):
+    check(lib.mm_learned_attach(scan_h, h), "mm_learned_attach")
+
+
+def mm_learned_make_pair(scan_h, x_f, x_k, r_w, t, e2, stream=None):
+    check(lib.mm_learned_make_pair(scan_h, _ptr(x_f, torch.float64, name="x_f"),
+                                   _ptr(x_k, torch.float64, name="x_k"),
+                                   _ptr(r_w, torch.float32, name="r_w"),
+                                   _ptr(t, torch.float32, name="t"), _ptr(e2, torch.float32, name="e2"),
+                                   _stream(stream)), "mm_learned_make_pair")
+
+
+def mm_learned_train(h, r_w, t, e2, npairs, opts, stream=None):
+    hist = (C.c_double * max(1, opts.epochs))()
+    check(lib.mm_learned_train(h, _ptr(r_w, torch.float32, name="r_w"),
+                               _ptr(t, torch.float32, name="t"), _ptr(e2, torch.float32, name="e2"),
+                               int(npairs), C.byref(opts), C.cast(hist, C.c_void_p), _stream(stream)),
+          "mm_learned_train")
+    return np.array(hist[: opts.epochs])
+
+
+def mm_learned_loss(h, r_w, t, e2, npairs, stream=None):
+    out = C.c_double()
+    check(lib.mm_learned_loss(h, _ptr(r_w, torch.float32, name="r_w"),
+                              _ptr(t, torch.float32, name="t"), _ptr(e2, torch.float32, name="e2"),
+                              int(npairs), C.byref(out), _stream(stream)), "mm_learned_loss")
+    return out.value
+
+
+def mm_learned_forward(h, x, B, y, a1=None, a2=None, a3=None, stream=None):
+    check(lib.mm_learned_forward(h, _ptr(x, torch.float32, name="x"), int(B),
+                                 _ptr(y, torch.float32, name="y"), _ptr(a1), _ptr(a2), _ptr(a3),
+                                 _stream(stream)), "mm_learned_forward")
+
+
+def mm_learned_grad(h, r_w, t, e2, B, ncomp, stream=None):
+    loss = C.c_double()
+    g1 = np.empty(16 * ncomp * 25, np.float32)
+    g2 = np.empty(16 * 16 * 25, np.float32)
+    check(lib.mm_learned_grad(h, _ptr(r_w, torch.float32, name="r_w"),
+                              _ptr(t, torch.float32, name="t"), _ptr(e2, torch.float32, name="e2"),
+                              int(B), C.byref(loss), g1.ctypes.data_as(C.c_void_p),
+                              g2.ctypes.data_as(C.c_void_p), _stream(stream)), "mm_learned_grad")
+    return loss.value, g1.reshape(16, ncomp, 5, 5), g2.reshape(16, 16, 5, 5)
+
+
+def mm_apply_precon_learned(h, r, z, stream=None):
+    check(lib.mm_apply_precon_learned(h, _ptr(r, torch.float64, name="r"),
+                                      _ptr(z, torch.float64, name="z"), _stream(stream)),
+          "mm_apply_precon_learned")
+
+
 def mm_last_error():
     return lib.mm_last_error().decode(errors="replace")
 
@@ -223,19 +310,30 @@ class Scan:
         z = self.new_map() if z is None else z
         if name == "circulant":
             mm_apply_precon_circulant(self.handle, r, z, stream)
+        elif name == "learned":
+            mm_apply_precon_learned(self.handle, r, z, stream)
         else:
             mm_apply_precon_binned(self.handle, PRECON[name], r, z, stream)
         return z
 
     def pcg(self, name, b, x=None, tol=1e-6, maxiter=5000, check_every=1, x0=False,
-            history=True, stream=None):
+            history=True, snapshots=None, snap_every=0, stream=None):
         x = self.new_map() if x is None else x
         o = mm_pcg_opts()
         o.tol, o.maxiter, o.check_every, o.use_x0 = float(tol), int(maxiter), int(check_every), int(x0)
+        if snapshots is not None:
+            o.snapshots = _ptr(snapshots, torch.float64, name="snapshots").value
+            o.snap_every = int(snap_every)
+            o.max_snaps = snapshots.numel() // (self.ncomp * self.npix)
         st, res = mm_pcg_solve(self.handle, PRECON[name], b, x, o, stream,
                                history_len=maxiter if history else 0)
         res["x"] = x
         return res
+
+    def attach_learned(self, learned):
+        """Attach a Learned correction (None detaches); the scan keeps it alive."""
+        mm_learned_attach(self.handle, None if learned is None else learned.handle)
+        self._learned = learned
 
     def info(self):
         return mm_get_info(self.handle)
@@ -249,6 +347,44 @@ class Scan:
         if getattr(self, "handle", None) is not None:
             mm_destroy_scan(self.handle)
             self.handle = None
+
+
+class Learned:
+    """A learned correction with its device workspace (owned here)."""
+
+    def __init__(self, ncomp, ny, nx, batch, w1, w2, device="cuda", stream=None):
+        self.ncomp, self.ny, self.nx, self.batch = ncomp, ny, nx, batch
+        nbytes = mm_learned_workspace_bytes(ncomp, ny, nx, batch)
+        if nbytes == 0:
+            raise MMError(MM_EINVAL, "mm_learned_workspace_bytes")
+        self._raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self._raw.data_ptr()) % 256
+        self.workspace = self._raw[off: off + nbytes]
+        self.handle = mm_learned_create(ncomp, ny, nx, batch, self.workspace, w1, w2, stream)
+
+    def weights(self):
+        return mm_learned_get(self.handle, self.ncomp)
+
+    def train(self, r_w, t, e2, epochs=20, batch=16, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              seed=0, shuffle=True, drop_last=False, stream=None):
+        o = mm_train_opts()
+        o.epochs, o.batch, o.lr, o.beta1, o.beta2, o.eps = epochs, batch, lr, beta1, beta2, eps
+        o.seed, o.shuffle, o.drop_last = seed, int(shuffle), int(drop_last)
+        return mm_learned_train(self.handle, r_w, t, e2, e2.numel(), o, stream)
+
+    def loss(self, r_w, t, e2, stream=None):
+        return mm_learned_loss(self.handle, r_w, t, e2, e2.numel(), stream)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            mm_learned_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def __del__(self):
         try:

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(_HERE, "libmm.so")
 
 MM_OK, MM_ENOCONV, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENOTBUILT, MM_EBREAKDOWN = 0, 1, -1, -2, -3, -4, -5
 MM_F32, MM_BF16, MM_F64 = 0, 1, 2
-MM_M_NONE, MM_M_JACOBI, MM_M_BINNED, MM_M_CIRCULANT = 0, 1, 2, 3
+MM_M_NONE, MM_M_JACOBI, MM_M_BINNED, MM_M_CIRCULANT, MM_M_LEARNED = 0, 1, 2, 3, 4
 
 STATUS_NAMES = {0: "MM_OK", 1: "MM_ENOCONV", -1: "MM_EINVAL", -2: "MM_ENOMEM",
                 -3: "MM_EDEVICE", -4: "MM_ENOTBUILT", -5: "MM_EBREAKDOWN"}
@@ -36,7 +36,14 @@ class mm_precon_opts(C.Structure):
 
 class mm_pcg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("check_every", C.c_int32),
-                ("use_x0", C.c_int32)]
+                ("use_x0", C.c_int32), ("snap_every", C.c_int32), ("max_snaps", C.c_int32),
+                ("snapshots", C.c_void_p)]
+
+
+class mm_train_opts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("seed", C.c_uint64), ("shuffle", C.c_int32), ("drop_last", C.c_int32)]
 
 
 class mm_pcg_result(C.Structure):
@@ -74,6 +81,24 @@ SIGNATURES = {
                                C.POINTER(mm_pcg_opts), C.POINTER(mm_pcg_result), C.c_void_p]),
     "mm_get_info": (C.c_int, [C.c_void_p, C.POINTER(mm_scan_info)]),
     "mm_get_mask": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mm_learned_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "mm_learned_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                    C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
+    "mm_learned_destroy": (None, [C.c_void_p]),
+    "mm_learned_get": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mm_learned_attach": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mm_learned_make_pair": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mm_learned_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                   C.POINTER(mm_train_opts), C.c_void_p, C.c_void_p]),
+    "mm_learned_loss": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                  C.POINTER(C.c_double), C.c_void_p]),
+    "mm_learned_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mm_learned_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.POINTER(C.c_double), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mm_apply_precon_learned": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mm_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "mm_profile_read": (C.c_int, [C.c_void_p, C.POINTER(mm_profile)]),
     "mm_last_error": (C.c_char_p, []),

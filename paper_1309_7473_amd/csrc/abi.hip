@@ -152,6 +152,7 @@ mm_status mm_build_precon(mm_scan scan, int32_t precon, const mm_precon_opts* op
     case MM_M_NONE:
     case MM_M_JACOBI:
     case MM_M_BINNED:
+    case MM_M_LEARNED:
       return MM_OK;
     case MM_M_CIRCULANT: {
       if (opts) {
@@ -188,9 +189,13 @@ mm_status mm_pcg_solve(mm_scan scan, int32_t precon, const double* b, double* x,
   if (!s) return fail(MM_EINVAL, "invalid scan handle");
   if (!b || !x || !opts) return fail(MM_EINVAL, "b, x and opts are required");
   if (!(opts->tol >= 0.0) || opts->maxiter < 0) return fail(MM_EINVAL, "bad tol or maxiter");
-  if (precon < MM_M_NONE || precon > MM_M_CIRCULANT) return fail(MM_EINVAL, "unknown preconditioner");
-  if (precon == MM_M_CIRCULANT && !s->circ_built)
+  if (precon < MM_M_NONE || precon > MM_M_LEARNED) return fail(MM_EINVAL, "unknown preconditioner");
+  if ((precon == MM_M_CIRCULANT || precon == MM_M_LEARNED) && !s->circ_built)
     return fail(MM_ENOTBUILT, "circulant preconditioner not built");
+  if (precon == MM_M_LEARNED && !s->learned)
+    return fail(MM_ENOTBUILT, "no learned correction attached");
+  if (opts->snapshots == nullptr && opts->snap_every > 0)
+    return fail(MM_EINVAL, "snap_every > 0 needs a snapshots buffer");
   const size_t bytes = size_t(s->nc) * s->npix * 8;
   const char* ba = reinterpret_cast<const char*>(b);
   const char* xa = reinterpret_cast<const char*>(x);
@@ -220,6 +225,91 @@ mm_status mm_get_mask(mm_scan scan, int32_t* dst, void* stream) {
   MM_HIP(hipMemcpyAsync(dst, s->ws + s->lay.mask, size_t(s->npix) * 4, hipMemcpyDeviceToDevice,
                         static_cast<hipStream_t>(stream)));
   return MM_OK;
+}
+
+size_t mm_learned_workspace_bytes(int32_t ncomp, int32_t ny, int32_t nx, int32_t batch) {
+  if ((ncomp != 1 && ncomp != 3) || ny < 1 || nx < 1 || batch < 1) {
+    fail(MM_EINVAL, "bad learned-correction shape");
+    return 0;
+  }
+  return learned_workspace_bytes(ncomp, ny, nx, batch);
+}
+
+mm_status mm_learned_create(int32_t ncomp, int32_t ny, int32_t nx, int32_t batch, void* workspace,
+                            size_t workspace_bytes, const float* w1, const float* w2, void* stream,
+                            mm_learned* out) {
+  if (!out) return fail(MM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if ((ncomp != 1 && ncomp != 3) || ny < 1 || nx < 1 || batch < 1)
+    return fail(MM_EINVAL, "bad learned-correction shape");
+  if (!w1 || !w2 || !workspace) return fail(MM_EINVAL, "w1, w2 and workspace are required");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(MM_EINVAL, "workspace must be 256-byte aligned");
+  if (workspace_bytes < learned_workspace_bytes(ncomp, ny, nx, batch))
+    return fail(MM_ENOMEM, "workspace_bytes smaller than mm_learned_workspace_bytes()");
+  return learned_create(ncomp, ny, nx, batch, workspace, workspace_bytes, w1, w2,
+                        static_cast<hipStream_t>(stream), out);
+}
+
+void mm_learned_destroy(mm_learned learned) { learned_destroy(learned); }
+
+mm_status mm_learned_get(mm_learned learned, float* w1, float* w2) {
+  if (!w1 || !w2) return fail(MM_EINVAL, "w1 and w2 are required");
+  return learned_get(learned, w1, w2);
+}
+
+mm_status mm_learned_attach(mm_scan scan, mm_learned learned) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  if (learned) {
+    mm_status r = learned_check(learned, s->nc, s->ny, s->nx);
+    if (r != MM_OK) return r;
+  }
+  s->learned = learned;
+  return MM_OK;
+}
+
+mm_status mm_learned_make_pair(mm_scan scan, const double* x_f, const double* x_k, float* r_w,
+                               float* t, float* e2, void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  if (!x_f || !x_k || !r_w || !t || !e2) return fail(MM_EINVAL, "null argument");
+  return learned_make_pair(s, x_f, x_k, r_w, t, e2, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_learned_train(mm_learned learned, const float* r_w, const float* t, const float* e2,
+                           int64_t npairs, const mm_train_opts* opts, double* loss_history,
+                           void* stream) {
+  if (!r_w || !t || !e2 || !opts) return fail(MM_EINVAL, "null argument");
+  if (opts->epochs < 0 || !(opts->lr >= 0.0)) return fail(MM_EINVAL, "bad training options");
+  return learned_train(learned, r_w, t, e2, npairs, opts, loss_history,
+                       static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_learned_loss(mm_learned learned, const float* r_w, const float* t, const float* e2,
+                          int64_t npairs, double* loss, void* stream) {
+  if (!r_w || !t || !e2 || !loss || npairs < 1) return fail(MM_EINVAL, "bad argument");
+  return learned_loss(learned, r_w, t, e2, npairs, loss, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_learned_forward(mm_learned learned, const float* x, int32_t B, float* y, float* a1,
+                             float* a2, float* a3, void* stream) {
+  if (!x || !y) return fail(MM_EINVAL, "x and y are required");
+  return learned_forward(learned, x, B, y, a1, a2, a3, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_learned_grad(mm_learned learned, const float* r_w, const float* t, const float* e2,
+                          int32_t B, double* loss, float* g1, float* g2, void* stream) {
+  if (!r_w || !t || !e2 || !loss || !g1 || !g2) return fail(MM_EINVAL, "null argument");
+  return learned_grad(learned, r_w, t, e2, B, loss, g1, g2, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_apply_precon_learned(mm_scan scan, const double* r, double* z, void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  if (!r || !z) return fail(MM_EINVAL, "r and z are required");
+  if (!s->circ_built) return fail(MM_ENOTBUILT, "circulant preconditioner not built");
+  return learned_apply(s, r, z, static_cast<hipStream_t>(stream));
 }
 
 mm_status mm_profile_enable(mm_scan scan, int32_t enable) {

@@ -101,10 +101,12 @@ template <int NC>
 __global__ void k_binned_finalize(const double* __restrict__ hits, const double* __restrict__ Bb,
                                   const double* __restrict__ Bj, int npix, double rcond,
                                   int32_t* __restrict__ mask, double* __restrict__ binv_b,
-                                  double* __restrict__ binv_j, double* __restrict__ siginv) {
+                                  double* __restrict__ binv_j, double* __restrict__ siginv,
+                                  double* __restrict__ sigma) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
   double ob[6] = {0, 0, 0, 0, 0, 0}, oj[6] = {0, 0, 0, 0, 0, 0}, os[6] = {0, 0, 0, 0, 0, 0};
+  double oq[6] = {0, 0, 0, 0, 0, 0};
   int on = 0;
   if (NC == 1) {
     const double b = Bb[6 * int64_t(p)], j = Bj[6 * int64_t(p)];
@@ -113,6 +115,7 @@ __global__ void k_binned_finalize(const double* __restrict__ hits, const double*
       ob[0] = 1.0 / b;
       oj[0] = 1.0 / j;
       os[0] = 1.0 / sqrt(b);
+      oq[0] = sqrt(b);
     }
   } else if (hits[p] > 0.0) {
     double A[3][3], V[3][3];
@@ -130,6 +133,8 @@ __global__ void k_binned_finalize(const double* __restrict__ hits, const double*
       pack_sym3(out, ob);
       sym3_func(V, lam, [](double l) { return 1.0 / sqrt(l); }, out);
       pack_sym3(out, os);
+      sym3_func(V, lam, [](double l) { return sqrt(l); }, out);
+      pack_sym3(out, oq);
       double Aj[3][3], Vj[3][3];
       unpack_sym3(Bj + 6 * int64_t(p), Aj);
       jacobi_eig<3>(Aj, Vj);
@@ -139,7 +144,7 @@ __global__ void k_binned_finalize(const double* __restrict__ hits, const double*
         sym3_func(Vj, lj, [](double l) { return 1.0 / l; }, out);
         pack_sym3(out, oj);
       } else {
-        for (int k = 0; k < 6; ++k) ob[k] = os[k] = 0.0;
+        for (int k = 0; k < 6; ++k) ob[k] = os[k] = oq[k] = 0.0;
       }
     }
   }
@@ -148,6 +153,7 @@ __global__ void k_binned_finalize(const double* __restrict__ hits, const double*
     binv_b[6 * int64_t(p) + k] = ob[k];
     binv_j[6 * int64_t(p) + k] = oj[k];
     siginv[6 * int64_t(p) + k] = os[k];
+    sigma[6 * int64_t(p) + k] = oq[k];
   }
 }
 
@@ -230,11 +236,13 @@ mm_status binned_setup(ScanImpl* s, hipStream_t st) {
   if (s->nc == 3)
     hipLaunchKernelGGL(k_binned_finalize<3>, g, b, 0, st, s->at<double>(L.hits),
                        s->at<double>(L.bb), s->at<double>(L.bj), npix, rc, s->at<int32_t>(L.mask),
-                       s->at<double>(L.binv_b), s->at<double>(L.binv_j), s->at<double>(L.siginv));
+                       s->at<double>(L.binv_b), s->at<double>(L.binv_j), s->at<double>(L.siginv),
+                       s->at<double>(L.sigma));
   else
     hipLaunchKernelGGL(k_binned_finalize<1>, g, b, 0, st, s->at<double>(L.hits),
                        s->at<double>(L.bb), s->at<double>(L.bj), npix, rc, s->at<int32_t>(L.mask),
-                       s->at<double>(L.binv_b), s->at<double>(L.binv_j), s->at<double>(L.siginv));
+                       s->at<double>(L.binv_b), s->at<double>(L.binv_j), s->at<double>(L.siginv),
+                       s->at<double>(L.sigma));
   int* cnt = s->at<int>(L.misc);
   if ((r = fill_zero(cnt, 4, st)) != MM_OK) return r;
   hipLaunchKernelGGL(k_count_active, dim3(64), dim3(256), 0, st, s->at<int32_t>(L.mask), npix, cnt);

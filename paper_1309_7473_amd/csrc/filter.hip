@@ -736,6 +736,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->binv_b = take(size_t(npix) * 6 * 8);
   L->binv_j = take(size_t(npix) * 6 * 8);
   L->siginv = take(size_t(npix) * 6 * 8);
+  L->sigma = take(size_t(npix) * 6 * 8);
   L->mask = take(size_t(npix) * 4);
   L->kinv = take(size_t(npix) * nc * nc * 16);
   L->planes = take(size_t(npix) * nc * nc * 16);

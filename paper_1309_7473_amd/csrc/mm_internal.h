@@ -57,6 +57,7 @@ struct Layout {
   size_t hits;       // npix double (hit counts, accumulated in f64)
   size_t bb, bj;     // npix * 6 double: binned / Jacobi blocks (packed symmetric)
   size_t binv_b, binv_j, siginv;  // npix * 6 double
+  size_t sigma;      // npix * 6 double: B^(1/2) (packed symmetric)
   size_t mask;       // npix int32
   size_t kinv;       // npix * nc*nc complex double
   size_t planes;     // ncomp^2 * npix complex double (FFT scratch, probe q planes)
@@ -103,6 +104,7 @@ struct ScanImpl {
   int circ_sym = 1;
   int maxdyn_lds = 65536;
   Profiler* prof = nullptr;
+  mm_learned learned = nullptr;
 
   template <typename P>
   P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
@@ -128,5 +130,23 @@ void prof_end(ScanImpl* s, hipStream_t st, hipEvent_t tok, int stage, int64_t sa
 mm_status profile_enable(ScanImpl* s, int enable);
 mm_status profile_read(ScanImpl* s, mm_profile* out);
 void profile_free(ScanImpl* s);
+// learned correction (learned.hip)
+mm_status learned_apply(ScanImpl* s, const double* r, double* z, hipStream_t st);
+mm_status learned_make_pair(ScanImpl* s, const double* xf, const double* xk, float* rw, float* t,
+                            float* e2, hipStream_t st);
+size_t learned_workspace_bytes(int nc, int ny, int nx, int batch);
+mm_status learned_create(int nc, int ny, int nx, int batch, void* ws, size_t ws_bytes,
+                         const float* w1, const float* w2, hipStream_t st, mm_learned* out);
+void learned_destroy(mm_learned h);
+mm_status learned_get(mm_learned h, float* w1, float* w2);
+mm_status learned_check(mm_learned h, int nc, int ny, int nx);
+mm_status learned_train(mm_learned h, const float* rw, const float* t, const float* e2,
+                        int64_t npairs, const mm_train_opts* o, double* loss_hist, hipStream_t st);
+mm_status learned_loss(mm_learned h, const float* rw, const float* t, const float* e2,
+                       int64_t npairs, double* loss, hipStream_t st);
+mm_status learned_forward(mm_learned h, const float* x, int B, float* y, float* a1, float* a2,
+                          float* a3, hipStream_t st);
+mm_status learned_grad(mm_learned h, const float* rw, const float* t, const float* e2, int B,
+                       double* loss, float* g1, float* g2, hipStream_t st);
 
 }  // namespace mm

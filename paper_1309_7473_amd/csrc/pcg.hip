@@ -221,6 +221,8 @@ static mm_status apply_precon_inner(ScanImpl* s, int precon, const double* r, do
       return binned_apply(s, 0, r, z, st);
     case MM_M_CIRCULANT:
       return circulant_apply(s, r, z, st);
+    case MM_M_LEARNED:
+      return learned_apply(s, r, z, st);
     default:
       return fail(MM_EINVAL, "unknown preconditioner");
   }
@@ -293,6 +295,10 @@ mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const m
     hipLaunchKernelGGL(k_update_p, gb, bb, 0, st, p, z, N, dev);
     MM_HIP(hipGetLastError());
     ++it;
+    if (o->snapshots && o->snap_every > 0 && it % o->snap_every == 0 &&
+        it / o->snap_every <= o->max_snaps)
+      MM_HIP(hipMemcpyAsync(o->snapshots + int64_t(it / o->snap_every - 1) * N, x, N * 8,
+                            hipMemcpyDeviceToDevice, st));
     if (it % every == 0 || it == maxiter) {
       MM_HIP(hipMemcpyAsync(&h, dev, sizeof(PcgDev), hipMemcpyDeviceToHost, st));
       MM_HIP(hipStreamSynchronize(st));

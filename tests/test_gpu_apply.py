@@ -24,6 +24,7 @@ TOL32_SKY = 2e-5
 
 
 def _check_apply(pair, tol, seed=0, label=""):
+    assert pair.mask.sum() > 0, "no active pixel: the comparison would be vacuous"
     x = pair.masked_random(seed)
     got, want = pair.A_gpu(x), pair.A_oracle(x)
     e = rel(got, want)
@@ -39,8 +40,9 @@ CASES = [
     ("single-f32-I", 1, 16, 16, 5, 2**10, "f32", 0, 0),
     ("single-f32-IQU", 3, 16, 16, 5, 2**12, "f32", 0, 0),
     ("single-f64-IQU", 3, 16, 16, 3, 2**13, "f64", 0, 0),
-    ("min-n", 3, 8, 8, 1, 16, "f32", 0, 0),
-    ("single-max-f32", 3, 32, 32, 2, 2**14, "f32", 0, 0),
+    ("min-n", 1, 8, 8, 1, 16, "f32", 0, 0),
+    ("min-n-IQU", 3, 8, 8, 6, 32, "f64", 0, 0),
+    ("single-max-f32", 3, 32, 32, 6, 2**14, "f32", 0, 0),
     ("fourstep-f32-ragged", 3, 32, 32, 5, 2**15, "f32", 2, 0),
     ("fourstep-f32-m1=16", 3, 32, 32, 3, 2**15, "f32", 0, 16),
     ("fourstep-f32-m1=512", 1, 32, 32, 2, 2**18, "f32", 1, 512),
@@ -68,7 +70,9 @@ def test_apply_A_parity(case, scatter):
     tol = TOL64 if dt == "f64" else TOL32_WHITE
     _check_apply(pair, tol, label=label)
     sky = make_sky(nc, ny, nx) * pair.mask.reshape(1, ny, nx)
-    e = rel(pair.A_gpu(sky.ravel()), pair.A_oracle(sky.ravel()))
+    want = pair.A_oracle(sky.ravel())
+    assert np.linalg.norm(want) > 0
+    e = rel(pair.A_gpu(sky.ravel()), want)
     print(f"[apply {label}] rel err sky map = {e:.3e}", flush=True)
     assert e <= (TOL64 if dt == "f64" else TOL32_SKY), e
 
@@ -120,23 +124,31 @@ def test_mask_and_hits_match_oracle():
 
 
 def test_collision_stress_long_runs():
-    # every sample of detector 0 in one pixel, detector 1 alternating between
-    # two pixels, detector 2 entirely off the map
-    inp = small_raster(ncomp=3, ny=16, nx=16, ndet=3, sweeps=128)  # n = 8192
+    # intensity only, so that every hit pixel is an unknown: every sample of
+    # detector 0 in one pixel, detector 1 alternating between two pixels,
+    # detector 2 entirely off the map, detector 3 an ordinary raster
+    inp = small_raster(ncomp=1, ny=16, nx=16, ndet=4, sweeps=128)  # n = 8192
     inp.pix[0, :] = 5 * 16 + 7
     inp.pix[1, :] = np.where(np.arange(inp.nsamp) % 2 == 0, 3, 200)
     inp.pix[2, :] = -1
     for dt, tol in (("f32", TOL32_WHITE), ("f64", TOL64)):
         pair = Pair(inp, tod_dtype=dt)
+        assert pair.mask[5 * 16 + 7] and pair.mask[3] and pair.mask[200]
         _check_apply(pair, tol, label=f"collision-{dt}")
-    # the same on the four-step pipeline with the pixel-major gather
-    inp2 = small_raster(ncomp=3, ny=16, nx=16, ndet=3, sweeps=512)  # n = 2^15
+    # the same on the four-step pipeline, both forms of P^T
+    inp2 = small_raster(ncomp=1, ny=16, nx=16, ndet=4, sweeps=512)  # n = 2^15
     inp2.pix[0, :] = 5 * 16 + 7
     inp2.pix[1, :] = np.where(np.arange(inp2.nsamp) % 2 == 0, 3, 200)
     inp2.pix[2, :] = -1
     for scatter in ("auto", "atomic"):
         pair = Pair(inp2, tod_dtype="f64", det_group=2, scatter=scatter)
         _check_apply(pair, TOL64, label=f"collision-fourstep-{scatter}")
+    # I,Q,U: six detectors with distinct angles share one pixel for all samples
+    inp3 = small_raster(ncomp=3, ny=8, nx=8, ndet=6, sweeps=64)
+    inp3.pix[:3, :] = 3 * 8 + 4
+    pair = Pair(inp3, tod_dtype="f64")
+    assert pair.mask[3 * 8 + 4]
+    _check_apply(pair, TOL64, label="collision-IQU")
 
 
 def test_apply_A_bitwise_repeatable():
