@@ -149,6 +149,40 @@ def summarize(trace_dir, fetch_dir, write_dir, bench_log, out_dir):
     print("wrote", out_dir)
 
 
+def learned_leg(mm, scan, b, args, npairs=16, snap_every=4, epochs=8, batch=8):
+    """Train the learned correction on pairs from this scan's own circulant
+    PCG iterates (in-sample), then time its solve to 1e-6."""
+    import numpy as np
+    import torch
+    t0 = time.perf_counter()
+    per = scan.ncomp * scan.npix
+    xf = scan.pcg("circulant", b, tol=1e-7, maxiter=2000, check_every=10, history=False)["x"]
+    snaps = torch.zeros(npairs * per, dtype=torch.float64, device="cuda")
+    scan.pcg("circulant", b, tol=0.0, maxiter=npairs * snap_every, check_every=npairs * snap_every,
+             snapshots=snaps, snap_every=snap_every, history=False)
+    rw = torch.empty((npairs, per), dtype=torch.float32, device="cuda")
+    tt = torch.empty((npairs, per), dtype=torch.float32, device="cuda")
+    e2 = torch.empty(npairs, dtype=torch.float32, device="cuda")
+    for k in range(npairs):
+        mm.mm_learned_make_pair(scan.handle, xf, snaps[k * per:(k + 1) * per], rw[k], tt[k],
+                                e2[k:k + 1])
+    rng = np.random.default_rng(0)
+    w1 = rng.standard_normal((16, scan.ncomp, 5, 5)) * 0.1 / np.sqrt(scan.ncomp * 25)
+    w2 = rng.standard_normal((16, 16, 5, 5)) * 0.1 / np.sqrt(16 * 25)
+    lrn = mm.Learned(scan.ncomp, scan.ny, scan.nx, batch, w1, w2)
+    l0 = lrn.loss(rw, tt, e2)
+    hist = lrn.train(rw, tt, e2, epochs=epochs, batch=batch, lr=3e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    scan.attach_learned(lrn)
+    r = scan.pcg("learned", b, tol=1e-6, maxiter=5000, check_every=10, history=False)
+    scan.attach_learned(None)
+    return {"iters": r["iters"], "converged": r["converged"], "time_s": round(r["t_solve_s"], 4),
+            "rel_resid": r["rel_resid"], "train_s": round(t_train, 3), "pairs": npairs,
+            "epochs": epochs, "loss_first_last": [round(l0, 4), round(float(hist[-1]), 4)],
+            "note": "trained in-sample on this scan's own circulant PCG iterates"}
+
+
 def cpu_baseline(inp, ndet_sample=8, reps=2):
     """The FP64 oracle's A-apply on the first ndet_sample detectors."""
     import numpy as np
@@ -267,6 +301,7 @@ def main():
             solves[name] = {"iters": r["iters"], "converged": r["converged"],
                             "time_s": round(r["t_solve_s"], 4), "rel_resid": r["rel_resid"]}
         solves["circulant"]["setup_s"] = round(t_setup_circ, 4)
+        solves["learned"] = learned_leg(mm, scan, b, args)
 
     if args.calibrate_copy:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")

@@ -64,6 +64,54 @@ __device__ __forceinline__ void dft_reg(Cx<T> (&v)[R]) {
   }
 }
 
+// Length-(A*B) DFT of values held in registers, natural order in and out:
+// with n = B n1 + n2 and k = k1 + A k2,
+//   X[k] = sum_n2 W_B^(n2 k2) W_AB^(n2 k1) sum_n1 W_A^(n1 k1) x[B n1 + n2].
+// tw(m) returns W_AB^m (forward sign); the inverse uses conjugates.
+template <typename T, int A, int B, bool INV, typename TW>
+__device__ __forceinline__ void dft_2level(Cx<T> (&v)[A * B], TW tw) {
+  Cx<T> y[B][A];
+#pragma unroll
+  for (int n2 = 0; n2 < B; ++n2) {
+    Cx<T> t[A];
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) t[n1] = v[B * n1 + n2];
+    dft_reg<T, A, INV>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      if (n2 * k1 == 0) {
+        y[n2][k1] = t[k1];
+      } else {
+        Cx<T> w = tw(n2 * k1);
+        if (INV) w.y = -w.y;
+        y[n2][k1] = t[k1] * w;
+      }
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < A; ++k1) {
+    Cx<T> s[B];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) s[n2] = y[n2][k1];
+    dft_reg<T, B, INV>(s);
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = s[k2];
+  }
+}
+
+// In-register DFT of length E in {8, 16, 32}; tw(m) = W_E^m.
+template <typename T, int E, bool INV, typename TW>
+__device__ __forceinline__ void dft_regs(Cx<T> (&v)[E], TW tw) {
+  if constexpr (E == 8) {
+    dft_reg<T, 8, INV>(v);
+  } else if constexpr (E == 16) {
+    dft_2level<T, 4, 4, INV>(v, tw);
+  } else {
+    static_assert(E == 32, "E must be 8, 16 or 32");
+    dft_2level<T, 4, 8, INV>(v, tw);
+  }
+}
+
 struct FftShape {
   int logL;      // transform length L = 2^logL
   int logB;      // batch count B = 2^logB

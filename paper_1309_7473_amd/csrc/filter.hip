@@ -411,6 +411,185 @@ __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T> a) {
   }
 }
 
+// Pass 2 with one wavefront per row, for rows of M2 = 64 E (E = 8, 16, 32).
+// A block holds PB row pairs (2 PB waves).  Per row the length-M2 FFT is a
+// radix-E stage in registers fed straight from global memory (lane l holds
+// elements l + 64 r), then two radix-8 Stockham stages through this wave's
+// padded LDS row; the spectrum ends in natural order.  Stage twiddles come
+// from the global table (it stays in cache); keeping them out of LDS lets
+// more blocks share a CU.  The pair filter runs on the two rows of a pair,
+// the inverse FFT mirrors the forward one and its last stage stores straight
+// to global memory.
+#ifndef MM_PASS2W
+#define MM_PASS2W 1
+#endif
+
+template <int LOGE>
+__device__ __forceinline__ int pad_e(int i) {
+  return i + (i >> LOGE);
+}
+
+template <typename T, int E, int PB>
+__global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T> a) {
+  constexpr int LOGE = (E == 8) ? 3 : (E == 16) ? 4 : 5;
+  constexpr int L = 64 * E;              // = M2
+  constexpr int LOGL = LOGE + 6;
+  constexpr int RS = L + (L >> LOGE);    // padded LDS row
+  constexpr int NB = E / 8;              // radix-8 butterflies per lane
+  constexpr int NW = 2 * PB;             // waves (rows) per block
+  constexpr int NT = 64 * NW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<T>* rows = reinterpret_cast<Cx<T>*>(smem);   // [NW][RS]
+  Cx<T>* tA = rows + NW * RS;                      // [NW][E]
+  Cx<T>* tB = tA + NW * E;                         // [NW][64]
+  const int M1 = 1 << a.logM1;
+  const int M = 1 << a.logM;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lhalf = a.logM1 - 1;
+  auto row_of = [&](int w) {
+    const int prw = (blockIdx.x * PB + (w >> 1)) & ((1 << lhalf) - 1);
+    return (w & 1) ? ((prw == 0) ? (M1 >> 1) : (M1 - prw)) : prw;
+  };
+  const int pair = blockIdx.x * PB + (wave >> 1);
+  const int g = pair >> lhalf;
+  const int pr = pair & ((1 << lhalf) - 1);
+  const int ra = pr;
+  const int rb = (pr == 0) ? (M1 >> 1) : (M1 - pr);
+  const int myrow = row_of(wave);
+  for (int t = threadIdx.x; t < NW * E; t += NT)
+    tA[t] = a.wn(2 * int64_t(row_of(t / E)) * (int64_t(t % E) << 6));
+  for (int t = threadIdx.x; t < NW * 64; t += NT) tB[t] = a.wn(2 * int64_t(row_of(t >> 6)) * (t & 63));
+  __syncthreads();
+  const int tsh = a.logLmax - LOGL;
+  auto twL = [&](int m) { return a.tw[m << tsh]; };   // W_L^m, from the cached table
+  Cx<T>* R = rows + wave * RS;
+  Cx<T>* w = a.work + (int64_t(g) << a.logM) + int64_t(myrow) * L;
+  const Cx<T> tb = tB[wave * 64 + lane];
+  auto twE = [&](int m) { return twL(m << 6); };   // W_E^m = W_L^(64 m)
+  // ---------------- forward: radix-E from global, then 2 x radix-8
+  {
+    Cx<T> v[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = w[lane + 64 * r] * (tA[wave * E + r] * tb);
+    dft_regs<T, E, false>(v, twE);
+#pragma unroll
+    for (int r = 0; r < E; ++r) R[pad_e<LOGE>(lane * E + r)] = v[r];
+  }
+  __syncthreads();
+  auto radix8 = [&](int logNs, bool inv, bool to_lds) {
+    Cx<T> u[NB][8];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int j = lane + 64 * i;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) u[i][r] = R[pad_e<LOGE>(j + (L / 8) * r)];
+    }
+    __syncthreads();
+    const int Ns = 1 << logNs;
+    const int sh = LOGL - logNs - 3;     // W_{8 Ns}^(r k) = W_L^(r k << sh)
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int j = lane + 64 * i;
+      const int k = j & (Ns - 1);
+      Cx<T> t1 = twL(k << sh), t4 = twL((4 * k) << sh);
+      if (inv) {
+        t1.y = -t1.y;
+        t4.y = -t4.y;
+      }
+      const Cx<T> t2 = t1 * t1, t3 = t2 * t1;
+      u[i][1] = u[i][1] * t1;
+      u[i][2] = u[i][2] * t2;
+      u[i][3] = u[i][3] * t3;
+      u[i][4] = u[i][4] * t4;
+      u[i][5] = u[i][5] * (t4 * t1);
+      u[i][6] = u[i][6] * (t4 * t2);
+      u[i][7] = u[i][7] * (t4 * t3);
+      if (inv)
+        dft_reg<T, 8, true>(u[i]);
+      else
+        dft_reg<T, 8, false>(u[i]);
+      const int out = ((j - k) << 3) + k;
+      if (to_lds) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) R[pad_e<LOGE>(out + r * Ns)] = u[i][r];
+      } else {
+        // last inverse stage: natural order out = j + r * L/8; conjugate twiddle, store
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int idx = out + r * Ns;
+          w[idx] = u[i][r] * conj(tA[wave * E + (idx >> 6)] * tB[wave * 64 + (idx & 63)]);
+        }
+      }
+    }
+    if (to_lds) __syncthreads();
+  };
+  radix8(LOGE, false, true);
+  radix8(LOGE + 3, false, true);
+  // ---------------- pair filter on rows ra (wave 2h) and rb (wave 2h+1)
+  {
+    const int h = wave >> 1;
+    Cx<T>* Ra = rows + (2 * h) * RS;
+    Cx<T>* Rb = Ra + RS;
+    const int tp = threadIdx.x & 127;   // thread within the pair
+    const float* iN = a.iNt + int64_t(g) * (M + 1);
+    const T sc = a.scale;
+    if (pr != 0) {
+      const Cx<T> wa = a.wn(ra);
+      const float* ia = iN + int64_t(ra) * L;
+      const float* ib = iN + int64_t(rb) * L;
+      for (int k2 = tp; k2 < L; k2 += 128) {
+        const int i0 = pad_e<LOGE>(k2), i1 = pad_e<LOGE>(L - 1 - k2);
+        Cx<T> zk = Ra[i0], zm = Rb[i1];
+        pair_filter(zk, zm, wa * a.tw2[k2], sc * T(ia[k2]), sc * T(ib[L - 1 - k2]));
+        Ra[i0] = zk;
+        Rb[i1] = zm;
+      }
+    } else {
+      const Cx<T> wh = a.wn(M1 >> 1);
+      const float* ih = iN + int64_t(M1 >> 1) * L;
+      for (int t = tp; t < L; t += 128) {
+        if (t < L / 2) {
+          const int k2 = t;
+          if (k2 == 0) {
+            Ra[0] = dc_filter(Ra[0], sc * T(iN[0]), sc * T(iN[M]));
+            const int hh = pad_e<LOGE>(L / 2);
+            Cx<T> zk = Ra[hh], zm = Ra[hh];
+            pair_filter(zk, zm, a.tw2[L / 2], sc * T(iN[L / 2]), sc * T(iN[L / 2]));
+            Ra[hh] = zk;
+          } else {
+            const int i0 = pad_e<LOGE>(k2), i1 = pad_e<LOGE>(L - k2);
+            Cx<T> zk = Ra[i0], zm = Ra[i1];
+            pair_filter(zk, zm, a.tw2[k2], sc * T(iN[k2]), sc * T(iN[L - k2]));
+            Ra[i0] = zk;
+            Ra[i1] = zm;
+          }
+        } else {
+          const int k2 = t - L / 2;
+          const int i0 = pad_e<LOGE>(k2), i1 = pad_e<LOGE>(L - 1 - k2);
+          Cx<T> zk = Rb[i0], zm = Rb[i1];
+          pair_filter(zk, zm, wh * a.tw2[k2], sc * T(ih[k2]), sc * T(ih[L - 1 - k2]));
+          Rb[i0] = zk;
+          Rb[i1] = zm;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // ---------------- inverse: radix-E from LDS, then 2 x radix-8, store
+  {
+    Cx<T> v[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = R[pad_e<LOGE>(lane + 64 * r)];
+    __syncthreads();
+    dft_regs<T, E, true>(v, twE);
+#pragma unroll
+    for (int r = 0; r < E; ++r) R[pad_e<LOGE>(lane * E + r)] = v[r];
+  }
+  __syncthreads();
+  radix8(LOGE, true, true);
+  radix8(LOGE + 3, true, false);
+}
+
 // CSR = true: store the filtered, packed timestream back in place (the block
 // owns exactly the addresses it loaded); the per-pixel reduce applies P^T.
 template <typename T, int NC, bool CSR>
@@ -571,7 +750,21 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       prof_end(s, st, tok, kProfPass1, gs);
       prof_begin(s, st, &tok);
       const dim3 g2(gd * (M1 / 2));
-      if (M2 <= 1024) {
+      // one row pair per block: two waves
+      constexpr int PB = 1;
+      const size_t lds2w = size_t(2 * PB) * (M2 + 64 + M2 / 64 + 64) * sizeof(Cx<T>);
+      const bool wave_rows = MM_PASS2W && lds2w <= 80 * 1024 && ((int64_t(gd) * M1 / 2) % PB) == 0;
+      const dim3 g2w(unsigned(int64_t(gd) * M1 / 2 / PB)), b2w(128 * PB);
+      if (wave_rows && M2 == 512) {
+        raise_lds_limit(k_pass2w<T, 8, PB>, lds2w);
+        hipLaunchKernelGGL((k_pass2w<T, 8, PB>), g2w, b2w, lds2w, st, a);
+      } else if (wave_rows && M2 == 1024) {
+        raise_lds_limit(k_pass2w<T, 16, PB>, lds2w);
+        hipLaunchKernelGGL((k_pass2w<T, 16, PB>), g2w, b2w, lds2w, st, a);
+      } else if (wave_rows && M2 == 2048) {
+        raise_lds_limit(k_pass2w<T, 32, PB>, lds2w);
+        hipLaunchKernelGGL((k_pass2w<T, 32, PB>), g2w, b2w, lds2w, st, a);
+      } else if (M2 <= 1024) {
         raise_lds_limit(k_pass2<T, 8>, lds2);
         hipLaunchKernelGGL((k_pass2<T, 8>), g2, dim3(kNT), lds2, st, a);
       } else if (M2 <= 2048) {
