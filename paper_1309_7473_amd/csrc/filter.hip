@@ -43,7 +43,7 @@ struct PassArgs {
   const float* s2;
   const float* iN;      // group base [G][M+1]
   const T* tod;         // group base [G][n] (rhs source)
-  const V4<T>* gmap;    // [npix]
+  const V4<T>* gmap;    // [npix + 1], entry npix = 0
   double* acc;          // [npix][4]
   Cx<T>* work;          // [G][M]
   const Cx<T>* tw;      // Stockham table W_Lmax^m
@@ -67,8 +67,8 @@ __device__ __forceinline__ T source_sample(const PassArgs<T>& a, int64_t s) {
     return a.tod[s];
   } else {
     const int p = a.pix[s];
-    if (unsigned(p) >= unsigned(a.npix)) return T(0);
-    const V4<T> m = a.gmap[p];
+    // off-map samples read the zero entry gmap[npix]: no branch around the gather
+    const V4<T> m = a.gmap[unsigned(p) < unsigned(a.npix) ? p : a.npix];
     if constexpr (NC == 3) {
       return m.x + T(a.c2[s]) * m.y + T(a.s2[s]) * m.z;
     } else {
@@ -137,7 +137,13 @@ template <typename T>
 __global__ void k_prologue(const double* __restrict__ x, const int32_t* __restrict__ mask,
                            V4<T>* __restrict__ gmap, double* __restrict__ acc, int npix, int nc) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
+  if (p > npix) return;
+  if (p == npix) {   // zero entry read by off-map samples
+    V4<T> z;
+    z.x = z.y = z.z = z.w = T(0);
+    gmap[npix] = z;
+    return;
+  }
   const bool on = mask[p] != 0;
   V4<T> g;
   g.x = on ? T(x[p]) : T(0);
@@ -235,13 +241,8 @@ __device__ __forceinline__ void source4(const PassArgs<T>& a, int64_t s, T (&v)[
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int p = pp[i];
-      if (unsigned(p) < unsigned(a.npix)) {
-        const V4<T> m = a.gmap[p];
-        v[i] = (NC == 3) ? m.x + T(cc[i]) * m.y + T(ss[i]) * m.z : m.x;
-      } else {
-        v[i] = T(0);
-      }
+      const V4<T> m = a.gmap[unsigned(pp[i]) < unsigned(a.npix) ? pp[i] : a.npix];
+      v[i] = (NC == 3) ? m.x + T(cc[i]) * m.y + T(ss[i]) * m.z : m.x;
     }
   }
 }
@@ -294,15 +295,24 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T> a) {
   const int64_t base = int64_t(g) * a.n;
   stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
   const int nq = (C * M1) >> 1;  // groups of 4 samples
-#pragma unroll 4
-  for (int e4 = threadIdx.x; e4 < nq; e4 += kNT13) {
-    const int e = e4 << 2;
-    const int j1 = e >> (a.logC + 1);
-    const int q = e & (2 * C - 1);
-    const int64_t s = base + 2 * (int64_t(j1) * M2 + j20) + q;
-    T v[4];
-    source4<T, NC, SRC>(a, s, v);
-    store4(bufr + e, v);
+  // U groups per thread per trip, every load of a trip issued before the
+  // first use; a group past the end re-reads group e40 and is not stored.
+  constexpr int U = 4;
+  for (int e40 = threadIdx.x; e40 < nq; e40 += U * kNT13) {
+    T v[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e4 = e40 + u * kNT13;
+      const int e = (e4 < nq ? e4 : e40) << 2;
+      const int j1 = e >> (a.logC + 1);
+      const int q = e & (2 * C - 1);
+      source4<T, NC, SRC>(a, base + 2 * (int64_t(j1) * M2 + j20) + q, v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e4 = e40 + u * kNT13;
+      if (e4 < nq) store4(bufr + (e4 << 2), v[u]);
+    }
   }
   __syncthreads();
   FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
@@ -808,11 +818,12 @@ mm_status filter_pipeline(ScanImpl* s, int src, const void* tod, const double* x
   hipEvent_t tok;
   prof_begin(s, st, &tok);
   if (src == 0) {
+    const dim3 grd1((npix + 1 + 255) / 256);   // npix + 1: the zero entry too
     if (s->plan.f64)
-      hipLaunchKernelGGL(k_prologue<double>, grd, blk, 0, st, x, mask,
+      hipLaunchKernelGGL(k_prologue<double>, grd1, blk, 0, st, x, mask,
                          s->at<V4<double>>(s->lay.gmap), acc, npix, s->nc);
     else
-      hipLaunchKernelGGL(k_prologue<float>, grd, blk, 0, st, x, mask,
+      hipLaunchKernelGGL(k_prologue<float>, grd1, blk, 0, st, x, mask,
                          s->at<V4<float>>(s->lay.gmap), acc, npix, s->nc);
   } else {
     hipLaunchKernelGGL(k_zero_acc, grd, blk, 0, st, acc, npix);
@@ -920,7 +931,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->int_ = take(pl->single ? 0 : size_t(d->ndet) * size_t(M + 1) * 4);
   L->wn_hi = take((size_t(1) << (pl->logn - pl->logS)) * cxb);
   L->wn_lo = take((size_t(1) << pl->logS) * cxb);
-  L->gmap = take(size_t(npix) * 4 * (pl->f64 ? 8 : 4));
+  L->gmap = take(size_t(npix + 1) * 4 * (pl->f64 ? 8 : 4));
   L->acc = take(size_t(npix) * 4 * 8);
   L->detw = take(size_t(d->ndet) * 8);
   L->hits = take(size_t(npix) * 8);

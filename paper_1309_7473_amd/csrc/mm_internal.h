@@ -51,7 +51,7 @@ struct Layout {
   size_t tw2;        // W_{2 M2}^k2 table, M2 complex (four-step)
   size_t int_;       // ndet * (M+1) float: 1/N(f) in four-step order
   size_t wn_hi, wn_lo;
-  size_t gmap;       // npix * 4 real (gather map)
+  size_t gmap;       // (npix + 1) * 4 real (gather map; entry npix is zero)
   size_t acc;        // npix * 4 double (scatter accumulator)
   size_t detw;       // ndet double
   size_t hits;       // npix double (hit counts, accumulated in f64)
