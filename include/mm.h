@@ -56,6 +56,12 @@ typedef enum {
 
 typedef enum { MM_F32 = 0, MM_BF16 = 1, MM_F64 = 2 } mm_dtype;
 
+/* Arithmetic of the long sums: the pixel accumulation of P^T and the PCG
+ * inner products.  MM_ACC_F64: float64.  MM_ACC_F32X2: compensated float32
+ * pairs (hi + lo, error-free sums and fma products, about 48 bits); the map
+ * vectors stay float64 in memory. */
+typedef enum { MM_ACC_F64 = 0, MM_ACC_F32X2 = 1 } mm_acc;
+
 typedef enum {
   MM_M_NONE = 0,       /* identity */
   MM_M_JACOBI = 1,     /* eq. 5: per-pixel blocks of P^T P */
@@ -69,8 +75,11 @@ typedef struct {
   int32_t ncomp;            /* 1 (I) or 3 (I,Q,U) */
   int32_t ny, nx;           /* map shape; powers of two in [4, 4096] */
   int32_t ndet;             /* detectors, >= 1 */
-  int32_t tod_dtype;        /* mm_dtype of the timestream arithmetic:
-                               MM_F32 (FFT and filter in float32) or
+  int32_t tod_dtype;        /* mm_dtype of the timestream and its arithmetic:
+                               MM_F32 (FFT and filter in float32),
+                               MM_BF16 (d and the pass buffers between the
+                               FFT kernels stored as bfloat16, rounded to
+                               nearest even; FFT and filter math in float32),
                                MM_F64 (everything in float64) */
   int64_t nsamp;            /* samples per detector: power of two, 16 ..2^22 */
   double  fsample;          /* sample rate in Hz (reporting only) */
@@ -100,7 +109,11 @@ typedef struct {
                                creation (no atomics; 12 B/sample of workspace for
                                I,Q,U, 4 B for I); MM_SCATTER_ATOMIC = float64
                                atomic scatter (no index).  The one-kernel path
-                               always scatters atomically. */
+                               scatters atomically unless acc = MM_ACC_F32X2. */
+  int32_t acc;              /* mm_acc of the P^T accumulation and the PCG inner
+                               products.  MM_ACC_F32X2 needs scatter =
+                               MM_SCATTER_AUTO (it always takes the per-pixel
+                               gather, also on the one-kernel path). */
 } mm_scan_desc;
 
 enum { MM_SCATTER_AUTO = 0, MM_SCATTER_ATOMIC = 1 };
@@ -122,15 +135,16 @@ mm_status mm_create_scan(const mm_scan_desc* desc /*[host]*/, void* stream,
 void mm_destroy_scan(mm_scan scan);
 
 /* b = P^T N^-1 d (right-hand side of eq. 2) on the active pixels.
- * tod: [ndet][nsamp] in the scan's tod_dtype (float or double).
+ * tod: [ndet][nsamp] in the scan's tod_dtype (float, bfloat16 bit patterns
+ * as uint16, or double), 16-byte aligned.
  * b: [ncomp][ny][nx] float64, overwritten. */
 mm_status mm_rhs(mm_scan scan, const void* tod, double* b, void* stream);
 
 /* y = A x = P^T N^-1 P x (eq. 2), the per-iteration operator: a nearest-pixel
  * gather of x into timestreams, a per-detector real FFT, multiplication by
- * 1/N(f), the inverse FFT, and an atomic scatter-add back to pixels
- * (accumulated in float64).  x, y: [ncomp][ny][nx] float64; y is
- * overwritten; x and y must not overlap. */
+ * 1/N(f), the inverse FFT, and P^T back to pixels (per-pixel gather or
+ * atomic scatter, see desc->scatter; accumulated in float64).
+ * x, y: [ncomp][ny][nx] float64; y is overwritten; x and y must not overlap. */
 mm_status mm_apply_A(mm_scan scan, const double* x, double* y, void* stream);
 
 /* Options of the circulant preconditioner (Implementation, Regularization and

@@ -19,7 +19,7 @@ from ._abi import (  # noqa: F401
     mm_scan_info, MM_OK, MM_ENOCONV, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENOTBUILT,
     MM_EBREAKDOWN, MM_F32, MM_BF16, MM_F64, MM_M_NONE, MM_M_JACOBI, MM_M_BINNED,
     MM_M_CIRCULANT, MM_M_LEARNED, LIB_PATH, mm_profile, PROFILE_STAGES, MM_SCATTER_AUTO,
-    MM_SCATTER_ATOMIC, mm_train_opts,
+    MM_SCATTER_ATOMIC, mm_train_opts, MM_ACC_F64, MM_ACC_F32X2,
 )
 
 PRECON = {"none": MM_M_NONE, "jacobi": MM_M_JACOBI, "binned": MM_M_BINNED,
@@ -238,7 +238,7 @@ class Scan:
     """
 
     def __init__(self, inputs, tod_dtype="f32", det_group=0, fft_m1=0, fft_cols=0,
-                 mask_rcond=0.0, scatter="auto", device="cuda", stream=None):
+                 mask_rcond=0.0, scatter="auto", acc="f64", device="cuda", stream=None):
         self.device = torch.device(device)
         dev = self.device
 
@@ -256,8 +256,10 @@ class Scan:
         self.ncomp, self.ny, self.nx = int(inputs.ncomp), int(inputs.ny), int(inputs.nx)
         self.ndet, self.nsamp = int(self.pix.shape[0]), int(self.pix.shape[1])
         self.npix = self.ny * self.nx
-        self.tod_dtype = {"f32": MM_F32, "f64": MM_F64}[tod_dtype]
-        self.real_dtype = torch.float32 if tod_dtype == "f32" else torch.float64
+        self.tod_dtype = {"f32": MM_F32, "bf16": MM_BF16, "f64": MM_F64}[tod_dtype]
+        # dtype of the timestream handed to rhs (bf16: rounded to nearest even)
+        self.real_dtype = {"f32": torch.float32, "bf16": torch.bfloat16,
+                           "f64": torch.float64}[tod_dtype]
         d = mm_scan_desc()
         d.ncomp, d.ny, d.nx, d.ndet = self.ncomp, self.ny, self.nx, self.ndet
         d.tod_dtype = self.tod_dtype
@@ -272,6 +274,7 @@ class Scan:
         d.fft_cols = int(fft_cols)
         d.mask_rcond = float(mask_rcond)
         d.scatter = {"auto": MM_SCATTER_AUTO, "atomic": MM_SCATTER_ATOMIC}[scatter]
+        d.acc = {"f64": MM_ACC_F64, "f32x2": MM_ACC_F32X2}[acc]
         nbytes = mm_scan_workspace_bytes(d)
         if nbytes == 0:
             raise MMError(MM_EINVAL, "mm_scan_workspace_bytes")

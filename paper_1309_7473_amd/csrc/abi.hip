@@ -41,8 +41,8 @@ static mm_status validate_shape(const mm_scan_desc* d) {
   if (d->ndet < 1) return fail(MM_EINVAL, "ndet must be >= 1");
   if (!pow2(d->nsamp) || d->nsamp < 16 || d->nsamp > (int64_t(1) << 22))
     return fail(MM_EINVAL, "nsamp must be a power of two in [16, 2^22]");
-  if (d->tod_dtype != MM_F32 && d->tod_dtype != MM_F64)
-    return fail(MM_EINVAL, "tod_dtype must be MM_F32 or MM_F64");
+  if (d->tod_dtype != MM_F32 && d->tod_dtype != MM_BF16 && d->tod_dtype != MM_F64)
+    return fail(MM_EINVAL, "tod_dtype must be MM_F32, MM_BF16 or MM_F64");
   if (d->det_group < 0) return fail(MM_EINVAL, "det_group must be >= 0");
   if (d->fft_m1 < 0 || (d->fft_m1 > 0 && !pow2(d->fft_m1)))
     return fail(MM_EINVAL, "fft_m1 must be 0 or a power of two");
@@ -50,6 +50,10 @@ static mm_status validate_shape(const mm_scan_desc* d) {
     return fail(MM_EINVAL, "fft_cols must be 0 or a power of two");
   if (d->scatter != MM_SCATTER_AUTO && d->scatter != MM_SCATTER_ATOMIC)
     return fail(MM_EINVAL, "scatter must be MM_SCATTER_AUTO or MM_SCATTER_ATOMIC");
+  if (d->acc != MM_ACC_F64 && d->acc != MM_ACC_F32X2)
+    return fail(MM_EINVAL, "acc must be MM_ACC_F64 or MM_ACC_F32X2");
+  if (d->acc == MM_ACC_F32X2 && d->scatter == MM_SCATTER_ATOMIC)
+    return fail(MM_EINVAL, "acc = MM_ACC_F32X2 needs scatter = MM_SCATTER_AUTO");
   return MM_OK;
 }
 
@@ -131,6 +135,7 @@ mm_status mm_rhs(mm_scan scan, const void* tod, double* b, void* stream) {
   ScanImpl* s = get(scan);
   if (!s) return fail(MM_EINVAL, "invalid scan handle");
   if (!tod || !b) return fail(MM_EINVAL, "tod and b are required");
+  if (reinterpret_cast<uintptr_t>(tod) % 16 != 0) return fail(MM_EINVAL, "tod must be 16-byte aligned");
   return filter_pipeline(s, 1, tod, nullptr, b, static_cast<hipStream_t>(stream));
 }
 

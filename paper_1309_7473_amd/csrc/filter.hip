@@ -23,6 +23,12 @@
 //   pass 3: inverse length-M1 column FFTs, then scatter P^T back to pixels.
 // The scatter pre-sums runs of equal pixels across the lanes of a wavefront
 // and accumulates with float64 atomics into a [npix][4] accumulator.
+//
+// Storage: the timestream d and the pass buffers hold the math type (float
+// or double), or bfloat16 under float math (MM_BF16): every value is rounded
+// to nearest-even as it is stored and widened exactly as it is loaded, so
+// only the stores between passes lose precision.
+#include <type_traits>
 #include <vector>
 #include <cmath>
 
@@ -36,16 +42,49 @@ struct alignas(4 * sizeof(T)) V4 {
   T x, y, z, w;
 };
 
-template <typename T>
+struct Bf16 {};  // storage tag: bfloat16 pass buffers under float math
+
+template <typename T, typename S>
+struct Sto {  // storage in the math type itself
+  using W = Cx<T>;  // one complex of the pass buffer
+  using R = T;      // one real timestream sample
+  static __device__ __forceinline__ Cx<T> ld(const W* p) { return *p; }
+  static __device__ __forceinline__ void st(W* p, Cx<T> v) { *p = v; }
+  static __device__ __forceinline__ T ldr(const R* p) { return *p; }
+};
+
+template <>
+struct Sto<float, Bf16> {
+  using W = uint32_t;  // real part in the low half, imaginary in the high
+  using R = uint16_t;
+  static __device__ __forceinline__ float up(uint32_t h) { return __uint_as_float(h << 16); }
+  static __device__ __forceinline__ uint32_t down(float f) {  // round to nearest even
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // NaN stays NaN
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  }
+  static __device__ __forceinline__ Cx<float> ld(const W* p) {
+    const uint32_t v = *p;
+    return cx(__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u));
+  }
+  static __device__ __forceinline__ void st(W* p, Cx<float> v) {
+    *p = down(v.x) | (down(v.y) << 16);
+  }
+  static __device__ __forceinline__ float ldr(const R* p) { return up(*p); }
+};
+
+template <typename T, typename S>
 struct PassArgs {
+  using W = typename Sto<T, S>::W;
+  using R = typename Sto<T, S>::R;
   const int32_t* pix;   // group base [G][n]
   const float* c2;
   const float* s2;
   const float* iN;      // group base [G][M+1]
-  const T* tod;         // group base [G][n] (rhs source)
+  const R* tod;         // group base [G][n] (rhs source)
   const V4<T>* gmap;    // [npix + 1], entry npix = 0
   double* acc;          // [npix][4]
-  Cx<T>* work;          // [G][M]
+  W* work;              // [G][M] pass buffer
   const Cx<T>* tw;      // Stockham table W_Lmax^m
   TwoLevel<T> wn;       // W_n^m
   const int32_t* csr_off;  // group [npix+1]
@@ -61,10 +100,10 @@ struct PassArgs {
 };
 
 // --------------------------------------------------------------- samples
-template <typename T, int NC, int SRC>
-__device__ __forceinline__ T source_sample(const PassArgs<T>& a, int64_t s) {
+template <typename T, typename S, int NC, int SRC>
+__device__ __forceinline__ T source_sample(const PassArgs<T, S>& a, int64_t s) {
   if constexpr (SRC == 1) {
-    return a.tod[s];
+    return Sto<T, S>::ldr(a.tod + s);
   } else {
     const int p = a.pix[s];
     // off-map samples read the zero entry gmap[npix]: no branch around the gather
@@ -79,8 +118,8 @@ __device__ __forceinline__ T source_sample(const PassArgs<T>& a, int64_t s) {
 
 // Scatter one sample per lane; must be reached by every lane of the wave
 // (inactive lanes pass s < 0).
-template <typename T, int NC>
-__device__ __forceinline__ void scatter_sample(const PassArgs<T>& a, int64_t s, T u) {
+template <typename T, int NC, typename A>
+__device__ __forceinline__ void scatter_sample(const A& a, int64_t s, T u) {
   int p = -1;
   double v[NC];
   v[0] = 0.0;
@@ -164,12 +203,20 @@ __global__ void k_zero_acc(double* __restrict__ acc, int npix) {
   reinterpret_cast<double4*>(acc)[p] = z;
 }
 
+// cf: the accumulator holds float-float pairs (hi, lo) instead of doubles
 __global__ void k_epilogue(const double* __restrict__ acc, const int32_t* __restrict__ mask,
-                           double* __restrict__ y, int npix, int nc) {
+                           double* __restrict__ y, int npix, int nc, int cf) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
   const bool on = mask[p] != 0;
-  const double4 a = reinterpret_cast<const double4*>(acc)[p];
+  double4 a = reinterpret_cast<const double4*>(acc)[p];
+  if (cf) {
+    const float4 q = reinterpret_cast<const float4*>(acc)[2 * p];
+    const float2 r = reinterpret_cast<const float2*>(acc)[4 * p + 2];
+    a.x = f2_value(F2{q.x, q.y});
+    a.y = f2_value(F2{q.z, q.w});
+    a.z = f2_value(F2{r.x, r.y});
+  }
   y[p] = on ? a.x : 0.0;
   if (nc == 3) {
     y[npix + p] = on ? a.y : 0.0;
@@ -178,8 +225,10 @@ __global__ void k_epilogue(const double* __restrict__ acc, const int32_t* __rest
 }
 
 // ------------------------------------------------------------- single pass
-template <typename T, int NC, int SRC>
-__global__ void __launch_bounds__(kNT) k_single(PassArgs<T> a) {
+// CSR = true: store the filtered, packed timestream to the pass buffer for the
+// per-pixel reduce instead of scattering it.
+template <typename T, typename S, int NC, int SRC, bool CSR>
+__global__ void __launch_bounds__(kNT) k_single(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
   T* bufr = reinterpret_cast<T*>(smem);
@@ -187,7 +236,7 @@ __global__ void __launch_bounds__(kNT) k_single(PassArgs<T> a) {
   const int g = blockIdx.x;
   const int64_t base = int64_t(g) * a.n;
   const int nsamp = 2 * M;
-  for (int e = threadIdx.x; e < nsamp; e += kNT) bufr[e] = source_sample<T, NC, SRC>(a, base + e);
+  for (int e = threadIdx.x; e < nsamp; e += kNT) bufr[e] = source_sample<T, S, NC, SRC>(a, base + e);
   __syncthreads();
   FftShape sh{a.logM, 0, 1, M, false, a.logLmax};
   lds_fft<T, kNT, kE, false>(buf, sh, a.tw);
@@ -204,6 +253,11 @@ __global__ void __launch_bounds__(kNT) k_single(PassArgs<T> a) {
   }
   __syncthreads();
   lds_fft<T, kNT, kE, true>(buf, sh, a.tw);
+  if constexpr (CSR) {
+    auto* w = a.work + (int64_t(g) << a.logM);
+    for (int j = threadIdx.x; j < M; j += kNT) Sto<T, S>::st(w + j, buf[j]);
+    return;
+  }
   // every lane of a wave takes the same number of trips (the scatter shuffles)
   for (int e0 = 0; e0 < nsamp; e0 += kNT) {
     const int e = e0 + threadIdx.x;
@@ -218,10 +272,16 @@ constexpr int kE13 = 8;      // complex elements per thread (C * M1 <= 8192)
 constexpr int kPad2 = 3;     // pass-2 LDS padding: one slot per 8 elements
 
 // Four consecutive samples s..s+3 (s a multiple of 4) with 16-byte loads.
-template <typename T, int NC, int SRC>
-__device__ __forceinline__ void source4(const PassArgs<T>& a, int64_t s, T (&v)[4]) {
+template <typename T, typename S, int NC, int SRC>
+__device__ __forceinline__ void source4(const PassArgs<T, S>& a, int64_t s, T (&v)[4]) {
   if constexpr (SRC == 1) {
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (std::is_same<S, Bf16>::value) {
+      const uint2 t = *reinterpret_cast<const uint2*>(a.tod + s);
+      v[0] = __uint_as_float(t.x << 16);
+      v[1] = __uint_as_float(t.x & 0xffff0000u);
+      v[2] = __uint_as_float(t.y << 16);
+      v[3] = __uint_as_float(t.y & 0xffff0000u);
+    } else if constexpr (sizeof(T) == 4) {
       const float4 t = *reinterpret_cast<const float4*>(a.tod + s);
       v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
     } else {
@@ -280,8 +340,8 @@ __device__ __forceinline__ void col_block(int logNB, int* g, int* cb) {
   }
 }
 
-template <typename T, int NC, int SRC>
-__global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T> a) {
+template <typename T, typename S, int NC, int SRC>
+__global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
   T* bufr = reinterpret_cast<T*>(smem);
@@ -306,7 +366,7 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T> a) {
       const int e = (e4 < nq ? e4 : e40) << 2;
       const int j1 = e >> (a.logC + 1);
       const int q = e & (2 * C - 1);
-      source4<T, NC, SRC>(a, base + 2 * (int64_t(j1) * M2 + j20) + q, v[u]);
+      source4<T, S, NC, SRC>(a, base + 2 * (int64_t(j1) * M2 + j20) + q, v[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -317,11 +377,11 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T> a) {
   __syncthreads();
   FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
   lds_fft<T, kNT13, kE13, false>(buf, sh, stw);
-  Cx<T>* w = a.work + (int64_t(g) << a.logM);
+  auto* w = a.work + (int64_t(g) << a.logM);
   for (int e = threadIdx.x; e < C * M1; e += kNT13) {
     const int k1 = e >> a.logC;
     const int c = e & (C - 1);
-    w[int64_t(k1) * M2 + j20 + c] = buf[e];
+    Sto<T, S>::st(w + int64_t(k1) * M2 + j20 + c, buf[e]);
   }
 }
 
@@ -329,8 +389,8 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T> a) {
 // four-step twiddle W_M^(k1 j2) = A[j2 >> 6] * B[j2 & 63] comes from two
 // small per-row LDS tables; W_n^k = W_n^k1 * W_2M2^k2; 1/N(f) is read from
 // its copy in four-step order (row k1 contiguous).
-template <typename T, int E>
-__global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T> a) {
+template <typename T, typename S, int E>
+__global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M1 = 1 << a.logM1, M2 = 1 << a.logM2;
   const int M = 1 << a.logM;
@@ -355,12 +415,12 @@ __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T> a) {
     tB[t] = a.wn(2 * int64_t(r ? rb : ra) * jl);
   }
   __syncthreads();
-  Cx<T>* w = a.work + (int64_t(g) << a.logM);
+  auto* w = a.work + (int64_t(g) << a.logM);
   for (int e = threadIdx.x; e < 2 * M2; e += kNT) {
     const int row = e >> a.logM2;
     const int j2 = e & (M2 - 1);
     const int k1 = row ? rb : ra;
-    const Cx<T> v = w[int64_t(k1) * M2 + j2];
+    const Cx<T> v = Sto<T, S>::ld(w + int64_t(k1) * M2 + j2);
     buf[lds_at<kPad2>(e)] = v * (tA[row * JH + (j2 >> logJL)] * tB[row * JL + (j2 & (JL - 1))]);
   }
   __syncthreads();
@@ -416,8 +476,9 @@ __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T> a) {
     const int row = e >> a.logM2;
     const int j2 = e & (M2 - 1);
     const int k1 = row ? rb : ra;
-    w[int64_t(k1) * M2 + j2] =
-        buf[lds_at<kPad2>(e)] * conj(tA[row * JH + (j2 >> logJL)] * tB[row * JL + (j2 & (JL - 1))]);
+    Sto<T, S>::st(w + int64_t(k1) * M2 + j2,
+                  buf[lds_at<kPad2>(e)] *
+                      conj(tA[row * JH + (j2 >> logJL)] * tB[row * JL + (j2 & (JL - 1))]));
   }
 }
 
@@ -439,8 +500,8 @@ __device__ __forceinline__ int pad_e(int i) {
   return i + (i >> LOGE);
 }
 
-template <typename T, int E, int PB>
-__global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T> a) {
+template <typename T, typename S, int E, int PB>
+__global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
   constexpr int LOGE = (E == 8) ? 3 : (E == 16) ? 4 : 5;
   constexpr int L = 64 * E;              // = M2
   constexpr int LOGL = LOGE + 6;
@@ -473,14 +534,14 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T> a) {
   const int tsh = a.logLmax - LOGL;
   auto twL = [&](int m) { return a.tw[m << tsh]; };   // W_L^m, from the cached table
   Cx<T>* R = rows + wave * RS;
-  Cx<T>* w = a.work + (int64_t(g) << a.logM) + int64_t(myrow) * L;
+  auto* w = a.work + (int64_t(g) << a.logM) + int64_t(myrow) * L;
   const Cx<T> tb = tB[wave * 64 + lane];
   auto twE = [&](int m) { return twL(m << 6); };   // W_E^m = W_L^(64 m)
   // ---------------- forward: radix-E from global, then 2 x radix-8
   {
     Cx<T> v[E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) v[r] = w[lane + 64 * r] * (tA[wave * E + r] * tb);
+    for (int r = 0; r < E; ++r) v[r] = Sto<T, S>::ld(w + lane + 64 * r) * (tA[wave * E + r] * tb);
     dft_regs<T, E, false>(v, twE);
 #pragma unroll
     for (int r = 0; r < E; ++r) R[pad_e<LOGE>(lane * E + r)] = v[r];
@@ -527,7 +588,7 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T> a) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           const int idx = out + r * Ns;
-          w[idx] = u[i][r] * conj(tA[wave * E + (idx >> 6)] * tB[wave * 64 + (idx & 63)]);
+          Sto<T, S>::st(w + idx, u[i][r] * conj(tA[wave * E + (idx >> 6)] * tB[wave * 64 + (idx & 63)]));
         }
       }
     }
@@ -602,8 +663,8 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T> a) {
 
 // CSR = true: store the filtered, packed timestream back in place (the block
 // owns exactly the addresses it loaded); the per-pixel reduce applies P^T.
-template <typename T, int NC, bool CSR>
-__global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T> a) {
+template <typename T, typename S, int NC, bool CSR>
+__global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
   T* bufr = reinterpret_cast<T*>(smem);
@@ -615,21 +676,21 @@ __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T> a) {
   Cx<T>* stw = buf + C * M1;
   const int j20 = cb << a.logC;
   stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
-  const Cx<T>* w = a.work + (int64_t(g) << a.logM);
+  const auto* w = a.work + (int64_t(g) << a.logM);
   for (int e = threadIdx.x; e < C * M1; e += kNT13) {
     const int k1 = e >> a.logC;
     const int c = e & (C - 1);
-    buf[e] = w[int64_t(k1) * M2 + j20 + c];
+    buf[e] = Sto<T, S>::ld(w + int64_t(k1) * M2 + j20 + c);
   }
   __syncthreads();
   FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
   lds_fft<T, kNT13, kE13, true>(buf, sh, stw);
   if constexpr (CSR) {
-    Cx<T>* wo = a.work + (int64_t(g) << a.logM);
+    auto* wo = a.work + (int64_t(g) << a.logM);
     for (int e = threadIdx.x; e < C * M1; e += kNT13) {
       const int k1 = e >> a.logC;
       const int c = e & (C - 1);
-      wo[int64_t(k1) * M2 + j20 + c] = buf[e];
+      Sto<T, S>::st(wo + int64_t(k1) * M2 + j20 + c, buf[e]);
     }
     return;
   }
@@ -646,41 +707,78 @@ __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T> a) {
 // P^T for one detector group as a per-pixel gather: 16 lanes per pixel walk
 // its CSR entries, each lane summing a fixed stride of them, then a fixed
 // xor-tree; acc[p] += (sum u, sum c u, sum s u).  No atomics.
-template <typename T, int NC>
-__global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T> a) {
+template <typename T, typename S, int NC, bool CF>
+__global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
   constexpr int LPP = 16;
   const int sub = threadIdx.x / LPP;
   const int l = threadIdx.x % LPP;
   const int p = blockIdx.x * (256 / LPP) + sub;
   if (p >= a.npix) return;            // whole 16-lane groups leave together
   if (!a.mask[p]) return;
-  const T* u = reinterpret_cast<const T*>(a.work);
+  // the pass buffer read as packed reals: sample 2j is Re z[j], 2j+1 is Im z[j]
+  const auto* u = reinterpret_cast<const typename Sto<T, S>::R*>(a.work);
   const int b = a.csr_off[p], e = a.csr_off[p + 1];
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if constexpr (!CF) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll 4
-  for (int k = b + l; k < e; k += LPP) {
-    const double uu = double(u[a.csr_idx[k]]);
-    s0 += uu;
-    if constexpr (NC == 3) {
-      const float2 cs = a.csr_w[k];
-      s1 += double(cs.x) * uu;
-      s2 += double(cs.y) * uu;
+    for (int k = b + l; k < e; k += LPP) {
+      const double uu = double(Sto<T, S>::ldr(u + a.csr_idx[k]));
+      s0 += uu;
+      if constexpr (NC == 3) {
+        const float2 cs = a.csr_w[k];
+        s1 += double(cs.x) * uu;
+        s2 += double(cs.y) * uu;
+      }
     }
-  }
 #pragma unroll
-  for (int off = LPP / 2; off > 0; off >>= 1) {
-    s0 += __shfl_xor(s0, off, LPP);
-    if constexpr (NC == 3) {
-      s1 += __shfl_xor(s1, off, LPP);
-      s2 += __shfl_xor(s2, off, LPP);
+    for (int off = LPP / 2; off > 0; off >>= 1) {
+      s0 += __shfl_xor(s0, off, LPP);
+      if constexpr (NC == 3) {
+        s1 += __shfl_xor(s1, off, LPP);
+        s2 += __shfl_xor(s2, off, LPP);
+      }
     }
-  }
-  if (l == 0) {
-    double* d = a.acc + 4 * int64_t(p);
-    d[0] += s0;
-    if constexpr (NC == 3) {
-      d[1] += s1;
-      d[2] += s2;
+    if (l == 0) {
+      double* d = a.acc + 4 * int64_t(p);
+      d[0] += s0;
+      if constexpr (NC == 3) {
+        d[1] += s1;
+        d[2] += s2;
+      }
+    }
+  } else {
+    // compensated float32: products exact as (p, fma error), sums error-free
+    F2 s0{0.f, 0.f}, s1{0.f, 0.f}, s2{0.f, 0.f};
+#pragma unroll 4
+    for (int k = b + l; k < e; k += LPP) {
+      const T ut = Sto<T, S>::ldr(u + a.csr_idx[k]);
+      F2 uu;
+      if constexpr (sizeof(T) == 8)
+        uu = f2_split(ut);
+      else
+        uu = F2{float(ut), 0.f};
+      f2_acc(s0, uu.hi, uu.lo);
+      if constexpr (NC == 3) {
+        const float2 cs = a.csr_w[k];
+        f2_fma_acc(s1, cs.x, uu);
+        f2_fma_acc(s2, cs.y, uu);
+      }
+    }
+#pragma unroll
+    for (int off = LPP / 2; off > 0; off >>= 1) {
+      s0 = f2_add(s0, f2_shfl_xor(s0, off, LPP));
+      if constexpr (NC == 3) {
+        s1 = f2_add(s1, f2_shfl_xor(s1, off, LPP));
+        s2 = f2_add(s2, f2_shfl_xor(s2, off, LPP));
+      }
+    }
+    if (l == 0) {
+      F2* d = reinterpret_cast<F2*>(a.acc + 4 * int64_t(p));
+      d[0] = f2_add(d[0], s0);
+      if constexpr (NC == 3) {
+        d[1] = f2_add(d[1], s1);
+        d[2] = f2_add(d[2], s2);
+      }
     }
   }
 }
@@ -699,14 +797,24 @@ static void raise_lds_limit(K kernel, size_t bytes) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
-template <typename T, int NC, int SRC>
+template <typename T, typename S, int NC>
+static void launch_reduce(ScanImpl* s, const PassArgs<T, S>& a, hipStream_t st) {
+  const dim3 grid((s->npix + 15) / 16);   // 16 pixels of 16 lanes per block
+  if (s->plan.acc32)
+    hipLaunchKernelGGL((k_csr_reduce<T, S, NC, true>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_csr_reduce<T, S, NC, false>), grid, dim3(256), 0, st, a);
+}
+
+template <typename T, typename S, int NC, int SRC>
 static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
+  using A = PassArgs<T, S>;
   const Plan& pl = s->plan;
   const int M = 1 << pl.logM;
-  PassArgs<T> a;
+  A a;
   a.gmap = s->at<V4<T>>(s->lay.gmap);
   a.acc = s->at<double>(s->lay.acc);
-  a.work = s->at<Cx<T>>(s->lay.tod);
+  a.work = s->at<typename A::W>(s->lay.tod);
   a.tw = s->at<Cx<T>>(s->lay.tw);
   a.wn.hi = s->at<Cx<T>>(s->lay.wn_hi);
   a.wn.lo = s->at<Cx<T>>(s->lay.wn_lo);
@@ -730,7 +838,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
     a.s2 = s->d.sin2psi ? s->d.sin2psi + off : nullptr;
     a.iN = s->d.inv_noise + int64_t(d0) * (M + 1);
     a.iNt = pl.single ? nullptr : s->at<float>(s->lay.int_) + int64_t(d0) * (M + 1);
-    a.tod = tod ? static_cast<const T*>(tod) + off : nullptr;
+    a.tod = tod ? static_cast<const typename A::R*>(tod) + off : nullptr;
     if (pl.csr) {
       const int gi = d0 / G;
       a.csr_off = s->at<int32_t>(s->lay.csr_off) + int64_t(gi) * (s->npix + 1);
@@ -741,10 +849,20 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
     hipEvent_t tok;
     if (pl.single) {
       const size_t lds = size_t(M) * sizeof(Cx<T>);
-      raise_lds_limit(k_single<T, NC, SRC>, lds);
       prof_begin(s, st, &tok);
-      hipLaunchKernelGGL((k_single<T, NC, SRC>), dim3(gd), dim3(kNT), lds, st, a);
+      if (pl.csr) {
+        raise_lds_limit(k_single<T, S, NC, SRC, true>, lds);
+        hipLaunchKernelGGL((k_single<T, S, NC, SRC, true>), dim3(gd), dim3(kNT), lds, st, a);
+      } else {
+        raise_lds_limit(k_single<T, S, NC, SRC, false>, lds);
+        hipLaunchKernelGGL((k_single<T, S, NC, SRC, false>), dim3(gd), dim3(kNT), lds, st, a);
+      }
       prof_end(s, st, tok, kProfSingle, gs);
+      if (pl.csr) {
+        prof_begin(s, st, &tok);
+        launch_reduce<T, S, NC>(s, a, st);
+        prof_end(s, st, tok, kProfReduce, gs);
+      }
     } else {
       const int C = 1 << pl.logC;
       const int M1 = 1 << pl.logM1, M2 = 1 << pl.logM2;
@@ -752,11 +870,11 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const int JL = M2 < 64 ? M2 : 64;
       const size_t lds2 =
           (size_t(2) * M2 + (size_t(2) * M2 >> kPad2) + M2 + 2 * (M2 / JL) + 2 * JL) * sizeof(Cx<T>);
-      raise_lds_limit(k_pass1<T, NC, SRC>, lds13);
-      raise_lds_limit(k_pass3<T, NC, false>, lds13);
-      raise_lds_limit(k_pass3<T, NC, true>, lds13);
+      raise_lds_limit(k_pass1<T, S, NC, SRC>, lds13);
+      raise_lds_limit(k_pass3<T, S, NC, false>, lds13);
+      raise_lds_limit(k_pass3<T, S, NC, true>, lds13);
       prof_begin(s, st, &tok);
-      hipLaunchKernelGGL((k_pass1<T, NC, SRC>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
+      hipLaunchKernelGGL((k_pass1<T, S, NC, SRC>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
       prof_end(s, st, tok, kProfPass1, gs);
       prof_begin(s, st, &tok);
       const dim3 g2(gd * (M1 / 2));
@@ -766,34 +884,34 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const bool wave_rows = MM_PASS2W && lds2w <= 80 * 1024 && ((int64_t(gd) * M1 / 2) % PB) == 0;
       const dim3 g2w(unsigned(int64_t(gd) * M1 / 2 / PB)), b2w(128 * PB);
       if (wave_rows && M2 == 512) {
-        raise_lds_limit(k_pass2w<T, 8, PB>, lds2w);
-        hipLaunchKernelGGL((k_pass2w<T, 8, PB>), g2w, b2w, lds2w, st, a);
+        raise_lds_limit(k_pass2w<T, S, 8, PB>, lds2w);
+        hipLaunchKernelGGL((k_pass2w<T, S, 8, PB>), g2w, b2w, lds2w, st, a);
       } else if (wave_rows && M2 == 1024) {
-        raise_lds_limit(k_pass2w<T, 16, PB>, lds2w);
-        hipLaunchKernelGGL((k_pass2w<T, 16, PB>), g2w, b2w, lds2w, st, a);
+        raise_lds_limit(k_pass2w<T, S, 16, PB>, lds2w);
+        hipLaunchKernelGGL((k_pass2w<T, S, 16, PB>), g2w, b2w, lds2w, st, a);
       } else if (wave_rows && M2 == 2048) {
-        raise_lds_limit(k_pass2w<T, 32, PB>, lds2w);
-        hipLaunchKernelGGL((k_pass2w<T, 32, PB>), g2w, b2w, lds2w, st, a);
+        raise_lds_limit(k_pass2w<T, S, 32, PB>, lds2w);
+        hipLaunchKernelGGL((k_pass2w<T, S, 32, PB>), g2w, b2w, lds2w, st, a);
       } else if (M2 <= 1024) {
-        raise_lds_limit(k_pass2<T, 8>, lds2);
-        hipLaunchKernelGGL((k_pass2<T, 8>), g2, dim3(kNT), lds2, st, a);
+        raise_lds_limit(k_pass2<T, S, 8>, lds2);
+        hipLaunchKernelGGL((k_pass2<T, S, 8>), g2, dim3(kNT), lds2, st, a);
       } else if (M2 <= 2048) {
-        raise_lds_limit(k_pass2<T, 16>, lds2);
-        hipLaunchKernelGGL((k_pass2<T, 16>), g2, dim3(kNT), lds2, st, a);
+        raise_lds_limit(k_pass2<T, S, 16>, lds2);
+        hipLaunchKernelGGL((k_pass2<T, S, 16>), g2, dim3(kNT), lds2, st, a);
       } else {
-        raise_lds_limit(k_pass2<T, 32>, lds2);
-        hipLaunchKernelGGL((k_pass2<T, 32>), g2, dim3(kNT), lds2, st, a);
+        raise_lds_limit(k_pass2<T, S, 32>, lds2);
+        hipLaunchKernelGGL((k_pass2<T, S, 32>), g2, dim3(kNT), lds2, st, a);
       }
       prof_end(s, st, tok, kProfPass2, gs);
       prof_begin(s, st, &tok);
       if (pl.csr)
-        hipLaunchKernelGGL((k_pass3<T, NC, true>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
+        hipLaunchKernelGGL((k_pass3<T, S, NC, true>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
       else
-        hipLaunchKernelGGL((k_pass3<T, NC, false>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
+        hipLaunchKernelGGL((k_pass3<T, S, NC, false>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
       prof_end(s, st, tok, kProfPass3, gs);
       if (pl.csr) {
         prof_begin(s, st, &tok);
-        hipLaunchKernelGGL((k_csr_reduce<T, NC>), dim3((s->npix + 15) / 16), dim3(256), 0, st, a);
+        launch_reduce<T, S, NC>(s, a, st);
         prof_end(s, st, tok, kProfReduce, gs);
       }
     }
@@ -802,11 +920,11 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
   return MM_OK;
 }
 
-template <typename T>
+template <typename T, typename S>
 static mm_status run_pipeline(ScanImpl* s, int src, const void* tod, hipStream_t st) {
   if (s->nc == 3)
-    return src ? run_pipeline_t<T, 3, 1>(s, tod, st) : run_pipeline_t<T, 3, 0>(s, tod, st);
-  return src ? run_pipeline_t<T, 1, 1>(s, tod, st) : run_pipeline_t<T, 1, 0>(s, tod, st);
+    return src ? run_pipeline_t<T, S, 3, 1>(s, tod, st) : run_pipeline_t<T, S, 3, 0>(s, tod, st);
+  return src ? run_pipeline_t<T, S, 1, 1>(s, tod, st) : run_pipeline_t<T, S, 1, 0>(s, tod, st);
 }
 
 mm_status filter_pipeline(ScanImpl* s, int src, const void* tod, const double* x, double* y,
@@ -829,10 +947,11 @@ mm_status filter_pipeline(ScanImpl* s, int src, const void* tod, const double* x
     hipLaunchKernelGGL(k_zero_acc, grd, blk, 0, st, acc, npix);
   }
   MM_HIP(hipGetLastError());
-  mm_status r = s->plan.f64 ? run_pipeline<double>(s, src, tod, st)
-                            : run_pipeline<float>(s, src, tod, st);
+  mm_status r = s->plan.f64    ? run_pipeline<double, double>(s, src, tod, st)
+                : s->plan.bf16 ? run_pipeline<float, Bf16>(s, src, tod, st)
+                               : run_pipeline<float, float>(s, src, tod, st);
   if (r != MM_OK) return r;
-  hipLaunchKernelGGL(k_epilogue, grd, blk, 0, st, acc, mask, y, npix, s->nc);
+  hipLaunchKernelGGL(k_epilogue, grd, blk, 0, st, acc, mask, y, npix, s->nc, s->plan.acc32 ? 1 : 0);
   MM_HIP(hipGetLastError());
   prof_end(s, st, tok, kProfApplyA, int64_t(s->ndet) * s->n);
   return MM_OK;
@@ -869,17 +988,24 @@ mm_status permute_inverse_spectrum(ScanImpl* s, hipStream_t st) {
 mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   const int64_t n = d->nsamp;
   pl->f64 = d->tod_dtype == MM_F64;
+  pl->bf16 = d->tod_dtype == MM_BF16;
   pl->logn = ilog2(n);
   pl->logM = pl->logn - 1;
   const int M = 1 << pl->logM;
-  const size_t cxb = pl->f64 ? 16 : 8;
+  const size_t cxb = pl->f64 ? 16 : 8;          // one complex in the math type
+  const size_t wxb = pl->bf16 ? 4 : cxb;         // ... in the pass buffer
+  pl->acc32 = d->acc == MM_ACC_F32X2;
   pl->single = (M <= kE * kNT);
-  pl->csr = !pl->single && d->scatter != MM_SCATTER_ATOMIC;
+  // the compensated accumulation exists only in the per-pixel gather
+  pl->csr = d->scatter != MM_SCATTER_ATOMIC && (!pl->single || pl->acc32);
   if (pl->single) {
     pl->logM1 = 0;
     pl->logM2 = pl->logM;
     pl->logC = 0;
-    pl->G = d->ndet;
+    int G = d->ndet;
+    if (pl->csr && d->det_group > 0 && d->det_group < G) G = d->det_group;
+    while (G > 1 && int64_t(G) * n > (int64_t(1) << 31) - 1) --G;
+    pl->G = G;
     pl->logLmax = pl->logM;
   } else {
     int l1;
@@ -904,7 +1030,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     int G = d->det_group;
     if (G <= 0) {
       // about 256 MiB of timestream scratch per group (large launches)
-      const int64_t per = int64_t(M) * int64_t(cxb);
+      const int64_t per = int64_t(M) * int64_t(wxb);
       G = int((int64_t(256) << 20) / per);
       if (G < 1) G = 1;
     }
@@ -925,7 +1051,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     off += (bytes + 255) & ~size_t(255);
     return o;
   };
-  L->tod = take(pl->single ? 0 : size_t(pl->G) * size_t(M) * cxb);
+  L->tod = take(pl->single && !pl->csr ? 0 : size_t(pl->G) * size_t(M) * wxb);
   L->tw = take((size_t(1) << pl->logLmax) * cxb);
   L->tw2 = take(pl->single ? 0 : (size_t(1) << pl->logM2) * cxb);
   L->int_ = take(pl->single ? 0 : size_t(d->ndet) * size_t(M + 1) * 4);
@@ -951,7 +1077,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->pcg = take(sizeof(PcgDev));
   L->hist = take(size_t(3) * (kHistCap + 1) * 8);
   L->misc = take(256);
-  const int ngroups = pl->single ? 0 : (d->ndet + pl->G - 1) / pl->G;
+  const int ngroups = (d->ndet + pl->G - 1) / pl->G;
   const size_t csr_n = pl->csr ? size_t(ngroups) * pl->G * size_t(n) : 0;
   L->csr_cnt = take(pl->csr ? size_t(ngroups) * npix * 4 : 0);
   L->csr_off = take(pl->csr ? size_t(ngroups) * (npix + 1) * 4 : 0);

@@ -41,7 +41,7 @@ struct PcgDev {
   int iters;
   int done;
   int breakdown;
-  int pad;
+  int cf;          // reductions in compensated float32 pairs
 };
 
 // Offsets of the sub-buffers inside the caller's workspace.
@@ -77,6 +77,8 @@ struct Layout {
 
 struct Plan {
   bool f64;
+  bool bf16;         // bfloat16 timestream and pass buffers (float math)
+  bool acc32;        // compensated float32 accumulation (MM_ACC_F32X2)
   bool single;       // whole detector filtered in one kernel
   bool csr;          // P^T by per-pixel gather (else atomic scatter)
   int logn, logM;    // n = 2^logn samples, M = n/2 packed complex

@@ -7,7 +7,11 @@
 //          beta = rho' / rho;  p = z + beta p
 //
 // Dot products are two-kernel reductions with a fixed summation order (block
-// partials, then one block), so a solve is bit-reproducible.  The kernels read
+// partials, then one block), so a solve is bit-reproducible.  Under
+// MM_ACC_F32X2 (template CF) the products and sums are compensated float32
+// pairs: each double is split into hi + lo floats, products take their fma
+// error, sums are error-free, and a block partial is stored as (hi, lo) in
+// the 8 bytes of its double slot.  The kernels read
 // a `done` flag that the reductions set on convergence or breakdown
 // (p.s <= 0, rho <= 0 or a non-finite scalar); after it, updates are no-ops,
 // so the host only needs to look every check_every iterations.
@@ -21,27 +25,67 @@ namespace mm {
 
 constexpr int kRedBlocks = 512;
 
+// block partial of NV sums, each as a double or as a float-float pair
+template <bool CF>
+struct Acc2 {
+  double d[2] = {0.0, 0.0};
+  F2 f[2] = {F2{0.f, 0.f}, F2{0.f, 0.f}};
+  __device__ __forceinline__ void add_prod(int i, double x, double y) {
+    if constexpr (CF)
+      f2_fma_acc(f[i], f2_split(x), f2_split(y));
+    else
+      d[i] += x * y;
+  }
+  // block-reduce and store the block's two partials
+  __device__ __forceinline__ void store(double* part) {
+    __shared__ double sm[32];
+    if constexpr (CF) {
+      block_sum_f2<2>(f, reinterpret_cast<F2*>(sm));
+      if (threadIdx.x == 0) {
+        reinterpret_cast<F2*>(part)[2 * blockIdx.x] = f[0];
+        reinterpret_cast<F2*>(part)[2 * blockIdx.x + 1] = f[1];
+      }
+    } else {
+      block_sum<2>(d, sm);
+      if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = d[0];
+        part[2 * blockIdx.x + 1] = d[1];
+      }
+    }
+  }
+};
+
 // partial sums of a.b (and c.d if c != nullptr)
+template <bool CF>
 __global__ void __launch_bounds__(256) k_dot_partial(const double* __restrict__ a,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ c,
                                                      const double* __restrict__ d, int64_t n,
                                                      double* __restrict__ part) {
-  double v[2] = {0.0, 0.0};
+  Acc2<CF> v;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
-    v[0] += a[i] * b[i];
-    if (c) v[1] += c[i] * d[i];
+    v.add_prod(0, a[i], b[i]);
+    if (c) v.add_prod(1, c[i], d[i]);
   }
-  __shared__ double sm[32];
-  block_sum<2>(v, sm);
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = v[0];
-    part[2 * blockIdx.x + 1] = v[1];
-  }
+  v.store(part);
 }
 
-__device__ __forceinline__ void sum_partials(const double* part, int nb, double (&v)[2], double* sm) {
+// final sum of the block partials (cf: they are float-float pairs)
+__device__ __forceinline__ void sum_partials(const double* part, int nb, double (&v)[2], double* sm,
+                                             int cf) {
+  if (cf) {
+    F2 f[2] = {F2{0.f, 0.f}, F2{0.f, 0.f}};
+    const F2* pf = reinterpret_cast<const F2*>(part);
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+      f[0] = f2_add(f[0], pf[2 * i]);
+      f[1] = f2_add(f[1], pf[2 * i + 1]);
+    }
+    block_sum_f2<2>(f, reinterpret_cast<F2*>(sm));
+    v[0] = f2_value(f[0]);
+    v[1] = f2_value(f[1]);
+    return;
+  }
   v[0] = v[1] = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
     v[0] += part[2 * i];
@@ -54,7 +98,7 @@ __device__ __forceinline__ void sum_partials(const double* part, int nb, double 
 __global__ void k_fin_init(const double* __restrict__ part, int nb, PcgDev* st, double* hist) {
   __shared__ double sm[32];
   double v[2];
-  sum_partials(part, nb, v, sm);
+  sum_partials(part, nb, v, sm, st->cf);
   if (threadIdx.x == 0) {
     st->bb = v[0];
     st->rr = v[1];
@@ -79,7 +123,7 @@ __global__ void k_fin_init(const double* __restrict__ part, int nb, PcgDev* st, 
 __global__ void k_fin_rho0(const double* __restrict__ part, int nb, PcgDev* st) {
   __shared__ double sm[32];
   double v[2];
-  sum_partials(part, nb, v, sm);
+  sum_partials(part, nb, v, sm, st->cf);
   if (threadIdx.x == 0) st->rho = v[0];
 }
 
@@ -94,7 +138,7 @@ __global__ void k_mask_vec(double* __restrict__ x, const int32_t* __restrict__ m
 __global__ void k_fin_ps(const double* __restrict__ part, int nb, PcgDev* st) {
   __shared__ double sm[32];
   double v[2];
-  sum_partials(part, nb, v, sm);
+  sum_partials(part, nb, v, sm, st->cf);
   if (threadIdx.x == 0 && !st->done) {
     const double ps = v[0], rho = st->rho;
     st->ps = ps;
@@ -109,6 +153,7 @@ __global__ void k_fin_ps(const double* __restrict__ part, int nb, PcgDev* st) {
 }
 
 // x += alpha p ; r -= alpha s ; partial r.r
+template <bool CF>
 __global__ void __launch_bounds__(256) k_update_xr(double* __restrict__ x, double* __restrict__ r,
                                                    const double* __restrict__ p,
                                                    const double* __restrict__ s, int64_t n,
@@ -116,20 +161,15 @@ __global__ void __launch_bounds__(256) k_update_xr(double* __restrict__ x, doubl
                                                    double* __restrict__ part) {
   if (st->done) return;
   const double alpha = st->alpha;
-  double v[2] = {0.0, 0.0};
+  Acc2<CF> v;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * s[i];
     r[i] = ri;
-    v[0] += ri * ri;
+    v.add_prod(0, ri, ri);
   }
-  __shared__ double sm[32];
-  block_sum<2>(v, sm);
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = v[0];
-    part[2 * blockIdx.x + 1] = 0.0;
-  }
+  v.store(part);
 }
 
 __global__ void k_fin_rr(const double* __restrict__ part, int nb, PcgDev* st, double* hist,
@@ -137,7 +177,7 @@ __global__ void k_fin_rr(const double* __restrict__ part, int nb, PcgDev* st, do
   if (st->done) return;
   __shared__ double sm[32];
   double v[2];
-  sum_partials(part, nb, v, sm);
+  sum_partials(part, nb, v, sm, st->cf);
   if (threadIdx.x == 0) {
     const double rr = v[0];
     st->rr = rr;
@@ -162,7 +202,7 @@ __global__ void k_fin_rz(const double* __restrict__ part, int nb, PcgDev* st) {
   if (st->done) return;
   __shared__ double sm[32];
   double v[2];
-  sum_partials(part, nb, v, sm);
+  sum_partials(part, nb, v, sm, st->cf);
   if (threadIdx.x == 0) {
     const double rz = v[0];
     st->rz = rz;
@@ -247,6 +287,15 @@ mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const m
 
   PcgDev init{};
   init.tol2 = o->tol * o->tol;
+  init.cf = s->plan.acc32 ? 1 : 0;
+  const bool cf = s->plan.acc32;
+  auto dot = [&](const double* a, const double* b2, const double* c, const double* d) {
+    if (cf)
+      hipLaunchKernelGGL(k_dot_partial<true>, gb, bb, 0, st, a, b2, c, d, N, part);
+    else
+      hipLaunchKernelGGL(k_dot_partial<false>, gb, bb, 0, st, a, b2, c, d, N, part);
+  };
+  const double* none = nullptr;
   MM_HIP(hipMemcpyAsync(dev, &init, sizeof(PcgDev), hipMemcpyHostToDevice, st));
   // r = b - A x0  (or b), x0 = 0 unless use_x0
   if (o->use_x0) {
@@ -266,12 +315,11 @@ mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const m
   hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, z, b, 1.0, static_cast<const double*>(nullptr), 0.0, N);
   hipLaunchKernelGGL(k_mask_vec, dim3((s->npix + 255) / 256), bb, 0, st, z,
                      s->at<int32_t>(L.mask), s->npix, s->nc);
-  hipLaunchKernelGGL(k_dot_partial, gb, bb, 0, st, z, z, r, r, N, part);
+  dot(z, z, r, r);
   hipLaunchKernelGGL(k_fin_init, dim3(1), bb, 0, st, part, nb, dev, hist);
   if ((rc = apply_precon(s, precon, r, z, st)) != MM_OK) return rc;
   hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, p, z, 1.0, static_cast<const double*>(nullptr), 0.0, N);
-  hipLaunchKernelGGL(k_dot_partial, gb, bb, 0, st, r, z, static_cast<const double*>(nullptr),
-                     static_cast<const double*>(nullptr), N, part);
+  dot(r, z, none, none);
   hipLaunchKernelGGL(k_fin_rho0, dim3(1), bb, 0, st, part, nb, dev);
   MM_HIP(hipGetLastError());
   const int maxiter = o->maxiter;
@@ -283,14 +331,15 @@ mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const m
   while (it < maxiter) {
     // s = A p
     if ((rc = filter_pipeline(s, 0, nullptr, p, sv, st)) != MM_OK) return rc;
-    hipLaunchKernelGGL(k_dot_partial, gb, bb, 0, st, p, sv, static_cast<const double*>(nullptr),
-                       static_cast<const double*>(nullptr), N, part);
+    dot(p, sv, none, none);
     hipLaunchKernelGGL(k_fin_ps, dim3(1), bb, 0, st, part, nb, dev);
-    hipLaunchKernelGGL(k_update_xr, gb, bb, 0, st, x, r, p, sv, N, dev, part);
+    if (cf)
+      hipLaunchKernelGGL(k_update_xr<true>, gb, bb, 0, st, x, r, p, sv, N, dev, part);
+    else
+      hipLaunchKernelGGL(k_update_xr<false>, gb, bb, 0, st, x, r, p, sv, N, dev, part);
     hipLaunchKernelGGL(k_fin_rr, dim3(1), bb, 0, st, part, nb, dev, hist, kHistCap);
     if ((rc = apply_precon(s, precon, r, z, st)) != MM_OK) return rc;
-    hipLaunchKernelGGL(k_dot_partial, gb, bb, 0, st, r, z, static_cast<const double*>(nullptr),
-                       static_cast<const double*>(nullptr), N, part);
+    dot(r, z, none, none);
     hipLaunchKernelGGL(k_fin_rz, dim3(1), bb, 0, st, part, nb, dev);
     hipLaunchKernelGGL(k_update_p, gb, bb, 0, st, p, z, N, dev);
     MM_HIP(hipGetLastError());

@@ -69,9 +69,27 @@ def test_pixel_index_workspace(mm):
     assert 4 * S <= b1 - a1 <= 4 * S + 2 * 4 * (64 * 64 + 1) + 3 * 256
 
 
+def test_bf16_pass_buffer_is_half_of_f32(mm):
+    # bfloat16 storage: 4 B per packed complex in the pass buffer instead of 8
+    a = mm.mm_scan_workspace_bytes(_desc(mm, det_group=4, scatter=mm.MM_SCATTER_ATOMIC))
+    b = mm.mm_scan_workspace_bytes(_desc(mm, det_group=4, scatter=mm.MM_SCATTER_ATOMIC,
+                                         tod_dtype=mm.MM_BF16))
+    assert a - b == 4 * (1 << 15) * 4
+
+
+def test_compensated_accumulation_takes_the_gather_on_one_kernel_plans(mm):
+    # nsamp = 2^12 is a one-kernel plan: the gather index (12 B/sample) and a
+    # pass buffer appear only under MM_ACC_F32X2
+    a = mm.mm_scan_workspace_bytes(_desc(mm, nsamp=1 << 12))
+    b = mm.mm_scan_workspace_bytes(_desc(mm, nsamp=1 << 12, acc=mm.MM_ACC_F32X2))
+    S = 4 * (1 << 12)
+    assert 12 * S + 4 * S <= b - a <= 16 * S + 2 * 4 * (64 * 64 + 1) + 4 * 256
+
+
 @pytest.mark.parametrize("field,value", [
     ("ncomp", 2), ("ny", 48), ("nx", 2), ("ndet", 0), ("nsamp", 1000), ("nsamp", 8),
     ("nsamp", 1 << 23), ("tod_dtype", 7), ("fft_m1", 3), ("det_group", -1), ("scatter", 5),
+    ("acc", 2),
 ])
 def test_invalid_descriptions_rejected(mm, field, value):
     d = _desc(mm, **{field: value})
@@ -80,6 +98,12 @@ def test_invalid_descriptions_rejected(mm, field, value):
     h = C.c_void_p()
     st = mm.lib.mm_create_scan(C.byref(d), None, C.byref(h))
     assert st == mm.MM_EINVAL and not h.value
+
+
+def test_compensated_accumulation_needs_the_gather(mm):
+    d = _desc(mm, acc=mm.MM_ACC_F32X2, scatter=mm.MM_SCATTER_ATOMIC)
+    assert mm.mm_scan_workspace_bytes(d) == 0
+    assert "MM_ACC_F32X2" in mm.mm_last_error()
 
 
 def test_create_requires_pointers_and_workspace(mm):
