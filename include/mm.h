@@ -188,6 +188,10 @@ typedef struct {
   int32_t snap_every;       /* > 0: copy the iterate x_k into snapshots[k/snap_every - 1] */
   int32_t max_snaps;        /*      for k = snap_every, 2 snap_every, ... up to max_snaps */
   double* snapshots;        /* device [max_snaps][ncomp][ny][nx] float64, or NULL */
+  int32_t graph;            /* 1: capture one iteration (A-apply, M, reductions and
+                               updates) into a HIP graph on a private stream
+                               forked from the caller's, and replay it; results
+                               are those of the eager loop */
 } mm_pcg_opts;
 
 typedef struct {
@@ -209,6 +213,21 @@ typedef struct {
 mm_status mm_pcg_solve(mm_scan scan, int32_t precon, const double* b, double* x,
                        const mm_pcg_opts* opts /*[host]*/,
                        mm_pcg_result* res /*[host]*/, void* stream);
+
+/* Independent solves of n scans, e.g. a batch of scans of uneven detector
+ * count, length and map size.  Each run gets its own stream, forked from
+ * `stream` and joined back; every round enqueues opts->check_every
+ * iterations of every unfinished run before the host reads any state, so
+ * the scans overlap on the device.  With opts->graph each run replays its
+ * captured iteration.  No snapshots are taken.  scans: [host] n distinct
+ * handles; b, x: [host] arrays of n device pointers ([ncomp][ny][nx] float64
+ * of the matching scan); res: [host] n results; status: [host] n statuses or
+ * NULL.  Synchronises.  Returns the first error of any run, else MM_ENOCONV
+ * if a run stopped at maxiter, else MM_OK. */
+mm_status mm_pcg_solve_batch(const mm_scan* scans /*[host]*/, int32_t n, int32_t precon,
+                             const double* const* b /*[host]*/, double* const* x /*[host]*/,
+                             const mm_pcg_opts* opts /*[host]*/, mm_pcg_result* res /*[host]*/,
+                             int32_t* status /*[host]*/, void* stream);
 
 /* ---- Learned correction to the circulant preconditioner (not in the paper):
  * M_L r = M_C r + Sigma^-1 H^T H Sigma^-T r, H = C2 o C1 with C1 (ncomp -> 16

@@ -116,6 +116,24 @@ def mm_pcg_solve(h, precon, b, x, opts, stream=None, history_len=0):
     return st, out
 
 
+def mm_pcg_solve_batch(handles, precon, bs, xs, opts, stream=None):
+    """Independent solves of several scans.  Returns (status, [result dict])."""
+    n = len(handles)
+    if not (len(bs) == len(xs) == n) or n < 1:
+        raise ValueError("handles, bs and xs must have the same non-zero length")
+    H = (C.c_void_p * n)(*[C.c_void_p(h.value if isinstance(h, C.c_void_p) else h) for h in handles])
+    B = (C.c_void_p * n)(*[_ptr(b, torch.float64, name="b") for b in bs])
+    X = (C.c_void_p * n)(*[_ptr(x, torch.float64, name="x") for x in xs])
+    res = (mm_pcg_result * n)()
+    sts = (C.c_int32 * n)()
+    st = lib.mm_pcg_solve_batch(H, n, int(precon), B, X, C.byref(opts), res, sts, _stream(stream))
+    if st not in (MM_OK, MM_ENOCONV, MM_EBREAKDOWN):
+        check(st, "mm_pcg_solve_batch")
+    out = [dict(status=int(sts[i]), iters=res[i].iters, converged=bool(res[i].converged),
+                rel_resid=res[i].rel_resid, t_solve_s=res[i].t_solve_s) for i in range(n)]
+    return st, out
+
+
 def mm_get_info(h):
     info = mm_scan_info()
     check(lib.mm_get_info(h, C.byref(info)), "mm_get_info")
@@ -320,10 +338,11 @@ class Scan:
         return z
 
     def pcg(self, name, b, x=None, tol=1e-6, maxiter=5000, check_every=1, x0=False,
-            history=True, snapshots=None, snap_every=0, stream=None):
+            history=True, snapshots=None, snap_every=0, graph=False, stream=None):
         x = self.new_map() if x is None else x
         o = mm_pcg_opts()
         o.tol, o.maxiter, o.check_every, o.use_x0 = float(tol), int(maxiter), int(check_every), int(x0)
+        o.graph = 1 if graph else 0
         if snapshots is not None:
             o.snapshots = _ptr(snapshots, torch.float64, name="snapshots").value
             o.snap_every = int(snap_every)
@@ -394,3 +413,17 @@ class Learned:
             self.close()
         except Exception:
             pass
+
+
+def pcg_batch(scans, name, bs, xs=None, tol=1e-6, maxiter=5000, check_every=8, graph=True,
+              stream=None):
+    """Solve several scans together (mm_pcg_solve_batch); returns the result
+    dicts, each with its solution under "x"."""
+    xs = [sc.new_map() for sc in scans] if xs is None else xs
+    o = mm_pcg_opts()
+    o.tol, o.maxiter, o.check_every = float(tol), int(maxiter), int(check_every)
+    o.graph = 1 if graph else 0
+    _, out = mm_pcg_solve_batch([sc.handle for sc in scans], PRECON[name], bs, xs, o, stream)
+    for r, x in zip(out, xs):
+        r["x"] = x
+    return out

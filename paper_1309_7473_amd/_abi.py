@@ -38,7 +38,7 @@ class mm_precon_opts(C.Structure):
 class mm_pcg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("check_every", C.c_int32),
                 ("use_x0", C.c_int32), ("snap_every", C.c_int32), ("max_snaps", C.c_int32),
-                ("snapshots", C.c_void_p)]
+                ("snapshots", C.c_void_p), ("graph", C.c_int32)]
 
 
 class mm_train_opts(C.Structure):
@@ -80,6 +80,10 @@ SIGNATURES = {
     "mm_apply_precon_circulant": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mm_pcg_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                C.POINTER(mm_pcg_opts), C.POINTER(mm_pcg_result), C.c_void_p]),
+    "mm_pcg_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32,
+                                     C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.POINTER(mm_pcg_opts), C.POINTER(mm_pcg_result),
+                                     C.POINTER(C.c_int32), C.c_void_p]),
     "mm_get_info": (C.c_int, [C.c_void_p, C.POINTER(mm_scan_info)]),
     "mm_get_mask": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mm_learned_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),

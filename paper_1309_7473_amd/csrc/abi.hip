@@ -6,6 +6,8 @@
 #include <new>
 #include <string>
 
+#include <vector>
+
 #include "mm_internal.h"
 
 namespace mm {
@@ -188,9 +190,8 @@ mm_status mm_apply_precon_circulant(mm_scan scan, const double* r, double* z, vo
   return circulant_apply(s, r, z, static_cast<hipStream_t>(stream));
 }
 
-mm_status mm_pcg_solve(mm_scan scan, int32_t precon, const double* b, double* x,
-                       const mm_pcg_opts* opts, mm_pcg_result* res, void* stream) {
-  ScanImpl* s = get(scan);
+static mm_status check_solve(ScanImpl* s, int32_t precon, const double* b, double* x,
+                             const mm_pcg_opts* opts) {
   if (!s) return fail(MM_EINVAL, "invalid scan handle");
   if (!b || !x || !opts) return fail(MM_EINVAL, "b, x and opts are required");
   if (!(opts->tol >= 0.0) || opts->maxiter < 0) return fail(MM_EINVAL, "bad tol or maxiter");
@@ -205,7 +206,35 @@ mm_status mm_pcg_solve(mm_scan scan, int32_t precon, const double* b, double* x,
   const char* ba = reinterpret_cast<const char*>(b);
   const char* xa = reinterpret_cast<const char*>(x);
   if (ba < xa + bytes && xa < ba + bytes) return fail(MM_EINVAL, "b and x overlap");
+  return MM_OK;
+}
+
+mm_status mm_pcg_solve(mm_scan scan, int32_t precon, const double* b, double* x,
+                       const mm_pcg_opts* opts, mm_pcg_result* res, void* stream) {
+  ScanImpl* s = get(scan);
+  const mm_status rc = check_solve(s, precon, b, x, opts);
+  if (rc != MM_OK) return rc;
   return pcg_solve(s, precon, b, x, opts, res, static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_pcg_solve_batch(const mm_scan* scans, int32_t n, int32_t precon,
+                             const double* const* b, double* const* x, const mm_pcg_opts* opts,
+                             mm_pcg_result* res, int32_t* status, void* stream) {
+  if (n < 1 || !scans || !b || !x || !opts) return fail(MM_EINVAL, "scans, b, x, opts and n >= 1 are required");
+  std::vector<ScanImpl*> ss(n);
+  for (int i = 0; i < n; ++i) {
+    ss[i] = get(scans[i]);
+    const mm_status rc = check_solve(ss[i], precon, b[i], x[i], opts);
+    if (rc != MM_OK) return rc;
+    for (int j = 0; j < i; ++j)
+      if (ss[j] == ss[i]) return fail(MM_EINVAL, "a scan appears twice in the batch");
+  }
+  std::vector<mm_status> st(n, MM_OK);
+  const mm_status rc = pcg_solve_batch(ss.data(), n, precon, b, x, opts, res, st.data(),
+                                       static_cast<hipStream_t>(stream));
+  if (status)
+    for (int i = 0; i < n; ++i) status[i] = st[i];
+  return rc;
 }
 
 mm_status mm_get_info(mm_scan scan, mm_scan_info* out) {

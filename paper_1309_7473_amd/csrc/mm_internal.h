@@ -106,6 +106,7 @@ struct ScanImpl {
   int circ_sym = 1;
   int maxdyn_lds = 65536;
   Profiler* prof = nullptr;
+  bool capturing = false;   // launches are being recorded into a graph
   mm_learned learned = nullptr;
 
   template <typename P>
@@ -125,6 +126,9 @@ mm_status circulant_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st);
 mm_status circulant_apply(ScanImpl* s, const double* r, double* z, hipStream_t st);
 mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x,
                     const mm_pcg_opts* o, mm_pcg_result* res, hipStream_t st);
+mm_status pcg_solve_batch(ScanImpl* const* scans, int n, int precon, const double* const* b,
+                          double* const* x, const mm_pcg_opts* o, mm_pcg_result* res,
+                          mm_status* status, hipStream_t st);
 mm_status fill_zero(void* p, size_t bytes, hipStream_t st);
 mm_status apply_precon(ScanImpl* s, int precon, const double* r, double* z, hipStream_t st);
 void prof_begin(ScanImpl* s, hipStream_t st, hipEvent_t* tok);

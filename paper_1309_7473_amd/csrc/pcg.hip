@@ -16,6 +16,7 @@
 // (p.s <= 0, rho <= 0 or a non-finite scalar); after it, updates are no-ops,
 // so the host only needs to look every check_every iterations.
 #include <chrono>
+#include <memory>
 #include <vector>
 
 #include "mm_device.h"
@@ -268,26 +269,90 @@ static mm_status apply_precon_inner(ScanImpl* s, int precon, const double* r, do
   }
 }
 
-mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const mm_pcg_opts* o,
-                    mm_pcg_result* res, hipStream_t st) {
-  const auto t0 = std::chrono::steady_clock::now();
+// ------------------------------------------------------------- host driver
+// One solve in flight.  pcg_start enqueues r0, z0, p0 and rho0 and reads the
+// state back; pcg_iterate enqueues one iteration (eager, or one launch of the
+// captured graph); pcg_poll reads the device scalars; pcg_finish fills the
+// result.  A batch interleaves several runs, each on its own stream.
+struct PcgRun {
+  ScanImpl* s = nullptr;
+  int precon = 0;
+  const double* b = nullptr;
+  double* x = nullptr;
+  mm_pcg_opts o{};
+  mm_pcg_result* res = nullptr;
+  hipStream_t st = nullptr;
+  int it = 0;
+  bool finished = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  PcgDev h{};
+  std::chrono::steady_clock::time_point t0;
+  ~PcgRun() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+// the launches of one iteration (no host synchronisation, no memset/memcpy:
+// safe to capture)
+static mm_status pcg_iteration_launches(ScanImpl* s, int precon, double* x, hipStream_t st) {
   const Layout& L = s->lay;
   const int64_t N = int64_t(s->nc) * s->npix;
   double* vec = s->at<double>(L.vec);
-  double* r = vec;
-  double* z = vec + N;
-  double* p = vec + 2 * N;
-  double* sv = vec + 3 * N;
+  double *r = vec, *z = vec + N, *p = vec + 2 * N, *sv = vec + 3 * N;
   double* part = s->at<double>(L.partials);
   PcgDev* dev = s->at<PcgDev>(L.pcg);
   double* hist = s->at<double>(L.hist);
   const int nb = red_blocks(N);
   const dim3 gb(nb), bb(256);
+  const bool cf = s->plan.acc32;
+  const double* none = nullptr;
+  auto dot = [&](const double* a, const double* b2) {
+    if (cf)
+      hipLaunchKernelGGL(k_dot_partial<true>, gb, bb, 0, st, a, b2, none, none, N, part);
+    else
+      hipLaunchKernelGGL(k_dot_partial<false>, gb, bb, 0, st, a, b2, none, none, N, part);
+  };
   mm_status rc;
+  // s = A p
+  if ((rc = filter_pipeline(s, 0, nullptr, p, sv, st)) != MM_OK) return rc;
+  dot(p, sv);
+  hipLaunchKernelGGL(k_fin_ps, dim3(1), bb, 0, st, part, nb, dev);
+  if (cf)
+    hipLaunchKernelGGL(k_update_xr<true>, gb, bb, 0, st, x, r, p, sv, N, dev, part);
+  else
+    hipLaunchKernelGGL(k_update_xr<false>, gb, bb, 0, st, x, r, p, sv, N, dev, part);
+  hipLaunchKernelGGL(k_fin_rr, dim3(1), bb, 0, st, part, nb, dev, hist, kHistCap);
+  if ((rc = apply_precon(s, precon, r, z, st)) != MM_OK) return rc;
+  dot(r, z);
+  hipLaunchKernelGGL(k_fin_rz, dim3(1), bb, 0, st, part, nb, dev);
+  hipLaunchKernelGGL(k_update_p, gb, bb, 0, st, p, z, N, dev);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
 
-  PcgDev init{};
-  init.tol2 = o->tol * o->tol;
-  init.cf = s->plan.acc32 ? 1 : 0;
+static mm_status pcg_poll(PcgRun& R) {
+  MM_HIP(hipMemcpyAsync(&R.h, R.s->at<PcgDev>(R.s->lay.pcg), sizeof(PcgDev),
+                        hipMemcpyDeviceToHost, R.st));
+  MM_HIP(hipStreamSynchronize(R.st));
+  return MM_OK;
+}
+
+static mm_status pcg_start(PcgRun& R) {
+  R.t0 = std::chrono::steady_clock::now();
+  ScanImpl* s = R.s;
+  hipStream_t st = R.st;
+  const Layout& L = s->lay;
+  const int64_t N = int64_t(s->nc) * s->npix;
+  double* vec = s->at<double>(L.vec);
+  double *r = vec, *z = vec + N, *p = vec + 2 * N, *sv = vec + 3 * N;
+  double* part = s->at<double>(L.partials);
+  PcgDev* dev = s->at<PcgDev>(L.pcg);
+  double* hist = s->at<double>(L.hist);
+  const int nb = red_blocks(N);
+  const dim3 gb(nb), bb(256);
+  const double* none = nullptr;
   const bool cf = s->plan.acc32;
   auto dot = [&](const double* a, const double* b2, const double* c, const double* d) {
     if (cf)
@@ -295,78 +360,87 @@ mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const m
     else
       hipLaunchKernelGGL(k_dot_partial<false>, gb, bb, 0, st, a, b2, c, d, N, part);
   };
-  const double* none = nullptr;
+  mm_status rc;
+  PcgDev init{};
+  init.tol2 = R.o.tol * R.o.tol;
+  init.cf = cf ? 1 : 0;
   MM_HIP(hipMemcpyAsync(dev, &init, sizeof(PcgDev), hipMemcpyHostToDevice, st));
   // r = b - A x0  (or b), x0 = 0 unless use_x0
-  if (o->use_x0) {
-    hipLaunchKernelGGL(k_mask_vec, dim3((s->npix + 255) / 256), bb, 0, st, x,
+  if (R.o.use_x0) {
+    hipLaunchKernelGGL(k_mask_vec, dim3((s->npix + 255) / 256), bb, 0, st, R.x,
                        s->at<int32_t>(L.mask), s->npix, s->nc);
-    if ((rc = filter_pipeline(s, 0, nullptr, x, sv, st)) != MM_OK) return rc;
-    hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, r, b, 1.0, sv, -1.0, N);
+    if ((rc = filter_pipeline(s, 0, nullptr, R.x, sv, st)) != MM_OK) return rc;
+    hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, r, R.b, 1.0, sv, -1.0, N);
   } else {
-    hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, r, b, 1.0, static_cast<const double*>(nullptr), 0.0, N);
-    hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, x, b, 0.0, static_cast<const double*>(nullptr), 0.0, N);
+    hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, r, R.b, 1.0, none, 0.0, N);
+    hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, R.x, R.b, 0.0, none, 0.0, N);
   }
   // inactive entries of b are ignored: r (and with it every later vector) is masked
   hipLaunchKernelGGL(k_mask_vec, dim3((s->npix + 255) / 256), bb, 0, st, r,
                      s->at<int32_t>(L.mask), s->npix, s->nc);
   MM_HIP(hipGetLastError());
   // ||b|| over the active entries (z is free until the first M r)
-  hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, z, b, 1.0, static_cast<const double*>(nullptr), 0.0, N);
+  hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, z, R.b, 1.0, none, 0.0, N);
   hipLaunchKernelGGL(k_mask_vec, dim3((s->npix + 255) / 256), bb, 0, st, z,
                      s->at<int32_t>(L.mask), s->npix, s->nc);
   dot(z, z, r, r);
   hipLaunchKernelGGL(k_fin_init, dim3(1), bb, 0, st, part, nb, dev, hist);
-  if ((rc = apply_precon(s, precon, r, z, st)) != MM_OK) return rc;
-  hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, p, z, 1.0, static_cast<const double*>(nullptr), 0.0, N);
+  if ((rc = apply_precon(s, R.precon, r, z, st)) != MM_OK) return rc;
+  hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, p, z, 1.0, none, 0.0, N);
   dot(r, z, none, none);
   hipLaunchKernelGGL(k_fin_rho0, dim3(1), bb, 0, st, part, nb, dev);
   MM_HIP(hipGetLastError());
-  const int maxiter = o->maxiter;
-  const int every = o->check_every > 0 ? o->check_every : 1;
-  PcgDev h{};
-  MM_HIP(hipMemcpyAsync(&h, dev, sizeof(PcgDev), hipMemcpyDeviceToHost, st));
-  MM_HIP(hipStreamSynchronize(st));
-  int it = h.done ? maxiter : 0;
-  while (it < maxiter) {
-    // s = A p
-    if ((rc = filter_pipeline(s, 0, nullptr, p, sv, st)) != MM_OK) return rc;
-    dot(p, sv, none, none);
-    hipLaunchKernelGGL(k_fin_ps, dim3(1), bb, 0, st, part, nb, dev);
-    if (cf)
-      hipLaunchKernelGGL(k_update_xr<true>, gb, bb, 0, st, x, r, p, sv, N, dev, part);
-    else
-      hipLaunchKernelGGL(k_update_xr<false>, gb, bb, 0, st, x, r, p, sv, N, dev, part);
-    hipLaunchKernelGGL(k_fin_rr, dim3(1), bb, 0, st, part, nb, dev, hist, kHistCap);
-    if ((rc = apply_precon(s, precon, r, z, st)) != MM_OK) return rc;
-    dot(r, z, none, none);
-    hipLaunchKernelGGL(k_fin_rz, dim3(1), bb, 0, st, part, nb, dev);
-    hipLaunchKernelGGL(k_update_p, gb, bb, 0, st, p, z, N, dev);
-    MM_HIP(hipGetLastError());
-    ++it;
-    if (o->snapshots && o->snap_every > 0 && it % o->snap_every == 0 &&
-        it / o->snap_every <= o->max_snaps)
-      MM_HIP(hipMemcpyAsync(o->snapshots + int64_t(it / o->snap_every - 1) * N, x, N * 8,
-                            hipMemcpyDeviceToDevice, st));
-    if (it % every == 0 || it == maxiter) {
-      MM_HIP(hipMemcpyAsync(&h, dev, sizeof(PcgDev), hipMemcpyDeviceToHost, st));
-      MM_HIP(hipStreamSynchronize(st));
-      if (h.done) break;
-    }
+  if ((rc = pcg_poll(R)) != MM_OK) return rc;
+  R.it = R.h.done ? R.o.maxiter : 0;
+  if (R.o.graph && R.it < R.o.maxiter) {
+    // capture one iteration; every later iteration is one graph launch
+    s->capturing = true;
+    MM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    rc = pcg_iteration_launches(s, R.precon, R.x, st);
+    const hipError_t ec = hipStreamEndCapture(st, &R.graph);
+    s->capturing = false;
+    if (rc != MM_OK) return rc;
+    MM_HIP(ec);
+    MM_HIP(hipGraphInstantiateWithFlags(&R.exec, R.graph, 0));
   }
-  MM_HIP(hipMemcpyAsync(&h, dev, sizeof(PcgDev), hipMemcpyDeviceToHost, st));
-  MM_HIP(hipStreamSynchronize(st));
+  return MM_OK;
+}
+
+// enqueue one iteration (and the snapshot copy after it, if asked for)
+static mm_status pcg_iterate(PcgRun& R) {
+  if (R.exec) {
+    MM_HIP(hipGraphLaunch(R.exec, R.st));
+  } else {
+    const mm_status rc = pcg_iteration_launches(R.s, R.precon, R.x, R.st);
+    if (rc != MM_OK) return rc;
+  }
+  ++R.it;
+  const mm_pcg_opts& o = R.o;
+  if (o.snapshots && o.snap_every > 0 && R.it % o.snap_every == 0 && R.it / o.snap_every <= o.max_snaps) {
+    const int64_t N = int64_t(R.s->nc) * R.s->npix;
+    MM_HIP(hipMemcpyAsync(o.snapshots + int64_t(R.it / o.snap_every - 1) * N, R.x, N * 8,
+                          hipMemcpyDeviceToDevice, R.st));
+  }
+  return MM_OK;
+}
+
+static mm_status pcg_finish(PcgRun& R) {
+  mm_status rc;
+  if ((rc = pcg_poll(R)) != MM_OK) return rc;
+  R.finished = true;
+  const PcgDev& h = R.h;
   const int iters = h.iters;
   const int nh = iters < kHistCap ? iters : kHistCap;
   std::vector<double> hh(size_t(3) * (kHistCap + 1));
-  MM_HIP(hipMemcpy(hh.data(), hist, hh.size() * 8, hipMemcpyDeviceToHost));
+  MM_HIP(hipMemcpy(hh.data(), R.s->at<double>(R.s->lay.hist), hh.size() * 8, hipMemcpyDeviceToHost));
   const bool converged = h.done && !h.breakdown;
-  if (res) {
+  if (R.res) {
+    mm_pcg_result* res = R.res;
     res->iters = iters;
     res->converged = converged ? 1 : 0;
     res->rel_resid = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
     if (iters == 0) res->rel_resid = h.bb > 0 ? hh[0] : 0.0;
-    res->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    res->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - R.t0).count();
     if (res->history)
       for (int k = 0; k <= nh; ++k) res->history[k] = hh[k];
     if (res->alpha)
@@ -380,6 +454,116 @@ mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const m
     return MM_ENOCONV;
   }
   return MM_OK;
+}
+
+// run on a private stream forked from / joined to the caller's (a captured
+// stream must not be the null stream)
+struct ForkedStream {
+  hipStream_t caller, st = nullptr;
+  hipEvent_t ev = nullptr;
+  explicit ForkedStream(hipStream_t c) : caller(c) {}
+  mm_status open() {
+    MM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    MM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    MM_HIP(hipEventRecord(ev, caller));
+    MM_HIP(hipStreamWaitEvent(st, ev, 0));
+    return MM_OK;
+  }
+  mm_status join() {
+    MM_HIP(hipEventRecord(ev, st));
+    MM_HIP(hipStreamWaitEvent(caller, ev, 0));
+    return MM_OK;
+  }
+  ~ForkedStream() {
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
+mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const mm_pcg_opts* o,
+                    mm_pcg_result* res, hipStream_t st) {
+  ForkedStream fs(st);
+  PcgRun R;
+  R.s = s;
+  R.precon = precon;
+  R.b = b;
+  R.x = x;
+  R.o = *o;
+  R.res = res;
+  R.st = st;
+  mm_status rc;
+  if (o->graph) {
+    if ((rc = fs.open()) != MM_OK) return rc;
+    R.st = fs.st;
+  }
+  if ((rc = pcg_start(R)) != MM_OK) return rc;
+  const int every = o->check_every > 0 ? o->check_every : 1;
+  while (R.it < o->maxiter) {
+    if ((rc = pcg_iterate(R)) != MM_OK) return rc;
+    if (R.it % every == 0 || R.it == o->maxiter) {
+      if ((rc = pcg_poll(R)) != MM_OK) return rc;
+      if (R.h.done) break;
+    }
+  }
+  rc = pcg_finish(R);
+  if (o->graph) {
+    const mm_status rj = fs.join();
+    if (rj != MM_OK) return rj;
+  }
+  return rc;
+}
+
+// Independent solves interleaved: each run gets its own stream (forked from
+// the caller's), every round enqueues check_every iterations of every
+// unfinished run before any host read, so small scans overlap on the device.
+mm_status pcg_solve_batch(ScanImpl* const* scans, int n, int precon, const double* const* b,
+                          double* const* x, const mm_pcg_opts* o, mm_pcg_result* res,
+                          mm_status* status, hipStream_t st) {
+  std::vector<std::unique_ptr<ForkedStream>> fs;
+  std::vector<PcgRun> R(n);
+  mm_status rc;
+  for (int i = 0; i < n; ++i) {
+    fs.emplace_back(new ForkedStream(st));
+    if ((rc = fs.back()->open()) != MM_OK) return rc;
+    R[i].s = scans[i];
+    R[i].precon = precon;
+    R[i].b = b[i];
+    R[i].x = x[i];
+    R[i].o = *o;
+    R[i].o.snapshots = nullptr;
+    R[i].o.snap_every = 0;
+    R[i].res = res ? &res[i] : nullptr;
+    R[i].st = fs.back()->st;
+  }
+  for (int i = 0; i < n; ++i)
+    if ((rc = pcg_start(R[i])) != MM_OK) return rc;
+  const int every = o->check_every > 0 ? o->check_every : 1;
+  for (;;) {
+    bool any = false;
+    for (int i = 0; i < n; ++i) {
+      PcgRun& r = R[i];
+      if (r.finished || r.h.done || r.it >= o->maxiter) continue;
+      any = true;
+      for (int k = 0; k < every && r.it < o->maxiter; ++k)
+        if ((rc = pcg_iterate(r)) != MM_OK) return rc;
+    }
+    if (!any) break;
+    for (int i = 0; i < n; ++i)
+      if (!R[i].h.done && (rc = pcg_poll(R[i])) != MM_OK) return rc;
+  }
+  // first error of any run, else MM_ENOCONV if one did not converge
+  mm_status worst = MM_OK;
+  for (int i = 0; i < n; ++i) {
+    const mm_status ri = pcg_finish(R[i]);
+    if (status) status[i] = ri;
+    if (ri < 0 && worst >= 0) worst = ri;
+    if (ri == MM_ENOCONV && worst == MM_OK) worst = MM_ENOCONV;
+    if ((rc = fs[i]->join()) != MM_OK) return rc;
+  }
+  return worst;
 }
 
 }  // namespace mm

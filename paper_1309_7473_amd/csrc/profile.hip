@@ -47,7 +47,7 @@ struct Profiler {
 
 void prof_begin(ScanImpl* s, hipStream_t st, hipEvent_t* tok) {
   *tok = nullptr;
-  if (!s->prof) return;
+  if (!s->prof || s->capturing) return;   // no timing inside a captured graph
   if (s->prof->used > 32768) s->prof->flush();
   hipEvent_t e = s->prof->take();
   if (e && hipEventRecord(e, st) == hipSuccess) *tok = e;

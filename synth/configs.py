@@ -10,6 +10,10 @@ Workloads (sizes as in the project's benchmark definitions):
    +-10 deg in total, psi_d ~ U[0, pi), sigma_d log-normal with 10 % scatter,
    f_knee,d ~ U(0.5, 3) Hz, index -3;
 3. the pattern of 2 at 1024 detectors x 2^21 samples on a 1024 x 1024 map;
+4. a batch of 64 independent scans: per scan ndet ~ U{32..512}, nsamp =
+   2^U{16..21}, square L x L maps with L = 2^U{7..10}, 4 samples per pixel
+   along a sweep (so the row advance per sweep is 4 L^2 / nsamp), a hex focal
+   plane max(60 px, twice the row advance) across, noise as in 2;
 5. the shape of 2 (scan ids 0..7 train, 1000.. held out).
 
 `make_config(cid, scan_id, **overrides)` draws one scan; overrides shrink a
@@ -36,7 +40,20 @@ CONFIG_DEFS = {
 }
 
 
+def config4_spec(scan_id):
+    """Shape of scan `scan_id` (0..63) of the batched workload 4."""
+    import numpy as np
+    rng = np.random.default_rng(np.random.SeedSequence([4, 0, int(scan_id)]))
+    ndet = int(rng.integers(32, 513))
+    nsamp = 2 ** int(rng.integers(16, 22))
+    side = 2 ** int(rng.integers(7, 11))
+    advance = 4.0 * side * side / nsamp
+    return dict(ncomp=3, ndet=ndet, nsamp=nsamp, fsample=400.0, ny=side, nx=side,
+                layout="hex", hex_diameter_px=max(60.0, 2.0 * advance), sigma=1.0,
+                sigma_scatter=0.1, fknee=(0.5, 3.0), alpha=-3.0, drift_deg=10.0)
+
+
 def make_config(cid, scan_id=0, **overrides):
-    spec = dict(CONFIG_DEFS[cid])
+    spec = config4_spec(scan_id) if cid == 4 else dict(CONFIG_DEFS[cid])
     spec.update(overrides)
     return raster_scan(seed=(cid, scan_id), **spec)

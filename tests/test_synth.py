@@ -67,3 +67,16 @@ def test_crosslinked_torus_geometry():
     assert s.ndet == 24
     h = np.bincount(s.pix.ravel(), minlength=64)
     assert np.all(h == h[0])
+
+
+def test_config4_recipe_is_seeded_and_in_range():
+    from synth.configs import config4_spec
+    specs = [config4_spec(i) for i in range(64)]
+    assert specs == [config4_spec(i) for i in range(64)]
+    for sp in specs:
+        assert 32 <= sp["ndet"] <= 512
+        assert 2**16 <= sp["nsamp"] <= 2**21 and sp["nsamp"] & (sp["nsamp"] - 1) == 0
+        assert sp["ny"] == sp["nx"] and 128 <= sp["ny"] <= 1024
+        assert sp["hex_diameter_px"] == max(60.0, 8.0 * sp["ny"] ** 2 / sp["nsamp"])
+    # uneven: several lengths, detector counts and map sizes
+    assert len({sp["nsamp"] for sp in specs}) >= 4 and len({sp["ny"] for sp in specs}) >= 3
