@@ -5,8 +5,8 @@ Workload: the 256-detector I,Q,U raster scan (2^20 samples per detector at
 400 Hz, 512 x 512 map, hexagonal focal plane, scan-angle drift, white + 1/f
 noise), float32 timestreams, float64 maps and CG scalars.  A step is one PCG
 iteration with the circulant preconditioner: the A-apply (gather, per-detector
-real FFT, 1/N(f), inverse FFT, atomic scatter), the preconditioner apply and
-the CG reductions/updates.  The right-hand side is b = A m_sky (a noiseless
+real FFT, 1/N(f), inverse FFT, per-pixel gather of P^T), the preconditioner
+apply and the CG reductions/updates.  The right-hand side is b = A m_sky (a noiseless
 timestream, as in the paper's test), computed on the GPU.
 
 Prints one JSON line: throughput in timestream samples per second of PCG
@@ -52,7 +52,7 @@ def kernel_source_hash():
 def load_traffic(kernel, src_hash):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
     were taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_config2.json")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_iqu256.json")
     try:
         with open(path) as f:
             d = json.load(f)
@@ -123,9 +123,9 @@ def summarize(trace_dir, fetch_dir, write_dir, bench_log, out_dir):
                "calibration": f"plain device copy of {COPY_BYTES} bytes read + written",
                "kernels": kern}
     os.makedirs(out_dir, exist_ok=True)
-    with open(os.path.join(out_dir, "hbm_traffic_config2.json"), "w") as fh:
+    with open(os.path.join(out_dir, "hbm_traffic_iqu256.json"), "w") as fh:
         json.dump(traffic, fh, indent=1)
-    lines = ["# Kernel times, config-2 PCG iterations (rocprofv3 --kernel-trace --stats)", "",
+    lines = ["# Kernel times, iqu_256det PCG iterations (rocprofv3 --kernel-trace --stats)", "",
              "Command (repo root, GPU box):", "",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- "
              "python3 bench.py --steps 10 --warmup 2 --no-solve --no-cpu", "",
@@ -144,7 +144,7 @@ def summarize(trace_dir, fetch_dir, write_dir, bench_log, out_dir):
                      f"{v['write_bytes_per_launch']/1e6:.1f} |")
     lines += ["", "Bench line of the traced run: " + json.dumps(
         {k: bench[k] for k in ("value", "ms_per_step", "roofline", "apply_A")})]
-    with open(os.path.join(out_dir, "config2_pcg_kernels.md"), "w") as fh:
+    with open(os.path.join(out_dir, "pcg_kernels_iqu256.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("wrote", out_dir)
 
@@ -236,10 +236,10 @@ def main():
     import numpy as np
     import torch
     import paper_1309_7473_amd as mm
-    from synth import make_config
+    from synth import make_workload
 
     t0 = time.time()
-    inp = make_config(2, ndet=args.ndet)
+    inp = make_workload("iqu_256det", ndet=args.ndet)
     t_gen = time.time() - t0
     S = inp.ndet * inp.nsamp
     scan = mm.Scan(inp, tod_dtype="f32", det_group=args.det_group, fft_m1=args.fft_m1)
@@ -324,7 +324,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "config2: I,Q,U raster, 256 detectors x 2^20 samples @400 Hz, "
+        "config": {"workload": "iqu_256det: I,Q,U raster, 256 detectors x 2^20 samples @400 Hz, "
                                "512x512 map, hex focal plane 60 px, drift <=10 deg, white+1/f noise",
                    "step": "one PCG iteration, circulant preconditioner (A-apply + M_C + CG updates)",
                    "samples_per_step": S, "accumulate": "f64", "taper_px": args.taper,

@@ -17,4 +17,4 @@ from .scan import (  # noqa: F401
 )
 from .noise import noise_spectrum, inverse_spectrum, draw_noise  # noqa: F401
 from .sky import grf_sky  # noqa: F401
-from .configs import make_config, CONFIG_DEFS  # noqa: F401
+from .workloads import make_workload, WORKLOADS, batch_scan_spec  # noqa: F401

@@ -14,7 +14,7 @@ import pytest
 import oracle
 from conftest import small_raster
 from gpu_common import Pair, rel, need_gpu
-from synth import make_config, raster_scan
+from synth import make_workload, raster_scan
 
 pytestmark = pytest.mark.gpu
 
@@ -87,12 +87,12 @@ def make_sky(nc, ny, nx):
     return grf_sky(nc, ny, nx, np.random.default_rng(5))
 
 
-def test_config1_full_size_f64():
-    inp = make_config(1)
+def test_intensity_small_full_size_f64():
+    inp = make_workload("intensity_small")
     pair = Pair(inp, tod_dtype="f64")
     assert pair.g.info()["single_pass"] == 1
     assert pair.g.info()["n_active"] == int(pair.mask.sum())
-    _check_apply(pair, TOL64, label="config1")
+    _check_apply(pair, TOL64, label="intensity_small")
     sky = (inp.sky * pair.mask.reshape(1, 64, 64)).ravel()
     assert rel(pair.A_gpu(sky), pair.A_oracle(sky)) <= TOL64
 
@@ -175,16 +175,16 @@ def test_invalid_pixel_rejected():
     assert ei.value.status == mm.MM_EINVAL
 
 
-def test_config2_shape_detector_subset():
+def test_iqu256_detector_subset():
     """Config 2's recipe and the benchmark's launch geometry (n = 2^20,
     512 x 512, 16 detectors per group, four-step 512 x 1024) on a 16-detector
     draw, small enough for the oracle."""
-    inp = make_config(2, ndet=16)
+    inp = make_workload("iqu_256det", ndet=16)
     pair = Pair(inp, tod_dtype="f32")
     info = pair.g.info()
     assert (info["fft_m1"], info["fft_m2"], info["fft_cols"], info["det_group"]) == (512, 1024, 16, 16)
-    _check_apply(pair, TOL32_WHITE, label="config2-subset")
+    _check_apply(pair, TOL32_WHITE, label="iqu256-subset")
     sky = (inp.sky * pair.mask.reshape(1, 512, 512)).ravel()
     e = rel(pair.A_gpu(sky), pair.A_oracle(sky))
-    print(f"[config2 subset] sky rel err = {e:.3e}", flush=True)
+    print(f"[iqu256 subset] sky rel err = {e:.3e}", flush=True)
     assert e <= TOL32_SKY

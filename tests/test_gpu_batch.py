@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from gpu_common import Pair, rel
-from synth import make_config, raster_scan
+from synth import batch_scan_spec, make_workload, raster_scan
 
 pytestmark = pytest.mark.gpu
 
@@ -109,16 +109,15 @@ def test_batch_reports_each_status_and_rejects_duplicates():
         mm.pcg_batch([pairs[0].g, pairs[0].g], "binned", [bs[0], bs[0]])
 
 
-def test_batch_of_config4_shaped_scans():
+def test_batch_of_batch64_shaped_scans():
     # four scans of the batched workload's recipe, shrunk so the oracle can
     # check each answer: detectors / 16, samples / 16, map side / 4 (the
     # samples per pixel and the row advance per sweep stay as drawn)
     import paper_1309_7473_amd as mm
-    from synth.configs import config4_spec
     pairs = []
     for sid in range(4):
-        sp = config4_spec(sid)
-        inp = make_config(4, sid, ndet=max(4, sp["ndet"] // 16), nsamp=sp["nsamp"] // 16,
+        sp = batch_scan_spec(sid)
+        inp = make_workload("batch_64scans", sid, ndet=max(4, sp["ndet"] // 16), nsamp=sp["nsamp"] // 16,
                           ny=sp["ny"] // 4, nx=sp["nx"] // 4,
                           hex_diameter_px=sp["hex_diameter_px"] / 4)
         pairs.append(Pair(inp, tod_dtype="f32"))
@@ -131,6 +130,6 @@ def test_batch_of_config4_shaped_scans():
     for p, b, r in zip(pairs, bs, out):
         x = p.host(r["x"])
         t = rel(p.A_oracle(x), p.host(b))
-        print(f"[config4 batch] {p.inp.ndet} det x {p.inp.nsamp} on {p.inp.ny}^2: "
+        print(f"[batch_64scans] {p.inp.ndet} det x {p.inp.nsamp} on {p.inp.ny}^2: "
               f"iters {r['iters']} true resid {t:.2e}", flush=True)
         assert r["converged"] and t <= 2e-6

@@ -14,7 +14,7 @@ import oracle
 from oracle import learned as L
 from conftest import small_raster
 from gpu_common import Pair, rel, need_gpu
-from synth import make_config
+from synth import make_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -176,7 +176,7 @@ def test_training_lowers_loss_and_reports_iterations():
     per = 3 * ny * nx
     rws, ts, e2s = [], [], []
     for sid in (0, 1):
-        inp = make_config(5, sid, **kw)
+        inp = make_workload("iqu_256det_learned", sid, **kw)
         pair = Pair(inp, tod_dtype="f32")
         pair.g.build_precon("circulant", sigma=5.0)
         b = pair.dev(pair.A_oracle((inp.sky.reshape(3, -1) * pair.mask).ravel()))
@@ -198,7 +198,7 @@ def test_training_lowers_loss_and_reports_iterations():
     l1 = lrn.loss(RW, T, E2)
     print(f"[train] loss {l0:.4f} -> {l1:.4f}; epochs {np.round(hist, 4)}", flush=True)
     assert l1 < l0
-    held = make_config(5, 1000, **kw)
+    held = make_workload("iqu_256det_learned", 1000, **kw)
     pair = Pair(held, tod_dtype="f32")
     pair.g.build_precon("circulant", sigma=5.0)
     pair.g.attach_learned(lrn)

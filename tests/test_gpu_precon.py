@@ -15,7 +15,7 @@ import pytest
 import oracle
 from conftest import small_raster
 from gpu_common import Pair, rel
-from synth import make_config, crosslinked_torus_scan
+from synth import make_workload, crosslinked_torus_scan
 
 pytestmark = pytest.mark.gpu
 
@@ -106,9 +106,9 @@ def _true_resid(pair, x, b):
 
 
 @pytest.mark.parametrize("precon", ["binned", "jacobi", "circulant", "none"])
-def test_pcg_config1_matches_oracle(precon):
+def test_pcg_intensity_small_matches_oracle(precon):
     """Config 1 (I, 8 x 2^14, 64 x 64, plain FP64) solved to 1e-6."""
-    inp = make_config(1)
+    inp = make_workload("intensity_small")
     pair = Pair(inp, tod_dtype="f64")
     o = pair.o
     rng = np.random.default_rng(11)
@@ -131,7 +131,7 @@ def test_pcg_config1_matches_oracle(precon):
     rg = pair.g.pcg(precon, pair.dev(b), tol=1e-6, maxiter=3000)
     x = pair.host(rg["x"])
     tr = _true_resid(pair, x, b)
-    print(f"[pcg config1 {precon}] oracle iters={ro.iters} gpu iters={rg['iters']} "
+    print(f"[pcg intensity_small {precon}] oracle iters={ro.iters} gpu iters={rg['iters']} "
           f"true resid={tr:.2e}", flush=True)
     assert ro.converged and rg["converged"]
     assert abs(rg["iters"] - ro.iters) <= max(1, 0.05 * ro.iters)
@@ -141,10 +141,10 @@ def test_pcg_config1_matches_oracle(precon):
     np.testing.assert_allclose(rg["history"][:k], ro.history[:k], rtol=1e-6)
 
 
-def test_pcg_config2_shape_f32_true_residual():
+def test_pcg_iqu256_shape_f32_true_residual():
     """Config 2's recipe at a reduced size with the float32 timestream path:
     circulant and binned PCG to 1e-6; true residual under the oracle's FP64 A."""
-    inp = make_config(2, ndet=12, nsamp=2**15, ny=64, nx=64, hex_diameter_px=8.0)
+    inp = make_workload("iqu_256det", ndet=12, nsamp=2**15, ny=64, nx=64, hex_diameter_px=8.0)
     pair = Pair(inp, tod_dtype="f32")
     o = pair.o
     m = inp.sky * pair.mask.reshape(1, 64, 64)
@@ -155,13 +155,13 @@ def test_pcg_config2_shape_f32_true_residual():
         rg = pair.g.pcg(name, pair.dev(b), tol=1e-6, maxiter=4000)
         tr = _true_resid(pair, pair.host(rg["x"]), b)
         out[name] = (rg["iters"], tr)
-        print(f"[pcg config2-small f32 {name}] iters={rg['iters']} rel={rg['rel_resid']:.2e} "
+        print(f"[pcg iqu256-small f32 {name}] iters={rg['iters']} rel={rg['rel_resid']:.2e} "
               f"true={tr:.2e}", flush=True)
         assert rg["converged"]
         assert tr <= 1e-5
     Mo = oracle.CirculantPrecon(o, pair.mask, pair.B, sigma_taper=10.0)
     ro = oracle.pcg(pair.A_oracle, Mo, b, tol=1e-6, maxiter=4000)
-    print(f"[pcg config2-small oracle circulant] iters={ro.iters}", flush=True)
+    print(f"[pcg iqu256-small oracle circulant] iters={ro.iters}", flush=True)
     assert abs(out["circulant"][0] - ro.iters) <= max(2, 0.05 * ro.iters)
 
 

@@ -2,7 +2,7 @@
 
 import numpy as np
 
-from synth import (make_config, noise_spectrum, draw_noise, hex_focal_plane,
+from synth import (make_workload, noise_spectrum, draw_noise, hex_focal_plane,
                    raster_scan, crosslinked_torus_scan)
 
 
@@ -30,7 +30,7 @@ def test_spectrum_dc_bin_and_shape():
 
 
 def test_raster_line_four_samples_per_pixel_per_sweep():
-    s = make_config(1)
+    s = make_workload("intensity_small")
     assert s.pix.shape == (8, 2**14)
     # detector 0, row 0 sweep: each of 64 pixels hit exactly 4 times
     row0 = s.pix[0, :256]
@@ -69,10 +69,10 @@ def test_crosslinked_torus_geometry():
     assert np.all(h == h[0])
 
 
-def test_config4_recipe_is_seeded_and_in_range():
-    from synth.configs import config4_spec
-    specs = [config4_spec(i) for i in range(64)]
-    assert specs == [config4_spec(i) for i in range(64)]
+def test_batch_recipe_is_seeded_and_in_range():
+    from synth import batch_scan_spec
+    specs = [batch_scan_spec(i) for i in range(64)]
+    assert specs == [batch_scan_spec(i) for i in range(64)]
     for sp in specs:
         assert 32 <= sp["ndet"] <= 512
         assert 2**16 <= sp["nsamp"] <= 2**21 and sp["nsamp"] & (sp["nsamp"] - 1) == 0
