@@ -183,7 +183,7 @@ def learned_leg(mm, scan, b, args, npairs=16, snap_every=4, epochs=8, batch=8):
             "note": "trained in-sample on this scan's own circulant PCG iterates"}
 
 
-def cpu_baseline(inp, ndet_sample=8, reps=2):
+def cpu_baseline(inp, ndet_sample=128, reps=2):
     """The FP64 oracle's A-apply on the first ndet_sample detectors."""
     import numpy as np
     import oracle
