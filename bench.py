@@ -208,6 +208,76 @@ def cpu_baseline(inp, ndet_sample=128, reps=2):
                       f"(best of {reps}: {t:.2f} s per apply); numpy FFT and bincount, one thread"}
 
 
+def precision_study(args):
+    """Map error per Stokes component of each precision mode on a 128-detector
+    slice of the iqu_1024det workload (2^21 samples, 1024 x 1024 map): the
+    share of one GPU out of eight.  The float64 mode (float64 timestream and
+    accumulation) provides the reference map; every mode forms its own
+    right-hand side from the same noiseless timestream d = P m_sky (rounded
+    to its storage type) and solves to 1e-6 with the binned preconditioner."""
+    import numpy as np
+    import torch
+    import paper_1309_7473_amd as mm
+    from synth import make_workload
+    t0 = time.time()
+    inp = make_workload("iqu_1024det", ndet=args.precision_ndet)
+    nc, npix = inp.ncomp, inp.ny * inp.nx
+    sky = inp.sky.reshape(nc, npix)
+    tod = sky[0][np.maximum(inp.pix, 0)]
+    if nc == 3:
+        tod = tod + inp.cos2psi * sky[1][np.maximum(inp.pix, 0)] + \
+            inp.sin2psi * sky[2][np.maximum(inp.pix, 0)]
+    tod = np.where(inp.pix >= 0, tod, 0.0)
+    tod_dev = torch.from_numpy(tod).cuda()            # float64 on the device
+    del tod
+    t_gen = time.time() - t0
+    modes = [("f64", "f64"), ("f32", "f64"), ("f32", "f32x2"), ("bf16", "f64"), ("bf16", "f32x2")]
+    ref = None
+    A64 = None
+    out = []
+    for dt, acc in modes:
+        scan = mm.Scan(inp, tod_dtype=dt, acc=acc)
+        scan.build_precon("binned")
+        b = scan.rhs(tod_dev)
+        torch.cuda.synchronize()
+        r = scan.pcg("binned", b, tol=1e-6, maxiter=5000, check_every=10, history=False)
+        x = r["x"]
+        mask = scan.mask().bool().repeat(nc)
+        if ref is None:
+            ref, b64, A64 = x.clone(), b.clone(), scan
+        ax = A64.apply_A(x)
+        true_res = float(torch.linalg.norm((ax - b64)[mask]) / torch.linalg.norm(b64[mask]))
+        xs, xr = x.view(nc, npix), ref.view(nc, npix)
+        m1 = scan.mask().bool()
+        sk = torch.from_numpy(sky).cuda()
+        err_ref = [float(torch.linalg.norm((xs[k] - xr[k])[m1]) / torch.linalg.norm(xr[k][m1]))
+                   for k in range(nc)]
+        err_sky = [float(torch.linalg.norm((xs[k] - sk[k])[m1]) / torch.linalg.norm(sk[k][m1]))
+                   for k in range(nc)]
+        y = scan.new_map()
+        for _ in range(2):
+            scan.apply_A(x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            scan.apply_A(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append({"tod": dt, "acc": acc, "iters": r["iters"], "converged": r["converged"],
+                    "rel_resid": r["rel_resid"], "true_resid_f64": true_res,
+                    "map_err_vs_f64_IQU": err_ref, "map_err_vs_sky_IQU": err_sky,
+                    "apply_ms": round(e0.elapsed_time(e1) / 5, 3), "solve_s": round(r["t_solve_s"], 3)})
+        print(json.dumps({"mode": out[-1]}), flush=True)
+        if scan is not A64:
+            scan.close()
+    print(json.dumps({"precision_study": {
+        "workload": f"iqu_1024det slice: {inp.ndet} of 1024 detectors x {inp.nsamp} samples, "
+                    f"{inp.ny}x{inp.nx} I,Q,U map",
+        "reference": "float64 timestream and accumulation on the GPU",
+        "precon": "binned", "tol": 1e-6, "gen_s": round(t_gen, 1), "modes": out}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +293,9 @@ def main():
                     help="end with a plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--summarize", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "LOG", "OUT"),
                     help="summarise rocprofv3 outputs into OUT and exit")
+    ap.add_argument("--precision", action="store_true",
+                    help="run the precision study (iqu_1024det slice) instead of the benchmark")
+    ap.add_argument("--precision-ndet", type=int, default=128, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.summarize:
         summarize(*args.summarize)
@@ -232,6 +305,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if args.precision:
+        precision_study(args)
+        return
 
     import numpy as np
     import torch
