@@ -183,6 +183,27 @@ def learned_leg(mm, scan, b, args, npairs=16, snap_every=4, epochs=8, batch=8):
             "note": "trained in-sample on this scan's own circulant PCG iterates"}
 
 
+def ps_leg(scan, b, x_sky, dell=1000.0, nbins=21, block=10):
+    """Per multipole bin, the CG step at which binned and circulant PCG bring
+    the TT/EE/BB spectrum error below 0.1 cosmic variance (Results-section
+    diagnostic; errors averaged over blocks of `block` steps, the runs here
+    being far shorter than the paper's), and the ratio of the two."""
+    import numpy as np
+    from paper_1309_7473_amd import diagnostics as G
+    out = {}
+    for name in ("binned", "circulant"):
+        d = G.ps_convergence(scan, name, b, x_sky, pixel_arcmin=0.5, dell=dell, nbins=nbins,
+                             tol=1e-6, maxiter=400, snap_every=1, block=block)
+        out[name] = d["conv_steps"]
+    ratio = out["binned"] / out["circulant"]
+    comp = ["TT", "EE", "BB"][: ratio.shape[0]]
+    return {"dell": dell, "nbins": nbins, "block_steps": block, "threshold_cv": 0.1,
+            "median_steps": {n: {c: float(np.nanmedian(out[n][i])) for i, c in enumerate(comp)}
+                             for n in out},
+            "median_speedup_binned_over_circulant": {c: float(np.nanmedian(ratio[i]))
+                                                     for i, c in enumerate(comp)}}
+
+
 def cpu_baseline(inp, ndet_sample=128, reps=2):
     """The FP64 oracle's A-apply on the first ndet_sample detectors."""
     import numpy as np
@@ -378,6 +399,7 @@ def main():
                             "time_s": round(r["t_solve_s"], 4), "rel_resid": r["rel_resid"]}
         solves["circulant"]["setup_s"] = round(t_setup_circ, 4)
         solves["learned"] = learned_leg(mm, scan, b, args)
+        solves["ps_convergence"] = ps_leg(scan, b, x_sky)
 
     if args.calibrate_copy:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")

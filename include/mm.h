@@ -281,6 +281,30 @@ mm_status mm_learned_grad(mm_learned learned, const float* r_w, const float* t, 
 /* z = M_L r (circulant built, learned correction attached). */
 mm_status mm_apply_precon_learned(mm_scan scan, const double* r, double* z, void* stream);
 
+/* Flat-sky binned auto-spectra of a map, the power-spectrum diagnostic of the
+ * Results section.  x: [ncomp][ny][nx] float64 device map; inactive pixels
+ * count as zero (no apodisation).  Each component's unnormalised 2-D DFT X(k);
+ * for I,Q,U also E = Q cos 2phi + U sin 2phi and B = -Q sin 2phi + U cos 2phi
+ * with phi the wavevector angle.  Bin b holds the modes with
+ * ell = 2 pi |k| / pixel_size in [b dell, (b+1) dell), |k| in cycles per
+ * pixel, pixel_size = pixel_arcmin arcminutes; its value is
+ * (pixel solid angle / ny nx) times the mean |X(k)|^2 over those modes.
+ * spectra: [host] [ncomp == 3 ? 3 : 1][nbins] (TT, EE, BB); counts: [host]
+ * [nbins] modes per bin (full Fourier plane), or NULL.  1 <= nbins <= 512.
+ * Uses the preconditioner's FFT scratch (not concurrently with an apply on the
+ * same handle).  Synchronises `stream`. */
+mm_status mm_map_spectra(mm_scan scan, const double* x, double pixel_arcmin, double dell,
+                         int32_t nbins, double* spectra /*[host]*/, double* counts /*[host]*/,
+                         void* stream);
+
+/* Delayed A-norm error estimate of PCG (footnote of the Results section,
+ * with r_j.z_j for ||r_j||^2 under a preconditioner): est[k] =
+ * sum_{j=k}^{k+delay-1} alpha_j rho_j for k = 0..n-delay, an estimate of
+ * ||x_k - x||_A^2.  alpha, rho: [host] n scalars as returned in
+ * mm_pcg_result; est: [host] max(n - delay + 1, 0) entries.  Host only. */
+mm_status mm_anorm_error_estimate(const double* alpha /*[host]*/, const double* rho /*[host]*/,
+                                  int32_t n, int32_t delay, double* est /*[host]*/);
+
 /* Diagnostics of a scan handle. */
 typedef struct {
   int32_t n_active;         /* active pixels */

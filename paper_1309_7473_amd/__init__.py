@@ -134,6 +134,30 @@ def mm_pcg_solve_batch(handles, precon, bs, xs, opts, stream=None):
     return st, out
 
 
+def mm_map_spectra(h, x, pixel_arcmin, dell, nbins, ncomp, stream=None):
+    """Binned TT (and EE, BB) spectra of a device map: (spectra (1 or 3, nbins),
+    counts (nbins,))."""
+    nout = 3 if ncomp == 3 else 1
+    spec = np.zeros((nout, int(nbins)), np.float64)
+    cnt = np.zeros(int(nbins), np.float64)
+    check(lib.mm_map_spectra(h, _ptr(x, torch.float64, name="x"), float(pixel_arcmin), float(dell),
+                             int(nbins), spec.ctypes.data_as(C.c_void_p),
+                             cnt.ctypes.data_as(C.c_void_p), _stream(stream)), "mm_map_spectra")
+    return spec, cnt
+
+
+def mm_anorm_error_estimate(alpha, rho, delay=4):
+    """Delayed A-norm error estimate from recorded PCG scalars (host)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    n = min(len(a), len(r))
+    est = np.zeros(max(n - int(delay) + 1, 0), np.float64)
+    check(lib.mm_anorm_error_estimate(a.ctypes.data_as(C.c_void_p), r.ctypes.data_as(C.c_void_p),
+                                      int(n), int(delay), est.ctypes.data_as(C.c_void_p)),
+          "mm_anorm_error_estimate")
+    return est
+
+
 def mm_get_info(h):
     info = mm_scan_info()
     check(lib.mm_get_info(h, C.byref(info)), "mm_get_info")
@@ -356,6 +380,10 @@ class Scan:
         """Attach a Learned correction (None detaches); the scan keeps it alive."""
         mm_learned_attach(self.handle, None if learned is None else learned.handle)
         self._learned = learned
+
+    def spectra(self, x, pixel_arcmin=0.5, dell=100.0, nbins=200, stream=None):
+        """Binned flat-sky TT (EE, BB) spectra of the map x and the mode counts."""
+        return mm_map_spectra(self.handle, x, pixel_arcmin, dell, nbins, self.ncomp, stream)
 
     def info(self):
         return mm_get_info(self.handle)

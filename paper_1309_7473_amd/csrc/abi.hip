@@ -2,6 +2,7 @@
 // (before anything is enqueued), handle lifetime and the thread-local error
 // message.  The compute lives in filter.hip, binned.hip, circulant.hip and
 // pcg.hip.
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -235,6 +236,30 @@ mm_status mm_pcg_solve_batch(const mm_scan* scans, int32_t n, int32_t precon,
   if (status)
     for (int i = 0; i < n; ++i) status[i] = st[i];
   return rc;
+}
+
+mm_status mm_map_spectra(mm_scan scan, const double* x, double pixel_arcmin, double dell,
+                         int32_t nbins, double* spectra, double* counts, void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  if (!x || !spectra) return fail(MM_EINVAL, "x and spectra are required");
+  if (!(pixel_arcmin > 0.0) || !(dell > 0.0) || !std::isfinite(pixel_arcmin) || !std::isfinite(dell))
+    return fail(MM_EINVAL, "pixel_arcmin and dell must be positive");
+  if (nbins < 1 || nbins > kSpecMaxBins) return fail(MM_EINVAL, "nbins must be in [1, 512]");
+  return map_spectra(s, x, pixel_arcmin, dell, nbins, spectra, counts,
+                     static_cast<hipStream_t>(stream));
+}
+
+mm_status mm_anorm_error_estimate(const double* alpha, const double* rho, int32_t n, int32_t delay,
+                                  double* est) {
+  if (n < 0 || delay < 1) return fail(MM_EINVAL, "n must be >= 0 and delay >= 1");
+  if (n >= delay && (!alpha || !rho || !est)) return fail(MM_EINVAL, "alpha, rho and est are required");
+  for (int k = 0; k + delay <= n; ++k) {
+    double e = 0.0;
+    for (int j = k; j < k + delay; ++j) e += alpha[j] * rho[j];
+    est[k] = e;
+  }
+  return MM_OK;
 }
 
 mm_status mm_get_info(mm_scan scan, mm_scan_info* out) {

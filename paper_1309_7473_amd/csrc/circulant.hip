@@ -156,7 +156,7 @@ static int ilog2i(int v) {
   return l;
 }
 
-static mm_status map_fft(ScanImpl* s, Cx<double>* planes, int nplanes, bool inv, hipStream_t st) {
+mm_status map_fft(ScanImpl* s, Cx<double>* planes, int nplanes, bool inv, hipStream_t st) {
   const int logny = ilog2i(s->ny), lognx = ilog2i(s->nx);
   const int cap = kMapE * kNT;  // complex elements per block
   int logRB = ilog2i(cap) - lognx;

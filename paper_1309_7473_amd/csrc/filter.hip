@@ -1077,6 +1077,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->pcg = take(sizeof(PcgDev));
   L->hist = take(size_t(3) * (kHistCap + 1) * 8);
   L->misc = take(256);
+  L->spec = take(size_t(kSpecBlocks + 1) * kSpecMaxBins * 4 * 8);
   const int ngroups = (d->ndet + pl->G - 1) / pl->G;
   const size_t csr_n = pl->csr ? size_t(ngroups) * pl->G * size_t(n) : 0;
   L->csr_cnt = take(pl->csr ? size_t(ngroups) * npix * 4 : 0);

@@ -16,6 +16,8 @@ constexpr int kMapE = 16;        // ... in the float64 map FFTs
 constexpr int kHistCap = 65536;  // PCG history entries kept on the device
 constexpr int kMaxPartials = 1024;
 constexpr int kProfStages = 8;   // see mm_profile in mm.h
+constexpr int kSpecBlocks = 256;   // blocks of the map-spectra binning
+constexpr int kSpecMaxBins = 512;  // multipole bins of mm_map_spectra
 constexpr int kProfSingle = 0, kProfPass1 = 1, kProfPass2 = 2, kProfPass3 = 3, kProfApplyA = 4,
               kProfPrecon = 5, kProfReduce = 6;
 
@@ -68,6 +70,7 @@ struct Layout {
   size_t pcg;        // PcgDev
   size_t hist;       // 3 * (kHistCap+1) double
   size_t misc;       // small ints / doubles (ref key, floor count, lambda max)
+  size_t spec;       // map-spectra partials and result (kSpecBlocks+1) * kSpecMaxBins * 4 double
   size_t csr_cnt;    // ngroups * npix int32 (counts, then fill cursors)
   size_t csr_off;    // ngroups * (npix+1) int32
   size_t csr_idx;    // ngroups * G * n int32 (group-relative sample index)
@@ -91,6 +94,8 @@ struct Plan {
 };
 
 struct Profiler;
+template <typename T>
+struct Cx;
 
 struct ScanImpl {
   mm_scan_desc d;
@@ -124,6 +129,10 @@ mm_status permute_inverse_spectrum(ScanImpl* s, hipStream_t st);
 mm_status binned_apply(ScanImpl* s, int jacobi, const double* r, double* z, hipStream_t st);
 mm_status circulant_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st);
 mm_status circulant_apply(ScanImpl* s, const double* r, double* z, hipStream_t st);
+// 2-D FFT of nplanes complex double [ny][nx] planes in place (unnormalised)
+mm_status map_fft(ScanImpl* s, Cx<double>* planes, int nplanes, bool inv, hipStream_t st);
+mm_status map_spectra(ScanImpl* s, const double* x, double pixel_arcmin, double dell, int nbins,
+                      double* spectra, double* counts, hipStream_t st);
 mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x,
                     const mm_pcg_opts* o, mm_pcg_result* res, hipStream_t st);
 mm_status pcg_solve_batch(ScanImpl* const* scans, int n, int precon, const double* const* b,
