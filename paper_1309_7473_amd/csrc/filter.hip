@@ -268,7 +268,8 @@ __global__ void __launch_bounds__(kNT) k_single(PassArgs<T, S> a) {
 
 // ------------------------------------------------------------- four-step
 constexpr int kNT13 = 1024;  // threads per pass-1/3 block
-constexpr int kE13 = 8;      // complex elements per thread (C * M1 <= 8192)
+// complex elements per thread: 8 (C * M1 <= 8192) or 16 (C * M1 <= 16384,
+// float math only: 128 KB of LDS per block)
 constexpr int kPad2 = 3;     // pass-2 LDS padding: one slot per 8 elements
 
 // Four consecutive samples s..s+3 (s a multiple of 4) with 16-byte loads.
@@ -340,7 +341,7 @@ __device__ __forceinline__ void col_block(int logNB, int* g, int* cb) {
   }
 }
 
-template <typename T, typename S, int NC, int SRC>
+template <typename T, typename S, int NC, int SRC, int E13>
 __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
@@ -376,7 +377,7 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
   }
   __syncthreads();
   FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
-  lds_fft<T, kNT13, kE13, false>(buf, sh, stw);
+  lds_fft<T, kNT13, E13, false>(buf, sh, stw);
   auto* w = a.work + (int64_t(g) << a.logM);
   for (int e = threadIdx.x; e < C * M1; e += kNT13) {
     const int k1 = e >> a.logC;
@@ -486,7 +487,7 @@ __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T, S> a) {
 // A block holds PB row pairs (2 PB waves).  Per row the length-M2 FFT is a
 // radix-E stage in registers fed straight from global memory (lane l holds
 // elements l + 64 r), then two radix-8 Stockham stages through this wave's
-// padded LDS row; the spectrum ends in natural order.  Stage twiddles come
+// swizzled LDS row; the spectrum ends in natural order.  Stage twiddles come
 // from the global table (it stays in cache); keeping them out of LDS lets
 // more blocks share a CU.  The pair filter runs on the two rows of a pair,
 // the inverse FFT mirrors the forward one and its last stage stores straight
@@ -495,9 +496,15 @@ __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T, S> a) {
 #define MM_PASS2W 1
 #endif
 
+// LDS slot of element i of a row: XOR of bits LOGE.. onto the low five bits.
+// A bank model of every access of the kernel (radix-E writes at stride E,
+// radix-8 reads and writes, the filter's forward and reversed walks) finds
+// this conflict-free or nearly so for 8-byte accesses on 32 or 64 banks,
+// where a one-slot-per-E padding costs up to 1.8x; it is a bijection on
+// [0, 64 E) and needs no padding.
 template <int LOGE>
 __device__ __forceinline__ int pad_e(int i) {
-  return i + (i >> LOGE);
+  return i ^ ((i >> LOGE) & 31);
 }
 
 template <typename T, typename S, int E, int PB>
@@ -505,7 +512,7 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
   constexpr int LOGE = (E == 8) ? 3 : (E == 16) ? 4 : 5;
   constexpr int L = 64 * E;              // = M2
   constexpr int LOGL = LOGE + 6;
-  constexpr int RS = L + (L >> LOGE);    // padded LDS row
+  constexpr int RS = L;                  // LDS row (swizzled, unpadded)
   constexpr int NB = E / 8;              // radix-8 butterflies per lane
   constexpr int NW = 2 * PB;             // waves (rows) per block
   constexpr int NT = 64 * NW;
@@ -663,7 +670,7 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
 
 // CSR = true: store the filtered, packed timestream back in place (the block
 // owns exactly the addresses it loaded); the per-pixel reduce applies P^T.
-template <typename T, typename S, int NC, bool CSR>
+template <typename T, typename S, int NC, bool CSR, int E13>
 __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
@@ -684,7 +691,7 @@ __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
   }
   __syncthreads();
   FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
-  lds_fft<T, kNT13, kE13, true>(buf, sh, stw);
+  lds_fft<T, kNT13, E13, true>(buf, sh, stw);
   if constexpr (CSR) {
     auto* wo = a.work + (int64_t(g) << a.logM);
     for (int e = threadIdx.x; e < C * M1; e += kNT13) {
@@ -870,17 +877,24 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const int JL = M2 < 64 ? M2 : 64;
       const size_t lds2 =
           (size_t(2) * M2 + (size_t(2) * M2 >> kPad2) + M2 + 2 * (M2 / JL) + 2 * JL) * sizeof(Cx<T>);
-      raise_lds_limit(k_pass1<T, S, NC, SRC>, lds13);
-      raise_lds_limit(k_pass3<T, S, NC, false>, lds13);
-      raise_lds_limit(k_pass3<T, S, NC, true>, lds13);
+      const bool e16 = size_t(C) * M1 > size_t(8) * kNT13;   // 16 elements per thread
       prof_begin(s, st, &tok);
-      hipLaunchKernelGGL((k_pass1<T, S, NC, SRC>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
+      if constexpr (sizeof(T) == 4) {
+        if (e16) {
+          raise_lds_limit(k_pass1<T, S, NC, SRC, 16>, lds13);
+          hipLaunchKernelGGL((k_pass1<T, S, NC, SRC, 16>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
+        }
+      }
+      if (!e16) {
+        raise_lds_limit(k_pass1<T, S, NC, SRC, 8>, lds13);
+        hipLaunchKernelGGL((k_pass1<T, S, NC, SRC, 8>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
+      }
       prof_end(s, st, tok, kProfPass1, gs);
       prof_begin(s, st, &tok);
       const dim3 g2(gd * (M1 / 2));
       // one row pair per block: two waves
       constexpr int PB = 1;
-      const size_t lds2w = size_t(2 * PB) * (M2 + 64 + M2 / 64 + 64) * sizeof(Cx<T>);
+      const size_t lds2w = size_t(2 * PB) * (M2 + M2 / 64 + 64) * sizeof(Cx<T>);
       const bool wave_rows = MM_PASS2W && lds2w <= 80 * 1024 && ((int64_t(gd) * M1 / 2) % PB) == 0;
       const dim3 g2w(unsigned(int64_t(gd) * M1 / 2 / PB)), b2w(128 * PB);
       if (wave_rows && M2 == 512) {
@@ -904,10 +918,27 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       }
       prof_end(s, st, tok, kProfPass2, gs);
       prof_begin(s, st, &tok);
-      if (pl.csr)
-        hipLaunchKernelGGL((k_pass3<T, S, NC, true>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
-      else
-        hipLaunchKernelGGL((k_pass3<T, S, NC, false>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
+      const dim3 g13(gd * (M2 / C));
+      if constexpr (sizeof(T) == 4) {
+        if (e16) {
+          if (pl.csr) {
+            raise_lds_limit(k_pass3<T, S, NC, true, 16>, lds13);
+            hipLaunchKernelGGL((k_pass3<T, S, NC, true, 16>), g13, dim3(kNT13), lds13, st, a);
+          } else {
+            raise_lds_limit(k_pass3<T, S, NC, false, 16>, lds13);
+            hipLaunchKernelGGL((k_pass3<T, S, NC, false, 16>), g13, dim3(kNT13), lds13, st, a);
+          }
+        }
+      }
+      if (!e16) {
+        if (pl.csr) {
+          raise_lds_limit(k_pass3<T, S, NC, true, 8>, lds13);
+          hipLaunchKernelGGL((k_pass3<T, S, NC, true, 8>), g13, dim3(kNT13), lds13, st, a);
+        } else {
+          raise_lds_limit(k_pass3<T, S, NC, false, 8>, lds13);
+          hipLaunchKernelGGL((k_pass3<T, S, NC, false, 8>), g13, dim3(kNT13), lds13, st, a);
+        }
+      }
       prof_end(s, st, tok, kProfPass3, gs);
       if (pl.csr) {
         prof_begin(s, st, &tok);
@@ -1021,7 +1052,12 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     if (pl->logM1 < 2 || pl->logM2 < 5 || pl->logM2 > 12 || pl->logM1 > 9)
       return fail(MM_EINVAL, "fft_m1 gives an unsupported four-step split");
     int lc = d->fft_cols > 0 ? ilog2(d->fft_cols) : 4;
-    while (lc > 0 && ((1 << lc) << pl->logM1) > kE * kNT) --lc;
+    // pass-1/3 tile: C * M1 complex in LDS, at most 16 per thread (float
+    // math) or 8 (double), and within 160 KB with the twiddles
+    const int64_t cap = pl->f64 ? int64_t(8) * kNT13 : int64_t(16) * kNT13;
+    while (lc > 0 && (((int64_t(1) << lc) << pl->logM1) > cap ||
+                      (((int64_t(1) << lc) + 1) << pl->logM1) * int64_t(cxb) > 160 * 1024))
+      --lc;
     if (lc > pl->logM2) lc = pl->logM2;
     if (lc < 1) return fail(MM_EINVAL, "fft_cols leaves fewer than two columns per block");
     pl->logC = lc;

@@ -188,3 +188,19 @@ def test_iqu256_detector_subset():
     e = rel(pair.A_gpu(sky), pair.A_oracle(sky))
     print(f"[iqu256 subset] sky rel err = {e:.3e}", flush=True)
     assert e <= TOL32_SKY
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_apply_parity_wide_column_tiles(dt):
+    # 32 columns x 512 rows per pass-1/3 block: 16 elements per thread
+    n = 2**18
+    inp = raster_scan(ncomp=3, ny=32, nx=32, ndet=3, nsamp=n, fsample=100.0, layout="hex",
+                      hex_diameter_px=6.0, sigma_scatter=0.1, fknee=(0.5, 2.0), drift_deg=10.0,
+                      seed=(77, n // 128))
+    pair = Pair(inp, tod_dtype=dt, fft_m1=512, fft_cols=32)
+    info = pair.g.info()
+    assert (info["fft_m1"], info["fft_cols"]) == (512, 32)
+    x = pair.masked_random(1)
+    e = rel(pair.A_gpu(x), pair.A_oracle(x))
+    print(f"[apply wide tiles {dt}] rel err {e:.3e}", flush=True)
+    assert e <= (TOL32_WHITE if dt == "f32" else 2.0**-8)
