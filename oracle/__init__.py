@@ -7,9 +7,10 @@ from it; its inputs come from the seeded generator package `synth`.
 
 Everything is float64 NumPy/SciPy, written for clarity over speed:
 
-* operators.py - pointing P and its transpose, the stationary per-detector
-  noise filter N^-1, A = P^T N^-1 P and b = P^T N^-1 d (eq. 1-2), the binned
-  blocks and the active-pixel mask (eq. 3-5, 7);
+* operators.py - pointing P and its transpose, the stationary noise filter
+  N^-1 (per detector, or with inter-detector correlations as a matrix over
+  detectors per frequency bin), A = P^T N^-1 P and b = P^T N^-1 d (eq. 1-2),
+  the binned blocks and the active-pixel mask (eq. 3-5, 7);
 * precon.py    - binned and Jacobi preconditioners (eq. 3-5) and the circulant
   ("constant correlation") preconditioner with Gaussian regularisation and
   polarisation blocks (eq. 7-13 and the Regularization / Polarization
@@ -19,7 +20,9 @@ Everything is float64 NumPy/SciPy, written for clarity over speed:
 * dense.py     - dense A by probing unit vectors (eq. 6) and a direct solve;
 * learned.py   - the learned linear symmetric correction M_L = M_C +
   Sigma^-1 H^T H Sigma^-T (not in the paper): convolutions, adjoints, loss,
-  gradients, Adam and training pairs.
+  gradients, Adam and training pairs;
+* diagnostics.py - the Results section's convergence measures: binned
+  TT/EE/BB spectra, errors in cosmic-variance units, crossing steps.
 
 Each module states the readings it takes where the paper is silent; functions
 cite the equation or section they follow.  Parity unpinned: none of the

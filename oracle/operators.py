@@ -6,9 +6,12 @@ Follows the linear data model d = P m + n and the map-making equation
 * P has one non-zero per row (nearest-pixel pointing, the footnote to eq. 1)
   with weights (1, cos 2psi, sin 2psi) for T, Q, U (Test setup section);
   pix = -1 marks an off-map sample, whose row of P is zero.
-* N is stationary per detector and detectors are independent, so N^-1 is
-  circulant per detector: N^-1 v = irfft(iN * rfft(v)) with iN = 1/S(f) on
-  the n/2+1 real-FFT frequencies, with no padding or apodisation.
+* N is stationary, so N^-1 is circulant in time: N^-1 v = irfft(iN * rfft(v))
+  per detector with iN = 1/S(f) on the n/2+1 real-FFT frequencies, with no
+  padding or apodisation.  With inter-detector correlations (the ACT-like
+  noise model of the Test setup section) N^-1 is a matrix over detectors at
+  each frequency: N^-1(k) = diag(iN[:, k]) - V_b V_b^T for the frequency bin b
+  holding k, applied to the vector of all detectors' spectra at k.
 * The unknowns are restricted to the active pixels (hit, and for I,Q,U with
   a well-conditioned binned block); inactive entries are zero on input and
   output of every operator.
@@ -40,6 +43,16 @@ class OracleScan:
         self.iN = np.asarray(inputs.inv_noise, dtype=np.float64)
         if self.iN.shape != (self.ndet, self.nsamp // 2 + 1):
             raise ValueError("inverse spectrum must be [ndet][nsamp/2+1]")
+        edges = getattr(inputs, "corr_edges", None)
+        self.corr = None
+        if edges is not None:
+            V = np.asarray(inputs.corr_V, dtype=np.float64)
+            edges = np.asarray(edges, dtype=np.int64)
+            if edges[0] != 0 or edges[-1] != self.nsamp // 2 + 1 or np.any(np.diff(edges) <= 0):
+                raise ValueError("correlation bins must tile 0..nsamp/2")
+            if V.shape[:2] != (len(edges) - 1, self.ndet):
+                raise ValueError("V must be [nbins][ndet][rank]")
+            self.corr = (edges, V)
         if self.ncomp not in (1, 3):
             raise ValueError("ncomp must be 1 or 3")
 
@@ -91,10 +104,21 @@ def pointing_T(scan, tod, d0=0, d1=None):
 
 
 def inv_noise(scan, tod, d0=0, d1=None):
-    """N^-1 t per detector as a circulant filter: irfft(iN_d * rfft(t_d))."""
+    """N^-1 t per detector as a circulant filter: irfft(iN_d * rfft(t_d)).
+    With correlations tod must hold every detector (d0 = 0, d1 = ndet): at
+    each frequency k of bin b, F[:, k] <- iN[:, k] F[:, k] - V_b (V_b^T F[:, k])."""
     d1 = scan.ndet if d1 is None else d1
     f = np.fft.rfft(np.asarray(tod, dtype=np.float64), axis=1)
-    f *= scan.iN[d0:d1]
+    if scan.corr is None:
+        f *= scan.iN[d0:d1]
+    else:
+        assert d0 == 0 and d1 == scan.ndet, "correlated noise couples all detectors"
+        edges, V = scan.corr
+        g = f * scan.iN
+        for b in range(len(edges) - 1):
+            k0, k1 = edges[b], edges[b + 1]
+            g[:, k0:k1] -= V[b] @ (V[b].T @ f[:, k0:k1])
+        f = g
     return np.fft.irfft(f, scan.nsamp, axis=1)
 
 
@@ -104,8 +128,13 @@ def detector_weights(scan):
     N^-1_tt of eq. 3-4).  Equals 1/sigma^2 for white noise."""
     n = scan.nsamp
     out = np.empty(scan.ndet)
+    diag = scan.iN.copy()
+    if scan.corr is not None:   # diagonal of N^-1(k): iN_d(k) - sum_j V_b[d, j]^2
+        edges, V = scan.corr
+        for b in range(len(edges) - 1):
+            diag[:, edges[b]:edges[b + 1]] -= (V[b] ** 2).sum(axis=1)[:, None]
     for d in range(scan.ndet):
-        half = scan.iN[d]
+        half = diag[d]
         two_sided = np.concatenate([half, half[1:n // 2][::-1]])
         assert two_sided.size == n
         out[d] = two_sided.mean()
@@ -151,12 +180,17 @@ def active_mask(scan, B, rcond=1e-3):
     return act
 
 
+def _groups(scan):
+    # correlated noise couples all detectors: one group
+    return [(0, scan.ndet)] if scan.corr is not None else list(_chunks(scan.ndet))
+
+
 def apply_A(scan, x, mask):
     """A x = P^T N^-1 P x (eq. 2) on the active set.  x: (ncomp*npix,) or
     (ncomp, npix); returns the same flat shape (ncomp*npix,)."""
     xm = np.asarray(x, dtype=np.float64).reshape(scan.ncomp, scan.npix) * mask
     y = np.zeros((scan.ncomp, scan.npix))
-    for d0, d1 in _chunks(scan.ndet):
+    for d0, d1 in _groups(scan):
         t = pointing(scan, xm, d0, d1)
         t = inv_noise(scan, t, d0, d1)
         y += pointing_T(scan, t, d0, d1)
@@ -166,7 +200,7 @@ def apply_A(scan, x, mask):
 def rhs(scan, d, mask):
     """b = P^T N^-1 d (eq. 2) on the active set.  d: (ndet, nsamp)."""
     y = np.zeros((scan.ncomp, scan.npix))
-    for d0, d1 in _chunks(scan.ndet):
+    for d0, d1 in _groups(scan):
         t = inv_noise(scan, np.asarray(d[d0:d1], dtype=np.float64), d0, d1)
         y += pointing_T(scan, t, d0, d1)
     return (y * mask).reshape(-1)

@@ -15,6 +15,16 @@ from .scan import (  # noqa: F401
     crosslinked_torus_scan,
     hex_focal_plane,
 )
-from .noise import noise_spectrum, inverse_spectrum, draw_noise  # noqa: F401
+from .noise import (noise_spectrum, inverse_spectrum, draw_noise,  # noqa: F401
+                    correlated_inverse_noise)
 from .sky import grf_sky  # noqa: F401
 from .workloads import make_workload, WORKLOADS, batch_scan_spec  # noqa: F401
+
+
+def with_correlated_noise(inp, rank=2, nbins=16, beta_max=0.9, f_atm=1.0, seed=(0, 0)):
+    """A copy of scan inputs whose inverse noise gains the inter-detector
+    correlated part of correlated_inverse_noise."""
+    import dataclasses
+    edges, V = correlated_inverse_noise(inp.inv_noise, inp.fsample, rank, nbins, beta_max,
+                                        f_atm, seed)
+    return dataclasses.replace(inp, corr_edges=edges, corr_V=V)

@@ -37,6 +37,10 @@ class ScanInputs:
     spectrum: np.ndarray             # float64 [ndet][nsamp//2 + 1] (for noise draws)
     sky: np.ndarray | None = None    # float64 [ncomp][ny][nx]
     meta: dict = field(default_factory=dict)
+    # inter-detector correlated part of N^-1 (None: detectors independent):
+    # real-FFT bins edges[b] <= k < edges[b+1] share V[b] (float32 [ndet][rank])
+    corr_edges: np.ndarray | None = None   # int32 [nbins + 1]
+    corr_V: np.ndarray | None = None       # float32 [nbins][ndet][rank]
 
     @property
     def npix(self):
