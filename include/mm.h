@@ -114,6 +114,20 @@ typedef struct {
                                products.  MM_ACC_F32X2 needs scatter =
                                MM_SCATTER_AUTO (it always takes the per-pixel
                                gather, also on the one-kernel path). */
+  /* Inter-detector correlated inverse noise (the atmosphere and detector
+   * correlations of the Test setup section's noise model).  corr_rank = 0:
+   * detectors are independent and the three fields below are ignored.
+   * corr_rank in 1..16: at real-FFT frequency k of bin b,
+   *   N^-1(k) = diag(inv_noise[:, k]) - V_b V_b^T   (ndet x ndet),
+   * which the caller keeps positive definite.  All detectors then form one
+   * group (det_group is ignored) and the four-step pipeline runs with rows
+   * of 512-2048 bins: nsamp in [2^13, 2^21]. */
+  int32_t corr_rank;
+  int32_t corr_nbins;       /* frequency bins, 1..4096 */
+  const int32_t* corr_edges;/* [host] [corr_nbins + 1]: bin b holds edges[b] <= k <
+                               edges[b+1]; edges[0] = 0, edges[corr_nbins] =
+                               nsamp/2 + 1, strictly increasing.  Copied at create. */
+  const float* corr_V;      /* [corr_nbins][ndet][corr_rank] device.  BORROWED */
 } mm_scan_desc;
 
 enum { MM_SCATTER_AUTO = 0, MM_SCATTER_ATOMIC = 1 };

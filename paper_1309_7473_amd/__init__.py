@@ -317,6 +317,14 @@ class Scan:
         d.mask_rcond = float(mask_rcond)
         d.scatter = {"auto": MM_SCATTER_AUTO, "atomic": MM_SCATTER_ATOMIC}[scatter]
         d.acc = {"f64": MM_ACC_F64, "f32x2": MM_ACC_F32X2}[acc]
+        edges = getattr(inputs, "corr_edges", None)
+        if edges is not None:   # inter-detector correlated inverse noise
+            self.corr_edges = np.ascontiguousarray(edges, dtype=np.int32)   # host, copied at create
+            self.corr_V = up(inputs.corr_V, torch.float32)
+            d.corr_nbins = len(self.corr_edges) - 1
+            d.corr_rank = int(self.corr_V.shape[-1])
+            d.corr_edges = self.corr_edges.ctypes.data
+            d.corr_V = self.corr_V.data_ptr()
         nbytes = mm_scan_workspace_bytes(d)
         if nbytes == 0:
             raise MMError(MM_EINVAL, "mm_scan_workspace_bytes")

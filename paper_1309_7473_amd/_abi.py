@@ -27,6 +27,8 @@ class mm_scan_desc(C.Structure):
         ("inv_noise", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("det_group", C.c_int32), ("fft_m1", C.c_int32), ("mask_rcond", C.c_double),
         ("fft_cols", C.c_int32), ("scatter", C.c_int32), ("acc", C.c_int32),
+        ("corr_rank", C.c_int32), ("corr_nbins", C.c_int32), ("corr_edges", C.c_void_p),
+        ("corr_V", C.c_void_p),
     ]
 
 

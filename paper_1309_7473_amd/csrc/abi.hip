@@ -57,6 +57,17 @@ static mm_status validate_shape(const mm_scan_desc* d) {
     return fail(MM_EINVAL, "acc must be MM_ACC_F64 or MM_ACC_F32X2");
   if (d->acc == MM_ACC_F32X2 && d->scatter == MM_SCATTER_ATOMIC)
     return fail(MM_EINVAL, "acc = MM_ACC_F32X2 needs scatter = MM_SCATTER_AUTO");
+  if (d->corr_rank < 0 || d->corr_rank > 16) return fail(MM_EINVAL, "corr_rank must be in [0, 16]");
+  if (d->corr_rank > 0) {
+    if (d->corr_nbins < 1 || d->corr_nbins > 4096)
+      return fail(MM_EINVAL, "corr_nbins must be in [1, 4096]");
+    if (!d->corr_edges) return fail(MM_EINVAL, "corr_edges is required when corr_rank > 0");
+    const int32_t* e = d->corr_edges;
+    if (e[0] != 0 || int64_t(e[d->corr_nbins]) != d->nsamp / 2 + 1)
+      return fail(MM_EINVAL, "corr_edges must run from 0 to nsamp/2 + 1");
+    for (int b = 0; b < d->corr_nbins; ++b)
+      if (e[b + 1] <= e[b]) return fail(MM_EINVAL, "corr_edges must increase strictly");
+  }
   return MM_OK;
 }
 
@@ -92,6 +103,7 @@ mm_status mm_create_scan(const mm_scan_desc* desc, void* stream, mm_scan* out) {
     return fail(MM_EINVAL, "cos2psi/sin2psi must be given iff ncomp == 3");
   if (desc->ncomp == 1 && (desc->cos2psi || desc->sin2psi))
     return fail(MM_EINVAL, "cos2psi/sin2psi must be NULL when ncomp == 1");
+  if (desc->corr_rank > 0 && !desc->corr_V) return fail(MM_EINVAL, "corr_V is required");
   Plan pl;
   Layout L;
   if ((r = plan_and_layout(desc, &pl, &L)) != MM_OK) return r;

@@ -44,6 +44,34 @@ __global__ void k_det_weights(const float* __restrict__ iN, int64_t n, double* _
   if (threadIdx.x == 0) w[d] = v[0] / double(n);
 }
 
+// With inter-detector correlations the diagonal of N^-1(k) is
+// iN_d(k) - sum_j V_b[d][j]^2: subtract its mean over the n two-sided
+// frequencies (bin b holds 2 (e1 - e0) of them, less k = 0 and k = n/2).
+__global__ void k_det_weights_corr(const float* __restrict__ V, const int32_t* __restrict__ edges,
+                                   int nbins, int rank, int ndet, int64_t n,
+                                   double* __restrict__ w) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= ndet) return;
+  double s = 0.0;
+  for (int b = 0; b < nbins; ++b) {
+    const int64_t e0 = edges[b], e1 = edges[b + 1];
+    const int64_t cnt = 2 * (e1 - e0) - (e0 == 0 ? 1 : 0) - (e1 == n / 2 + 1 ? 1 : 0);
+    double v2 = 0.0;
+    for (int j = 0; j < rank; ++j) {
+      const double v = double(V[(int64_t(b) * ndet + d) * rank + j]);
+      v2 += v * v;
+    }
+    s += double(cnt) * v2;
+  }
+  w[d] -= s / double(n);
+}
+
+__global__ void k_validate_finite(const float* __restrict__ v, int64_t count, int* __restrict__ bad) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x)
+    if (!isfinite(v[i])) atomicOr(bad, 1);
+}
+
 // One lane per sample; every lane of a wave takes the same number of trips.
 template <int NC>
 __global__ void __launch_bounds__(256) k_binned_accum(const int32_t* __restrict__ pix,
@@ -208,14 +236,23 @@ mm_status binned_setup(ScanImpl* s, hipStream_t st) {
     const int64_t niN = int64_t(s->ndet) * (s->n / 2 + 1);
     hipLaunchKernelGGL(k_validate, dim3(2048), dim3(256), 0, st, s->d.pix, total, npix,
                        s->d.inv_noise, niN, bad);
+    if (s->plan.corr_rank > 0)
+      hipLaunchKernelGGL(k_validate_finite, dim3(256), dim3(256), 0, st, s->d.corr_V,
+                         int64_t(s->plan.corr_nbins) * s->ndet * s->plan.corr_rank, bad);
     MM_HIP(hipGetLastError());
     int h = 0;
     MM_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, st));
     MM_HIP(hipStreamSynchronize(st));
-    if (h) return fail(MM_EINVAL, "pix outside [-1, ny*nx) or inv_noise negative / non-finite");
+    if (h)
+      return fail(MM_EINVAL,
+                  "pix outside [-1, ny*nx), inv_noise negative / non-finite or corr_V non-finite");
   }
   hipLaunchKernelGGL(k_det_weights, dim3(s->ndet), dim3(256), 0, st, s->d.inv_noise, s->n,
                      s->at<double>(L.detw));
+  if (s->plan.corr_rank > 0)
+    hipLaunchKernelGGL(k_det_weights_corr, dim3((s->ndet + 255) / 256), dim3(256), 0, st,
+                       s->d.corr_V, s->at<int32_t>(L.corr_edges), s->plan.corr_nbins,
+                       s->plan.corr_rank, s->ndet, s->n, s->at<double>(L.detw));
   mm_status r;
   if ((r = fill_zero(s->ws + L.hits, size_t(npix) * 8, st)) != MM_OK) return r;
   if ((r = fill_zero(s->ws + L.bb, size_t(npix) * 6 * 8, st)) != MM_OK) return r;

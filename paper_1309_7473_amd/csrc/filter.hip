@@ -171,6 +171,39 @@ __device__ __forceinline__ Cx<T> dc_filter(Cx<T> Z0, T a0, T aM) {
   return cx(T(0.5) * (y0 + yM), T(0.5) * (y0 - yM));
 }
 
+// The two halves of pair_filter, for a filter that mixes detectors:
+// unpack (Z[k], Z[M-k]) into the real-input spectrum (X[k], X[M-k]), and
+// repack a filtered (Y[k], Y[M-k]) into the packed pair.  pair_filter(a, b)
+// equals pair_repack(a X[k], b X[M-k]).
+template <typename T>
+__device__ __forceinline__ void pair_unpack(Cx<T>& Zk, Cx<T>& Zmk, Cx<T> W) {
+  const T h = T(0.5);
+  const Cx<T> E = cx(h * (Zk.x + Zmk.x), h * (Zk.y - Zmk.y));
+  const Cx<T> D = cx(h * (Zk.x - Zmk.x), h * (Zk.y + Zmk.y));
+  const Cx<T> WO = W * cx(D.y, -D.x);
+  Zk = E + WO;
+  Zmk = conj(E - WO);
+}
+
+template <typename T>
+__device__ __forceinline__ void pair_repack(Cx<T>& Yk, Cx<T>& Ymk, Cx<T> W) {
+  const T h = T(0.5);
+  const Cx<T> E = cx(h * (Yk.x + Ymk.x), h * (Yk.y - Ymk.y));
+  const Cx<T> O = cx(h * (Yk.x - Ymk.x), h * (Yk.y + Ymk.y)) * conj(W);
+  Yk = cx(E.x - O.y, E.y + O.x);
+  Ymk = cx(E.x + O.y, O.x - E.y);
+}
+
+// slot 0: Z[0] <-> (X[0], X[M]) as (re, im), both real
+template <typename T>
+__device__ __forceinline__ Cx<T> dc_unpack(Cx<T> Z0) {
+  return cx(Z0.x + Z0.y, Z0.x - Z0.y);
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> dc_repack(Cx<T> Y) {
+  return cx(T(0.5) * (Y.x + Y.y), T(0.5) * (Y.x - Y.y));
+}
+
 // ------------------------------------------------------ prologue / epilogue
 template <typename T>
 __global__ void k_prologue(const double* __restrict__ x, const int32_t* __restrict__ mask,
@@ -507,7 +540,11 @@ __device__ __forceinline__ int pad_e(int i) {
   return i ^ ((i >> LOGE) & 31);
 }
 
-template <typename T, typename S, int E, int PB>
+// MODE 0: forward FFT, 1/N(f) filter, inverse FFT.  MODE 1 (correlated
+// noise): forward FFT and unpack to the real-input spectrum X, stored in
+// place in natural order.  MODE 2: load the filtered spectrum Y, repack,
+// inverse FFT.
+template <typename T, typename S, int E, int PB, int MODE>
 __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
   constexpr int LOGE = (E == 8) ? 3 : (E == 16) ? 4 : 5;
   constexpr int L = 64 * E;              // = M2
@@ -545,13 +582,15 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
   const Cx<T> tb = tB[wave * 64 + lane];
   auto twE = [&](int m) { return twL(m << 6); };   // W_E^m = W_L^(64 m)
   // ---------------- forward: radix-E from global, then 2 x radix-8
-  {
+  if constexpr (MODE != 2) {
     Cx<T> v[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) v[r] = Sto<T, S>::ld(w + lane + 64 * r) * (tA[wave * E + r] * tb);
     dft_regs<T, E, false>(v, twE);
 #pragma unroll
     for (int r = 0; r < E; ++r) R[pad_e<LOGE>(lane * E + r)] = v[r];
+  } else {
+    for (int i = lane; i < L; i += 64) R[pad_e<LOGE>(i)] = Sto<T, S>::ld(w + i);
   }
   __syncthreads();
   auto radix8 = [&](int logNs, bool inv, bool to_lds) {
@@ -601,9 +640,28 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
     }
     if (to_lds) __syncthreads();
   };
-  radix8(LOGE, false, true);
-  radix8(LOGE + 3, false, true);
-  // ---------------- pair filter on rows ra (wave 2h) and rb (wave 2h+1)
+  if constexpr (MODE != 2) {
+    radix8(LOGE, false, true);
+    radix8(LOGE + 3, false, true);
+  }
+  // the pair operation: the filter, or the unpack / repack of MODE 1 / 2
+  auto pair_op = [&](Cx<T>& zk, Cx<T>& zm, Cx<T> W, T fa, T fb) {
+    if constexpr (MODE == 0)
+      pair_filter(zk, zm, W, fa, fb);
+    else if constexpr (MODE == 1)
+      pair_unpack(zk, zm, W);
+    else
+      pair_repack(zk, zm, W);
+  };
+  auto dc_op = [&](Cx<T> z, T f0, T fM) {
+    if constexpr (MODE == 0)
+      return dc_filter(z, f0, fM);
+    else if constexpr (MODE == 1)
+      return dc_unpack(z);
+    else
+      return dc_repack(z);
+  };
+  // ---------------- pair operation on rows ra (wave 2h) and rb (wave 2h+1)
   {
     const int h = wave >> 1;
     Cx<T>* Ra = rows + (2 * h) * RS;
@@ -611,6 +669,8 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
     const int tp = threadIdx.x & 127;   // thread within the pair
     const float* iN = a.iNt + int64_t(g) * (M + 1);
     const T sc = a.scale;
+    // the filter's gains (MODE 0 only reads 1/N(f))
+    auto gain = [&](const float* p, int i) { return MODE == 0 ? sc * T(p[i]) : T(0); };
     if (pr != 0) {
       const Cx<T> wa = a.wn(ra);
       const float* ia = iN + int64_t(ra) * L;
@@ -618,7 +678,7 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
       for (int k2 = tp; k2 < L; k2 += 128) {
         const int i0 = pad_e<LOGE>(k2), i1 = pad_e<LOGE>(L - 1 - k2);
         Cx<T> zk = Ra[i0], zm = Rb[i1];
-        pair_filter(zk, zm, wa * a.tw2[k2], sc * T(ia[k2]), sc * T(ib[L - 1 - k2]));
+        pair_op(zk, zm, wa * a.tw2[k2], gain(ia, k2), gain(ib, L - 1 - k2));
         Ra[i0] = zk;
         Rb[i1] = zm;
       }
@@ -629,15 +689,15 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
         if (t < L / 2) {
           const int k2 = t;
           if (k2 == 0) {
-            Ra[0] = dc_filter(Ra[0], sc * T(iN[0]), sc * T(iN[M]));
+            Ra[0] = dc_op(Ra[0], gain(iN, 0), gain(iN, M));
             const int hh = pad_e<LOGE>(L / 2);
             Cx<T> zk = Ra[hh], zm = Ra[hh];
-            pair_filter(zk, zm, a.tw2[L / 2], sc * T(iN[L / 2]), sc * T(iN[L / 2]));
+            pair_op(zk, zm, a.tw2[L / 2], gain(iN, L / 2), gain(iN, L / 2));
             Ra[hh] = zk;
           } else {
             const int i0 = pad_e<LOGE>(k2), i1 = pad_e<LOGE>(L - k2);
             Cx<T> zk = Ra[i0], zm = Ra[i1];
-            pair_filter(zk, zm, a.tw2[k2], sc * T(iN[k2]), sc * T(iN[L - k2]));
+            pair_op(zk, zm, a.tw2[k2], gain(iN, k2), gain(iN, L - k2));
             Ra[i0] = zk;
             Ra[i1] = zm;
           }
@@ -645,7 +705,7 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
           const int k2 = t - L / 2;
           const int i0 = pad_e<LOGE>(k2), i1 = pad_e<LOGE>(L - 1 - k2);
           Cx<T> zk = Rb[i0], zm = Rb[i1];
-          pair_filter(zk, zm, wh * a.tw2[k2], sc * T(ih[k2]), sc * T(ih[L - 1 - k2]));
+          pair_op(zk, zm, wh * a.tw2[k2], gain(ih, k2), gain(ih, L - 1 - k2));
           Rb[i0] = zk;
           Rb[i1] = zm;
         }
@@ -653,6 +713,10 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
     }
   }
   __syncthreads();
+  if constexpr (MODE == 1) {   // store the unpacked spectrum of this wave's row
+    for (int i = lane; i < L; i += 64) Sto<T, S>::st(w + i, R[pad_e<LOGE>(i)]);
+    return;
+  }
   // ---------------- inverse: radix-E from LDS, then 2 x radix-8, store
   {
     Cx<T> v[E];
@@ -666,6 +730,90 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
   __syncthreads();
   radix8(LOGE, true, true);
   radix8(LOGE + 3, true, false);
+}
+
+// Inter-detector correlated N^-1 on the unpacked spectra of one group that
+// holds every detector: slot s = k1*M2 + k2 holds X_d[k] for frequency
+// k = k1 + M1*k2 (slot 0: X_d[0] and X_d[M] as re and im).  With b the bin
+// of k, Y_d = (1/M) (iN_d[k] X_d - sum_j V_b[d][j] t_j), t_j = sum_d V_b[d][j] X_d.
+// One thread per slot; V rows are shared by the threads of a bin.
+constexpr int kMaxCorrRank = 16;
+
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_corr_mix(PassArgs<T, S> a, const float* __restrict__ V,
+                                                  const int32_t* __restrict__ edges, int nbins,
+                                                  int rank, int ndet) {
+  extern __shared__ int32_t sedge[];
+  for (int i = threadIdx.x; i <= nbins; i += blockDim.x) sedge[i] = edges[i];
+  __syncthreads();
+  const int M = 1 << a.logM;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= M) return;
+  auto bin_of = [&](int k) {   // largest b with edges[b] <= k
+    int lo = 0, hi = nbins - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sedge[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  const int k = (s >> a.logM2) + ((s & ((1 << a.logM2) - 1)) << a.logM1);
+  const T sc = a.scale;
+  // two passes over the detectors (the second re-reads X from cache)
+  auto mix = [&](int b, auto getx, auto iNd, auto put) {
+    T tr[kMaxCorrRank], ti[kMaxCorrRank];   // fully unrolled: stays in registers
+#pragma unroll
+    for (int j = 0; j < kMaxCorrRank; ++j) tr[j] = ti[j] = T(0);
+    for (int d = 0; d < ndet; ++d) {
+      const Cx<T> x = getx(d);
+      const float* v = V + (int64_t(b) * ndet + d) * rank;
+#pragma unroll
+      for (int j = 0; j < kMaxCorrRank; ++j) {
+        if (j < rank) {
+          tr[j] += T(v[j]) * x.x;
+          ti[j] += T(v[j]) * x.y;
+        }
+      }
+    }
+    for (int d = 0; d < ndet; ++d) {
+      const Cx<T> x = getx(d);
+      const float* v = V + (int64_t(b) * ndet + d) * rank;
+      T yr = T(iNd(d)) * x.x, yi = T(iNd(d)) * x.y;
+#pragma unroll
+      for (int j = 0; j < kMaxCorrRank; ++j) {
+        if (j < rank) {
+          yr -= T(v[j]) * tr[j];
+          yi -= T(v[j]) * ti[j];
+        }
+      }
+      put(d, cx(sc * yr, sc * yi));
+    }
+  };
+  auto* w = a.work;
+  const float* iNt = a.iNt;
+  if (s != 0) {
+    mix(bin_of(k), [&](int d) { return Sto<T, S>::ld(w + (int64_t(d) << a.logM) + s); },
+        [&](int d) { return iNt[int64_t(d) * (M + 1) + s]; },
+        [&](int d, Cx<T> y) { Sto<T, S>::st(w + (int64_t(d) << a.logM) + s, y); });
+  } else {
+    // DC (re part, bin of k = 0) and Nyquist (im part, bin of k = M), both real;
+    // the results are combined into slot 0 after both passes
+    const int bN = bin_of(M);
+    mix(0, [&](int d) { return cx(Sto<T, S>::ld(w + (int64_t(d) << a.logM)).x, T(0)); },
+        [&](int d) { return iNt[int64_t(d) * (M + 1)]; },
+        [&](int d, Cx<T> y) {
+          Cx<T> z = Sto<T, S>::ld(w + (int64_t(d) << a.logM));
+          z.x = y.x;
+          Sto<T, S>::st(w + (int64_t(d) << a.logM), z);
+        });
+    mix(bN, [&](int d) { return cx(Sto<T, S>::ld(w + (int64_t(d) << a.logM)).y, T(0)); },
+        [&](int d) { return iNt[int64_t(d) * (M + 1) + M]; },
+        [&](int d, Cx<T> y) {
+          Cx<T> z = Sto<T, S>::ld(w + (int64_t(d) << a.logM));
+          z.y = y.x;
+          Sto<T, S>::st(w + (int64_t(d) << a.logM), z);
+        });
+  }
 }
 
 // CSR = true: store the filtered, packed timestream back in place (the block
@@ -804,6 +952,22 @@ static void raise_lds_limit(K kernel, size_t bytes) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
+// pass 2 with one wavefront per row (one row pair per block) in a given mode
+template <typename T, typename S, int MODE>
+static void launch_pass2w(int M2, dim3 g, size_t lds, hipStream_t st, const PassArgs<T, S>& a) {
+  const dim3 b(128);
+  if (M2 == 512) {
+    raise_lds_limit(k_pass2w<T, S, 8, 1, MODE>, lds);
+    hipLaunchKernelGGL((k_pass2w<T, S, 8, 1, MODE>), g, b, lds, st, a);
+  } else if (M2 == 1024) {
+    raise_lds_limit(k_pass2w<T, S, 16, 1, MODE>, lds);
+    hipLaunchKernelGGL((k_pass2w<T, S, 16, 1, MODE>), g, b, lds, st, a);
+  } else {
+    raise_lds_limit(k_pass2w<T, S, 32, 1, MODE>, lds);
+    hipLaunchKernelGGL((k_pass2w<T, S, 32, 1, MODE>), g, b, lds, st, a);
+  }
+}
+
 template <typename T, typename S, int NC>
 static void launch_reduce(ScanImpl* s, const PassArgs<T, S>& a, hipStream_t st) {
   const dim3 grid((s->npix + 15) / 16);   // 16 pixels of 16 lanes per block
@@ -897,15 +1061,25 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const size_t lds2w = size_t(2 * PB) * (M2 + M2 / 64 + 64) * sizeof(Cx<T>);
       const bool wave_rows = MM_PASS2W && lds2w <= 80 * 1024 && ((int64_t(gd) * M1 / 2) % PB) == 0;
       const dim3 g2w(unsigned(int64_t(gd) * M1 / 2 / PB)), b2w(128 * PB);
-      if (wave_rows && M2 == 512) {
-        raise_lds_limit(k_pass2w<T, S, 8, PB>, lds2w);
-        hipLaunchKernelGGL((k_pass2w<T, S, 8, PB>), g2w, b2w, lds2w, st, a);
+      if (pl.corr_rank > 0) {
+        // correlated noise: unpack every detector's spectrum, mix across
+        // detectors, repack and invert (the plan keeps M2 in 512..2048)
+        if (!wave_rows || M2 < 512 || M2 > 2048)
+          return fail(MM_EINVAL, "correlated noise: unsupported pass-2 row length");
+        launch_pass2w<T, S, 1>(M2, g2w, lds2w, st, a);
+        hipLaunchKernelGGL((k_corr_mix<T, S>), dim3((M + 255) / 256), dim3(256),
+                           size_t(pl.corr_nbins + 1) * 4, st, a, s->d.corr_V,
+                           s->at<int32_t>(s->lay.corr_edges), pl.corr_nbins, pl.corr_rank, gd);
+        launch_pass2w<T, S, 2>(M2, g2w, lds2w, st, a);
+      } else if (wave_rows && M2 == 512) {
+        raise_lds_limit(k_pass2w<T, S, 8, PB, 0>, lds2w);
+        hipLaunchKernelGGL((k_pass2w<T, S, 8, PB, 0>), g2w, b2w, lds2w, st, a);
       } else if (wave_rows && M2 == 1024) {
-        raise_lds_limit(k_pass2w<T, S, 16, PB>, lds2w);
-        hipLaunchKernelGGL((k_pass2w<T, S, 16, PB>), g2w, b2w, lds2w, st, a);
+        raise_lds_limit(k_pass2w<T, S, 16, PB, 0>, lds2w);
+        hipLaunchKernelGGL((k_pass2w<T, S, 16, PB, 0>), g2w, b2w, lds2w, st, a);
       } else if (wave_rows && M2 == 2048) {
-        raise_lds_limit(k_pass2w<T, S, 32, PB>, lds2w);
-        hipLaunchKernelGGL((k_pass2w<T, S, 32, PB>), g2w, b2w, lds2w, st, a);
+        raise_lds_limit(k_pass2w<T, S, 32, PB, 0>, lds2w);
+        hipLaunchKernelGGL((k_pass2w<T, S, 32, PB, 0>), g2w, b2w, lds2w, st, a);
       } else if (M2 <= 1024) {
         raise_lds_limit(k_pass2<T, S, 8>, lds2);
         hipLaunchKernelGGL((k_pass2<T, S, 8>), g2, dim3(kNT), lds2, st, a);
@@ -1026,7 +1200,11 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   const size_t cxb = pl->f64 ? 16 : 8;          // one complex in the math type
   const size_t wxb = pl->bf16 ? 4 : cxb;         // ... in the pass buffer
   pl->acc32 = d->acc == MM_ACC_F32X2;
-  pl->single = (M <= kE * kNT);
+  pl->corr_rank = d->corr_rank;
+  pl->corr_nbins = d->corr_rank > 0 ? d->corr_nbins : 0;
+  // correlated noise needs every detector's spectrum at once: the four-step
+  // pipeline with wavefront rows of 512-2048 bins
+  pl->single = (M <= kE * kNT) && pl->corr_rank == 0;
   // the compensated accumulation exists only in the per-pixel gather
   pl->csr = d->scatter != MM_SCATTER_ATOMIC && (!pl->single || pl->acc32);
   if (pl->single) {
@@ -1040,7 +1218,12 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     pl->logLmax = pl->logM;
   } else {
     int l1;
-    if (d->fft_m1 > 0) {
+    if (pl->corr_rank > 0) {
+      l1 = pl->logM - 9;                   // rows of 512 bins
+      if (l1 > 9) l1 = 9;                  // up to 2048 at M = 2^20
+      if (l1 < 3 || pl->logM - l1 > 11)
+        return fail(MM_EINVAL, "correlated noise needs nsamp in [2^13, 2^21]");
+    } else if (d->fft_m1 > 0) {
       l1 = ilog2(d->fft_m1);
     } else {
       l1 = pl->logM / 2;
@@ -1063,7 +1246,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     pl->logC = lc;
     if ((2 << (lc + pl->logM1)) % kNT != 0 || (2 << pl->logM2) % kNT != 0)
       return fail(MM_EINVAL, "four-step blocks too small for the thread count");
-    int G = d->det_group;
+    int G = pl->corr_rank > 0 ? d->ndet : d->det_group;
     if (G <= 0) {
       // about 256 MiB of timestream scratch per group (large launches)
       const int64_t per = int64_t(M) * int64_t(wxb);
@@ -1072,6 +1255,8 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     }
     if (G > d->ndet) G = d->ndet;
     while (G > 1 && int64_t(G) * n > (int64_t(1) << 31) - 1) --G;
+    if (pl->corr_rank > 0 && G != d->ndet)
+      return fail(MM_EINVAL, "correlated noise needs ndet * nsamp < 2^31");
     pl->G = G;
     pl->logLmax = pl->logM1 > pl->logM2 ? pl->logM1 : pl->logM2;
   }
@@ -1114,6 +1299,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->hist = take(size_t(3) * (kHistCap + 1) * 8);
   L->misc = take(256);
   L->spec = take(size_t(kSpecBlocks + 1) * kSpecMaxBins * 4 * 8);
+  L->corr_edges = take(pl->corr_rank > 0 ? size_t(pl->corr_nbins + 1) * 4 : 0);
   const int ngroups = (d->ndet + pl->G - 1) / pl->G;
   const size_t csr_n = pl->csr ? size_t(ngroups) * pl->G * size_t(n) : 0;
   L->csr_cnt = take(pl->csr ? size_t(ngroups) * npix * 4 : 0);
@@ -1163,6 +1349,9 @@ static mm_status upload_t(ScanImpl* s, hipStream_t st) {
   table(tm, Lm, 1, Lm);
   MM_HIP(hipMemcpyAsync(s->ws + s->lay.tw_map, tm.data(), tm.size() * sizeof(Cx<double>),
                         hipMemcpyHostToDevice, st));
+  if (pl.corr_rank > 0)
+    MM_HIP(hipMemcpyAsync(s->ws + s->lay.corr_edges, s->d.corr_edges,
+                          size_t(pl.corr_nbins + 1) * 4, hipMemcpyHostToDevice, st));
   MM_HIP(hipStreamSynchronize(st));
   return MM_OK;
 }

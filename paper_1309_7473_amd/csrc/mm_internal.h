@@ -71,6 +71,7 @@ struct Layout {
   size_t hist;       // 3 * (kHistCap+1) double
   size_t misc;       // small ints / doubles (ref key, floor count, lambda max)
   size_t spec;       // map-spectra partials and result (kSpecBlocks+1) * kSpecMaxBins * 4 double
+  size_t corr_edges; // corr_nbins + 1 int32 (copied from the descriptor)
   size_t csr_cnt;    // ngroups * npix int32 (counts, then fill cursors)
   size_t csr_off;    // ngroups * (npix+1) int32
   size_t csr_idx;    // ngroups * G * n int32 (group-relative sample index)
@@ -82,6 +83,8 @@ struct Plan {
   bool f64;
   bool bf16;         // bfloat16 timestream and pass buffers (float math)
   bool acc32;        // compensated float32 accumulation (MM_ACC_F32X2)
+  int corr_rank;     // > 0: inter-detector correlated N^-1 (one group, split pass 2)
+  int corr_nbins;
   bool single;       // whole detector filtered in one kernel
   bool csr;          // P^T by per-pixel gather (else atomic scatter)
   int logn, logM;    // n = 2^logn samples, M = n/2 packed complex

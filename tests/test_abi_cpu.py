@@ -100,6 +100,26 @@ def test_invalid_descriptions_rejected(mm, field, value):
     assert st == mm.MM_EINVAL and not h.value
 
 
+def test_correlated_noise_descriptions(mm):
+    import numpy as np
+    n = 1 << 16
+    edges = np.array([0, 10, 100, n // 2 + 1], np.int32)
+    ok = _desc(mm, corr_rank=2, corr_nbins=3, corr_edges=edges.ctypes.data)
+    assert mm.mm_scan_workspace_bytes(ok) > 0
+    bad = [dict(corr_rank=17, corr_nbins=3, corr_edges=edges.ctypes.data),
+           dict(corr_rank=2, corr_nbins=0, corr_edges=edges.ctypes.data),
+           dict(corr_rank=2, corr_nbins=3, corr_edges=None)]
+    short = np.array([0, 10, 100, n // 2], np.int32)          # does not reach n/2 + 1
+    flat = np.array([0, 10, 10, n // 2 + 1], np.int32)       # not increasing
+    bad += [dict(corr_rank=2, corr_nbins=3, corr_edges=short.ctypes.data),
+            dict(corr_rank=2, corr_nbins=3, corr_edges=flat.ctypes.data)]
+    tiny = np.array([0, 10, (1 << 12) // 2 + 1], np.int32)    # nsamp below 2^13
+    bad += [dict(corr_rank=2, corr_nbins=2, corr_edges=tiny.ctypes.data, nsamp=1 << 12)]
+    for kw in bad:
+        assert mm.mm_scan_workspace_bytes(_desc(mm, **kw)) == 0, kw
+        assert mm.mm_last_error()
+
+
 def test_compensated_accumulation_needs_the_gather(mm):
     d = _desc(mm, acc=mm.MM_ACC_F32X2, scatter=mm.MM_SCATTER_ATOMIC)
     assert mm.mm_scan_workspace_bytes(d) == 0
