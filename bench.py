@@ -204,6 +204,41 @@ def ps_leg(scan, b, x_sky, dell=1000.0, nbins=21, block=10):
                                                      for i, c in enumerate(comp)}}
 
 
+def correlated_leg(inp, x_sky, rank=2, nbins=16, reps=10):
+    """The same workload with the inter-detector correlated inverse noise
+    (common mode and rank-1 more, 16 log-spaced frequency bins): A-apply
+    time, its stages, and circulant PCG to 1e-6."""
+    import torch
+    import paper_1309_7473_amd as mm
+    from synth import with_correlated_noise
+    cin = with_correlated_noise(inp, rank=rank, nbins=nbins, seed=(2, 0))
+    scan = mm.Scan(cin, tod_dtype="f32")
+    y = scan.new_map()
+    for _ in range(2):
+        scan.apply_A(x_sky, y)
+    mm.mm_profile_enable(scan.handle, True)
+    mm.mm_profile_read(scan.handle)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        scan.apply_A(x_sky, y)
+    torch.cuda.synchronize()
+    prof = mm.mm_profile_read(scan.handle)
+    mm.mm_profile_enable(scan.handle, False)
+    a_ms = prof["apply_A"][0] / prof["apply_A"][1]
+    S = cin.ndet * cin.nsamp
+    b = scan.apply_A(x_sky)
+    scan.build_precon("circulant", sigma=20.0)
+    r = scan.pcg("circulant", b, tol=1e-6, maxiter=5000, check_every=10, history=False)
+    out = {"rank": rank, "nbins": len(cin.corr_edges) - 1, "apply_ms": round(a_ms, 4),
+           "samples_per_s": S / (a_ms * 1e-3),
+           "stage_us_per_launch": {k: round(v[0] / v[1] * 1e3, 1) for k, v in prof.items()
+                                   if k != "apply_A"},
+           "circulant_iters": r["iters"], "circulant_time_s": round(r["t_solve_s"], 4),
+           "converged": r["converged"]}
+    scan.close()
+    return out
+
+
 def cpu_baseline(inp, ndet_sample=128, reps=2):
     """The FP64 oracle's A-apply on the first ndet_sample detectors."""
     import numpy as np
@@ -400,6 +435,7 @@ def main():
         solves["circulant"]["setup_s"] = round(t_setup_circ, 4)
         solves["learned"] = learned_leg(mm, scan, b, args)
         solves["ps_convergence"] = ps_leg(scan, b, x_sky)
+        solves["correlated_noise"] = correlated_leg(inp, x_sky)
 
     if args.calibrate_copy:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")

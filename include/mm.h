@@ -344,8 +344,10 @@ mm_status mm_get_mask(mm_scan scan, int32_t* dst, void* stream);
  * column FFTs), 2 pass 2 (row FFTs + 1/N(f) + inverse row FFTs), 3 pass 3
  * (inverse column FFTs, + atomic scatter without the pixel index), 4 one
  * whole A-apply or right-hand side, 5 one preconditioner apply, 6 the
- * per-pixel gather of P^T.  samples[i] counts the timestream samples
- * (stages 0-4, 6) or map entries (stage 5) the launches processed. */
+ * per-pixel gather of P^T, 7 the cross-detector projection of correlated
+ * noise (pass 2 then times its unpack and its filtered repack).
+ * samples[i] counts the timestream samples (stages 0-4, 6, 7) or map entries
+ * (stage 5) the launches processed. */
 typedef struct {
   int32_t n_stages;
   double  ms[8];

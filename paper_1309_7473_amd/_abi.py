@@ -66,7 +66,7 @@ class mm_profile(C.Structure):
                 ("samples", C.c_int64 * 8)]
 
 
-PROFILE_STAGES = ["single", "pass1", "pass2", "pass3", "apply_A", "precon", "reduce", ""]
+PROFILE_STAGES = ["single", "pass1", "pass2", "pass3", "apply_A", "precon", "reduce", "corr"]
 MM_SCATTER_AUTO, MM_SCATTER_ATOMIC = 0, 1
 
 

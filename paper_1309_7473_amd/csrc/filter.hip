@@ -99,6 +99,16 @@ struct PassArgs {
   T scale;              // 1/M
 };
 
+// Inter-detector correlated inverse noise (pass 2 in three steps).
+constexpr int kMaxCorrRank = 16;
+
+struct CorrArgs {
+  const float* V;          // [nbins][ndet][rank]
+  const int16_t* bin;      // [M + 1] bin of each four-step slot (entry M: bin of k = M)
+  void* t;                 // [rank][M] complex: the projections sum_d V_b[d][j] X_d
+  int rank, ndet;
+};
+
 // --------------------------------------------------------------- samples
 template <typename T, typename S, int NC, int SRC>
 __device__ __forceinline__ T source_sample(const PassArgs<T, S>& a, int64_t s) {
@@ -545,7 +555,7 @@ __device__ __forceinline__ int pad_e(int i) {
 // place in natural order.  MODE 2: load the filtered spectrum Y, repack,
 // inverse FFT.
 template <typename T, typename S, int E, int PB, int MODE>
-__global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
+__global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a, CorrArgs c) {
   constexpr int LOGE = (E == 8) ? 3 : (E == 16) ? 4 : 5;
   constexpr int L = 64 * E;              // = M2
   constexpr int LOGL = LOGE + 6;
@@ -590,7 +600,50 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
 #pragma unroll
     for (int r = 0; r < E; ++r) R[pad_e<LOGE>(lane * E + r)] = v[r];
   } else {
-    for (int i = lane; i < L; i += 64) R[pad_e<LOGE>(i)] = Sto<T, S>::ld(w + i);
+    // Y = (1/M) (iN_d X - sum_j V_b[d][j] t_j) for this wave's row (detector g)
+    const Cx<T>* t = static_cast<const Cx<T>*>(c.t);
+    const float* iNr = a.iNt + int64_t(g) * (M + 1);
+    const T sc = a.scale;
+    // all loads of the row first (lane holds elements lane + 64 r), then the
+    // rank terms, whose V rows depend on the loaded bins
+    Cx<T> xs[E];
+    T dn[E];
+    int bs[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int slot = myrow * L + lane + 64 * r;
+      xs[r] = Sto<T, S>::ld(w + lane + 64 * r);
+      dn[r] = T(iNr[slot]);
+      bs[r] = c.bin[slot];
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = lane + 64 * r;
+      const int slot = myrow * L + i;
+      const Cx<T> x = xs[r];
+      Cx<T> y;
+      if (slot != 0) {
+        const float* v = c.V + (int64_t(bs[r]) * c.ndet + g) * c.rank;
+        T yr = dn[r] * x.x, yi = dn[r] * x.y;
+        for (int j = 0; j < c.rank; ++j) {
+          const Cx<T> tj = t[(int64_t(j) << a.logM) + slot];
+          yr -= T(v[j]) * tj.x;
+          yi -= T(v[j]) * tj.y;
+        }
+        y = cx(sc * yr, sc * yi);
+      } else {   // X[0] and X[M], real, with their own bins and gains
+        const float* v0 = c.V + (int64_t(c.bin[0]) * c.ndet + g) * c.rank;
+        const float* vN = c.V + (int64_t(c.bin[M]) * c.ndet + g) * c.rank;
+        T y0 = T(iNr[0]) * x.x, yM = T(iNr[M]) * x.y;
+        for (int j = 0; j < c.rank; ++j) {
+          const Cx<T> tj = t[int64_t(j) << a.logM];
+          y0 -= T(v0[j]) * tj.x;
+          yM -= T(vN[j]) * tj.y;
+        }
+        y = cx(sc * y0, sc * yM);
+      }
+      R[pad_e<LOGE>(i)] = y;
+    }
   }
   __syncthreads();
   auto radix8 = [&](int logNs, bool inv, bool to_lds) {
@@ -732,88 +785,64 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a) {
   radix8(LOGE + 3, true, false);
 }
 
-// Inter-detector correlated N^-1 on the unpacked spectra of one group that
-// holds every detector: slot s = k1*M2 + k2 holds X_d[k] for frequency
-// k = k1 + M1*k2 (slot 0: X_d[0] and X_d[M] as re and im).  With b the bin
-// of k, Y_d = (1/M) (iN_d[k] X_d - sum_j V_b[d][j] t_j), t_j = sum_d V_b[d][j] X_d.
-// One thread per slot; V rows are shared by the threads of a bin.
-constexpr int kMaxCorrRank = 16;
+// Inter-detector correlated N^-1, first half: on the unpacked spectra of the
+// one group that holds every detector (slot s = k1*M2 + k2 holds X_d[k] for
+// k = k1 + M1*k2; slot 0 holds X_d[0] and X_d[M] as re and im), the low-rank
+// projections t_j[s] = sum_d V_b[d][j] X_d[s] with b = bin[s] (slot 0: bins of
+// k = 0 and k = M for the two real parts).  The second half,
+// Y_d = (1/M) (iN_d X_d - sum_j V_b[d][j] t_j), is fused into the repack of
+// pass 2 (MODE 2).  One thread per slot, detectors unrolled four deep.
+template <typename T, typename S, int RMAX, int SPT>
+__global__ void __launch_bounds__(256) k_corr_t(PassArgs<T, S> a, CorrArgs c) {
+  // SPT consecutive slots per thread, so a wavefront reads 64 * SPT
+  // contiguous entries of each detector's spectrum
+  const int M = 1 << a.logM;
+  const int s0 = (blockIdx.x * blockDim.x + threadIdx.x) * SPT;
+  if (s0 >= M) return;
+  int b[SPT];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) b[q] = c.bin[s0 + q];
+  const int bN = c.bin[M];   // slot 0's imaginary part is the Nyquist bin
+  T tr[SPT][RMAX], ti[SPT][RMAX];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q)
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) tr[q][j] = ti[q][j] = T(0);
+  const auto* w = a.work + s0;
+  for (int d = 0; d < c.ndet; ++d) {
+    Cx<T> x[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) x[q] = Sto<T, S>::ld(w + (int64_t(d) << a.logM) + q);
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      const float* vr = c.V + (int64_t(b[q]) * c.ndet + d) * c.rank;
+      const float* vi = (s0 + q == 0) ? c.V + (int64_t(bN) * c.ndet + d) * c.rank : vr;
+#pragma unroll
+      for (int j = 0; j < RMAX; ++j)
+        if (j < c.rank) {
+          tr[q][j] += T(vr[j]) * x[q].x;
+          ti[q][j] += T(vi[j]) * x[q].y;
+        }
+    }
+  }
+  Cx<T>* t = static_cast<Cx<T>*>(c.t);
+#pragma unroll
+  for (int q = 0; q < SPT; ++q)
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j)
+      if (j < c.rank) t[(int64_t(j) << a.logM) + s0 + q] = cx(tr[q][j], ti[q][j]);
+}
 
 template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_corr_mix(PassArgs<T, S> a, const float* __restrict__ V,
-                                                  const int32_t* __restrict__ edges, int nbins,
-                                                  int rank, int ndet) {
-  extern __shared__ int32_t sedge[];
-  for (int i = threadIdx.x; i <= nbins; i += blockDim.x) sedge[i] = edges[i];
-  __syncthreads();
-  const int M = 1 << a.logM;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= M) return;
-  auto bin_of = [&](int k) {   // largest b with edges[b] <= k
-    int lo = 0, hi = nbins - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (sedge[mid] <= k) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-  };
-  const int k = (s >> a.logM2) + ((s & ((1 << a.logM2) - 1)) << a.logM1);
-  const T sc = a.scale;
-  // two passes over the detectors (the second re-reads X from cache)
-  auto mix = [&](int b, auto getx, auto iNd, auto put) {
-    T tr[kMaxCorrRank], ti[kMaxCorrRank];   // fully unrolled: stays in registers
-#pragma unroll
-    for (int j = 0; j < kMaxCorrRank; ++j) tr[j] = ti[j] = T(0);
-    for (int d = 0; d < ndet; ++d) {
-      const Cx<T> x = getx(d);
-      const float* v = V + (int64_t(b) * ndet + d) * rank;
-#pragma unroll
-      for (int j = 0; j < kMaxCorrRank; ++j) {
-        if (j < rank) {
-          tr[j] += T(v[j]) * x.x;
-          ti[j] += T(v[j]) * x.y;
-        }
-      }
-    }
-    for (int d = 0; d < ndet; ++d) {
-      const Cx<T> x = getx(d);
-      const float* v = V + (int64_t(b) * ndet + d) * rank;
-      T yr = T(iNd(d)) * x.x, yi = T(iNd(d)) * x.y;
-#pragma unroll
-      for (int j = 0; j < kMaxCorrRank; ++j) {
-        if (j < rank) {
-          yr -= T(v[j]) * tr[j];
-          yi -= T(v[j]) * ti[j];
-        }
-      }
-      put(d, cx(sc * yr, sc * yi));
-    }
-  };
-  auto* w = a.work;
-  const float* iNt = a.iNt;
-  if (s != 0) {
-    mix(bin_of(k), [&](int d) { return Sto<T, S>::ld(w + (int64_t(d) << a.logM) + s); },
-        [&](int d) { return iNt[int64_t(d) * (M + 1) + s]; },
-        [&](int d, Cx<T> y) { Sto<T, S>::st(w + (int64_t(d) << a.logM) + s, y); });
-  } else {
-    // DC (re part, bin of k = 0) and Nyquist (im part, bin of k = M), both real;
-    // the results are combined into slot 0 after both passes
-    const int bN = bin_of(M);
-    mix(0, [&](int d) { return cx(Sto<T, S>::ld(w + (int64_t(d) << a.logM)).x, T(0)); },
-        [&](int d) { return iNt[int64_t(d) * (M + 1)]; },
-        [&](int d, Cx<T> y) {
-          Cx<T> z = Sto<T, S>::ld(w + (int64_t(d) << a.logM));
-          z.x = y.x;
-          Sto<T, S>::st(w + (int64_t(d) << a.logM), z);
-        });
-    mix(bN, [&](int d) { return cx(Sto<T, S>::ld(w + (int64_t(d) << a.logM)).y, T(0)); },
-        [&](int d) { return iNt[int64_t(d) * (M + 1) + M]; },
-        [&](int d, Cx<T> y) {
-          Cx<T> z = Sto<T, S>::ld(w + (int64_t(d) << a.logM));
-          z.y = y.x;
-          Sto<T, S>::st(w + (int64_t(d) << a.logM), z);
-        });
-  }
+static void launch_corr_t(int M, hipStream_t st, const PassArgs<T, S>& a, const CorrArgs& c) {
+  constexpr int SPT = sizeof(T) == 8 ? 2 : 1;   // measured best at 256 detectors
+  const dim3 g((M / SPT + 255) / 256), b(256);
+  if (c.rank <= 4)
+    hipLaunchKernelGGL((k_corr_t<T, S, 4, SPT>), g, b, 0, st, a, c);
+  else if (c.rank <= 8)
+    hipLaunchKernelGGL((k_corr_t<T, S, 8, SPT>), g, b, 0, st, a, c);
+  else
+    hipLaunchKernelGGL((k_corr_t<T, S, kMaxCorrRank, 1>), dim3((M + 255) / 256), b, 0, st, a, c);
 }
 
 // CSR = true: store the filtered, packed timestream back in place (the block
@@ -954,17 +983,18 @@ static void raise_lds_limit(K kernel, size_t bytes) {
 
 // pass 2 with one wavefront per row (one row pair per block) in a given mode
 template <typename T, typename S, int MODE>
-static void launch_pass2w(int M2, dim3 g, size_t lds, hipStream_t st, const PassArgs<T, S>& a) {
+static void launch_pass2w(int M2, dim3 g, size_t lds, hipStream_t st, const PassArgs<T, S>& a,
+                          const CorrArgs& c) {
   const dim3 b(128);
   if (M2 == 512) {
     raise_lds_limit(k_pass2w<T, S, 8, 1, MODE>, lds);
-    hipLaunchKernelGGL((k_pass2w<T, S, 8, 1, MODE>), g, b, lds, st, a);
+    hipLaunchKernelGGL((k_pass2w<T, S, 8, 1, MODE>), g, b, lds, st, a, c);
   } else if (M2 == 1024) {
     raise_lds_limit(k_pass2w<T, S, 16, 1, MODE>, lds);
-    hipLaunchKernelGGL((k_pass2w<T, S, 16, 1, MODE>), g, b, lds, st, a);
+    hipLaunchKernelGGL((k_pass2w<T, S, 16, 1, MODE>), g, b, lds, st, a, c);
   } else {
     raise_lds_limit(k_pass2w<T, S, 32, 1, MODE>, lds);
-    hipLaunchKernelGGL((k_pass2w<T, S, 32, 1, MODE>), g, b, lds, st, a);
+    hipLaunchKernelGGL((k_pass2w<T, S, 32, 1, MODE>), g, b, lds, st, a, c);
   }
 }
 
@@ -1066,20 +1096,28 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
         // detectors, repack and invert (the plan keeps M2 in 512..2048)
         if (!wave_rows || M2 < 512 || M2 > 2048)
           return fail(MM_EINVAL, "correlated noise: unsupported pass-2 row length");
-        launch_pass2w<T, S, 1>(M2, g2w, lds2w, st, a);
-        hipLaunchKernelGGL((k_corr_mix<T, S>), dim3((M + 255) / 256), dim3(256),
-                           size_t(pl.corr_nbins + 1) * 4, st, a, s->d.corr_V,
-                           s->at<int32_t>(s->lay.corr_edges), pl.corr_nbins, pl.corr_rank, gd);
-        launch_pass2w<T, S, 2>(M2, g2w, lds2w, st, a);
+        CorrArgs c;
+        c.V = s->d.corr_V;
+        c.bin = s->at<int16_t>(s->lay.corr_bin);
+        c.t = s->at<void>(s->lay.corr_t);
+        c.rank = pl.corr_rank;
+        c.ndet = gd;
+        launch_pass2w<T, S, 1>(M2, g2w, lds2w, st, a, c);
+        prof_end(s, st, tok, kProfPass2, gs);
+        prof_begin(s, st, &tok);
+        launch_corr_t<T, S>(M, st, a, c);
+        prof_end(s, st, tok, kProfCorr, gs);
+        prof_begin(s, st, &tok);
+        launch_pass2w<T, S, 2>(M2, g2w, lds2w, st, a, c);
       } else if (wave_rows && M2 == 512) {
         raise_lds_limit(k_pass2w<T, S, 8, PB, 0>, lds2w);
-        hipLaunchKernelGGL((k_pass2w<T, S, 8, PB, 0>), g2w, b2w, lds2w, st, a);
+        hipLaunchKernelGGL((k_pass2w<T, S, 8, PB, 0>), g2w, b2w, lds2w, st, a, CorrArgs{});
       } else if (wave_rows && M2 == 1024) {
         raise_lds_limit(k_pass2w<T, S, 16, PB, 0>, lds2w);
-        hipLaunchKernelGGL((k_pass2w<T, S, 16, PB, 0>), g2w, b2w, lds2w, st, a);
+        hipLaunchKernelGGL((k_pass2w<T, S, 16, PB, 0>), g2w, b2w, lds2w, st, a, CorrArgs{});
       } else if (wave_rows && M2 == 2048) {
         raise_lds_limit(k_pass2w<T, S, 32, PB, 0>, lds2w);
-        hipLaunchKernelGGL((k_pass2w<T, S, 32, PB, 0>), g2w, b2w, lds2w, st, a);
+        hipLaunchKernelGGL((k_pass2w<T, S, 32, PB, 0>), g2w, b2w, lds2w, st, a, CorrArgs{});
       } else if (M2 <= 1024) {
         raise_lds_limit(k_pass2<T, S, 8>, lds2);
         hipLaunchKernelGGL((k_pass2<T, S, 8>), g2, dim3(kNT), lds2, st, a);
@@ -1181,8 +1219,30 @@ __global__ void k_permute_iN(const float* __restrict__ iN, float* __restrict__ o
   }
 }
 
+// bin[s] of four-step slot s = k1*M2 + k2 (frequency k1 + M1*k2), bin[M] of k = M
+__global__ void k_corr_bins(const int32_t* __restrict__ edges, int nbins, int logM1, int logM2,
+                            int16_t* __restrict__ bin) {
+  const int M = 1 << (logM1 + logM2);
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > M) return;
+  const int k = (s == M) ? M : (s >> logM2) + ((s & ((1 << logM2) - 1)) << logM1);
+  int lo = 0, hi = nbins - 1;   // largest b with edges[b] <= k
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (edges[mid] <= k) lo = mid; else hi = mid - 1;
+  }
+  bin[s] = int16_t(lo);
+}
+
 mm_status permute_inverse_spectrum(ScanImpl* s, hipStream_t st) {
   if (s->plan.single) return MM_OK;
+  if (s->plan.corr_rank > 0) {
+    const int M = 1 << s->plan.logM;
+    hipLaunchKernelGGL(k_corr_bins, dim3((M + 1 + 255) / 256), dim3(256), 0, st,
+                       s->at<int32_t>(s->lay.corr_edges), s->plan.corr_nbins, s->plan.logM1,
+                       s->plan.logM2, s->at<int16_t>(s->lay.corr_bin));
+    MM_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_permute_iN, dim3(64, s->ndet), dim3(256), 0, st, s->d.inv_noise,
                      s->at<float>(s->lay.int_), s->plan.logM1, s->plan.logM2);
   MM_HIP(hipGetLastError());
@@ -1300,6 +1360,8 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->misc = take(256);
   L->spec = take(size_t(kSpecBlocks + 1) * kSpecMaxBins * 4 * 8);
   L->corr_edges = take(pl->corr_rank > 0 ? size_t(pl->corr_nbins + 1) * 4 : 0);
+  L->corr_bin = take(pl->corr_rank > 0 ? size_t(M + 1) * 2 : 0);
+  L->corr_t = take(pl->corr_rank > 0 ? size_t(pl->corr_rank) * M * cxb : 0);
   const int ngroups = (d->ndet + pl->G - 1) / pl->G;
   const size_t csr_n = pl->csr ? size_t(ngroups) * pl->G * size_t(n) : 0;
   L->csr_cnt = take(pl->csr ? size_t(ngroups) * npix * 4 : 0);

@@ -19,7 +19,7 @@ constexpr int kProfStages = 8;   // see mm_profile in mm.h
 constexpr int kSpecBlocks = 256;   // blocks of the map-spectra binning
 constexpr int kSpecMaxBins = 512;  // multipole bins of mm_map_spectra
 constexpr int kProfSingle = 0, kProfPass1 = 1, kProfPass2 = 2, kProfPass3 = 3, kProfApplyA = 4,
-              kProfPrecon = 5, kProfReduce = 6;
+              kProfPrecon = 5, kProfReduce = 6, kProfCorr = 7;
 
 void set_error(const std::string& msg);
 mm_status fail(mm_status st, const std::string& msg);
@@ -72,6 +72,8 @@ struct Layout {
   size_t misc;       // small ints / doubles (ref key, floor count, lambda max)
   size_t spec;       // map-spectra partials and result (kSpecBlocks+1) * kSpecMaxBins * 4 double
   size_t corr_edges; // corr_nbins + 1 int32 (copied from the descriptor)
+  size_t corr_bin;   // M + 1 int16: frequency bin of each four-step slot
+  size_t corr_t;     // corr_rank * M complex: low-rank projections of the spectra
   size_t csr_cnt;    // ngroups * npix int32 (counts, then fill cursors)
   size_t csr_off;    // ngroups * (npix+1) int32
   size_t csr_idx;    // ngroups * G * n int32 (group-relative sample index)

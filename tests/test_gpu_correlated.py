@@ -30,6 +30,9 @@ CASES = [
     ("f32-rank2", 3, 6, 2**14, 2, "f32"),
     ("f32-I-rank3", 1, 4, 2**13, 3, "f32"),
     ("f64-m2=1024", 3, 3, 2**20, 2, "f64"),
+    ("f32-rank6", 3, 8, 2**14, 6, "f32"),
+    ("f64-rank12", 3, 14, 2**14, 12, "f64"),
+    ("bf16-rank2", 3, 6, 2**14, 2, "bf16"),
 ]
 
 
@@ -46,15 +49,18 @@ def test_correlated_apply_and_rhs_parity(case):
         e = rel(pair.A_gpu(v), pair.A_oracle(v))
         print(f"[corr {label}] A {name} rel err {e:.3e} (m1 {info['fft_m1']} m2 {info['fft_m2']})",
               flush=True)
-        assert e <= (TOL64 if dt == "f64" else t32), e
+        assert e <= {"f64": TOL64, "f32": t32, "bf16": 2.0**-8}[dt], e
     import torch
     tod = np.random.default_rng(5).standard_normal((ndet, n))
     b_want = oracle.rhs(pair.o, tod, pair.mask)
+    if dt == "bf16":   # the caller hands bfloat16 data: both sides see it
+        tod = torch.from_numpy(tod.astype(np.float32)).to(torch.bfloat16).double().numpy()
+        b_want = oracle.rhs(pair.o, tod, pair.mask)
     tdev = torch.from_numpy(tod.astype(np.float64 if dt == "f64" else np.float32)).cuda()
     b_got = pair.host(pair.g.rhs(tdev))
     e = rel(b_got, b_want)
     print(f"[corr {label}] rhs rel err {e:.3e}", flush=True)
-    assert e <= (TOL64 if dt == "f64" else 3e-6), e
+    assert e <= {"f64": TOL64, "f32": 3e-6, "bf16": 2 * 2.0**-8}[dt], e
 
 
 def test_zero_correlation_equals_the_independent_path():
