@@ -67,7 +67,10 @@ typedef enum {
   MM_M_JACOBI = 1,     /* eq. 5: per-pixel blocks of P^T P */
   MM_M_BINNED = 2,     /* eq. 3-4: per-pixel blocks of P^T diag(N^-1_tt) P */
   MM_M_CIRCULANT = 3,  /* eq. 8-13: Sigma^-1 F^-1 K(k)^-1 F Sigma^-T */
-  MM_M_LEARNED = 4     /* M_C + Sigma^-1 H^T H Sigma^-T (mm_learned_attach) */
+  MM_M_LEARNED = 4,    /* M_C + Sigma^-1 H^T H Sigma^-T (mm_learned_attach) */
+  MM_M_TILED = 5       /* Summary section: overlapping tiles, each with its own
+                          constant-correlation kernel, merged by a partition
+                          of unity (mm_apply_precon_tiled) */
 } mm_precon;
 
 /* Description of one scan (one set of detector timestreams and pointing). */
@@ -172,7 +175,17 @@ typedef struct {
                                eigenvalue floor; 0: eq. 12 literally (general
                                3x3 inverse per wavenumber, no floor) */
   double  eig_floor_rel;    /* floor = eig_floor_rel * max eigenvalue over all
-                               wavenumbers; <= 0 selects 1e-6 */
+                               wavenumbers (of the tile, for MM_M_TILED);
+                               <= 0 selects 1e-6 */
+  /* MM_M_TILED only (ref_y/ref_x and symmetrize are ignored there: each tile
+   * probes the active pixel nearest its centre and is always symmetrised) */
+  int32_t tile;             /* tile side T: a power of two, 8 <= T <= min(ny, nx);
+                               tiles start every T/2 pixels */
+  void*   tiled_workspace;  /* device memory of mm_tiled_workspace_bytes(scan,
+                               tile) bytes, 256-byte aligned, owned by the caller
+                               and kept alive (unchanged) while the preconditioner
+                               is used */
+  size_t  tiled_workspace_bytes;
 } mm_precon_opts;
 
 /* Builds a preconditioner on `stream`.  JACOBI, BINNED: per-pixel inverse
@@ -193,6 +206,22 @@ mm_status mm_apply_precon_binned(mm_scan scan, int32_t precon, const double* r,
  * circulant preconditioner was not built. */
 mm_status mm_apply_precon_circulant(mm_scan scan, const double* r, double* z,
                                     void* stream);
+
+/* Bytes of device workspace the tiled preconditioner (Summary section) needs
+ * for tile side `tile` on this scan's map: the per-tile inverse kernels
+ * (ntiles T^2 ncomp^2 complex float64), the tile planes, four probe responses
+ * and small tables, with ntiles = (2 ny/T - 1)(2 nx/T - 1).  0 if the tile
+ * size is invalid (not a power of two in [8, min(ny, nx)], or more than 65535
+ * tiles). */
+size_t mm_tiled_workspace_bytes(mm_scan scan, int32_t tile);
+
+/* z = M_T r = Sigma^-1 [sum_t sqrt(W_t) F_t^-1 K_t^-1 F_t sqrt(W_t)] Sigma^-T r
+ * (Summary section): per T x T tile t at stride T/2, the tile's own kernel
+ * K_t (built like eq. 10-11 from a probe at the tile's reference pixel on the
+ * tile's periodic displacement grid), merged by sin^2 weights W_t that sum to
+ * one at every pixel.  r, z: [ncomp][ny][nx] float64.  MM_ENOTBUILT if
+ * mm_build_precon(MM_M_TILED) has not run. */
+mm_status mm_apply_precon_tiled(mm_scan scan, const double* r, double* z, void* stream);
 
 typedef struct {
   double  tol;              /* stop when ||r||_2 <= tol ||b||_2 (recursive residual) */

@@ -18,12 +18,12 @@ from ._abi import (  # noqa: F401
     lib, check, MMError, mm_scan_desc, mm_precon_opts, mm_pcg_opts, mm_pcg_result,
     mm_scan_info, MM_OK, MM_ENOCONV, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENOTBUILT,
     MM_EBREAKDOWN, MM_F32, MM_BF16, MM_F64, MM_M_NONE, MM_M_JACOBI, MM_M_BINNED,
-    MM_M_CIRCULANT, MM_M_LEARNED, LIB_PATH, mm_profile, PROFILE_STAGES, MM_SCATTER_AUTO,
+    MM_M_CIRCULANT, MM_M_LEARNED, MM_M_TILED, LIB_PATH, mm_profile, PROFILE_STAGES, MM_SCATTER_AUTO,
     MM_SCATTER_ATOMIC, mm_train_opts, MM_ACC_F64, MM_ACC_F32X2,
 )
 
 PRECON = {"none": MM_M_NONE, "jacobi": MM_M_JACOBI, "binned": MM_M_BINNED,
-          "circulant": MM_M_CIRCULANT, "learned": MM_M_LEARNED}
+          "circulant": MM_M_CIRCULANT, "learned": MM_M_LEARNED, "tiled": MM_M_TILED}
 
 
 def _stream(stream):
@@ -88,6 +88,16 @@ def mm_apply_precon_circulant(h, r, z, stream=None):
     check(lib.mm_apply_precon_circulant(h, _ptr(r, torch.float64, name="r"),
                                         _ptr(z, torch.float64, name="z"), _stream(stream)),
           "mm_apply_precon_circulant")
+
+
+def mm_tiled_workspace_bytes(h, tile):
+    return int(lib.mm_tiled_workspace_bytes(h, int(tile)))
+
+
+def mm_apply_precon_tiled(h, r, z, stream=None):
+    check(lib.mm_apply_precon_tiled(h, _ptr(r, torch.float64, name="r"),
+                                    _ptr(z, torch.float64, name="z"), _stream(stream)),
+          "mm_apply_precon_tiled")
 
 
 def mm_pcg_solve(h, precon, b, x, opts, stream=None, history_len=0):
@@ -351,18 +361,30 @@ class Scan:
         return b
 
     def build_precon(self, name, ref=None, sigma=0.0, symmetrize=True, eig_floor_rel=0.0,
-                     stream=None):
+                     tile=0, stream=None):
+        """tile: side of the tiles of the "tiled" preconditioner; its device
+        workspace is allocated here and held by this object."""
         o = mm_precon_opts()
         o.ref_y, o.ref_x = (-1, -1) if ref is None else (int(ref[0]), int(ref[1]))
         o.gauss_sigma_px = float(sigma) if sigma else 0.0
         o.symmetrize = 1 if symmetrize else 0
         o.eig_floor_rel = float(eig_floor_rel)
+        if name == "tiled":
+            nb = mm_tiled_workspace_bytes(self.handle, tile)
+            if nb == 0:
+                raise ValueError(f"invalid tile size {tile} for a {self.ny} x {self.nx} map")
+            self._tiled_ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            o.tile = int(tile)
+            o.tiled_workspace = self._tiled_ws.data_ptr()
+            o.tiled_workspace_bytes = nb
         mm_build_precon(self.handle, PRECON[name], o, stream)
 
     def apply_precon(self, name, r, z=None, stream=None):
         z = self.new_map() if z is None else z
         if name == "circulant":
             mm_apply_precon_circulant(self.handle, r, z, stream)
+        elif name == "tiled":
+            mm_apply_precon_tiled(self.handle, r, z, stream)
         elif name == "learned":
             mm_apply_precon_learned(self.handle, r, z, stream)
         else:

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libmm.so")
 MM_OK, MM_ENOCONV, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENOTBUILT, MM_EBREAKDOWN = 0, 1, -1, -2, -3, -4, -5
 MM_F32, MM_BF16, MM_F64 = 0, 1, 2
 MM_ACC_F64, MM_ACC_F32X2 = 0, 1
-MM_M_NONE, MM_M_JACOBI, MM_M_BINNED, MM_M_CIRCULANT, MM_M_LEARNED = 0, 1, 2, 3, 4
+MM_M_NONE, MM_M_JACOBI, MM_M_BINNED, MM_M_CIRCULANT, MM_M_LEARNED, MM_M_TILED = 0, 1, 2, 3, 4, 5
 
 STATUS_NAMES = {0: "MM_OK", 1: "MM_ENOCONV", -1: "MM_EINVAL", -2: "MM_ENOMEM",
                 -3: "MM_EDEVICE", -4: "MM_ENOTBUILT", -5: "MM_EBREAKDOWN"}
@@ -34,7 +34,9 @@ class mm_scan_desc(C.Structure):
 
 class mm_precon_opts(C.Structure):
     _fields_ = [("ref_y", C.c_int32), ("ref_x", C.c_int32), ("gauss_sigma_px", C.c_double),
-                ("symmetrize", C.c_int32), ("eig_floor_rel", C.c_double)]
+                ("symmetrize", C.c_int32), ("eig_floor_rel", C.c_double),
+                ("tile", C.c_int32), ("tiled_workspace", C.c_void_p),
+                ("tiled_workspace_bytes", C.c_size_t)]
 
 
 class mm_pcg_opts(C.Structure):
@@ -80,6 +82,8 @@ SIGNATURES = {
     "mm_build_precon": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(mm_precon_opts), C.c_void_p]),
     "mm_apply_precon_binned": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mm_apply_precon_circulant": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mm_tiled_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int32]),
+    "mm_apply_precon_tiled": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mm_pcg_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                C.POINTER(mm_pcg_opts), C.POINTER(mm_pcg_result), C.c_void_p]),
     "mm_pcg_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32,

@@ -181,6 +181,16 @@ mm_status mm_build_precon(mm_scan scan, int32_t precon, const mm_precon_opts* op
       }
       return circulant_build(s, opts, static_cast<hipStream_t>(stream));
     }
+    case MM_M_TILED: {
+      if (!opts) return fail(MM_EINVAL, "MM_M_TILED needs opts (tile and workspace)");
+      if (!tiled_size_ok(s, opts->tile))
+        return fail(MM_EINVAL, "tile must be a power of two in [8, min(ny, nx)] with <= 65535 tiles");
+      if (!opts->tiled_workspace || reinterpret_cast<uintptr_t>(opts->tiled_workspace) % 256 != 0)
+        return fail(MM_EINVAL, "tiled_workspace must be a 256-byte aligned device pointer");
+      if (opts->tiled_workspace_bytes < tiled_workspace_bytes(s, opts->tile))
+        return fail(MM_ENOMEM, "tiled_workspace_bytes below mm_tiled_workspace_bytes");
+      return tiled_build(s, opts, static_cast<hipStream_t>(stream));
+    }
     default:
       return fail(MM_EINVAL, "unknown preconditioner");
   }
@@ -203,12 +213,26 @@ mm_status mm_apply_precon_circulant(mm_scan scan, const double* r, double* z, vo
   return circulant_apply(s, r, z, static_cast<hipStream_t>(stream));
 }
 
+size_t mm_tiled_workspace_bytes(mm_scan scan, int32_t tile) {
+  ScanImpl* s = get(scan);
+  return s ? tiled_workspace_bytes(s, tile) : 0;
+}
+
+mm_status mm_apply_precon_tiled(mm_scan scan, const double* r, double* z, void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  if (!r || !z) return fail(MM_EINVAL, "r and z are required");
+  return tiled_apply(s, r, z, static_cast<hipStream_t>(stream));
+}
+
 static mm_status check_solve(ScanImpl* s, int32_t precon, const double* b, double* x,
                              const mm_pcg_opts* opts) {
   if (!s) return fail(MM_EINVAL, "invalid scan handle");
   if (!b || !x || !opts) return fail(MM_EINVAL, "b, x and opts are required");
   if (!(opts->tol >= 0.0) || opts->maxiter < 0) return fail(MM_EINVAL, "bad tol or maxiter");
-  if (precon < MM_M_NONE || precon > MM_M_LEARNED) return fail(MM_EINVAL, "unknown preconditioner");
+  if (precon < MM_M_NONE || precon > MM_M_TILED) return fail(MM_EINVAL, "unknown preconditioner");
+  if (precon == MM_M_TILED && !s->tiled_built)
+    return fail(MM_ENOTBUILT, "tiled preconditioner not built");
   if ((precon == MM_M_CIRCULANT || precon == MM_M_LEARNED) && !s->circ_built)
     return fail(MM_ENOTBUILT, "circulant preconditioner not built");
   if (precon == MM_M_LEARNED && !s->learned)

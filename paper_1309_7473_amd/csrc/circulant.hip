@@ -15,6 +15,9 @@
 // passes of the LDS Stockham FFT over complex planes [plane][ny][nx].
 #include "fft_lds.h"
 #include "linalg_small.h"
+#include <cmath>
+#include <vector>
+
 #include "mm_internal.h"
 
 namespace mm {
@@ -156,8 +159,17 @@ static int ilog2i(int v) {
   return l;
 }
 
+static mm_status map_fft_dims(ScanImpl* s, Cx<double>* planes, int logny, int lognx, int nplanes,
+                              bool inv, hipStream_t st);
+
 mm_status map_fft(ScanImpl* s, Cx<double>* planes, int nplanes, bool inv, hipStream_t st) {
-  const int logny = ilog2i(s->ny), lognx = ilog2i(s->nx);
+  return map_fft_dims(s, planes, ilog2i(s->ny), ilog2i(s->nx), nplanes, inv, st);
+}
+
+// nplanes [2^logny][2^lognx] planes (sides up to the map's)
+static mm_status map_fft_dims(ScanImpl* s, Cx<double>* planes, int logny, int lognx, int nplanes,
+                              bool inv, hipStream_t st) {
+  const int ny = 1 << logny, nx = 1 << lognx;
   const int cap = kMapE * kNT;  // complex elements per block
   int logRB = ilog2i(cap) - lognx;
   if (logRB > logny) logRB = logny;
@@ -167,18 +179,23 @@ mm_status map_fft(ScanImpl* s, Cx<double>* planes, int nplanes, bool inv, hipStr
   if (logCB < 0) logCB = 0;
   const Cx<double>* tw = s->at<Cx<double>>(s->lay.tw_map);
   const int logL = s->plan.logMapL;
-  const size_t ldsr = (size_t(s->nx) << logRB) * sizeof(Cx<double>);
-  const size_t ldsc = (size_t(s->ny) << logCB) * sizeof(Cx<double>);
-  const dim3 gr(unsigned(s->ny >> logRB), unsigned(nplanes));
-  const dim3 gc(unsigned(s->nx >> logCB), unsigned(nplanes));
-  if (!inv) {
-    hipLaunchKernelGGL(k_map_rows<false>, gr, dim3(kNT), ldsr, st, planes, logny, lognx, logRB, logL, tw);
-    hipLaunchKernelGGL(k_map_cols<false>, gc, dim3(kNT), ldsc, st, planes, logny, lognx, logCB, logL, tw);
-  } else {
-    hipLaunchKernelGGL(k_map_cols<true>, gc, dim3(kNT), ldsc, st, planes, logny, lognx, logCB, logL, tw);
-    hipLaunchKernelGGL(k_map_rows<true>, gr, dim3(kNT), ldsr, st, planes, logny, lognx, logRB, logL, tw);
+  const size_t ldsr = (size_t(nx) << logRB) * sizeof(Cx<double>);
+  const size_t ldsc = (size_t(ny) << logCB) * sizeof(Cx<double>);
+  // planes go in chunks of at most 65535 (the grid's y limit)
+  for (int p0 = 0; p0 < nplanes; p0 += 65535) {
+    const int np = nplanes - p0 < 65535 ? nplanes - p0 : 65535;
+    Cx<double>* pl = planes + (int64_t(p0) << (logny + lognx));
+    const dim3 gr(unsigned(ny >> logRB), unsigned(np));
+    const dim3 gc(unsigned(nx >> logCB), unsigned(np));
+    if (!inv) {
+      hipLaunchKernelGGL(k_map_rows<false>, gr, dim3(kNT), ldsr, st, pl, logny, lognx, logRB, logL, tw);
+      hipLaunchKernelGGL(k_map_cols<false>, gc, dim3(kNT), ldsc, st, pl, logny, lognx, logCB, logL, tw);
+    } else {
+      hipLaunchKernelGGL(k_map_cols<true>, gc, dim3(kNT), ldsc, st, pl, logny, lognx, logCB, logL, tw);
+      hipLaunchKernelGGL(k_map_rows<true>, gr, dim3(kNT), ldsr, st, pl, logny, lognx, logRB, logL, tw);
+    }
+    MM_HIP(hipGetLastError());
   }
-  MM_HIP(hipGetLastError());
   return MM_OK;
 }
 
@@ -213,9 +230,13 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* addr, double 
   if (v > 0.0) atomicMax(addr, static_cast<unsigned long long>(__double_as_longlong(v)));
 }
 
+// blockIdx.y batches independent kernels (the tiles of the tiled
+// preconditioner): planes, inverses and the maximum advance by one kernel.
 template <int NC>
 __global__ void k_kinv_lmax(const Cx<double>* __restrict__ qhat, int npix,
                             unsigned long long* __restrict__ lmax_bits) {
+  qhat += int64_t(blockIdx.y) * NC * NC * npix;
+  lmax_bits += blockIdx.y;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   double m = 0.0;
   if (k < npix) {
@@ -233,10 +254,20 @@ __global__ void k_kinv_lmax(const Cx<double>* __restrict__ qhat, int npix,
 template <int NC>
 __global__ void k_kinv_floor(const Cx<double>* __restrict__ qhat, int npix,
                              const unsigned long long* __restrict__ lmax_bits, double eps,
-                             Cx<double>* __restrict__ kinv, int* __restrict__ nfloor) {
+                             Cx<double>* __restrict__ kinv, int* __restrict__ nfloor,
+                             const int32_t* __restrict__ skip = nullptr) {
+  qhat += int64_t(blockIdx.y) * NC * NC * npix;
+  kinv += int64_t(blockIdx.y) * NC * NC * npix;
+  lmax_bits += blockIdx.y;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npix) return;
   const double lmax = __longlong_as_double(static_cast<long long>(*lmax_bits));
+  // a tile without active pixels (or without a positive eigenvalue) adds nothing
+  if (skip && (skip[blockIdx.y] < 0 || !(lmax > 0.0))) {
+#pragma unroll
+    for (int i = 0; i < NC * NC; ++i) kinv[int64_t(k) * NC * NC + i] = cx(0.0, 0.0);
+    return;
+  }
   const double floor_v = eps * lmax;
   double R[2 * NC][2 * NC], V[2 * NC][2 * NC];
   embed_K<NC>(qhat, npix, k, R);
@@ -330,6 +361,8 @@ __global__ void k_circ_pre(const double* __restrict__ r, const double* __restric
 template <int NC>
 __global__ void k_circ_kmul(Cx<double>* __restrict__ planes, const Cx<double>* __restrict__ kinv,
                             int npix, double scale) {
+  planes += int64_t(blockIdx.y) * NC * npix;
+  kinv += int64_t(blockIdx.y) * NC * NC * npix;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npix) return;
   Cx<double> u[NC];
@@ -472,6 +505,294 @@ static mm_status apply_t(ScanImpl* s, const double* r, double* z, hipStream_t st
 mm_status circulant_apply(ScanImpl* s, const double* r, double* z, hipStream_t st) {
   if (!s->circ_built) return fail(MM_ENOTBUILT, "circulant preconditioner not built");
   return s->nc == 3 ? apply_t<3>(s, r, z, st) : apply_t<1>(s, r, z, st);
+}
+
+
+// ====================================================== tiled preconditioner
+// The position-dependent variant the Summary section proposes: T x T tiles at
+// stride T/2, each with its own constant-correlation kernel K_t built like
+// K but from a probe at the tile's reference pixel and on the tile's own
+// periodic T x T displacement grid, merged by a sin^2 partition of unity:
+//   M_T r = Sigma^-1 [ sum_t sqrt(W_t) F_t^-1 K_t^-1 F_t sqrt(W_t) ] Sigma^-T r.
+// Tiles fall into four interleaved probe sets by the parity of their tile row
+// and column; one A-apply per component and set probes all references of
+// the set at once.
+
+struct TiledLayout {
+  size_t kinv, planes, probes, tref, tset, swy, swx, lmax, nfloor, total;
+};
+
+static TiledLayout tiled_layout(const ScanImpl* s, int T) {
+  const int nc = s->nc;
+  const int nty = 2 * s->ny / T - 1, ntx = 2 * s->nx / T - 1;
+  const size_t nt = size_t(nty) * ntx, TT = size_t(T) * T;
+  TiledLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off += (b + 255) & ~size_t(255);
+    return o;
+  };
+  L.kinv = take(nt * TT * nc * nc * 16);
+  L.planes = take(nt * TT * nc * nc * 16);
+  L.probes = take(size_t(4) * nc * nc * s->npix * 8);
+  L.tref = take(nt * 4);
+  L.tset = take(nt * 4);
+  L.swy = take(size_t(nty) * T * 8);
+  L.swx = take(size_t(ntx) * T * 8);
+  L.lmax = take(nt * 8);
+  L.nfloor = take(8);
+  L.total = off;
+  return L;
+}
+
+// T a power of two in [8, map side]; the tile count fits a grid dimension
+bool tiled_size_ok(const ScanImpl* s, int T) {
+  if (T < 8 || (T & (T - 1)) != 0 || T > s->ny || T > s->nx) return false;
+  const long nt = long(2 * s->ny / T - 1) * (2 * s->nx / T - 1);
+  return nt <= 65535;
+}
+
+size_t tiled_workspace_bytes(const ScanImpl* s, int T) {
+  return tiled_size_ok(s, T) ? tiled_layout(s, T).total : 0;
+}
+
+// sqrt of the 1-D merge weight of tile i (of nt) at offset u
+static double tile_sqrt_weight(int i, int nt, int T, int u) {
+  if (nt == 1) return 1.0;
+  if ((i == 0 && u < T / 2) || (i == nt - 1 && u >= T / 2)) return 1.0;
+  const double sn = std::sin(3.14159265358979323846 * (u + 0.5) / T);
+  return std::fabs(sn);
+}
+
+__global__ void k_set_units(double* __restrict__ e, const int32_t* __restrict__ idx, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) e[idx[i]] = 1.0;
+}
+
+// planes[t][a*NC+b][y][x] = taper * sym q_t(d), d the minimal image of (y, x) on the tile
+template <int NC>
+__global__ void k_tq_assemble(const int32_t* __restrict__ mask, const double* __restrict__ probes,
+                              const double* __restrict__ siginv, int ny, int nx, int logT,
+                              const int32_t* __restrict__ tref, const int32_t* __restrict__ tset,
+                              double sigma, Cx<double>* __restrict__ planes) {
+  const int T = 1 << logT, TT = T * T;
+  const int t = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= TT) return;
+  Cx<double>* out = planes + int64_t(t) * NC * NC * TT + e;
+  const int ref = tref[t];
+  if (ref < 0) {
+#pragma unroll
+    for (int i = 0; i < NC * NC; ++i) out[int64_t(i) * TT] = cx(0.0, 0.0);
+    return;
+  }
+  const int npix = ny * nx;
+  const double* probe = probes + int64_t(tset[t]) * NC * NC * npix;
+  const int y = e >> logT, x = e & (T - 1);
+  // minimal images on the tile of d and of -d (both T/2 at the Nyquist index)
+  const int ym = (T - y) & (T - 1), xm = (T - x) & (T - 1);
+  const int my = y > T / 2 ? y - T : y, mx = x > T / 2 ? x - T : x;
+  const int mym = ym > T / 2 ? ym - T : ym, mxm = xm > T / 2 ? xm - T : xm;
+  const int ry = ref / nx, rx = ref % nx;
+  double q[NC][NC], qm[NC][NC];
+  q_raw<NC>((my + ny) % ny, (mx + nx) % nx, ry, rx, ny, nx, mask, probe, siginv, q);
+  q_raw<NC>((mym + ny) % ny, (mxm + nx) % nx, ry, rx, ny, nx, mask, probe, siginv, qm);
+  double g = 1.0;
+  if (sigma > 0.0) g = exp(-double(my * my + mx * mx) / (2.0 * sigma * sigma));
+#pragma unroll
+  for (int a = 0; a < NC; ++a)
+#pragma unroll
+    for (int b = 0; b < NC; ++b) out[int64_t(a * NC + b) * TT] = cx(g * 0.5 * (q[a][b] + qm[b][a]), 0.0);
+}
+
+// tile planes[t][a][y][x] = sqrt(W_t) * u_a(oy + y, ox + x), u = Sigma^-T r (global planes)
+template <int NC>
+__global__ void k_tile_gather(const Cx<double>* __restrict__ u, int ny, int nx, int logT, int ntx,
+                              const double* __restrict__ swy, const double* __restrict__ swx,
+                              Cx<double>* __restrict__ tp) {
+  const int T = 1 << logT, TT = T * T;
+  const int t = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= TT) return;
+  const int iy = t / ntx, ix = t % ntx;
+  const int y = e >> logT, x = e & (T - 1);
+  const int p = (iy * (T / 2) + y) * nx + ix * (T / 2) + x;
+  const double w = swy[iy * T + y] * swx[ix * T + x];
+  const int npix = ny * nx;
+#pragma unroll
+  for (int a = 0; a < NC; ++a)
+    tp[(int64_t(t) * NC + a) * TT + e] = cx(w * u[int64_t(a) * npix + p].x, 0.0);
+}
+
+// z = Sigma^-1 sum_t sqrt(W_t) v_t / T^2 over the (<= 4) tiles covering each pixel
+template <int NC>
+__global__ void k_tile_post(const Cx<double>* __restrict__ tp, const double* __restrict__ siginv,
+                            const int32_t* __restrict__ mask, int ny, int nx, int logT, int nty,
+                            int ntx, const double* __restrict__ swy, const double* __restrict__ swx,
+                            double* __restrict__ z) {
+  const int npix = ny * nx;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  const int T = 1 << logT, TT = T * T, h = T / 2;
+  const int y = p / nx, x = p % nx;
+  double v[NC];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) v[a] = 0.0;
+  for (int iy = y / h - 1; iy <= y / h; ++iy) {
+    if (iy < 0 || iy >= nty) continue;
+    const int uy = y - iy * h;
+    if (uy >= T) continue;
+    for (int ix = x / h - 1; ix <= x / h; ++ix) {
+      if (ix < 0 || ix >= ntx) continue;
+      const int ux = x - ix * h;
+      if (ux >= T) continue;
+      const int t = iy * ntx + ix;
+      const double w = swy[iy * T + uy] * swx[ix * T + ux];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) v[a] += w * tp[(int64_t(t) * NC + a) * TT + uy * T + ux].x;
+    }
+  }
+  const double sc = 1.0 / double(TT);
+  const double* S = siginv + 6 * int64_t(p);
+  const bool on = mask[p] != 0;
+  if constexpr (NC == 1) {
+    z[p] = on ? S[0] * v[0] * sc : 0.0;
+  } else {
+    z[p] = on ? (S[0] * v[0] + S[1] * v[1] + S[2] * v[2]) * sc : 0.0;
+    z[npix + p] = on ? (S[1] * v[0] + S[3] * v[1] + S[4] * v[2]) * sc : 0.0;
+    z[2 * int64_t(npix) + p] = on ? (S[2] * v[0] + S[4] * v[1] + S[5] * v[2]) * sc : 0.0;
+  }
+}
+
+template <int NC>
+static mm_status tiled_build_t(ScanImpl* s, const mm_precon_opts* o, hipStream_t st) {
+  const int T = o->tile, logT = ilog2i(T), TT = T * T;
+  const int ny = s->ny, nx = s->nx, npix = s->npix, h = T / 2;
+  const int nty = 2 * ny / T - 1, ntx = 2 * nx / T - 1, nt = nty * ntx;
+  char* tws = static_cast<char*>(o->tiled_workspace);
+  const TiledLayout TL = tiled_layout(s, T);
+  auto at = [&](size_t off) { return tws + off; };
+  // reference pixel per tile: the active pixel nearest the tile centre
+  std::vector<int32_t> mask(npix);
+  MM_HIP(hipMemcpyAsync(mask.data(), s->at<int32_t>(s->lay.mask), size_t(npix) * 4,
+                        hipMemcpyDeviceToHost, st));
+  MM_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> tref(nt, -1), tset(nt);
+  for (int iy = 0; iy < nty; ++iy)
+    for (int ix = 0; ix < ntx; ++ix) {
+      const int oy = iy * h, ox = ix * h, cy = oy + h, cxp = ox + h;
+      int best = -1;
+      long bd = 0;
+      for (int y = oy; y < oy + T; ++y)
+        for (int x = ox; x < ox + T; ++x) {
+          const int p = y * nx + x;
+          if (!mask[p]) continue;
+          const long d = long(y - cy) * (y - cy) + long(x - cxp) * (x - cxp);
+          if (best < 0 || d < bd || (d == bd && p < best)) {
+            best = p;
+            bd = d;
+          }
+        }
+      tref[iy * ntx + ix] = best;
+      tset[iy * ntx + ix] = 2 * (iy & 1) + (ix & 1);
+    }
+  std::vector<double> swy(size_t(nty) * T), swx(size_t(ntx) * T);
+  for (int i = 0; i < nty; ++i)
+    for (int u = 0; u < T; ++u) swy[size_t(i) * T + u] = tile_sqrt_weight(i, nty, T, u);
+  for (int i = 0; i < ntx; ++i)
+    for (int u = 0; u < T; ++u) swx[size_t(i) * T + u] = tile_sqrt_weight(i, ntx, T, u);
+  MM_HIP(hipMemcpyAsync(at(TL.tref), tref.data(), size_t(nt) * 4, hipMemcpyHostToDevice, st));
+  MM_HIP(hipMemcpyAsync(at(TL.tset), tset.data(), size_t(nt) * 4, hipMemcpyHostToDevice, st));
+  MM_HIP(hipMemcpyAsync(at(TL.swy), swy.data(), swy.size() * 8, hipMemcpyHostToDevice, st));
+  MM_HIP(hipMemcpyAsync(at(TL.swx), swx.data(), swx.size() * 8, hipMemcpyHostToDevice, st));
+  // probes: per set and component, every reference of the set at once
+  double* probes = reinterpret_cast<double*>(at(TL.probes));
+  double* e = s->at<double>(s->lay.vec) + 4 * int64_t(NC) * npix;   // the spare CG vector
+  mm_status r;
+  if ((r = fill_zero(probes, size_t(4) * NC * NC * npix * 8, st)) != MM_OK) return r;
+  int32_t* idx = reinterpret_cast<int32_t*>(at(TL.lmax));   // scratch until the floor
+  for (int set = 0; set < 4; ++set) {
+    std::vector<int32_t> refs;
+    for (int t = 0; t < nt; ++t)
+      if (tset[t] == set && tref[t] >= 0) refs.push_back(tref[t]);
+    if (refs.empty()) continue;
+    for (int g = 0; g < NC; ++g) {
+      std::vector<int32_t> units(refs.size());
+      for (size_t i = 0; i < refs.size(); ++i) units[i] = g * npix + refs[i];
+      if ((r = fill_zero(e, size_t(NC) * npix * 8, st)) != MM_OK) return r;
+      MM_HIP(hipMemcpyAsync(idx, units.data(), units.size() * 4, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_set_units, dim3(unsigned((units.size() + 255) / 256)), dim3(256), 0, st,
+                         e, idx, int(units.size()));
+      MM_HIP(hipGetLastError());
+      if ((r = filter_pipeline(s, 0, nullptr, e, probes + (int64_t(set) * NC + g) * NC * npix, st)) !=
+          MM_OK)
+        return r;
+      MM_HIP(hipStreamSynchronize(st));   // idx is reused by the next set
+    }
+  }
+  Cx<double>* planes = reinterpret_cast<Cx<double>*>(at(TL.planes));
+  const dim3 gt((TT + 255) / 256, nt), b(256);
+  hipLaunchKernelGGL(k_tq_assemble<NC>, gt, b, 0, st, s->at<int32_t>(s->lay.mask), probes,
+                     s->at<double>(s->lay.siginv), ny, nx, logT,
+                     reinterpret_cast<const int32_t*>(at(TL.tref)),
+                     reinterpret_cast<const int32_t*>(at(TL.tset)), o->gauss_sigma_px, planes);
+  MM_HIP(hipGetLastError());
+  if ((r = map_fft_dims(s, planes, logT, logT, nt * NC * NC, false, st)) != MM_OK) return r;
+  double eps = o->eig_floor_rel;
+  if (!(eps > 0.0)) eps = 1e-6;
+  unsigned long long* lmax = reinterpret_cast<unsigned long long*>(at(TL.lmax));
+  int* nfl = reinterpret_cast<int*>(at(TL.nfloor));
+  if ((r = fill_zero(lmax, size_t(nt) * 8, st)) != MM_OK) return r;
+  if ((r = fill_zero(nfl, 8, st)) != MM_OK) return r;
+  hipLaunchKernelGGL(k_kinv_lmax<NC>, gt, b, 0, st, planes, TT, lmax);
+  hipLaunchKernelGGL(k_kinv_floor<NC>, gt, b, 0, st, planes, TT, lmax, eps,
+                     reinterpret_cast<Cx<double>*>(at(TL.kinv)), nfl,
+                     reinterpret_cast<const int32_t*>(at(TL.tref)));
+  MM_HIP(hipGetLastError());
+  MM_HIP(hipStreamSynchronize(st));
+  s->tiled_T = T;
+  s->tiled_ws = tws;
+  s->tiled_built = true;
+  return MM_OK;
+}
+
+mm_status tiled_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st) {
+  s->tiled_built = false;
+  return s->nc == 3 ? tiled_build_t<3>(s, o, st) : tiled_build_t<1>(s, o, st);
+}
+
+template <int NC>
+static mm_status tiled_apply_t(ScanImpl* s, const double* rv, double* z, hipStream_t st) {
+  const int T = s->tiled_T, logT = ilog2i(T), TT = T * T;
+  const int ny = s->ny, nx = s->nx, npix = s->npix;
+  const int nty = 2 * ny / T - 1, ntx = 2 * nx / T - 1, nt = nty * ntx;
+  const TiledLayout TL = tiled_layout(s, T);
+  char* tws = s->tiled_ws;
+  Cx<double>* u = s->at<Cx<double>>(s->lay.planes);
+  Cx<double>* tp = reinterpret_cast<Cx<double>*>(tws + TL.planes);
+  const double* swy = reinterpret_cast<const double*>(tws + TL.swy);
+  const double* swx = reinterpret_cast<const double*>(tws + TL.swx);
+  const dim3 g((npix + 255) / 256), b(256), gt((TT + 255) / 256, nt);
+  hipLaunchKernelGGL(k_circ_pre<NC>, g, b, 0, st, rv, s->at<double>(s->lay.siginv),
+                     s->at<int32_t>(s->lay.mask), npix, u);
+  hipLaunchKernelGGL(k_tile_gather<NC>, gt, b, 0, st, u, ny, nx, logT, ntx, swy, swx, tp);
+  MM_HIP(hipGetLastError());
+  mm_status r;
+  if ((r = map_fft_dims(s, tp, logT, logT, nt * NC, false, st)) != MM_OK) return r;
+  hipLaunchKernelGGL(k_circ_kmul<NC>, gt, b, 0, st, tp,
+                     reinterpret_cast<const Cx<double>*>(tws + TL.kinv), TT, 1.0);
+  MM_HIP(hipGetLastError());
+  if ((r = map_fft_dims(s, tp, logT, logT, nt * NC, true, st)) != MM_OK) return r;
+  hipLaunchKernelGGL(k_tile_post<NC>, g, b, 0, st, tp, s->at<double>(s->lay.siginv),
+                     s->at<int32_t>(s->lay.mask), ny, nx, logT, nty, ntx, swy, swx, z);
+  MM_HIP(hipGetLastError());
+  return MM_OK;
+}
+
+mm_status tiled_apply(ScanImpl* s, const double* r, double* z, hipStream_t st) {
+  if (!s->tiled_built) return fail(MM_ENOTBUILT, "tiled preconditioner not built");
+  return s->nc == 3 ? tiled_apply_t<3>(s, r, z, st) : tiled_apply_t<1>(s, r, z, st);
 }
 
 }  // namespace mm

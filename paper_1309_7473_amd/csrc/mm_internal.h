@@ -113,6 +113,9 @@ struct ScanImpl {
   int n_floored = 0;
   int n_active = 0;
   bool circ_built = false;
+  bool tiled_built = false;   // tiled preconditioner
+  int tiled_T = 0;
+  char* tiled_ws = nullptr;   // caller-owned workspace of the tiled preconditioner
   int circ_sym = 1;
   int maxdyn_lds = 65536;
   Profiler* prof = nullptr;
@@ -134,6 +137,10 @@ mm_status permute_inverse_spectrum(ScanImpl* s, hipStream_t st);
 mm_status binned_apply(ScanImpl* s, int jacobi, const double* r, double* z, hipStream_t st);
 mm_status circulant_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st);
 mm_status circulant_apply(ScanImpl* s, const double* r, double* z, hipStream_t st);
+bool tiled_size_ok(const ScanImpl* s, int T);
+size_t tiled_workspace_bytes(const ScanImpl* s, int T);
+mm_status tiled_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st);
+mm_status tiled_apply(ScanImpl* s, const double* r, double* z, hipStream_t st);
 // 2-D FFT of nplanes complex double [ny][nx] planes in place (unnormalised)
 mm_status map_fft(ScanImpl* s, Cx<double>* planes, int nplanes, bool inv, hipStream_t st);
 mm_status map_spectra(ScanImpl* s, const double* x, double pixel_arcmin, double dell, int nbins,

@@ -264,6 +264,8 @@ static mm_status apply_precon_inner(ScanImpl* s, int precon, const double* r, do
       return circulant_apply(s, r, z, st);
     case MM_M_LEARNED:
       return learned_apply(s, r, z, st);
+    case MM_M_TILED:
+      return tiled_apply(s, r, z, st);
     default:
       return fail(MM_EINVAL, "unknown preconditioner");
   }

@@ -1,0 +1,127 @@
+"""GPU parity of the tiled constant-correlation preconditioner (Summary
+section) against the oracle's TiledCirculantPrecon, and its use in PCG.
+
+Tolerances as for the single circulant: float64 in the map domain, probe
+columns from the A-apply, so 1e-9 with the float64 timestream path and 1e-4
+with the float32 one.
+"""
+
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.tiled import TiledCirculantPrecon
+from conftest import small_raster
+from gpu_common import Pair, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _cut_corner(inp, n):
+    """Make the n x n top-left corner unhit (samples there go off the map)."""
+    y, x = np.divmod(inp.pix, inp.nx)
+    inp.pix[(inp.pix >= 0) & (y < n) & (x < n)] = -1
+    return inp
+
+
+TILED = [
+    # label, nc, map side, T, sigma, dtype, tol, corner cut
+    ("IQU-32-T8-f64", 3, 32, 8, 3.0, "f64", 1e-9, 0),
+    ("IQU-32-T16-f64", 3, 32, 16, 3.0, "f64", 1e-9, 0),
+    ("I-32-T8-f64", 1, 32, 8, 2.0, "f64", 1e-9, 0),
+    ("IQU-32-T8-empty-tile", 3, 32, 8, 3.0, "f64", 1e-9, 8),
+    ("IQU-64-T16-f32", 3, 64, 16, 4.0, "f32", 1e-4, 0),
+    ("IQU-64-T8-notaper", 3, 64, 8, 0.0, "f64", 1e-9, 0),
+]
+
+
+@pytest.mark.parametrize("case", TILED, ids=[c[0] for c in TILED])
+def test_tiled_apply_matches_oracle(case):
+    label, nc, n, T, sigma, dt, tol, cut = case
+    inp = small_raster(ncomp=nc, ny=n, nx=n, ndet=6, sweeps=2 * n, diameter=4.0)
+    if cut:
+        inp = _cut_corner(inp, cut)
+    pair = Pair(inp, tod_dtype=dt)
+    if cut:
+        assert not pair.mask.reshape(n, n)[:cut, :cut].any()
+    Mo = TiledCirculantPrecon(pair.o, pair.mask, pair.B, tile=T, sigma_taper=sigma or None)
+    if cut:
+        assert Mo.tiles[0]["ref"] < 0
+    print(f"[tiled {label}] building", flush=True)
+    pair.g.build_precon("tiled", tile=T, sigma=sigma)
+    worst = 0.0
+    for seed in (3, 4):
+        r = pair.masked_random(seed)
+        got = pair.host(pair.g.apply_precon("tiled", pair.dev(r)))
+        worst = max(worst, rel(got, Mo(r)))
+    print(f"[tiled {label}] rel={worst:.3e} tiles={len(Mo.tiles)}", flush=True)
+    assert worst <= tol
+
+
+def test_one_tile_equals_the_circulant_preconditioner():
+    inp = small_raster(ncomp=3, ny=32, nx=32, ndet=6, sweeps=64, diameter=4.0)
+    pair = Pair(inp, tod_dtype="f64")
+    r = pair.dev(pair.masked_random(5))
+    pair.g.build_precon("circulant", sigma=3.0)
+    zc = pair.host(pair.g.apply_precon("circulant", r))
+    pair.g.build_precon("tiled", tile=32, sigma=3.0)
+    zt = pair.host(pair.g.apply_precon("tiled", r))
+    e = rel(zt, zc)
+    print(f"[tiled T=map] rel to circulant {e:.3e}", flush=True)
+    assert e <= 1e-13
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_pcg_tiled_matches_oracle(graph):
+    n, T = 32, 8
+    inp = small_raster(ncomp=3, ny=n, nx=n, ndet=6, sweeps=2 * n, diameter=4.0)
+    pair = Pair(inp, tod_dtype="f64")
+    Mo = TiledCirculantPrecon(pair.o, pair.mask, pair.B, tile=T, sigma_taper=3.0)
+    m = np.random.default_rng(7).standard_normal((3, n * n)) * pair.mask
+    b = pair.A_oracle(m.ravel())
+    ro = oracle.pcg(pair.A_oracle, Mo, b, tol=1e-8, maxiter=2000)
+    pair.g.build_precon("tiled", tile=T, sigma=3.0)
+    rg = pair.g.pcg("tiled", pair.dev(b), tol=1e-8, maxiter=2000, graph=graph)
+    x = pair.host(rg["x"])
+    tr = np.linalg.norm(b - pair.A_oracle(x)) / np.linalg.norm(b)
+    print(f"[pcg tiled graph={graph}] oracle iters={ro.iters} gpu iters={rg['iters']} "
+          f"true resid={tr:.2e}", flush=True)
+    assert ro.converged and rg["converged"]
+    assert abs(rg["iters"] - ro.iters) <= max(1, 0.05 * ro.iters)
+    assert tr <= 1e-7
+    k = min(len(ro.history), len(rg["history"]), 20)
+    np.testing.assert_allclose(rg["history"][:k], ro.history[:k], rtol=1e-6)
+
+
+def test_tiled_errors():
+    import paper_1309_7473_amd as mm
+    inp = small_raster(ncomp=3, ny=16, nx=16, ndet=5, sweeps=32)
+    pair = Pair(inp, tod_dtype="f32")
+    h = pair.g.handle
+    r = pair.dev(pair.masked_random(1))
+    with pytest.raises(mm.MMError, match="ENOTBUILT"):
+        pair.g.apply_precon("tiled", r)
+    with pytest.raises(mm.MMError, match="ENOTBUILT"):
+        pair.g.pcg("tiled", r, maxiter=3)
+    for bad in (0, 4, 12, 32):
+        assert mm.mm_tiled_workspace_bytes(h, bad) == 0
+        with pytest.raises(ValueError):
+            pair.g.build_precon("tiled", tile=bad)
+    nb = mm.mm_tiled_workspace_bytes(h, 8)
+    assert nb > 0
+    ws = pair.torch.empty(nb, dtype=pair.torch.uint8, device="cuda")
+    o = mm.mm_precon_opts()
+    o.tile, o.tiled_workspace, o.tiled_workspace_bytes = 8, ws.data_ptr(), nb - 1
+    with pytest.raises(mm.MMError, match="ENOMEM"):
+        mm.mm_build_precon(h, mm.MM_M_TILED, o)
+    o.tiled_workspace_bytes, o.tiled_workspace = nb, ws.data_ptr() + 8
+    with pytest.raises(mm.MMError, match="EINVAL"):
+        mm.mm_build_precon(h, mm.MM_M_TILED, o)
+    with pytest.raises(mm.MMError, match="EINVAL"):
+        mm.mm_build_precon(h, mm.MM_M_TILED, None)
+    o.tiled_workspace = C.c_void_p(ws.data_ptr())
+    mm.mm_build_precon(h, mm.MM_M_TILED, o)
+    z = pair.host(pair.g.apply_precon("tiled", r))
+    assert np.isfinite(z).all()
