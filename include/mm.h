@@ -180,7 +180,9 @@ typedef struct {
   /* MM_M_TILED only (ref_y/ref_x and symmetrize are ignored there: each tile
    * probes the active pixel nearest its centre and is always symmetrised) */
   int32_t tile;             /* tile side T: a power of two, 8 <= T <= min(ny, nx);
-                               tiles start every T/2 pixels */
+                               tiles start every T/2 pixels.  Keep the taper
+                               below about T/4: q is cut off at the tile's half
+                               width, and a wider taper leaves K_t ill-conditioned */
   void*   tiled_workspace;  /* device memory of mm_tiled_workspace_bytes(scan,
                                tile) bytes, 256-byte aligned, owned by the caller
                                and kept alive (unchanged) while the preconditioner

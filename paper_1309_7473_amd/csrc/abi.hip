@@ -182,6 +182,7 @@ mm_status mm_build_precon(mm_scan scan, int32_t precon, const mm_precon_opts* op
       return circulant_build(s, opts, static_cast<hipStream_t>(stream));
     }
     case MM_M_TILED: {
+      s->tiled_built = false;   // a previous build's workspace may be gone
       if (!opts) return fail(MM_EINVAL, "MM_M_TILED needs opts (tile and workspace)");
       if (!tiled_size_ok(s, opts->tile))
         return fail(MM_EINVAL, "tile must be a power of two in [8, min(ny, nx)] with <= 65535 tiles");

@@ -125,3 +125,9 @@ def test_tiled_errors():
     mm.mm_build_precon(h, mm.MM_M_TILED, o)
     z = pair.host(pair.g.apply_precon("tiled", r))
     assert np.isfinite(z).all()
+    # a rebuild that fails validation leaves nothing built (the old workspace may be gone)
+    o.tiled_workspace_bytes = nb - 1
+    with pytest.raises(mm.MMError, match="ENOMEM"):
+        mm.mm_build_precon(h, mm.MM_M_TILED, o)
+    with pytest.raises(mm.MMError, match="ENOTBUILT"):
+        pair.g.apply_precon("tiled", r)
