@@ -23,6 +23,10 @@ Everything is float64 NumPy/SciPy, written for clarity over speed:
   gradients, Adam and training pairs;
 * diagnostics.py - the Results section's convergence measures: binned
   TT/EE/BB spectra, errors in cosmic-variance units, crossing steps.
+* tiled.py     - the tiled constant-correlation preconditioner the Summary
+  section proposes;
+* pointing.py  - per-sample pointing expanded from a boresight track, focal
+  plane offsets and polarisation angles (Test setup section).
 
 Each module states the readings it takes where the paper is silent; functions
 cite the equation or section they follow.  Parity unpinned: none of the
@@ -50,3 +54,4 @@ from .precon import (  # noqa: F401
 )
 from .pcg import pcg, anorm_estimate  # noqa: F401
 from .dense import dense_operator, dense_solve  # noqa: F401
+from .pointing import expand_pointing  # noqa: F401

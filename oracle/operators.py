@@ -28,7 +28,9 @@ class OracleScan:
     """Read-only view of one scan's inputs in the oracle's own terms.
 
     The pointing weights and inverse spectra arrive as float32 and are used
-    as the float64 numbers they represent.
+    as the float64 numbers they represent.  Inputs without pix carry the
+    boresight model instead (bore, det_off), which pointing.expand_pointing
+    turns into float64 per-sample pointing.
     """
 
     def __init__(self, inputs):
@@ -36,10 +38,17 @@ class OracleScan:
         self.ny = int(inputs.ny)
         self.nx = int(inputs.nx)
         self.npix = self.ny * self.nx
-        self.pix = np.asarray(inputs.pix)
+        if getattr(inputs, "pix", None) is None:
+            # pointing given only as the boresight model: expand it here
+            from .pointing import expand_pointing
+            self.pix, c2, s2 = expand_pointing(inputs.bore, inputs.det_off, self.ny, self.nx)
+            self.cos2psi = c2 if self.ncomp == 3 else None
+            self.sin2psi = s2 if self.ncomp == 3 else None
+        else:
+            self.pix = np.asarray(inputs.pix)
+            self.cos2psi = None if inputs.cos2psi is None else np.asarray(inputs.cos2psi)
+            self.sin2psi = None if inputs.sin2psi is None else np.asarray(inputs.sin2psi)
         self.ndet, self.nsamp = self.pix.shape
-        self.cos2psi = None if inputs.cos2psi is None else np.asarray(inputs.cos2psi)
-        self.sin2psi = None if inputs.sin2psi is None else np.asarray(inputs.sin2psi)
         self.iN = np.asarray(inputs.inv_noise, dtype=np.float64)
         if self.iN.shape != (self.ndet, self.nsamp // 2 + 1):
             raise ValueError("inverse spectrum must be [ndet][nsamp/2+1]")

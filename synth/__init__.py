@@ -14,6 +14,7 @@ from .scan import (  # noqa: F401
     periodic_torus_scan,
     crosslinked_torus_scan,
     hex_focal_plane,
+    boresight_only,
 )
 from .noise import (noise_spectrum, inverse_spectrum, draw_noise,  # noqa: F401
                     correlated_inverse_noise)

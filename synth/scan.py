@@ -41,6 +41,13 @@ class ScanInputs:
     # real-FFT bins edges[b] <= k < edges[b+1] share V[b] (float32 [ndet][rank])
     corr_edges: np.ndarray | None = None   # int32 [nbins + 1]
     corr_V: np.ndarray | None = None       # float32 [nbins][ndet][rank]
+    # the pointing model the per-sample pointing was expanded from (raster
+    # scans): boresight float64 [6][nsamp] = y_b, x_b (pixel coordinates),
+    # cos phi, sin phi, cos 2phi, sin 2phi of the scan-angle drift about the map
+    # centre; detectors float64 [4][ndet] = dy, dx (offsets before rotation),
+    # cos 2psi, sin 2psi.  pix/cos2psi/sin2psi may be None when these are given.
+    bore: np.ndarray | None = None
+    det_off: np.ndarray | None = None
 
     @property
     def npix(self):
@@ -153,6 +160,8 @@ def raster_scan(*, ncomp, ny, nx, ndet, nsamp, fsample, layout="hex",
     t = np.arange(nsamp, dtype=np.float64)
     phi = dphi * (t / nsamp - 0.5)
     pix, cos2, sin2 = _pointing_rows(ny, nx, yb, xb, dy, dx, phi, psi, ncomp)
+    bore = np.stack([yb, xb, np.cos(phi), np.sin(phi), np.cos(2 * phi), np.sin(2 * phi)])
+    det_off = np.stack([dy, dx, np.cos(2 * psi), np.sin(2 * psi)])
 
     S = noise_spectrum(nsamp, fsample, sig, fk, alpha)
     if white:
@@ -164,7 +173,17 @@ def raster_scan(*, ncomp, ny, nx, ndet, nsamp, fsample, layout="hex",
     meta = dict(psi=psi, sigma=sig, fknee=fk, dphi=dphi, dy=dy, dx=dx,
                 noise_seed=c_noise, layout=layout)
     return ScanInputs(ncomp, ny, nx, ndet, nsamp, fsample, pix, cos2, sin2,
-                      iN, S, sky, meta)
+                      iN, S, sky, meta, bore=np.ascontiguousarray(bore),
+                      det_off=np.ascontiguousarray(det_off))
+
+
+def boresight_only(inp):
+    """A copy of raster-scan inputs that carries its pointing only as the
+    boresight model (pix, cos2psi and sin2psi dropped)."""
+    import dataclasses
+    if inp.bore is None or inp.det_off is None:
+        raise ValueError("these inputs carry no boresight model")
+    return dataclasses.replace(inp, pix=None, cos2psi=None, sin2psi=None)
 
 
 def _identical_spectra(ndet, nsamp, fsample, sigma, fknee, alpha, white):
