@@ -25,7 +25,7 @@ Everything is float64 NumPy/SciPy, written for clarity over speed:
   TT/EE/BB spectra, errors in cosmic-variance units, crossing steps.
 * tiled.py     - the tiled constant-correlation preconditioner the Summary
   section proposes;
-* pointing.py  - per-sample pointing expanded from a boresight track, focal
+* boresight.py - per-sample pointing expanded from a boresight track, focal
   plane offsets and polarisation angles (Test setup section).
 
 Each module states the readings it takes where the paper is silent; functions
@@ -54,4 +54,4 @@ from .precon import (  # noqa: F401
 )
 from .pcg import pcg, anorm_estimate  # noqa: F401
 from .dense import dense_operator, dense_solve  # noqa: F401
-from .pointing import expand_pointing  # noqa: F401
+from .boresight import expand_pointing  # noqa: F401

@@ -29,7 +29,7 @@ class OracleScan:
 
     The pointing weights and inverse spectra arrive as float32 and are used
     as the float64 numbers they represent.  Inputs without pix carry the
-    boresight model instead (bore, det_off), which pointing.expand_pointing
+    boresight model instead (bore, det_off), which boresight.expand_pointing
     turns into float64 per-sample pointing.
     """
 
@@ -40,7 +40,7 @@ class OracleScan:
         self.npix = self.ny * self.nx
         if getattr(inputs, "pix", None) is None:
             # pointing given only as the boresight model: expand it here
-            from .pointing import expand_pointing
+            from .boresight import expand_pointing
             self.pix, c2, s2 = expand_pointing(inputs.bore, inputs.det_off, self.ny, self.nx)
             self.cos2psi = c2 if self.ncomp == 3 else None
             self.sin2psi = s2 if self.ncomp == 3 else None

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.pointing import expand_pointing
+from oracle.boresight import expand_pointing
 from conftest import small_raster
 from synth import boresight_only
 
