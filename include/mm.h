@@ -73,6 +73,14 @@ typedef enum {
                           of unity (mm_apply_precon_tiled) */
 } mm_precon;
 
+/* How a scan gives its pointing. */
+typedef enum {
+  MM_POINT_STORED = 0,     /* pix, cos2psi, sin2psi per sample */
+  MM_POINT_BORESIGHT = 1   /* boresight track and detector offsets (Test setup
+                              section); each sample's pixel and weights are
+                              computed where they are needed */
+} mm_pointing;
+
 /* Description of one scan (one set of detector timestreams and pointing). */
 typedef struct {
   int32_t ncomp;            /* 1 (I) or 3 (I,Q,U) */
@@ -87,8 +95,9 @@ typedef struct {
   int64_t nsamp;            /* samples per detector: power of two, 16 ..2^22 */
   double  fsample;          /* sample rate in Hz (reporting only) */
   const int32_t* pix;       /* [ndet][nsamp] pixel id, -1 = off-map (zero row
-                               of P).  BORROWED: must stay valid and unchanged
-                               until mm_destroy_scan. */
+                               of P); NULL with MM_POINT_BORESIGHT.  BORROWED:
+                               must stay valid and unchanged until
+                               mm_destroy_scan. */
   const float* cos2psi;     /* [ndet][nsamp] weight of Q; NULL iff ncomp == 1. BORROWED */
   const float* sin2psi;     /* [ndet][nsamp] weight of U; NULL iff ncomp == 1. BORROWED */
   const float* inv_noise;   /* [ndet][nsamp/2+1] 1/N_d(f_k) on the real-FFT
@@ -131,6 +140,25 @@ typedef struct {
                                edges[b+1]; edges[0] = 0, edges[corr_nbins] =
                                nsamp/2 + 1, strictly increasing.  Copied at create. */
   const float* corr_V;      /* [corr_nbins][ndet][corr_rank] device.  BORROWED */
+  /* Pointing.  MM_POINT_STORED: pix (and cos2psi/sin2psi for I,Q,U) as above;
+   * bore and det_off are ignored.  MM_POINT_BORESIGHT: pix, cos2psi and
+   * sin2psi must be NULL and the library computes, in float64 without fused
+   * multiply-add, for detector d at sample t (flat sky, pixel units, map
+   * centre (c_y, c_x) = ((ny-1)/2, (nx-1)/2)):
+   *   ry = (y_b - c_y) + dy_d,  rx = (x_b - c_x) + dx_d,
+   *   py = (c_y + sin(phi) rx) + cos(phi) ry,  px = (c_x + cos(phi) rx) - sin(phi) ry,
+   *   pixel (floor(py + 1/2), floor(px + 1/2)), off the map when outside,
+   *   weights cos 2(psi_d + phi) = c2psi c2phi - s2psi s2phi and
+   *           sin 2(psi_d + phi) = s2psi c2phi + c2psi s2phi.
+   * The pixel-major index of P^T is then always used (scatter must not be
+   * MM_SCATTER_ATOMIC) and holds no weights (4 B/sample of workspace). */
+  int32_t pointing;         /* mm_pointing */
+  const double* bore;       /* device [6][nsamp] float64, 16-byte aligned: y_b, x_b
+                               (pixel coordinates), cos phi, sin phi, cos 2phi,
+                               sin 2phi of the scan-angle turn.  BORROWED */
+  const double* det_off;    /* device [4][ndet] float64: dy, dx (offsets from the
+                               boresight before the turn), cos 2psi, sin 2psi.
+                               BORROWED */
 } mm_scan_desc;
 
 enum { MM_SCATTER_AUTO = 0, MM_SCATTER_ATOMIC = 1 };

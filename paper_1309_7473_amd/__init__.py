@@ -19,7 +19,8 @@ from ._abi import (  # noqa: F401
     mm_scan_info, MM_OK, MM_ENOCONV, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENOTBUILT,
     MM_EBREAKDOWN, MM_F32, MM_BF16, MM_F64, MM_M_NONE, MM_M_JACOBI, MM_M_BINNED,
     MM_M_CIRCULANT, MM_M_LEARNED, MM_M_TILED, LIB_PATH, mm_profile, PROFILE_STAGES, MM_SCATTER_AUTO,
-    MM_SCATTER_ATOMIC, mm_train_opts, MM_ACC_F64, MM_ACC_F32X2,
+    MM_SCATTER_ATOMIC, mm_train_opts, MM_ACC_F64, MM_ACC_F32X2, MM_POINT_STORED,
+    MM_POINT_BORESIGHT,
 )
 
 PRECON = {"none": MM_M_NONE, "jacobi": MM_M_JACOBI, "binned": MM_M_BINNED,
@@ -290,7 +291,12 @@ class Scan:
     """
 
     def __init__(self, inputs, tod_dtype="f32", det_group=0, fft_m1=0, fft_cols=0,
-                 mask_rcond=0.0, scatter="auto", acc="f64", device="cuda", stream=None):
+                 mask_rcond=0.0, scatter="auto", acc="f64", pointing="auto", device="cuda",
+                 stream=None):
+        """pointing: "stored" (inputs.pix, cos2psi, sin2psi), "boresight"
+        (inputs.bore [6][nsamp] and inputs.det_off [4][ndet], float64: each
+        sample's pointing is computed on the GPU when it is needed), or "auto"
+        (stored when inputs.pix is given)."""
         self.device = torch.device(device)
         dev = self.device
 
@@ -301,12 +307,28 @@ class Scan:
                 return a.to(device=dev, dtype=dt).contiguous()
             return torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)
 
-        self.pix = up(inputs.pix, torch.int32)
-        self.cos2psi = up(inputs.cos2psi, torch.float32)
-        self.sin2psi = up(inputs.sin2psi, torch.float32)
-        self.inv_noise = up(inputs.inv_noise, torch.float32)
+        if pointing == "auto":
+            pointing = "stored" if getattr(inputs, "pix", None) is not None else "boresight"
+        if pointing not in ("stored", "boresight"):
+            raise ValueError(f"unknown pointing {pointing!r}")
+        self.pointing = pointing
         self.ncomp, self.ny, self.nx = int(inputs.ncomp), int(inputs.ny), int(inputs.nx)
-        self.ndet, self.nsamp = int(self.pix.shape[0]), int(self.pix.shape[1])
+        self.inv_noise = up(inputs.inv_noise, torch.float32)
+        if pointing == "stored":
+            self.pix = up(inputs.pix, torch.int32)
+            self.cos2psi = up(inputs.cos2psi, torch.float32)
+            self.sin2psi = up(inputs.sin2psi, torch.float32)
+            self.bore = self.det_off = None
+            self.ndet, self.nsamp = int(self.pix.shape[0]), int(self.pix.shape[1])
+        else:
+            self.pix = self.cos2psi = self.sin2psi = None
+            self.bore = up(inputs.bore, torch.float64)
+            self.det_off = up(inputs.det_off, torch.float64)
+            if self.bore.dim() != 2 or self.bore.shape[0] != 6:
+                raise ValueError("bore must be [6][nsamp]")
+            if self.det_off.dim() != 2 or self.det_off.shape[0] != 4:
+                raise ValueError("det_off must be [4][ndet]")
+            self.ndet, self.nsamp = int(self.det_off.shape[1]), int(self.bore.shape[1])
         self.npix = self.ny * self.nx
         self.tod_dtype = {"f32": MM_F32, "bf16": MM_BF16, "f64": MM_F64}[tod_dtype]
         # dtype of the timestream handed to rhs (bf16: rounded to nearest even)
@@ -317,7 +339,11 @@ class Scan:
         d.tod_dtype = self.tod_dtype
         d.nsamp = self.nsamp
         d.fsample = float(getattr(inputs, "fsample", 0.0))
-        d.pix = self.pix.data_ptr()
+        d.pix = self.pix.data_ptr() if self.pix is not None else None
+        if pointing == "boresight":
+            d.pointing = MM_POINT_BORESIGHT
+            d.bore = self.bore.data_ptr()
+            d.det_off = self.det_off.data_ptr()
         d.cos2psi = self.cos2psi.data_ptr() if self.cos2psi is not None else None
         d.sin2psi = self.sin2psi.data_ptr() if self.sin2psi is not None else None
         d.inv_noise = self.inv_noise.data_ptr()

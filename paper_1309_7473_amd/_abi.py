@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libmm.so")
 MM_OK, MM_ENOCONV, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENOTBUILT, MM_EBREAKDOWN = 0, 1, -1, -2, -3, -4, -5
 MM_F32, MM_BF16, MM_F64 = 0, 1, 2
 MM_ACC_F64, MM_ACC_F32X2 = 0, 1
+MM_POINT_STORED, MM_POINT_BORESIGHT = 0, 1
 MM_M_NONE, MM_M_JACOBI, MM_M_BINNED, MM_M_CIRCULANT, MM_M_LEARNED, MM_M_TILED = 0, 1, 2, 3, 4, 5
 
 STATUS_NAMES = {0: "MM_OK", 1: "MM_ENOCONV", -1: "MM_EINVAL", -2: "MM_ENOMEM",
@@ -28,7 +29,8 @@ class mm_scan_desc(C.Structure):
         ("det_group", C.c_int32), ("fft_m1", C.c_int32), ("mask_rcond", C.c_double),
         ("fft_cols", C.c_int32), ("scatter", C.c_int32), ("acc", C.c_int32),
         ("corr_rank", C.c_int32), ("corr_nbins", C.c_int32), ("corr_edges", C.c_void_p),
-        ("corr_V", C.c_void_p),
+        ("corr_V", C.c_void_p), ("pointing", C.c_int32), ("bore", C.c_void_p),
+        ("det_off", C.c_void_p),
     ]
 
 

@@ -22,8 +22,17 @@ def default_cache_path():
     return os.path.join(root, "paper_1309_7473_amd", "autotune.json")
 
 
+def _shape(inputs):
+    """(ndet, nsamp) from the stored pointing [ndet][nsamp], else from the
+    boresight model (bore [6][nsamp], det_off [4][ndet])."""
+    pix = getattr(inputs, "pix", None)
+    if pix is not None:
+        return int(pix.shape[0]), int(pix.shape[1])
+    return int(inputs.det_off.shape[1]), int(inputs.bore.shape[1])
+
+
 def shape_key(inputs, tod_dtype, acc):
-    ndet, nsamp = int(inputs.pix.shape[0]), int(inputs.pix.shape[1])
+    ndet, nsamp = _shape(inputs)
     return f"{int(inputs.ncomp)}x{int(inputs.ny)}x{int(inputs.nx)}:{ndet}x{nsamp}:{tod_dtype}:{acc}"
 
 
@@ -79,7 +88,8 @@ def tune(inputs, tod_dtype="f32", acc="f64", reps=5, cache_path=None, use_cache=
             cache = {}
         if key in cache:
             return dict(cache[key]["plan"])
-    cands = candidates(int(inputs.pix.shape[1]), int(inputs.pix.shape[0]), tod_dtype)
+    ndet, nsamp = _shape(inputs)
+    cands = candidates(nsamp, ndet, tod_dtype)
     if not cands:
         return {}
     if timer is None:

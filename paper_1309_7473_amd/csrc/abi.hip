@@ -57,6 +57,10 @@ static mm_status validate_shape(const mm_scan_desc* d) {
     return fail(MM_EINVAL, "acc must be MM_ACC_F64 or MM_ACC_F32X2");
   if (d->acc == MM_ACC_F32X2 && d->scatter == MM_SCATTER_ATOMIC)
     return fail(MM_EINVAL, "acc = MM_ACC_F32X2 needs scatter = MM_SCATTER_AUTO");
+  if (d->pointing != MM_POINT_STORED && d->pointing != MM_POINT_BORESIGHT)
+    return fail(MM_EINVAL, "pointing must be MM_POINT_STORED or MM_POINT_BORESIGHT");
+  if (d->pointing == MM_POINT_BORESIGHT && d->scatter == MM_SCATTER_ATOMIC)
+    return fail(MM_EINVAL, "MM_POINT_BORESIGHT needs scatter = MM_SCATTER_AUTO");
   if (d->corr_rank < 0 || d->corr_rank > 16) return fail(MM_EINVAL, "corr_rank must be in [0, 16]");
   if (d->corr_rank > 0) {
     if (d->corr_nbins < 1 || d->corr_nbins > 4096)
@@ -98,11 +102,21 @@ mm_status mm_create_scan(const mm_scan_desc* desc, void* stream, mm_scan* out) {
   *out = nullptr;
   mm_status r = validate_shape(desc);
   if (r != MM_OK) return r;
-  if (!desc->pix || !desc->inv_noise) return fail(MM_EINVAL, "pix and inv_noise are required");
-  if ((desc->ncomp == 3) != (desc->cos2psi != nullptr && desc->sin2psi != nullptr))
-    return fail(MM_EINVAL, "cos2psi/sin2psi must be given iff ncomp == 3");
-  if (desc->ncomp == 1 && (desc->cos2psi || desc->sin2psi))
-    return fail(MM_EINVAL, "cos2psi/sin2psi must be NULL when ncomp == 1");
+  if (!desc->inv_noise) return fail(MM_EINVAL, "inv_noise is required");
+  if (desc->pointing == MM_POINT_BORESIGHT) {
+    if (desc->pix || desc->cos2psi || desc->sin2psi)
+      return fail(MM_EINVAL, "MM_POINT_BORESIGHT: pix, cos2psi and sin2psi must be NULL");
+    if (!desc->bore || !desc->det_off)
+      return fail(MM_EINVAL, "MM_POINT_BORESIGHT: bore and det_off are required");
+    if (reinterpret_cast<uintptr_t>(desc->bore) % 16 != 0)
+      return fail(MM_EINVAL, "bore must be 16-byte aligned");
+  } else {
+    if (!desc->pix) return fail(MM_EINVAL, "pix is required");
+    if ((desc->ncomp == 3) != (desc->cos2psi != nullptr && desc->sin2psi != nullptr))
+      return fail(MM_EINVAL, "cos2psi/sin2psi must be given iff ncomp == 3");
+    if (desc->ncomp == 1 && (desc->cos2psi || desc->sin2psi))
+      return fail(MM_EINVAL, "cos2psi/sin2psi must be NULL when ncomp == 1");
+  }
   if (desc->corr_rank > 0 && !desc->corr_V) return fail(MM_EINVAL, "corr_V is required");
   Plan pl;
   Layout L;

@@ -74,7 +74,7 @@ __global__ void k_validate_finite(const float* __restrict__ v, int64_t count, in
 
 // One lane per sample; every lane of a wave takes the same number of trips.
 template <int NC>
-__global__ void __launch_bounds__(256) k_binned_accum(const int32_t* __restrict__ pix,
+__global__ void __launch_bounds__(256) k_binned_accum(const int32_t* __restrict__ pix, Bore bo,
                                                       const float* __restrict__ c2,
                                                       const float* __restrict__ s2,
                                                       const double* __restrict__ detw,
@@ -94,13 +94,14 @@ __global__ void __launch_bounds__(256) k_binned_accum(const int32_t* __restrict_
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
     if (i < total) {
-      p = pix[i];
+      p = sample_pixel(pix, bo, i);
       if (unsigned(p) >= unsigned(npix)) p = -1;
       if (p >= 0) {
         const double wd = detw[i / n];
         double u[NU];
         if constexpr (NC == 3) {
-          const double c = c2[i], s = s2[i];
+          double c, s;
+          sample_weights(c2, s2, bo, i, &c, &s);
           u[0] = 1.0; u[1] = c; u[2] = s; u[3] = c * c; u[4] = c * s; u[5] = s * s;
         } else {
           u[0] = 1.0;
@@ -202,15 +203,21 @@ __global__ void k_binned_apply(const double* __restrict__ binv, const int32_t* _
   }
 }
 
-// counts pixel ids outside [-1, npix) and non-finite or negative 1/N(f)
+// counts pixel ids outside [-1, npix) (stored pointing), non-finite boresight
+// values, and non-finite or negative 1/N(f)
 __global__ void k_validate(const int32_t* __restrict__ pix, int64_t total, int npix,
+                           const double* __restrict__ bore, int64_t nbore,
                            const float* __restrict__ iN, int64_t niN, int* __restrict__ bad) {
   int c = 0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total; i += stride) {
-    const int p = pix[i];
-    c += (p < -1 || p >= npix) ? 1 : 0;
+  if (pix) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total; i += stride) {
+      const int p = pix[i];
+      c += (p < -1 || p >= npix) ? 1 : 0;
+    }
   }
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < nbore; i += stride)
+    c += isfinite(bore[i]) ? 0 : 1;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < niN; i += stride) {
     const float v = iN[i];
     c += (!(v >= 0.0f) || isinf(v)) ? 1 : 0;
@@ -234,8 +241,13 @@ mm_status binned_setup(ScanImpl* s, hipStream_t st) {
     if ((r0 = fill_zero(bad, 4, st)) != MM_OK) return r0;
     const int64_t total = int64_t(s->ndet) * s->n;
     const int64_t niN = int64_t(s->ndet) * (s->n / 2 + 1);
-    hipLaunchKernelGGL(k_validate, dim3(2048), dim3(256), 0, st, s->d.pix, total, npix,
+    const bool otf = s->plan.otf;
+    hipLaunchKernelGGL(k_validate, dim3(2048), dim3(256), 0, st, otf ? nullptr : s->d.pix, total,
+                       npix, otf ? s->d.bore : nullptr, otf ? int64_t(6) * s->n : 0,
                        s->d.inv_noise, niN, bad);
+    if (otf)
+      hipLaunchKernelGGL(k_validate, dim3(1), dim3(256), 0, st, nullptr, 0, npix, s->d.det_off,
+                         int64_t(4) * s->ndet, nullptr, 0, bad);
     if (s->plan.corr_rank > 0)
       hipLaunchKernelGGL(k_validate_finite, dim3(256), dim3(256), 0, st, s->d.corr_V,
                          int64_t(s->plan.corr_nbins) * s->ndet * s->plan.corr_rank, bad);
@@ -245,7 +257,8 @@ mm_status binned_setup(ScanImpl* s, hipStream_t st) {
     MM_HIP(hipStreamSynchronize(st));
     if (h)
       return fail(MM_EINVAL,
-                  "pix outside [-1, ny*nx), inv_noise negative / non-finite or corr_V non-finite");
+                  "pix outside [-1, ny*nx), bore / det_off non-finite, inv_noise negative / "
+                  "non-finite or corr_V non-finite");
   }
   hipLaunchKernelGGL(k_det_weights, dim3(s->ndet), dim3(256), 0, st, s->d.inv_noise, s->n,
                      s->at<double>(L.detw));
@@ -260,12 +273,13 @@ mm_status binned_setup(ScanImpl* s, hipStream_t st) {
   const int64_t total = int64_t(s->ndet) * s->n;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 16384) blocks = 16384;
+  const Bore bo = scan_bore(s);
   if (s->nc == 3)
-    hipLaunchKernelGGL(k_binned_accum<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix,
+    hipLaunchKernelGGL(k_binned_accum<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->at<double>(L.detw), s->n, total, npix,
                        s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
   else
-    hipLaunchKernelGGL(k_binned_accum<1>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix,
+    hipLaunchKernelGGL(k_binned_accum<1>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->at<double>(L.detw), s->n, total, npix,
                        s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
   const dim3 g((npix + 255) / 256), b(256);

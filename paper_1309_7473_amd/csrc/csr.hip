@@ -4,8 +4,9 @@
 //
 // For group g (detectors g*G .. g*G+G-1, G*n samples) the entries of pixel p
 // are off[g][p] .. off[g][p+1]-1; entry e holds the group-relative sample
-// index idx[e] = d_local*n + t and, for I,Q,U, its weights (cos 2psi,
-// sin 2psi).  Runs of equal pixels inside a wavefront claim their slots with
+// index idx[e] = d_local*n + t and, for I,Q,U with stored pointing, its
+// weights (cos 2psi, sin 2psi); with boresight pointing the gather computes
+// them from the index.  Runs of equal pixels inside a wavefront claim their slots with
 // one atomic, so the order inside a pixel is fixed once the index is built
 // (the per-pixel sum order of every later apply is then fixed too).
 #include "mm_device.h"
@@ -29,8 +30,8 @@ __device__ __forceinline__ void wave_runs(int key, bool force_head, int* head_la
   *run_len = next - h;
 }
 
-__global__ void __launch_bounds__(256) k_csr_count(const int32_t* __restrict__ pix, int64_t n,
-                                                   int64_t total, int G, int npix,
+__global__ void __launch_bounds__(256) k_csr_count(const int32_t* __restrict__ pix, Bore bo,
+                                                   int64_t n, int64_t total, int G, int npix,
                                                    int32_t* __restrict__ cnt) {
   const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
@@ -40,7 +41,7 @@ __global__ void __launch_bounds__(256) k_csr_count(const int32_t* __restrict__ p
     const int64_t i = base + lane;
     int p = -1;
     if (i < total) {
-      p = pix[i];
+      p = sample_pixel(pix, bo, i);
       if (unsigned(p) >= unsigned(npix)) p = -1;
     }
     int h, len;
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(1024) k_csr_scan(int32_t* __restrict__ cnt,
 }
 
 template <int NC>
-__global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pix,
+__global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pix, Bore bo,
                                                   const float* __restrict__ c2,
                                                   const float* __restrict__ s2, int64_t n,
                                                   int64_t total, int G, int npix,
@@ -101,7 +102,7 @@ __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pi
     const int64_t i = base + lane;
     int p = -1;
     if (i < total) {
-      p = pix[i];
+      p = sample_pixel(pix, bo, i);
       if (unsigned(p) >= unsigned(npix)) p = -1;
     }
     int h, len;
@@ -113,7 +114,9 @@ __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pi
     if (p >= 0) {
       const int64_t e = g * gsz + slot0 + (lane - h);
       idx[e] = int32_t(i - g * gsz);
-      if constexpr (NC == 3) w[e] = make_float2(c2[i], s2[i]);
+      if constexpr (NC == 3) {
+        if (w) w[e] = make_float2(c2[i], s2[i]);   // boresight pointing: no stored weights
+      }
     }
   }
 }
@@ -129,16 +132,18 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
   if ((r = fill_zero(cnt, size_t(ngroups) * npix * 4, st)) != MM_OK) return r;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(k_csr_count, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, s->n, total,
-                     G, npix, cnt);
+  const Bore bo = scan_bore(s);
+  hipLaunchKernelGGL(k_csr_count, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo, s->n,
+                     total, G, npix, cnt);
   hipLaunchKernelGGL(k_csr_scan, dim3(ngroups), dim3(1024), 0, st, cnt, s->at<int32_t>(L.csr_off),
                      npix);
   if (s->nc == 3)
-    hipLaunchKernelGGL(k_csr_fill<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix,
+    hipLaunchKernelGGL(k_csr_fill<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->n, total, G, npix, cnt,
-                       s->at<int32_t>(L.csr_idx), s->at<float2>(L.csr_w));
+                       s->at<int32_t>(L.csr_idx),
+                       s->plan.otf ? static_cast<float2*>(nullptr) : s->at<float2>(L.csr_w));
   else
-    hipLaunchKernelGGL(k_csr_fill<1>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix,
+    hipLaunchKernelGGL(k_csr_fill<1>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->n, total, G, npix, cnt,
                        s->at<int32_t>(L.csr_idx), static_cast<float2*>(nullptr));
   MM_HIP(hipGetLastError());

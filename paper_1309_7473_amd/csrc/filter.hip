@@ -93,6 +93,8 @@ struct PassArgs {
   const int32_t* mask;
   const float* iNt;        // group base [G][M+1], four-step order
   const Cx<T>* tw2;        // W_{2 M2}^k2, k2 < M2
+  Bore bo;                 // boresight model (SRC 2, and the gather's weights)
+  int det0;                // first detector of the group
   int64_t n;
   int npix;
   int logM, logM1, logM2, logC, logLmax;
@@ -114,6 +116,19 @@ template <typename T, typename S, int NC, int SRC>
 __device__ __forceinline__ T source_sample(const PassArgs<T, S>& a, int64_t s) {
   if constexpr (SRC == 1) {
     return Sto<T, S>::ldr(a.tod + s);
+  } else if constexpr (SRC == 2) {
+    // pointing from the boresight model: s = d_local * n + t
+    const int d = a.det0 + int(s >> a.bo.logn);
+    const int64_t t = s & ((int64_t(1) << a.bo.logn) - 1);
+    const int p = bore_pixel_at(a.bo, d, t);
+    const V4<T> m = a.gmap[p >= 0 ? p : a.npix];
+    if constexpr (NC == 3) {
+      double c, sn;
+      bore_weights_at(a.bo, d, t, &c, &sn);
+      return m.x + T(c) * m.y + T(sn) * m.z;
+    } else {
+      return m.x;
+    }
   } else {
     const int p = a.pix[s];
     // off-map samples read the zero entry gmap[npix]: no branch around the gather
@@ -315,6 +330,13 @@ constexpr int kNT13 = 1024;  // threads per pass-1/3 block
 // float math only: 128 KB of LDS per block)
 constexpr int kPad2 = 3;     // pass-2 LDS padding: one slot per 8 elements
 
+// Four consecutive doubles (16-byte aligned) with two 16-byte loads.
+__device__ __forceinline__ void ld4d(const double* p, double (&v)[4]) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0];
+  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
 // Four consecutive samples s..s+3 (s a multiple of 4) with 16-byte loads.
 template <typename T, typename S, int NC, int SRC>
 __device__ __forceinline__ void source4(const PassArgs<T, S>& a, int64_t s, T (&v)[4]) {
@@ -332,6 +354,33 @@ __device__ __forceinline__ void source4(const PassArgs<T, S>& a, int64_t s, T (&
       const double2 t0 = *reinterpret_cast<const double2*>(a.tod + s);
       const double2 t1 = *reinterpret_cast<const double2*>(a.tod + s + 2);
       v[0] = t0.x; v[1] = t0.y; v[2] = t1.x; v[3] = t1.y;
+    }
+  } else if constexpr (SRC == 2) {
+    // pointing from the boresight model for samples t..t+3 of one detector
+    const int d = a.det0 + int(s >> a.bo.logn);
+    const int64_t n = int64_t(1) << a.bo.logn;
+    const int64_t t = s & (n - 1);
+    const double* b = a.bo.b + t;
+    const double dy = a.bo.det[d], dx = a.bo.det[a.bo.ndet + d];
+    double yb[4], xb[4], cp[4], sp[4];
+    ld4d(b, yb);
+    ld4d(b + n, xb);
+    ld4d(b + 2 * n, cp);
+    ld4d(b + 3 * n, sp);
+    double cc[4] = {0.0, 0.0, 0.0, 0.0}, ss[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (NC == 3) {
+      double c2f[4], s2f[4];
+      ld4d(b + 4 * n, c2f);
+      ld4d(b + 5 * n, s2f);
+      const double c2p = a.bo.det[2 * a.bo.ndet + d], s2p = a.bo.det[3 * a.bo.ndet + d];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bore_weights(c2p, s2p, c2f[i], s2f[i], &cc[i], &ss[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int p = bore_pixel(yb[i], xb[i], cp[i], sp[i], dy, dx, a.bo.ny, a.bo.nx);
+      const V4<T> m = a.gmap[p >= 0 ? p : a.npix];
+      v[i] = (NC == 3) ? m.x + T(cc[i]) * m.y + T(ss[i]) * m.z : m.x;
     }
   } else {
     const int4 p4 = *reinterpret_cast<const int4*>(a.pix + s);
@@ -891,7 +940,22 @@ __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
 // P^T for one detector group as a per-pixel gather: 16 lanes per pixel walk
 // its CSR entries, each lane summing a fixed stride of them, then a fixed
 // xor-tree; acc[p] += (sum u, sum c u, sum s u).  No atomics.
-template <typename T, typename S, int NC, bool CF>
+// Weights of gather entry ik (group-relative sample d_local * n + t): stored
+// with the index, or from the boresight model.
+template <typename T, typename S, int NC, bool OTF>
+__device__ __forceinline__ void entry_weights(const PassArgs<T, S>& a, int k, int ik, double* c,
+                                              double* sn) {
+  if constexpr (OTF) {
+    const int d = a.det0 + (ik >> a.bo.logn);
+    bore_weights_at(a.bo, d, ik & ((1 << a.bo.logn) - 1), c, sn);
+  } else {
+    const float2 cs = a.csr_w[k];
+    *c = double(cs.x);
+    *sn = double(cs.y);
+  }
+}
+
+template <typename T, typename S, int NC, bool CF, bool OTF>
 __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
   constexpr int LPP = 16;
   const int sub = threadIdx.x / LPP;
@@ -906,12 +970,14 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll 4
     for (int k = b + l; k < e; k += LPP) {
-      const double uu = double(Sto<T, S>::ldr(u + a.csr_idx[k]));
+      const int ik = a.csr_idx[k];
+      const double uu = double(Sto<T, S>::ldr(u + ik));
       s0 += uu;
       if constexpr (NC == 3) {
-        const float2 cs = a.csr_w[k];
-        s1 += double(cs.x) * uu;
-        s2 += double(cs.y) * uu;
+        double c, sn;
+        entry_weights<T, S, NC, OTF>(a, k, ik, &c, &sn);
+        s1 += c * uu;
+        s2 += sn * uu;
       }
     }
 #pragma unroll
@@ -935,7 +1001,8 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
     F2 s0{0.f, 0.f}, s1{0.f, 0.f}, s2{0.f, 0.f};
 #pragma unroll 4
     for (int k = b + l; k < e; k += LPP) {
-      const T ut = Sto<T, S>::ldr(u + a.csr_idx[k]);
+      const int ik = a.csr_idx[k];
+      const T ut = Sto<T, S>::ldr(u + ik);
       F2 uu;
       if constexpr (sizeof(T) == 8)
         uu = f2_split(ut);
@@ -943,9 +1010,10 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
         uu = F2{float(ut), 0.f};
       f2_acc(s0, uu.hi, uu.lo);
       if constexpr (NC == 3) {
-        const float2 cs = a.csr_w[k];
-        f2_fma_acc(s1, cs.x, uu);
-        f2_fma_acc(s2, cs.y, uu);
+        double c, sn;
+        entry_weights<T, S, NC, OTF>(a, k, ik, &c, &sn);
+        f2_fma_acc(s1, float(c), uu);
+        f2_fma_acc(s2, float(sn), uu);
       }
     }
 #pragma unroll
@@ -1001,10 +1069,18 @@ static void launch_pass2w(int M2, dim3 g, size_t lds, hipStream_t st, const Pass
 template <typename T, typename S, int NC>
 static void launch_reduce(ScanImpl* s, const PassArgs<T, S>& a, hipStream_t st) {
   const dim3 grid((s->npix + 15) / 16);   // 16 pixels of 16 lanes per block
-  if (s->plan.acc32)
-    hipLaunchKernelGGL((k_csr_reduce<T, S, NC, true>), grid, dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_csr_reduce<T, S, NC, false>), grid, dim3(256), 0, st, a);
+  const bool otf = s->plan.otf && NC == 3;
+  if (s->plan.acc32) {
+    if (otf)
+      hipLaunchKernelGGL((k_csr_reduce<T, S, NC, true, true>), grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_csr_reduce<T, S, NC, true, false>), grid, dim3(256), 0, st, a);
+  } else {
+    if (otf)
+      hipLaunchKernelGGL((k_csr_reduce<T, S, NC, false, true>), grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_csr_reduce<T, S, NC, false, false>), grid, dim3(256), 0, st, a);
+  }
 }
 
 template <typename T, typename S, int NC, int SRC>
@@ -1030,11 +1106,13 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
   a.scale = T(1) / T(M);
   a.mask = s->at<int32_t>(s->lay.mask);
   a.tw2 = s->at<Cx<T>>(s->lay.tw2);
+  a.bo = scan_bore(s);
   const int G = pl.G;
   for (int d0 = 0; d0 < s->ndet; d0 += G) {
     const int gd = (s->ndet - d0 < G) ? (s->ndet - d0) : G;
     const int64_t off = int64_t(d0) * s->n;
-    a.pix = s->d.pix + off;
+    a.det0 = d0;
+    a.pix = s->d.pix ? s->d.pix + off : nullptr;
     a.c2 = s->d.cos2psi ? s->d.cos2psi + off : nullptr;
     a.s2 = s->d.sin2psi ? s->d.sin2psi + off : nullptr;
     a.iN = s->d.inv_noise + int64_t(d0) * (M + 1);
@@ -1044,7 +1122,8 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const int gi = d0 / G;
       a.csr_off = s->at<int32_t>(s->lay.csr_off) + int64_t(gi) * (s->npix + 1);
       a.csr_idx = s->at<int32_t>(s->lay.csr_idx) + int64_t(gi) * G * s->n;
-      a.csr_w = s->nc == 3 ? s->at<float2>(s->lay.csr_w) + int64_t(gi) * G * s->n : nullptr;
+      a.csr_w = s->nc == 3 && !pl.otf ? s->at<float2>(s->lay.csr_w) + int64_t(gi) * G * s->n
+                                      : nullptr;
     }
     const int64_t gs = int64_t(gd) * s->n;
     hipEvent_t tok;
@@ -1054,7 +1133,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       if (pl.csr) {
         raise_lds_limit(k_single<T, S, NC, SRC, true>, lds);
         hipLaunchKernelGGL((k_single<T, S, NC, SRC, true>), dim3(gd), dim3(kNT), lds, st, a);
-      } else {
+      } else if constexpr (SRC != 2) {   // boresight pointing always gathers
         raise_lds_limit(k_single<T, S, NC, SRC, false>, lds);
         hipLaunchKernelGGL((k_single<T, S, NC, SRC, false>), dim3(gd), dim3(kNT), lds, st, a);
       }
@@ -1163,11 +1242,18 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
   return MM_OK;
 }
 
+// src 0: the map through stored pointing (SRC 0) or the boresight model
+// (SRC 2); src 1: a timestream (SRC 1)
 template <typename T, typename S>
 static mm_status run_pipeline(ScanImpl* s, int src, const void* tod, hipStream_t st) {
+  const bool otf = s->plan.otf;
   if (s->nc == 3)
-    return src ? run_pipeline_t<T, S, 3, 1>(s, tod, st) : run_pipeline_t<T, S, 3, 0>(s, tod, st);
-  return src ? run_pipeline_t<T, S, 1, 1>(s, tod, st) : run_pipeline_t<T, S, 1, 0>(s, tod, st);
+    return src   ? run_pipeline_t<T, S, 3, 1>(s, tod, st)
+           : otf ? run_pipeline_t<T, S, 3, 2>(s, tod, st)
+                 : run_pipeline_t<T, S, 3, 0>(s, tod, st);
+  return src   ? run_pipeline_t<T, S, 1, 1>(s, tod, st)
+         : otf ? run_pipeline_t<T, S, 1, 2>(s, tod, st)
+               : run_pipeline_t<T, S, 1, 0>(s, tod, st);
 }
 
 mm_status filter_pipeline(ScanImpl* s, int src, const void* tod, const double* x, double* y,
@@ -1266,7 +1352,9 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   // pipeline with wavefront rows of 512-2048 bins
   pl->single = (M <= kE * kNT) && pl->corr_rank == 0;
   // the compensated accumulation exists only in the per-pixel gather
-  pl->csr = d->scatter != MM_SCATTER_ATOMIC && (!pl->single || pl->acc32);
+  pl->otf = d->pointing == MM_POINT_BORESIGHT;
+  // boresight pointing stores no per-sample pixels: P^T is always the gather
+  pl->csr = d->scatter != MM_SCATTER_ATOMIC && (!pl->single || pl->acc32 || pl->otf);
   if (pl->single) {
     pl->logM1 = 0;
     pl->logM2 = pl->logM;
@@ -1367,7 +1455,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->csr_cnt = take(pl->csr ? size_t(ngroups) * npix * 4 : 0);
   L->csr_off = take(pl->csr ? size_t(ngroups) * (npix + 1) * 4 : 0);
   L->csr_idx = take(csr_n * 4);
-  L->csr_w = take(nc == 3 ? csr_n * 8 : 0);
+  L->csr_w = take(nc == 3 && !pl->otf ? csr_n * 8 : 0);
   L->total = off;
   return MM_OK;
 }

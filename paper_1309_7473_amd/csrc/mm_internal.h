@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/mm.h"
+#include "pointing.h"
 
 namespace mm {
 
@@ -89,6 +90,7 @@ struct Plan {
   int corr_nbins;
   bool single;       // whole detector filtered in one kernel
   bool csr;          // P^T by per-pixel gather (else atomic scatter)
+  bool otf;          // pointing computed from the boresight model
   int logn, logM;    // n = 2^logn samples, M = n/2 packed complex
   int logM1, logM2;  // four-step split
   int logC;          // columns per pass-1/3 block
@@ -125,6 +127,20 @@ struct ScanImpl {
   template <typename P>
   P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
+
+// The boresight model of a scan (pointers null for stored pointing).
+inline Bore scan_bore(const ScanImpl* s) {
+  Bore b;
+  if (s->plan.otf) {
+    b.b = s->d.bore;
+    b.det = s->d.det_off;
+  }
+  b.logn = s->plan.logn;
+  b.ndet = s->ndet;
+  b.ny = s->ny;
+  b.nx = s->nx;
+  return b;
+}
 
 // ---- launchers implemented across the .hip files -------------------------
 mm_status plan_and_layout(const mm_scan_desc* d, Plan* plan, Layout* lay);

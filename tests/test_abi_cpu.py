@@ -131,6 +131,9 @@ def test_create_requires_pointers_and_workspace(mm):
     assert mm.lib.mm_create_scan(None, None, C.byref(h)) == mm.MM_EINVAL
     d = _desc(mm)
     assert mm.lib.mm_create_scan(C.byref(d), None, C.byref(h)) == mm.MM_EINVAL
+    assert "inv_noise" in mm.mm_last_error()
+    d.inv_noise = 0x2000
+    assert mm.lib.mm_create_scan(C.byref(d), None, C.byref(h)) == mm.MM_EINVAL
     assert "pix" in mm.mm_last_error()
     d.pix, d.inv_noise, d.cos2psi, d.sin2psi = 0x1000, 0x2000, 0x3000, 0x4000
     assert mm.lib.mm_create_scan(C.byref(d), None, C.byref(h)) == mm.MM_EINVAL
@@ -167,3 +170,33 @@ def test_last_error_is_thread_local(mm):
     t.start()
     t.join()
     assert mine and other == [b""]
+
+
+def test_boresight_pointing_descriptor(mm):
+    """Validation of the boresight pointing mode (no device work: every
+    rejection happens before the first HIP call)."""
+    h = C.c_void_p()
+    d = _desc(mm, nsamp=2**16)
+    stored = mm.mm_scan_workspace_bytes(d)
+    d.pointing = 2
+    assert mm.mm_scan_workspace_bytes(d) == 0 and "pointing" in mm.mm_last_error()
+    d.pointing = mm.MM_POINT_BORESIGHT
+    otf = mm.mm_scan_workspace_bytes(d)
+    # the pixel-major index holds no weights: 8 B per sample less
+    assert stored - otf >= 8 * d.ndet * d.nsamp - 4096
+    d.scatter = mm.MM_SCATTER_ATOMIC
+    assert mm.mm_scan_workspace_bytes(d) == 0 and "SCATTER_AUTO" in mm.mm_last_error()
+    d.scatter = mm.MM_SCATTER_AUTO
+    d.inv_noise = 0x2000
+    d.pix = 0x1000
+    assert mm.lib.mm_create_scan(C.byref(d), None, C.byref(h)) == mm.MM_EINVAL
+    assert "must be NULL" in mm.mm_last_error()
+    d.pix = None
+    assert mm.lib.mm_create_scan(C.byref(d), None, C.byref(h)) == mm.MM_EINVAL
+    assert "required" in mm.mm_last_error()
+    d.bore, d.det_off = 0x10008, 0x20000
+    assert mm.lib.mm_create_scan(C.byref(d), None, C.byref(h)) == mm.MM_EINVAL
+    assert "aligned" in mm.mm_last_error()
+    d.bore = 0x10000
+    assert mm.lib.mm_create_scan(C.byref(d), None, C.byref(h)) == mm.MM_EINVAL
+    assert "workspace" in mm.mm_last_error()
