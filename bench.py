@@ -239,6 +239,40 @@ def correlated_leg(inp, x_sky, rank=2, nbins=16, reps=10):
     return out
 
 
+def boresight_leg(inp, x_sky, taper, reps=10):
+    """The same workload with its pointing given as the boresight model
+    (pixel and weights computed inside the kernels instead of 12 B/sample of
+    stored pointing): A-apply time and stages, and circulant PCG to 1e-6."""
+    import torch
+    import paper_1309_7473_amd as mm
+    from synth import boresight_only
+    scan = mm.Scan(boresight_only(inp), tod_dtype="f32")
+    y = scan.new_map()
+    for _ in range(2):
+        scan.apply_A(x_sky, y)
+    mm.mm_profile_enable(scan.handle, True)
+    mm.mm_profile_read(scan.handle)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        scan.apply_A(x_sky, y)
+    torch.cuda.synchronize()
+    prof = mm.mm_profile_read(scan.handle)
+    mm.mm_profile_enable(scan.handle, False)
+    a_ms = prof["apply_A"][0] / prof["apply_A"][1]
+    S = inp.ndet * inp.nsamp
+    b = scan.apply_A(x_sky)
+    scan.build_precon("circulant", sigma=taper)
+    r = scan.pcg("circulant", b, tol=1e-6, maxiter=5000, check_every=10, history=False)
+    out = {"apply_ms": round(a_ms, 4), "samples_per_s": S / (a_ms * 1e-3),
+           "stage_us_per_launch": {k: round(v[0] / v[1] * 1e3, 1) for k, v in prof.items()
+                                   if k != "apply_A"},
+           "workspace_GiB": round(scan.workspace.numel() / 2**30, 3),
+           "circulant_iters": r["iters"], "circulant_time_s": round(r["t_solve_s"], 4),
+           "converged": r["converged"]}
+    scan.close()
+    return out
+
+
 def tiled_leg(scan, b, configs=((256, 60.0), (128, 32.0), (64, 16.0)), reps=20):
     """The tiled constant-correlation preconditioner (Summary section) on the
     same workload: build time, time per apply (HIP events over reps applies)
@@ -479,6 +513,7 @@ def main():
         solves["ps_convergence"] = ps_leg(scan, b, x_sky)
         solves["correlated_noise"] = correlated_leg(inp, x_sky)
         solves["tiled"] = tiled_leg(scan, b)
+        solves["boresight_pointing"] = boresight_leg(inp, x_sky, args.taper)
         solves["circulant_tapers"] = taper_leg(scan, b)
 
     if args.calibrate_copy:

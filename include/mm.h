@@ -151,7 +151,9 @@ typedef struct {
    *   weights cos 2(psi_d + phi) = c2psi c2phi - s2psi s2phi and
    *           sin 2(psi_d + phi) = s2psi c2phi + c2psi s2phi.
    * The pixel-major index of P^T is then always used (scatter must not be
-   * MM_SCATTER_ATOMIC) and holds no weights (4 B/sample of workspace). */
+   * MM_SCATTER_ATOMIC).  On the float64 path (MM_F64) it holds no weights
+   * (4 B/sample of workspace) and the gather computes them in float64; the
+   * float32 and bfloat16 paths keep float32 weights beside it (12 B/sample). */
   int32_t pointing;         /* mm_pointing */
   const double* bore;       /* device [6][nsamp] float64, 16-byte aligned: y_b, x_b
                                (pixel coordinates), cos phi, sin phi, cos 2phi,

@@ -4,9 +4,9 @@
 //
 // For group g (detectors g*G .. g*G+G-1, G*n samples) the entries of pixel p
 // are off[g][p] .. off[g][p+1]-1; entry e holds the group-relative sample
-// index idx[e] = d_local*n + t and, for I,Q,U with stored pointing, its
-// weights (cos 2psi, sin 2psi); with boresight pointing the gather computes
-// them from the index.  Runs of equal pixels inside a wavefront claim their slots with
+// index idx[e] = d_local*n + t and, for I,Q,U, its weights (cos 2psi,
+// sin 2psi) as float32, except for boresight pointing on the float64 path,
+// whose gather computes them from the index.  Runs of equal pixels inside a wavefront claim their slots with
 // one atomic, so the order inside a pixel is fixed once the index is built
 // (the per-pixel sum order of every later apply is then fixed too).
 #include "mm_device.h"
@@ -115,7 +115,11 @@ __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pi
       const int64_t e = g * gsz + slot0 + (lane - h);
       idx[e] = int32_t(i - g * gsz);
       if constexpr (NC == 3) {
-        if (w) w[e] = make_float2(c2[i], s2[i]);   // boresight pointing: no stored weights
+        if (w) {   // NULL: the gather computes the weights from the boresight model
+          double c, sn;
+          sample_weights(c2, s2, bo, i, &c, &sn);
+          w[e] = make_float2(float(c), float(sn));
+        }
       }
     }
   }
@@ -141,7 +145,7 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
     hipLaunchKernelGGL(k_csr_fill<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->n, total, G, npix, cnt,
                        s->at<int32_t>(L.csr_idx),
-                       s->plan.otf ? static_cast<float2*>(nullptr) : s->at<float2>(L.csr_w));
+                       s->plan.csr_w ? s->at<float2>(L.csr_w) : static_cast<float2*>(nullptr));
   else
     hipLaunchKernelGGL(k_csr_fill<1>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->n, total, G, npix, cnt,

@@ -326,6 +326,10 @@ __global__ void __launch_bounds__(kNT) k_single(PassArgs<T, S> a) {
 
 // ------------------------------------------------------------- four-step
 constexpr int kNT13 = 1024;  // threads per pass-1/3 block
+#ifndef MM_UB
+#define MM_UB 1
+#endif
+constexpr int UB = MM_UB;     // sample groups in flight per thread with boresight pointing
 // complex elements per thread: 8 (C * M1 <= 8192) or 16 (C * M1 <= 16384,
 // float math only: 128 KB of LDS per block)
 constexpr int kPad2 = 3;     // pass-2 LDS padding: one slot per 8 elements
@@ -420,8 +424,22 @@ __device__ __forceinline__ void stage_twiddles(Cx<T>* stw, const Cx<T>* tw, int 
 // For pass 1/3 the column blocks of a detector are renumbered so that XCD x
 // handles the x-th eighth of them: its samples then sit in one eighth of each
 // sweep, and the map pixels they touch stay in that XCD's L2.
+//
+// With boresight pointing (DET_FAST) the slots of an XCD take its column
+// blocks one at a time for every detector of the group in turn: the blocks
+// resident together then read the same boresight samples, which stay in
+// that XCD's L2 instead of being streamed once per detector.
+template <bool DET_FAST = false>
 __device__ __forceinline__ void col_block(int logNB, int* g, int* cb) {
   const int bid = blockIdx.x;
+  if (DET_FAST && logNB >= 3) {
+    const int x = bid & 7, slot = bid >> 3;
+    const int per = 1 << (logNB - 3);
+    const int gd = int(gridDim.x) >> logNB;                // detectors in the group
+    *g = slot % gd;
+    *cb = x * per + slot / gd;
+    return;
+  }
   if (logNB >= 3) {
     const int x = bid & 7, slot = bid >> 3;              // XCD, slot on it
     const int per = 1 << (logNB - 3);                      // column blocks per XCD
@@ -440,7 +458,7 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
   T* bufr = reinterpret_cast<T*>(smem);
   const int logNB = a.logM2 - a.logC;
   int g, cb;
-  col_block(logNB, &g, &cb);
+  col_block<SRC == 2>(logNB, &g, &cb);
   const int C = 1 << a.logC;
   const int M1 = 1 << a.logM1, M2 = 1 << a.logM2;
   Cx<T>* stw = buf + C * M1;
@@ -450,7 +468,7 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
   const int nq = (C * M1) >> 1;  // groups of 4 samples
   // U groups per thread per trip, every load of a trip issued before the
   // first use; a group past the end re-reads group e40 and is not stored.
-  constexpr int U = 4;
+  constexpr int U = (SRC == 2) ? UB : 4;
   for (int e40 = threadIdx.x; e40 < nq; e40 += U * kNT13) {
     T v[U][4];
 #pragma unroll
@@ -1069,7 +1087,7 @@ static void launch_pass2w(int M2, dim3 g, size_t lds, hipStream_t st, const Pass
 template <typename T, typename S, int NC>
 static void launch_reduce(ScanImpl* s, const PassArgs<T, S>& a, hipStream_t st) {
   const dim3 grid((s->npix + 15) / 16);   // 16 pixels of 16 lanes per block
-  const bool otf = s->plan.otf && NC == 3;
+  const bool otf = !s->plan.csr_w && NC == 3;
   if (s->plan.acc32) {
     if (otf)
       hipLaunchKernelGGL((k_csr_reduce<T, S, NC, true, true>), grid, dim3(256), 0, st, a);
@@ -1122,8 +1140,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const int gi = d0 / G;
       a.csr_off = s->at<int32_t>(s->lay.csr_off) + int64_t(gi) * (s->npix + 1);
       a.csr_idx = s->at<int32_t>(s->lay.csr_idx) + int64_t(gi) * G * s->n;
-      a.csr_w = s->nc == 3 && !pl.otf ? s->at<float2>(s->lay.csr_w) + int64_t(gi) * G * s->n
-                                      : nullptr;
+      a.csr_w = pl.csr_w ? s->at<float2>(s->lay.csr_w) + int64_t(gi) * G * s->n : nullptr;
     }
     const int64_t gs = int64_t(gd) * s->n;
     hipEvent_t tok;
@@ -1455,7 +1472,10 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->csr_cnt = take(pl->csr ? size_t(ngroups) * npix * 4 : 0);
   L->csr_off = take(pl->csr ? size_t(ngroups) * (npix + 1) * 4 : 0);
   L->csr_idx = take(csr_n * 4);
-  L->csr_w = take(nc == 3 && !pl->otf ? csr_n * 8 : 0);
+  // stored weights beside the index, except for boresight pointing on the
+  // float64 path, whose gather computes float64 weights from the model
+  pl->csr_w = nc == 3 && !(pl->otf && pl->f64);
+  L->csr_w = take(pl->csr_w ? csr_n * 8 : 0);
   L->total = off;
   return MM_OK;
 }

@@ -91,6 +91,7 @@ struct Plan {
   bool single;       // whole detector filtered in one kernel
   bool csr;          // P^T by per-pixel gather (else atomic scatter)
   bool otf;          // pointing computed from the boresight model
+  bool csr_w;        // the pixel-major index stores the (float32) weights
   int logn, logM;    // n = 2^logn samples, M = n/2 packed complex
   int logM1, logM2;  // four-step split
   int logC;          // columns per pass-1/3 block

@@ -181,9 +181,15 @@ def test_boresight_pointing_descriptor(mm):
     d.pointing = 2
     assert mm.mm_scan_workspace_bytes(d) == 0 and "pointing" in mm.mm_last_error()
     d.pointing = mm.MM_POINT_BORESIGHT
+    assert mm.mm_scan_workspace_bytes(d) == stored   # float32 weights kept beside the index
+    d.tod_dtype = mm.MM_F64
+    d.pointing = mm.MM_POINT_STORED
+    stored = mm.mm_scan_workspace_bytes(d)
+    d.pointing = mm.MM_POINT_BORESIGHT
     otf = mm.mm_scan_workspace_bytes(d)
-    # the pixel-major index holds no weights: 8 B per sample less
+    # float64 path: the index holds no weights, 8 B per sample less
     assert stored - otf >= 8 * d.ndet * d.nsamp - 4096
+    d.tod_dtype = mm.MM_F32
     d.scatter = mm.MM_SCATTER_ATOMIC
     assert mm.mm_scan_workspace_bytes(d) == 0 and "SCATTER_AUTO" in mm.mm_last_error()
     d.scatter = mm.MM_SCATTER_AUTO
