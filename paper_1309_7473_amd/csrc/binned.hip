@@ -125,6 +125,71 @@ __global__ void __launch_bounds__(256) k_binned_accum(const int32_t* __restrict_
   }
 }
 
+// The same sums as k_binned_accum through the pixel-major index (when the
+// scan has one): 16 lanes per pixel run over the pixel's entries of every
+// detector group in a fixed order, so no atomics and a deterministic result.
+// Entry ik of group g is detector g * G + (ik >> logn), sample ik & (n - 1).
+template <int NC>
+__global__ void __launch_bounds__(256) k_binned_gather(const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ idx,
+                                                       const float2* __restrict__ w, Bore bo,
+                                                       const double* __restrict__ detw,
+                                                       int ngroups, int G, int npix,
+                                                       double* __restrict__ hits,
+                                                       double* __restrict__ Bb,
+                                                       double* __restrict__ Bj) {
+  constexpr int LPP = 16;
+  constexpr int NU = (NC == 3) ? 6 : 1;
+  constexpr int NV = 1 + 2 * NU;
+  const int l = threadIdx.x % LPP;
+  const int p = blockIdx.x * (256 / LPP) + threadIdx.x / LPP;
+  if (p >= npix) return;               // whole 16-lane groups leave together
+  const int64_t gsz = int64_t(G) << bo.logn;
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0.0;
+  for (int g = 0; g < ngroups; ++g) {
+    const int32_t* o = off + int64_t(g) * (npix + 1);
+    const int b = o[p], e = o[p + 1];
+    for (int k = b + l; k < e; k += LPP) {
+      const int ik = idx[int64_t(g) * gsz + k];
+      const int d = g * G + (ik >> bo.logn);
+      const double wd = detw[d];
+      double u[NU];
+      u[0] = 1.0;
+      if constexpr (NC == 3) {
+        double c, sn;
+        if (w) {
+          const float2 cs = w[int64_t(g) * gsz + k];
+          c = double(cs.x);
+          sn = double(cs.y);
+        } else {
+          bore_weights_at(bo, d, ik & ((1 << bo.logn) - 1), &c, &sn);
+        }
+        u[1] = c; u[2] = sn; u[3] = c * c; u[4] = c * sn; u[5] = sn * sn;
+      }
+      v[0] += 1.0;
+#pragma unroll
+      for (int j = 0; j < NU; ++j) {
+        v[1 + j] += u[j];
+        v[1 + NU + j] += wd * u[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int o2 = LPP / 2; o2 > 0; o2 >>= 1) v[k] += __shfl_xor(v[k], o2, LPP);
+  if (l == 0) {
+    hits[p] = v[0];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      Bj[6 * int64_t(p) + j] = v[1 + j];
+      Bb[6 * int64_t(p) + j] = v[1 + NU + j];
+    }
+  }
+}
+
 // Mask, inverse blocks and Sigma^-1 per pixel.
 template <int NC>
 __global__ void k_binned_finalize(const double* __restrict__ hits, const double* __restrict__ Bb,
@@ -274,7 +339,22 @@ mm_status binned_setup(ScanImpl* s, hipStream_t st) {
   int64_t blocks = (total + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   const Bore bo = scan_bore(s);
-  if (s->nc == 3)
+  if (s->plan.csr) {
+    // build the pixel-major index first, then sum through it
+    if ((r = csr_setup(s, st)) != MM_OK) return r;
+    const int G = s->plan.G, ngroups = (s->ndet + G - 1) / G;
+    // boresight pointing: float64 weights from the model, not the index's float32 copy
+    const float2* w = s->plan.csr_w && !s->plan.otf ? s->at<float2>(L.csr_w) : nullptr;
+    const dim3 gg((npix + 15) / 16);
+    if (s->nc == 3)
+      hipLaunchKernelGGL(k_binned_gather<3>, gg, dim3(256), 0, st, s->at<int32_t>(L.csr_off),
+                         s->at<int32_t>(L.csr_idx), w, bo, s->at<double>(L.detw), ngroups, G,
+                         npix, s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
+    else
+      hipLaunchKernelGGL(k_binned_gather<1>, gg, dim3(256), 0, st, s->at<int32_t>(L.csr_off),
+                         s->at<int32_t>(L.csr_idx), w, bo, s->at<double>(L.detw), ngroups, G,
+                         npix, s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
+  } else if (s->nc == 3)
     hipLaunchKernelGGL(k_binned_accum<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->at<double>(L.detw), s->n, total, npix,
                        s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
