@@ -42,8 +42,8 @@ static mm_status validate_shape(const mm_scan_desc* d) {
   if (!pow2(d->ny) || !pow2(d->nx) || d->ny < 4 || d->nx < 4 || d->ny > 4096 || d->nx > 4096)
     return fail(MM_EINVAL, "ny and nx must be powers of two in [4, 4096]");
   if (d->ndet < 1) return fail(MM_EINVAL, "ndet must be >= 1");
-  if (!pow2(d->nsamp) || d->nsamp < 16 || d->nsamp > (int64_t(1) << 22))
-    return fail(MM_EINVAL, "nsamp must be a power of two in [16, 2^22]");
+  if (d->nsamp < 16 || d->nsamp > (int64_t(1) << 22) || (d->nsamp & 1))
+    return fail(MM_EINVAL, "nsamp must be even and in [16, 2^22]");
   if (d->tod_dtype != MM_F32 && d->tod_dtype != MM_BF16 && d->tod_dtype != MM_F64)
     return fail(MM_EINVAL, "tod_dtype must be MM_F32, MM_BF16 or MM_F64");
   if (d->det_group < 0) return fail(MM_EINVAL, "det_group must be >= 0");

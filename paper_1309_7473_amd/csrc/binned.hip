@@ -128,13 +128,13 @@ __global__ void __launch_bounds__(256) k_binned_accum(const int32_t* __restrict_
 // The same sums as k_binned_accum through the pixel-major index (when the
 // scan has one): 16 lanes per pixel run over the pixel's entries of every
 // detector group in a fixed order, so no atomics and a deterministic result.
-// Entry ik of group g is detector g * G + (ik >> logn), sample ik & (n - 1).
+// Entry ik of group g is detector g * G + ik / n, sample ik mod n.
 template <int NC>
 __global__ void __launch_bounds__(256) k_binned_gather(const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ idx,
                                                        const float2* __restrict__ w, Bore bo,
                                                        const double* __restrict__ detw,
-                                                       int ngroups, int G, int npix,
+                                                       int ngroups, int G, int n, int npix,
                                                        double* __restrict__ hits,
                                                        double* __restrict__ Bb,
                                                        double* __restrict__ Bj) {
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(256) k_binned_gather(const int32_t* __restrict
   const int l = threadIdx.x % LPP;
   const int p = blockIdx.x * (256 / LPP) + threadIdx.x / LPP;
   if (p >= npix) return;               // whole 16-lane groups leave together
-  const int64_t gsz = int64_t(G) << bo.logn;
+  const int64_t gsz = int64_t(G) * n;
   double v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = 0.0;
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(256) k_binned_gather(const int32_t* __restrict
     const int b = o[p], e = o[p + 1];
     for (int k = b + l; k < e; k += LPP) {
       const int ik = idx[int64_t(g) * gsz + k];
-      const int d = g * G + (ik >> bo.logn);
+      const int d = g * G + ik / n;
       const double wd = detw[d];
       double u[NU];
       u[0] = 1.0;
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(256) k_binned_gather(const int32_t* __restrict
           c = double(cs.x);
           sn = double(cs.y);
         } else {
-          bore_weights_at(bo, d, ik & ((1 << bo.logn) - 1), &c, &sn);
+          bore_weights_at(bo, d, ik % n, &c, &sn);
         }
         u[1] = c; u[2] = sn; u[3] = c * c; u[4] = c * sn; u[5] = sn * sn;
       }
@@ -349,11 +349,11 @@ mm_status binned_setup(ScanImpl* s, hipStream_t st) {
     if (s->nc == 3)
       hipLaunchKernelGGL(k_binned_gather<3>, gg, dim3(256), 0, st, s->at<int32_t>(L.csr_off),
                          s->at<int32_t>(L.csr_idx), w, bo, s->at<double>(L.detw), ngroups, G,
-                         npix, s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
+                         int(s->n), npix, s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
     else
       hipLaunchKernelGGL(k_binned_gather<1>, gg, dim3(256), 0, st, s->at<int32_t>(L.csr_off),
                          s->at<int32_t>(L.csr_idx), w, bo, s->at<double>(L.detw), ngroups, G,
-                         npix, s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
+                         int(s->n), npix, s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
   } else if (s->nc == 3)
     hipLaunchKernelGGL(k_binned_accum<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->at<double>(L.detw), s->n, total, npix,

@@ -33,6 +33,7 @@
 #include <cmath>
 
 #include "fft_lds.h"
+#include "fft_mixed.h"
 #include "mm_internal.h"
 
 namespace mm {
@@ -95,6 +96,8 @@ struct PassArgs {
   const Cx<T>* tw2;        // W_{2 M2}^k2, k2 < M2
   Bore bo;                 // boresight model (SRC 2, and the gather's weights)
   int det0;                // first detector of the group
+  int Mi;                  // M = n/2 (any 2^a 3^b 5^c on the one-kernel path)
+  uint32_t mix_code;       // stage radices of a mixed-radix M (0: M is a power of two)
   int64_t n;
   int npix;
   int logM, logM1, logM2, logC, logLmax;
@@ -290,14 +293,18 @@ __global__ void __launch_bounds__(kNT) k_single(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
   T* bufr = reinterpret_cast<T*>(smem);
-  const int M = 1 << a.logM;
+  const int M = a.Mi;
   const int g = blockIdx.x;
   const int64_t base = int64_t(g) * a.n;
   const int nsamp = 2 * M;
   for (int e = threadIdx.x; e < nsamp; e += kNT) bufr[e] = source_sample<T, S, NC, SRC>(a, base + e);
   __syncthreads();
   FftShape sh{a.logM, 0, 1, M, false, a.logLmax};
-  lds_fft<T, kNT, kE, false>(buf, sh, a.tw);
+  const MixShape mx{M, 1, 1, M, false, a.mix_code, 1};
+  if (a.mix_code)
+    lds_fft_mx<T, kNT, kE, false>(buf, mx, a.tw);
+  else
+    lds_fft<T, kNT, kE, false>(buf, sh, a.tw);
   const float* iN = a.iN + int64_t(g) * (M + 1);
   for (int k = threadIdx.x; k <= M / 2; k += kNT) {
     if (k == 0) {
@@ -310,9 +317,12 @@ __global__ void __launch_bounds__(kNT) k_single(PassArgs<T, S> a) {
     }
   }
   __syncthreads();
-  lds_fft<T, kNT, kE, true>(buf, sh, a.tw);
+  if (a.mix_code)
+    lds_fft_mx<T, kNT, kE, true>(buf, mx, a.tw);
+  else
+    lds_fft<T, kNT, kE, true>(buf, sh, a.tw);
   if constexpr (CSR) {
-    auto* w = a.work + (int64_t(g) << a.logM);
+    auto* w = a.work + int64_t(g) * M;
     for (int j = threadIdx.x; j < M; j += kNT) Sto<T, S>::st(w + j, buf[j]);
     return;
   }
@@ -1105,8 +1115,10 @@ template <typename T, typename S, int NC, int SRC>
 static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
   using A = PassArgs<T, S>;
   const Plan& pl = s->plan;
-  const int M = 1 << pl.logM;
+  const int M = int(s->n / 2);
   A a;
+  a.Mi = M;
+  a.mix_code = pl.mix_code;
   a.gmap = s->at<V4<T>>(s->lay.gmap);
   a.acc = s->at<double>(s->lay.acc);
   a.work = s->at<typename A::W>(s->lay.tod);
@@ -1357,9 +1369,20 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   const int64_t n = d->nsamp;
   pl->f64 = d->tod_dtype == MM_F64;
   pl->bf16 = d->tod_dtype == MM_BF16;
-  pl->logn = ilog2(n);
+  pl->logn = ilog2(n);                         // ceil(log2 n) for mixed-radix n
   pl->logM = pl->logn - 1;
-  const int M = 1 << pl->logM;
+  const int M = int(n / 2);
+  // n = 2^a 3^b 5^c that is not a power of two: mixed-radix one-kernel filter
+  pl->mix_code = (n & (n - 1)) == 0 ? 0u : mixed_radix_code(M);
+  if ((n & (n - 1)) != 0) {
+    if (pl->mix_code == 0) return fail(MM_EINVAL, "nsamp must be 2^a 3^b 5^c");
+    if (M > kE * kNT)
+      return fail(MM_EINVAL, "nsamp that is not a power of two needs nsamp/2 <= 8192");
+    if (d->corr_rank > 0)
+      return fail(MM_EINVAL, "correlated noise needs nsamp a power of two");
+    if (d->pointing == MM_POINT_BORESIGHT)
+      return fail(MM_EINVAL, "MM_POINT_BORESIGHT needs nsamp a power of two");
+  }
   const size_t cxb = pl->f64 ? 16 : 8;          // one complex in the math type
   const size_t wxb = pl->bf16 ? 4 : cxb;         // ... in the pass buffer
   pl->acc32 = d->acc == MM_ACC_F32X2;
@@ -1438,10 +1461,10 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     return o;
   };
   L->tod = take(pl->single && !pl->csr ? 0 : size_t(pl->G) * size_t(M) * wxb);
-  L->tw = take((size_t(1) << pl->logLmax) * cxb);
+  L->tw = take((pl->mix_code ? size_t(M) : (size_t(1) << pl->logLmax)) * cxb);
   L->tw2 = take(pl->single ? 0 : (size_t(1) << pl->logM2) * cxb);
   L->int_ = take(pl->single ? 0 : size_t(d->ndet) * size_t(M + 1) * 4);
-  L->wn_hi = take((size_t(1) << (pl->logn - pl->logS)) * cxb);
+  L->wn_hi = take(size_t((n + (int64_t(1) << pl->logS) - 1) >> pl->logS) * cxb);
   L->wn_lo = take((size_t(1) << pl->logS) * cxb);
   L->gmap = take(size_t(npix + 1) * 4 * (pl->f64 ? 8 : 4));
   L->acc = take(size_t(npix) * 4 * 8);
@@ -1496,10 +1519,13 @@ static mm_status upload_t(ScanImpl* s, hipStream_t st) {
   const Plan& pl = s->plan;
   std::vector<Cx<T>> tw, hi, lo;
   const int64_t Lmax = int64_t(1) << pl.logLmax;
-  table(tw, Lmax, 1, Lmax);
-  const int64_t n = int64_t(1) << pl.logn;
+  if (pl.mix_code)
+    table(tw, s->n / 2, 1, s->n / 2);   // W_M^m for the mixed-radix stages
+  else
+    table(tw, Lmax, 1, Lmax);
+  const int64_t n = s->n;
   const int64_t S = int64_t(1) << pl.logS;
-  table(hi, n / S, S, n);
+  table(hi, (n + S - 1) / S, S, n);
   table(lo, S, 1, n);
   MM_HIP(hipMemcpyAsync(s->ws + s->lay.tw, tw.data(), tw.size() * sizeof(Cx<T>),
                         hipMemcpyHostToDevice, st));

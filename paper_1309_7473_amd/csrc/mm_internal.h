@@ -92,6 +92,7 @@ struct Plan {
   bool csr;          // P^T by per-pixel gather (else atomic scatter)
   bool otf;          // pointing computed from the boresight model
   bool csr_w;        // the pixel-major index stores the (float32) weights
+  uint32_t mix_code; // mixed-radix stage code of M = n/2 (0: n a power of two)
   int logn, logM;    // n = 2^logn samples, M = n/2 packed complex
   int logM1, logM2;  // four-step split
   int logC;          // columns per pass-1/3 block

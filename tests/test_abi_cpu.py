@@ -87,7 +87,8 @@ def test_compensated_accumulation_takes_the_gather_on_one_kernel_plans(mm):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("ncomp", 2), ("ny", 48), ("nx", 2), ("ndet", 0), ("nsamp", 1000), ("nsamp", 8),
+    ("ncomp", 2), ("ny", 48), ("nx", 2), ("ndet", 0), ("nsamp", 1022), ("nsamp", 1001), ("nsamp", 8),
+    ("nsamp", 3 * 2**14), ("nsamp", 7 * 2**8),
     ("nsamp", 1 << 23), ("tod_dtype", 7), ("fft_m1", 3), ("det_group", -1), ("scatter", 5),
     ("acc", 2),
 ])
@@ -206,3 +207,19 @@ def test_boresight_pointing_descriptor(mm):
     d.bore = 0x10000
     assert mm.lib.mm_create_scan(C.byref(d), None, C.byref(h)) == mm.MM_EINVAL
     assert "workspace" in mm.mm_last_error()
+
+
+def test_mixed_radix_lengths(mm):
+    """n = 2^a 3^b 5^c with n/2 <= 8192 plans the one-kernel filter; larger
+    ones, correlated noise and boresight pointing need a power of two."""
+    for n in (30, 1000, 3 * 2**11, 15 * 2**9, 2 * 3**8, 2 * 5**5, 2**4 * 3 * 5**3):
+        d = _desc(mm, nsamp=n)
+        assert mm.mm_scan_workspace_bytes(d) > 0, n
+    d = _desc(mm, nsamp=3 * 2**14)
+    assert mm.mm_scan_workspace_bytes(d) == 0 and "8192" in mm.mm_last_error()
+    d = _desc(mm, nsamp=1000, pointing=mm.MM_POINT_BORESIGHT)
+    assert mm.mm_scan_workspace_bytes(d) == 0 and "power of two" in mm.mm_last_error()
+    import numpy as np
+    edges = np.array([0, 100, 501], np.int32)
+    d = _desc(mm, nsamp=1000, corr_rank=1, corr_nbins=2, corr_edges=edges.ctypes.data)
+    assert mm.mm_scan_workspace_bytes(d) == 0 and "power of two" in mm.mm_last_error()

@@ -71,13 +71,16 @@ def test_PT_of_ones_is_hit_map():
     np.testing.assert_array_equal(oracle.hits(sc), counts)
 
 
-def test_inv_noise_matches_dense_dft_circulant(rng):
+@pytest.mark.parametrize("n", [64, 60, 90])
+def test_inv_noise_matches_dense_dft_circulant(n, rng):
     # N^-1 = F^-1 diag(iN_two_sided) F with F_fj = exp(-2 pi i j f / n), built
-    # from explicit DFT matrices (the Fourier convention of eq. 11).
-    inp = small_raster(ncomp=1, ny=4, nx=4, ndet=2, sweeps=4)
+    # from explicit DFT matrices (the Fourier convention of eq. 11); also at
+    # lengths that are not powers of two (n/2 = 30 and the odd 45)
+    from synth import raster_scan
+    inp = raster_scan(ncomp=1, ny=4, nx=4, ndet=2, nsamp=n, fsample=100.0, layout="hex",
+                      hex_diameter_px=3.0, fknee=(1.0, 2.0), seed=(99, n))
     sc = oracle.OracleScan(inp)
-    n = sc.nsamp
-    assert n == 64
+    assert sc.nsamp == n
     j = np.arange(n)
     F = np.exp(-2j * np.pi * np.outer(j, j) / n)
     Finv = np.exp(2j * np.pi * np.outer(j, j) / n) / n
@@ -125,10 +128,12 @@ def test_A_symmetric_positive(ncomp, rng):
     assert np.all(Ax.reshape(ncomp, -1)[:, ~mask] == 0)
 
 
-def test_detector_weight_is_diagonal_of_Ninv():
-    inp = small_raster(ncomp=1, ny=4, nx=4, ndet=3, sweeps=4)
+@pytest.mark.parametrize("n", [64, 90])
+def test_detector_weight_is_diagonal_of_Ninv(n):
+    from synth import raster_scan
+    inp = raster_scan(ncomp=1, ny=4, nx=4, ndet=3, nsamp=n, fsample=100.0, layout="hex",
+                      hex_diameter_px=3.0, fknee=(1.0, 2.0), seed=(98, n))
     sc = oracle.OracleScan(inp)
-    n = sc.nsamp
     e0 = np.zeros((3, n))
     e0[:, 7] = 1.0
     diag = oracle.inv_noise(sc, e0)[:, 7]
