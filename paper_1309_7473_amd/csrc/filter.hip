@@ -96,8 +96,11 @@ struct PassArgs {
   const Cx<T>* tw2;        // W_{2 M2}^k2, k2 < M2
   Bore bo;                 // boresight model (SRC 2, and the gather's weights)
   int det0;                // first detector of the group
-  int Mi;                  // M = n/2 (any 2^a 3^b 5^c on the one-kernel path)
-  uint32_t mix_code;       // stage radices of a mixed-radix M (0: M is a power of two)
+  int Mi;                  // M = n/2
+  int M1i;                 // four-step column length (2^a 3^b 5^c)
+  uint32_t mix_code;       // stage radices of the mixed-radix LDS transform: M on the
+                           // one-kernel path, M1 in passes 1 and 3 (0: a power of two)
+  const Cx<T>* twm;        // W_M1^m, m < M1 (mixed-radix columns)
   int64_t n;
   int npix;
   int logM, logM1, logM2, logC, logLmax;
@@ -470,11 +473,14 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
   int g, cb;
   col_block<SRC == 2>(logNB, &g, &cb);
   const int C = 1 << a.logC;
-  const int M1 = 1 << a.logM1, M2 = 1 << a.logM2;
+  const int M1 = a.M1i, M2 = 1 << a.logM2;
   Cx<T>* stw = buf + C * M1;
   const int j20 = cb << a.logC;
   const int64_t base = int64_t(g) * a.n;
-  stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
+  if (a.mix_code)
+    for (int m = threadIdx.x; m < M1; m += kNT13) stw[m] = a.twm[m];
+  else
+    stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
   const int nq = (C * M1) >> 1;  // groups of 4 samples
   // U groups per thread per trip, every load of a trip issued before the
   // first use; a group past the end re-reads group e40 and is not stored.
@@ -497,8 +503,11 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
   }
   __syncthreads();
   FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
-  lds_fft<T, kNT13, E13, false>(buf, sh, stw);
-  auto* w = a.work + (int64_t(g) << a.logM);
+  if (a.mix_code)
+    lds_fft_mx<T, kNT13, E13, false>(buf, MixShape{M1, C, C, 1, true, a.mix_code, 1}, stw);
+  else
+    lds_fft<T, kNT13, E13, false>(buf, sh, stw);
+  auto* w = a.work + int64_t(g) * a.Mi;
   for (int e = threadIdx.x; e < C * M1; e += kNT13) {
     const int k1 = e >> a.logC;
     const int c = e & (C - 1);
@@ -513,17 +522,17 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
 template <typename T, typename S, int E>
 __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int M1 = 1 << a.logM1, M2 = 1 << a.logM2;
-  const int M = 1 << a.logM;
+  const int M1 = a.M1i, M2 = 1 << a.logM2;
+  const int M = a.Mi;
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
   Cx<T>* stw = buf + lds_at<kPad2>(2 * M2);   // length-M2 Stockham twiddles
   const int logJL = a.logM2 < 6 ? a.logM2 : 6;
   const int JL = 1 << logJL, JH = M2 >> logJL;
   Cx<T>* tA = stw + M2;      // [2][JH]
   Cx<T>* tB = tA + 2 * JH;   // [2][JL]
-  const int lhalf = a.logM1 - 1;
-  const int g = blockIdx.x >> lhalf;
-  const int pr = blockIdx.x & ((1 << lhalf) - 1);
+  const int half = M1 >> 1;   // row pairs per detector
+  const int g = blockIdx.x / half;
+  const int pr = blockIdx.x % half;
   const int ra = pr;
   const int rb = (pr == 0) ? (M1 >> 1) : (M1 - pr);
   stage_twiddles<T, kNT>(stw, a.tw, a.logM2, a.logLmax);
@@ -536,7 +545,7 @@ __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T, S> a) {
     tB[t] = a.wn(2 * int64_t(r ? rb : ra) * jl);
   }
   __syncthreads();
-  auto* w = a.work + (int64_t(g) << a.logM);
+  auto* w = a.work + int64_t(g) * M;
   for (int e = threadIdx.x; e < 2 * M2; e += kNT) {
     const int row = e >> a.logM2;
     const int j2 = e & (M2 - 1);
@@ -644,17 +653,17 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a, CorrArgs 
   Cx<T>* rows = reinterpret_cast<Cx<T>*>(smem);   // [NW][RS]
   Cx<T>* tA = rows + NW * RS;                      // [NW][E]
   Cx<T>* tB = tA + NW * E;                         // [NW][64]
-  const int M1 = 1 << a.logM1;
-  const int M = 1 << a.logM;
+  const int M1 = a.M1i;
+  const int M = a.Mi;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int lhalf = a.logM1 - 1;
+  const int half = M1 >> 1;   // row pairs per detector
   auto row_of = [&](int w) {
-    const int prw = (blockIdx.x * PB + (w >> 1)) & ((1 << lhalf) - 1);
+    const int prw = (blockIdx.x * PB + (w >> 1)) % half;
     return (w & 1) ? ((prw == 0) ? (M1 >> 1) : (M1 - prw)) : prw;
   };
   const int pair = blockIdx.x * PB + (wave >> 1);
-  const int g = pair >> lhalf;
-  const int pr = pair & ((1 << lhalf) - 1);
+  const int g = pair / half;
+  const int pr = pair % half;
   const int ra = pr;
   const int rb = (pr == 0) ? (M1 >> 1) : (M1 - pr);
   const int myrow = row_of(wave);
@@ -665,7 +674,7 @@ __global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a, CorrArgs 
   const int tsh = a.logLmax - LOGL;
   auto twL = [&](int m) { return a.tw[m << tsh]; };   // W_L^m, from the cached table
   Cx<T>* R = rows + wave * RS;
-  auto* w = a.work + (int64_t(g) << a.logM) + int64_t(myrow) * L;
+  auto* w = a.work + int64_t(g) * M + int64_t(myrow) * L;
   const Cx<T> tb = tB[wave * 64 + lane];
   auto twE = [&](int m) { return twL(m << 6); };   // W_E^m = W_L^(64 m)
   // ---------------- forward: radix-E from global, then 2 x radix-8
@@ -933,11 +942,14 @@ __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
   int g, cb;
   col_block(logNB, &g, &cb);
   const int C = 1 << a.logC;
-  const int M1 = 1 << a.logM1, M2 = 1 << a.logM2;
+  const int M1 = a.M1i, M2 = 1 << a.logM2;
   Cx<T>* stw = buf + C * M1;
   const int j20 = cb << a.logC;
-  stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
-  const auto* w = a.work + (int64_t(g) << a.logM);
+  if (a.mix_code)
+    for (int m = threadIdx.x; m < M1; m += kNT13) stw[m] = a.twm[m];
+  else
+    stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
+  const auto* w = a.work + int64_t(g) * a.Mi;
   for (int e = threadIdx.x; e < C * M1; e += kNT13) {
     const int k1 = e >> a.logC;
     const int c = e & (C - 1);
@@ -945,9 +957,12 @@ __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
   }
   __syncthreads();
   FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
-  lds_fft<T, kNT13, E13, true>(buf, sh, stw);
+  if (a.mix_code)
+    lds_fft_mx<T, kNT13, E13, true>(buf, MixShape{M1, C, C, 1, true, a.mix_code, 1}, stw);
+  else
+    lds_fft<T, kNT13, E13, true>(buf, sh, stw);
   if constexpr (CSR) {
-    auto* wo = a.work + (int64_t(g) << a.logM);
+    auto* wo = a.work + int64_t(g) * a.Mi;
     for (int e = threadIdx.x; e < C * M1; e += kNT13) {
       const int k1 = e >> a.logC;
       const int c = e & (C - 1);
@@ -1118,7 +1133,9 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
   const int M = int(s->n / 2);
   A a;
   a.Mi = M;
+  a.M1i = pl.M1;
   a.mix_code = pl.mix_code;
+  a.twm = pl.mix_code && !pl.single ? s->at<Cx<T>>(s->lay.tw_m1) : nullptr;
   a.gmap = s->at<V4<T>>(s->lay.gmap);
   a.acc = s->at<double>(s->lay.acc);
   a.work = s->at<typename A::W>(s->lay.tod);
@@ -1174,7 +1191,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       }
     } else {
       const int C = 1 << pl.logC;
-      const int M1 = 1 << pl.logM1, M2 = 1 << pl.logM2;
+      const int M1 = pl.M1, M2 = 1 << pl.logM2;
       const size_t lds13 = (size_t(C) * M1 + M1) * sizeof(Cx<T>);
       const int JL = M2 < 64 ? M2 : 64;
       const size_t lds2 =
@@ -1317,10 +1334,10 @@ mm_status filter_pipeline(ScanImpl* s, int src, const void* tod, const double* x
 
 // 1/N(f) of every detector in four-step order: out[k1*M2 + k2] = iN[k1 + M1*k2]
 // for k < M, out[M] = iN[M].
-__global__ void k_permute_iN(const float* __restrict__ iN, float* __restrict__ out, int logM1,
-                             int logM2) {
+__global__ void k_permute_iN(const float* __restrict__ iN, float* __restrict__ out, int M1,
+                             int M2) {
   const int d = blockIdx.y;
-  const int64_t M = int64_t(1) << (logM1 + logM2);
+  const int64_t M = int64_t(M1) * M2;
   const float* src = iN + d * (M + 1);
   float* dst = out + d * (M + 1);
   for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k <= M;
@@ -1328,8 +1345,8 @@ __global__ void k_permute_iN(const float* __restrict__ iN, float* __restrict__ o
     if (k == M) {
       dst[M] = src[M];
     } else {
-      const int64_t k1 = k & ((int64_t(1) << logM1) - 1), k2 = k >> logM1;
-      dst[(k1 << logM2) + k2] = src[k];
+      const int64_t k1 = k % M1, k2 = k / M1;
+      dst[k1 * M2 + k2] = src[k];
     }
   }
 }
@@ -1359,7 +1376,7 @@ mm_status permute_inverse_spectrum(ScanImpl* s, hipStream_t st) {
     MM_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_permute_iN, dim3(64, s->ndet), dim3(256), 0, st, s->d.inv_noise,
-                     s->at<float>(s->lay.int_), s->plan.logM1, s->plan.logM2);
+                     s->at<float>(s->lay.int_), s->plan.M1, 1 << s->plan.logM2);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
@@ -1372,12 +1389,15 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   pl->logn = ilog2(n);                         // ceil(log2 n) for mixed-radix n
   pl->logM = pl->logn - 1;
   const int M = int(n / 2);
-  // n = 2^a 3^b 5^c that is not a power of two: mixed-radix one-kernel filter
-  pl->mix_code = (n & (n - 1)) == 0 ? 0u : mixed_radix_code(M);
-  if ((n & (n - 1)) != 0) {
-    if (pl->mix_code == 0) return fail(MM_EINVAL, "nsamp must be 2^a 3^b 5^c");
-    if (M > kE * kNT)
-      return fail(MM_EINVAL, "nsamp that is not a power of two needs nsamp/2 <= 8192");
+  // n = 2^a 3^b 5^c that is not a power of two: mixed-radix LDS transforms
+  // (the whole of M on the one-kernel path, the columns M1 of the four-step)
+  const bool mixed = (n & (n - 1)) != 0;
+  pl->mix_code = 0;
+  if (mixed) {
+    int64_t r = M;
+    for (int f : {2, 3, 5})
+      while (r % f == 0) r /= f;
+    if (r != 1) return fail(MM_EINVAL, "nsamp must be 2^a 3^b 5^c");
     if (d->corr_rank > 0)
       return fail(MM_EINVAL, "correlated noise needs nsamp a power of two");
     if (d->pointing == MM_POINT_BORESIGHT)
@@ -1395,10 +1415,13 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   pl->otf = d->pointing == MM_POINT_BORESIGHT;
   // boresight pointing stores no per-sample pixels: P^T is always the gather
   pl->csr = d->scatter != MM_SCATTER_ATOMIC && (!pl->single || pl->acc32 || pl->otf);
+  pl->M1 = 1;
   if (pl->single) {
     pl->logM1 = 0;
     pl->logM2 = pl->logM;
     pl->logC = 0;
+    if (mixed && (pl->mix_code = mixed_radix_code(M)) == 0)
+      return fail(MM_EINVAL, "nsamp/2 needs more than 10 FFT stages");
     int G = d->ndet;
     if (pl->csr && d->det_group > 0 && d->det_group < G) G = d->det_group;
     while (G > 1 && int64_t(G) * n > (int64_t(1) << 31) - 1) --G;
@@ -1406,7 +1429,26 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     pl->logLmax = pl->logM;
   } else {
     int l1;
-    if (pl->corr_rank > 0) {
+    int64_t odd = M;
+    int e2 = 0;
+    while ((odd & 1) == 0) {
+      odd >>= 1;
+      ++e2;
+    }
+    if (mixed) {
+      // rows M2 = 2^l2 stay a power of two (2048 at most, 32 at least); the
+      // columns M1 = M / M2 carry every factor 3 and 5 and at least one 2
+      int l2 = e2 - 1 < 11 ? e2 - 1 : 11;
+      const int64_t cap1 = pl->f64 ? int64_t(4) * kNT13 : int64_t(8) * kNT13;   // C >= 2
+      while (l2 < 12 && l2 < e2 - 1 && (M >> l2) > cap1) ++l2;
+      if (l2 < 5 || (M >> l2) > cap1 || (M >> l2) % 2 != 0)
+        return fail(MM_EINVAL, "nsamp gives no four-step split (odd part of nsamp/2 too large)");
+      l1 = pl->logM - l2;   // ceil(log2 M1)
+      pl->logM1 = l1;
+      pl->logM2 = l2;
+      pl->M1 = int(M >> l2);
+      pl->mix_code = mixed_radix_code(pl->M1);
+    } else if (pl->corr_rank > 0) {
       l1 = pl->logM - 9;                   // rows of 512 bins
       if (l1 > 9) l1 = 9;                  // up to 2048 at M = 2^20
       if (l1 < 3 || pl->logM - l1 > 11)
@@ -1418,21 +1460,24 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
       if (l1 > 9) l1 = 9;
       if (pl->logM - l1 > 12) l1 = pl->logM - 12;
     }
-    pl->logM1 = l1;
-    pl->logM2 = pl->logM - l1;
-    if (pl->logM1 < 2 || pl->logM2 < 5 || pl->logM2 > 12 || pl->logM1 > 9)
-      return fail(MM_EINVAL, "fft_m1 gives an unsupported four-step split");
+    if (!mixed) {
+      pl->logM1 = l1;
+      pl->logM2 = pl->logM - l1;
+      pl->M1 = 1 << l1;
+      if (pl->logM1 < 2 || pl->logM2 < 5 || pl->logM2 > 12 || pl->logM1 > 9)
+        return fail(MM_EINVAL, "fft_m1 gives an unsupported four-step split");
+    }
     int lc = d->fft_cols > 0 ? ilog2(d->fft_cols) : 4;
     // pass-1/3 tile: C * M1 complex in LDS, at most 16 per thread (float
     // math) or 8 (double), and within 160 KB with the twiddles
     const int64_t cap = pl->f64 ? int64_t(8) * kNT13 : int64_t(16) * kNT13;
-    while (lc > 0 && (((int64_t(1) << lc) << pl->logM1) > cap ||
-                      (((int64_t(1) << lc) + 1) << pl->logM1) * int64_t(cxb) > 160 * 1024))
+    while (lc > 0 && ((int64_t(1) << lc) * pl->M1 > cap ||
+                      ((int64_t(1) << lc) + 1) * pl->M1 * int64_t(cxb) > 160 * 1024))
       --lc;
     if (lc > pl->logM2) lc = pl->logM2;
     if (lc < 1) return fail(MM_EINVAL, "fft_cols leaves fewer than two columns per block");
     pl->logC = lc;
-    if ((2 << (lc + pl->logM1)) % kNT != 0 || (2 << pl->logM2) % kNT != 0)
+    if (!mixed && ((2 << (lc + pl->logM1)) % kNT != 0 || (2 << pl->logM2) % kNT != 0))
       return fail(MM_EINVAL, "four-step blocks too small for the thread count");
     int G = pl->corr_rank > 0 ? d->ndet : d->det_group;
     if (G <= 0) {
@@ -1446,7 +1491,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     if (pl->corr_rank > 0 && G != d->ndet)
       return fail(MM_EINVAL, "correlated noise needs ndet * nsamp < 2^31");
     pl->G = G;
-    pl->logLmax = pl->logM1 > pl->logM2 ? pl->logM1 : pl->logM2;
+    pl->logLmax = mixed ? pl->logM2 : (pl->logM1 > pl->logM2 ? pl->logM1 : pl->logM2);
   }
   pl->logS = (pl->logn + 1) / 2;
   const int maxside = d->ny > d->nx ? d->ny : d->nx;
@@ -1461,8 +1506,9 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     return o;
   };
   L->tod = take(pl->single && !pl->csr ? 0 : size_t(pl->G) * size_t(M) * wxb);
-  L->tw = take((pl->mix_code ? size_t(M) : (size_t(1) << pl->logLmax)) * cxb);
+  L->tw = take((pl->mix_code && pl->single ? size_t(M) : (size_t(1) << pl->logLmax)) * cxb);
   L->tw2 = take(pl->single ? 0 : (size_t(1) << pl->logM2) * cxb);
+  L->tw_m1 = take(pl->mix_code && !pl->single ? size_t(pl->M1) * cxb : 0);
   L->int_ = take(pl->single ? 0 : size_t(d->ndet) * size_t(M + 1) * 4);
   L->wn_hi = take(size_t((n + (int64_t(1) << pl->logS) - 1) >> pl->logS) * cxb);
   L->wn_lo = take((size_t(1) << pl->logS) * cxb);
@@ -1519,10 +1565,17 @@ static mm_status upload_t(ScanImpl* s, hipStream_t st) {
   const Plan& pl = s->plan;
   std::vector<Cx<T>> tw, hi, lo;
   const int64_t Lmax = int64_t(1) << pl.logLmax;
-  if (pl.mix_code)
+  if (pl.mix_code && pl.single)
     table(tw, s->n / 2, 1, s->n / 2);   // W_M^m for the mixed-radix stages
   else
     table(tw, Lmax, 1, Lmax);
+  if (pl.mix_code && !pl.single) {     // W_M1^m for the mixed-radix columns
+    std::vector<Cx<T>> tm1;
+    table(tm1, pl.M1, 1, pl.M1);
+    MM_HIP(hipMemcpyAsync(s->ws + s->lay.tw_m1, tm1.data(), tm1.size() * sizeof(Cx<T>),
+                          hipMemcpyHostToDevice, st));
+    MM_HIP(hipStreamSynchronize(st));   // tm1 leaves scope
+  }
   const int64_t n = s->n;
   const int64_t S = int64_t(1) << pl.logS;
   table(hi, (n + S - 1) / S, S, n);

@@ -52,6 +52,7 @@ struct Layout {
   size_t tod;        // pipeline scratch: G * M complex (0 bytes if single pass)
   size_t tw;         // Stockham table, Lmax complex
   size_t tw2;        // W_{2 M2}^k2 table, M2 complex (four-step)
+  size_t tw_m1;      // M1 complex (W_M1^m, mixed-radix columns)
   size_t int_;       // ndet * (M+1) float: 1/N(f) in four-step order
   size_t wn_hi, wn_lo;
   size_t gmap;       // (npix + 1) * 4 real (gather map; entry npix is zero)
@@ -92,7 +93,8 @@ struct Plan {
   bool csr;          // P^T by per-pixel gather (else atomic scatter)
   bool otf;          // pointing computed from the boresight model
   bool csr_w;        // the pixel-major index stores the (float32) weights
-  uint32_t mix_code; // mixed-radix stage code of M = n/2 (0: n a power of two)
+  uint32_t mix_code; // mixed-radix stage code of M (one kernel) or M1 (four-step); 0: power of two
+  int M1;            // four-step column length (2^logM1 unless mixed)
   int logn, logM;    // n = 2^logn samples, M = n/2 packed complex
   int logM1, logM2;  // four-step split
   int logC;          // columns per pass-1/3 block

@@ -88,7 +88,7 @@ def test_compensated_accumulation_takes_the_gather_on_one_kernel_plans(mm):
 
 @pytest.mark.parametrize("field,value", [
     ("ncomp", 2), ("ny", 48), ("nx", 2), ("ndet", 0), ("nsamp", 1022), ("nsamp", 1001), ("nsamp", 8),
-    ("nsamp", 3 * 2**14), ("nsamp", 7 * 2**8),
+    ("nsamp", 2 * 3**9 * 2**4), ("nsamp", 7 * 2**8),
     ("nsamp", 1 << 23), ("tod_dtype", 7), ("fft_m1", 3), ("det_group", -1), ("scatter", 5),
     ("acc", 2),
 ])
@@ -210,13 +210,17 @@ def test_boresight_pointing_descriptor(mm):
 
 
 def test_mixed_radix_lengths(mm):
-    """n = 2^a 3^b 5^c with n/2 <= 8192 plans the one-kernel filter; larger
-    ones, correlated noise and boresight pointing need a power of two."""
-    for n in (30, 1000, 3 * 2**11, 15 * 2**9, 2 * 3**8, 2 * 5**5, 2**4 * 3 * 5**3):
+    """n = 2^a 3^b 5^c: n/2 <= 8192 plans the one-kernel filter; longer ones
+    the four-step with rows of 2^l (32..4096) and every factor 3 and 5 in the
+    columns (at most 8192 long); correlated noise and boresight pointing
+    need a power of two."""
+    for n in (30, 1000, 3 * 2**11, 15 * 2**9, 2 * 3**8, 2 * 5**5, 2**4 * 3 * 5**3,
+              3 * 2**14, 3 * 2**20, 15 * 2**18, 2 * 3**5 * 2**12, 2 * 5**4 * 2**10):
         d = _desc(mm, nsamp=n)
         assert mm.mm_scan_workspace_bytes(d) > 0, n
-    d = _desc(mm, nsamp=3 * 2**14)
-    assert mm.mm_scan_workspace_bytes(d) == 0 and "8192" in mm.mm_last_error()
+    for n in (2 * 3**9 * 2**4, 2 * 5**6 * 2**6):   # no four-step split
+        d = _desc(mm, nsamp=n)
+        assert mm.mm_scan_workspace_bytes(d) == 0 and "split" in mm.mm_last_error()
     d = _desc(mm, nsamp=1000, pointing=mm.MM_POINT_BORESIGHT)
     assert mm.mm_scan_workspace_bytes(d) == 0 and "power of two" in mm.mm_last_error()
     import numpy as np

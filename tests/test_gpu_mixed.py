@@ -24,6 +24,13 @@ CASES = [
     ("n13122-3pow8-f32-IQU", 3, 32, 32, 6, 2 * 3**8, "f32", "f64"),
     ("n16000-f32-IQU-gather", 3, 32, 32, 4, 16000, "f32", "f32x2"),
     ("n15000-bf16-IQU", 3, 32, 32, 4, 15000, "bf16", "f64"),
+    # four-step: rows 2^l, the factors 3 and 5 in the columns
+    ("fourstep-3x2^14-f32-IQU", 3, 32, 32, 4, 3 * 2**14, "f32", "f64"),
+    ("fourstep-15x2^14-f64-IQU", 3, 32, 32, 5, 15 * 2**14, "f64", "f64"),
+    ("fourstep-2x3^5x2^12-f32-I", 1, 32, 32, 2, 2 * 3**5 * 2**12, "f32", "f64"),
+    ("fourstep-2x5^4x2^10-f32-IQU", 3, 32, 32, 3, 2 * 5**4 * 2**10, "f32", "f64"),
+    ("fourstep-45x2^12-bf16-IQU", 3, 32, 32, 4, 45 * 2**12, "bf16", "f64"),
+    ("fourstep-75x2^10-f32x2-IQU", 3, 32, 32, 4, 75 * 2**10, "f32", "f32x2"),
 ]
 TOL = {"f64": 1e-12, "f32": 2e-6, "bf16": 4e-3}
 
@@ -40,7 +47,8 @@ def test_mixed_length_apply_and_rhs(case):
     pair = Pair(_inputs(nc, ny, nx, ndet, n), tod_dtype=dt, acc=acc)
     info = pair.g.info()
     print(f"[mixed {label}] {info}", flush=True)
-    assert info["single_pass"] == 1 and pair.mask.sum() > 0
+    assert info["single_pass"] == (0 if label.startswith("fourstep") else 1)
+    assert pair.mask.sum() > 0
     x = pair.masked_random(1)
     e = rel(pair.A_gpu(x), pair.A_oracle(x))
     tod = np.random.default_rng(n).standard_normal((ndet, n))
@@ -62,4 +70,20 @@ def test_mixed_length_pcg():
     x = pair.host(rg["x"])
     tr = np.linalg.norm(b - pair.A_oracle(x)) / np.linalg.norm(b)
     print(f"[mixed pcg n={n}] oracle {ro.iters} gpu {rg['iters']} true {tr:.2e}", flush=True)
+    assert rg["converged"] and abs(rg["iters"] - ro.iters) <= 1 and tr <= 1e-8
+
+
+def test_mixed_length_fourstep_pcg():
+    n = 2 * 3 * 5 * 2**12   # 122880: four-step, columns of 60
+    pair = Pair(_inputs(3, 32, 32, 6, n), tod_dtype="f64")
+    assert pair.g.info()["single_pass"] == 0 and pair.mask.sum() > 500
+    m = np.random.default_rng(4).standard_normal((3, 1024)) * pair.mask
+    b = pair.A_oracle(m.ravel())
+    ro = oracle.pcg(pair.A_oracle, oracle.BinnedPrecon(pair.B, pair.mask), b, tol=1e-9,
+                    maxiter=2000)
+    rg = pair.g.pcg("binned", pair.dev(b), tol=1e-9, maxiter=2000)
+    x = pair.host(rg["x"])
+    tr = np.linalg.norm(b - pair.A_oracle(x)) / np.linalg.norm(b)
+    print(f"[mixed four-step pcg n={n}] oracle {ro.iters} gpu {rg['iters']} true {tr:.2e}",
+          flush=True)
     assert rg["converged"] and abs(rg["iters"] - ro.iters) <= 1 and tr <= 1e-8
