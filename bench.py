@@ -273,6 +273,35 @@ def boresight_leg(inp, x_sky, taper, reps=10):
     return out
 
 
+def mixed_length_leg(x_sky, ndet=256, nsamp=15 * 2**16, reps=10):
+    """iqu_256det's recipe at a timestream length that is not a power of two
+    (n = 15 * 2^16 = 983040: four-step rows of 2048, columns of 240 through
+    the mixed-radix LDS transform): A-apply time and throughput."""
+    import torch
+    import paper_1309_7473_amd as mm
+    from synth import make_workload
+    inp = make_workload("iqu_256det", ndet=ndet, nsamp=nsamp)
+    scan = mm.Scan(inp, tod_dtype="f32")
+    y = scan.new_map()
+    for _ in range(2):
+        scan.apply_A(x_sky, y)
+    mm.mm_profile_enable(scan.handle, True)
+    mm.mm_profile_read(scan.handle)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        scan.apply_A(x_sky, y)
+    torch.cuda.synchronize()
+    prof = mm.mm_profile_read(scan.handle)
+    a_ms = prof["apply_A"][0] / prof["apply_A"][1]
+    info = scan.info()
+    out = {"nsamp": nsamp, "fft_m1": info["fft_m1"], "fft_m2": info["fft_m2"],
+           "apply_ms": round(a_ms, 4), "samples_per_s": ndet * nsamp / (a_ms * 1e-3),
+           "stage_us_per_launch": {k: round(v[0] / v[1] * 1e3, 1) for k, v in prof.items()
+                                   if k != "apply_A"}}
+    scan.close()
+    return out
+
+
 def tiled_leg(scan, b, configs=((256, 60.0), (128, 32.0), (64, 16.0)), reps=20):
     """The tiled constant-correlation preconditioner (Summary section) on the
     same workload: build time, time per apply (HIP events over reps applies)
@@ -514,6 +543,7 @@ def main():
         solves["correlated_noise"] = correlated_leg(inp, x_sky)
         solves["tiled"] = tiled_leg(scan, b)
         solves["boresight_pointing"] = boresight_leg(inp, x_sky, args.taper)
+        solves["mixed_length"] = mixed_length_leg(x_sky)
         solves["circulant_tapers"] = taper_leg(scan, b)
 
     if args.calibrate_copy:

@@ -321,7 +321,7 @@ mm_status mm_get_info(mm_scan scan, mm_scan_info* out) {
   out->ref_pixel = s->circ_built ? s->ref_pixel : -1;
   out->n_floored = s->n_floored;
   out->det_group = s->plan.G;
-  out->fft_m1 = s->plan.single ? 1 : (1 << s->plan.logM1);
+  out->fft_m1 = s->plan.single ? 1 : s->plan.M1;
   out->fft_m2 = s->plan.single ? (1 << s->plan.logM) : (1 << s->plan.logM2);
   out->fft_cols = s->plan.single ? 0 : (1 << s->plan.logC);
   out->single_pass = s->plan.single ? 1 : 0;

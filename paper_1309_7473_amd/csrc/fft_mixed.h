@@ -67,6 +67,18 @@ __device__ __forceinline__ void dft_any(Cx<T> (&v)[R]) {
   }
 }
 
+// Division of n < 2^16 by d < 2^16 as a multiply-high: q = (n * ceil(2^32 / d))
+// >> 32 is exact when n d < 2^32 (the rounding error of the reciprocal, at
+// most d / 2^32 per unit of n, stays below 1 / d).
+struct FastDiv {
+  uint32_t d, m;
+  __device__ __forceinline__ explicit FastDiv(uint32_t dd)
+      : d(dd), m(dd == 1 ? 0u : uint32_t((uint64_t(1) << 32) / dd + 1)) {}
+  __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    return d == 1 ? n : __umulhi(n, m);
+  }
+};
+
 struct MixShape {
   int L;          // transform length
   int B;          // batch count
@@ -83,19 +95,24 @@ __device__ __forceinline__ void stockham_stage_mx(Cx<T>* __restrict__ buf, const
   const int LR = s.L / R;
   const int nbf = s.B * LR;
   const int step = (LR / Ns) * s.tstride;   // W_{Ns R} = W_Lt^step
+  const FastDiv dB{uint32_t(s.B)}, dLR{uint32_t(LR)}, dNs{uint32_t(Ns)};
+  // butterfly w -> transform b, index j
+  auto split = [&](int w, int* b, int* j) {
+    if (s.batch_fast) {
+      *j = int(dB.div(uint32_t(w)));
+      *b = w - *j * s.B;
+    } else {
+      *b = int(dLR.div(uint32_t(w)));
+      *j = w - *b * LR;
+    }
+  };
   Cx<T> v[NB][R];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int w = threadIdx.x + i * NT;
     if (w < nbf) {
       int b, j;
-      if (s.batch_fast) {
-        b = w % s.B;
-        j = w / s.B;
-      } else {
-        j = w % LR;
-        b = w / LR;
-      }
+      split(w, &b, &j);
       const int base = b * s.bs + j * s.es;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = buf[base + (r * LR) * s.es];
@@ -107,14 +124,8 @@ __device__ __forceinline__ void stockham_stage_mx(Cx<T>* __restrict__ buf, const
     const int w = threadIdx.x + i * NT;
     if (w < nbf) {
       int b, j;
-      if (s.batch_fast) {
-        b = w % s.B;
-        j = w / s.B;
-      } else {
-        j = w % LR;
-        b = w / LR;
-      }
-      const int k = j % Ns;
+      split(w, &b, &j);
+      const int k = j - int(dNs.div(uint32_t(j))) * Ns;
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {

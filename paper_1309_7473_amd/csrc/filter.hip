@@ -1438,7 +1438,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     if (mixed) {
       // rows M2 = 2^l2 stay a power of two (2048 at most, 32 at least); the
       // columns M1 = M / M2 carry every factor 3 and 5 and at least one 2
-      int l2 = e2 - 1 < 11 ? e2 - 1 : 11;
+      int l2 = e2 - 1 < 10 ? e2 - 1 : 10;
       const int64_t cap1 = pl->f64 ? int64_t(4) * kNT13 : int64_t(8) * kNT13;   // C >= 2
       while (l2 < 12 && l2 < e2 - 1 && (M >> l2) > cap1) ++l2;
       if (l2 < 5 || (M >> l2) > cap1 || (M >> l2) % 2 != 0)
