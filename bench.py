@@ -43,7 +43,7 @@ ALG_BYTES = {"pass1": 16.0, "pass2": 10.0, "pass3": 16.0, "pass3_csr": 8.0, "red
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("filter.hip", "fft_lds.h", "mm_device.h"):
+    for f in ("filter.hip", "fft_lds.h", "fft_mixed.h", "pointing.h", "mm_device.h"):
         with open(os.path.join(ROOT, "paper_1309_7473_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

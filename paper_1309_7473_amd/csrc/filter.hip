@@ -291,7 +291,8 @@ __global__ void k_epilogue(const double* __restrict__ acc, const int32_t* __rest
 // ------------------------------------------------------------- single pass
 // CSR = true: store the filtered, packed timestream to the pass buffer for the
 // per-pixel reduce instead of scattering it.
-template <typename T, typename S, int NC, int SRC, bool CSR>
+// MIX: M is a mixed-radix length (2^a 3^b 5^c), transformed by lds_fft_mx.
+template <typename T, typename S, int NC, int SRC, bool CSR, bool MIX>
 __global__ void __launch_bounds__(kNT) k_single(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
@@ -304,7 +305,7 @@ __global__ void __launch_bounds__(kNT) k_single(PassArgs<T, S> a) {
   __syncthreads();
   FftShape sh{a.logM, 0, 1, M, false, a.logLmax};
   const MixShape mx{M, 1, 1, M, false, a.mix_code, 1};
-  if (a.mix_code)
+  if constexpr (MIX)
     lds_fft_mx<T, kNT, kE, false>(buf, mx, a.tw);
   else
     lds_fft<T, kNT, kE, false>(buf, sh, a.tw);
@@ -320,7 +321,7 @@ __global__ void __launch_bounds__(kNT) k_single(PassArgs<T, S> a) {
     }
   }
   __syncthreads();
-  if (a.mix_code)
+  if constexpr (MIX)
     lds_fft_mx<T, kNT, kE, true>(buf, mx, a.tw);
   else
     lds_fft<T, kNT, kE, true>(buf, sh, a.tw);
@@ -464,7 +465,8 @@ __device__ __forceinline__ void col_block(int logNB, int* g, int* cb) {
   }
 }
 
-template <typename T, typename S, int NC, int SRC, int E13>
+// MIX: the column length M1 is mixed-radix (lds_fft_mx on the columns).
+template <typename T, typename S, int NC, int SRC, int E13, bool MIX>
 __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
@@ -477,7 +479,7 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
   Cx<T>* stw = buf + C * M1;
   const int j20 = cb << a.logC;
   const int64_t base = int64_t(g) * a.n;
-  if (a.mix_code)
+  if constexpr (MIX)
     for (int m = threadIdx.x; m < M1; m += kNT13) stw[m] = a.twm[m];
   else
     stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
@@ -503,7 +505,7 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
   }
   __syncthreads();
   FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
-  if (a.mix_code)
+  if constexpr (MIX)
     lds_fft_mx<T, kNT13, E13, false>(buf, MixShape{M1, C, C, 1, true, a.mix_code, 1}, stw);
   else
     lds_fft<T, kNT13, E13, false>(buf, sh, stw);
@@ -933,7 +935,7 @@ static void launch_corr_t(int M, hipStream_t st, const PassArgs<T, S>& a, const 
 
 // CSR = true: store the filtered, packed timestream back in place (the block
 // owns exactly the addresses it loaded); the per-pixel reduce applies P^T.
-template <typename T, typename S, int NC, bool CSR, int E13>
+template <typename T, typename S, int NC, bool CSR, int E13, bool MIX>
 __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
@@ -945,7 +947,7 @@ __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
   const int M1 = a.M1i, M2 = 1 << a.logM2;
   Cx<T>* stw = buf + C * M1;
   const int j20 = cb << a.logC;
-  if (a.mix_code)
+  if constexpr (MIX)
     for (int m = threadIdx.x; m < M1; m += kNT13) stw[m] = a.twm[m];
   else
     stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
@@ -957,7 +959,7 @@ __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
   }
   __syncthreads();
   FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
-  if (a.mix_code)
+  if constexpr (MIX)
     lds_fft_mx<T, kNT13, E13, true>(buf, MixShape{M1, C, C, 1, true, a.mix_code, 1}, stw);
   else
     lds_fft<T, kNT13, E13, true>(buf, sh, stw);
@@ -1176,12 +1178,20 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
     if (pl.single) {
       const size_t lds = size_t(M) * sizeof(Cx<T>);
       prof_begin(s, st, &tok);
-      if (pl.csr) {
-        raise_lds_limit(k_single<T, S, NC, SRC, true>, lds);
-        hipLaunchKernelGGL((k_single<T, S, NC, SRC, true>), dim3(gd), dim3(kNT), lds, st, a);
-      } else if constexpr (SRC != 2) {   // boresight pointing always gathers
-        raise_lds_limit(k_single<T, S, NC, SRC, false>, lds);
-        hipLaunchKernelGGL((k_single<T, S, NC, SRC, false>), dim3(gd), dim3(kNT), lds, st, a);
+      auto single = [&](auto csr, auto mix) {
+        constexpr bool C_ = decltype(csr)::value, X_ = decltype(mix)::value;
+        raise_lds_limit(k_single<T, S, NC, SRC, C_, X_>, lds);
+        hipLaunchKernelGGL((k_single<T, S, NC, SRC, C_, X_>), dim3(gd), dim3(kNT), lds, st, a);
+      };
+      using TT = std::true_type;
+      using FF = std::false_type;
+      if constexpr (SRC == 2) {   // boresight pointing: gather, powers of two
+        single(TT{}, FF{});
+      } else {
+        if (pl.csr)
+          pl.mix_code ? single(TT{}, TT{}) : single(TT{}, FF{});
+        else
+          pl.mix_code ? single(FF{}, TT{}) : single(FF{}, FF{});
       }
       prof_end(s, st, tok, kProfSingle, gs);
       if (pl.csr) {
@@ -1198,15 +1208,31 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
           (size_t(2) * M2 + (size_t(2) * M2 >> kPad2) + M2 + 2 * (M2 / JL) + 2 * JL) * sizeof(Cx<T>);
       const bool e16 = size_t(C) * M1 > size_t(8) * kNT13;   // 16 elements per thread
       prof_begin(s, st, &tok);
+      using TT = std::true_type;
+      using FF = std::false_type;
+      auto pass1 = [&](auto e, auto mix) {
+        constexpr int E_ = decltype(e)::value;
+        constexpr bool X_ = decltype(mix)::value;
+        raise_lds_limit(k_pass1<T, S, NC, SRC, E_, X_>, lds13);
+        hipLaunchKernelGGL((k_pass1<T, S, NC, SRC, E_, X_>), dim3(gd * (M2 / C)), dim3(kNT13),
+                           lds13, st, a);
+      };
+      using E8 = std::integral_constant<int, 8>;
+      using E16 = std::integral_constant<int, 16>;
+      const bool mix1 = pl.mix_code != 0;
       if constexpr (sizeof(T) == 4) {
         if (e16) {
-          raise_lds_limit(k_pass1<T, S, NC, SRC, 16>, lds13);
-          hipLaunchKernelGGL((k_pass1<T, S, NC, SRC, 16>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
+          if constexpr (SRC == 2)
+            pass1(E16{}, FF{});
+          else
+            mix1 ? pass1(E16{}, TT{}) : pass1(E16{}, FF{});
         }
       }
       if (!e16) {
-        raise_lds_limit(k_pass1<T, S, NC, SRC, 8>, lds13);
-        hipLaunchKernelGGL((k_pass1<T, S, NC, SRC, 8>), dim3(gd * (M2 / C)), dim3(kNT13), lds13, st, a);
+        if constexpr (SRC == 2)
+          pass1(E8{}, FF{});
+        else
+          mix1 ? pass1(E8{}, TT{}) : pass1(E8{}, FF{});
       }
       prof_end(s, st, tok, kProfPass1, gs);
       prof_begin(s, st, &tok);
@@ -1256,26 +1282,22 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       prof_end(s, st, tok, kProfPass2, gs);
       prof_begin(s, st, &tok);
       const dim3 g13(gd * (M2 / C));
+      auto pass3 = [&](auto csr, auto e, auto mix) {
+        constexpr bool C_ = decltype(csr)::value, X_ = decltype(mix)::value;
+        constexpr int E_ = decltype(e)::value;
+        raise_lds_limit(k_pass3<T, S, NC, C_, E_, X_>, lds13);
+        hipLaunchKernelGGL((k_pass3<T, S, NC, C_, E_, X_>), g13, dim3(kNT13), lds13, st, a);
+      };
+      auto pass3e = [&](auto e) {
+        if (pl.csr)
+          mix1 ? pass3(TT{}, e, TT{}) : pass3(TT{}, e, FF{});
+        else
+          mix1 ? pass3(FF{}, e, TT{}) : pass3(FF{}, e, FF{});
+      };
       if constexpr (sizeof(T) == 4) {
-        if (e16) {
-          if (pl.csr) {
-            raise_lds_limit(k_pass3<T, S, NC, true, 16>, lds13);
-            hipLaunchKernelGGL((k_pass3<T, S, NC, true, 16>), g13, dim3(kNT13), lds13, st, a);
-          } else {
-            raise_lds_limit(k_pass3<T, S, NC, false, 16>, lds13);
-            hipLaunchKernelGGL((k_pass3<T, S, NC, false, 16>), g13, dim3(kNT13), lds13, st, a);
-          }
-        }
+        if (e16) pass3e(E16{});
       }
-      if (!e16) {
-        if (pl.csr) {
-          raise_lds_limit(k_pass3<T, S, NC, true, 8>, lds13);
-          hipLaunchKernelGGL((k_pass3<T, S, NC, true, 8>), g13, dim3(kNT13), lds13, st, a);
-        } else {
-          raise_lds_limit(k_pass3<T, S, NC, false, 8>, lds13);
-          hipLaunchKernelGGL((k_pass3<T, S, NC, false, 8>), g13, dim3(kNT13), lds13, st, a);
-        }
-      }
+      if (!e16) pass3e(E8{});
       prof_end(s, st, tok, kProfPass3, gs);
       if (pl.csr) {
         prof_begin(s, st, &tok);
