@@ -92,7 +92,12 @@ typedef struct {
                                FFT kernels stored as bfloat16, rounded to
                                nearest even; FFT and filter math in float32),
                                MM_F64 (everything in float64) */
-  int64_t nsamp;            /* samples per detector: power of two, 16 ..2^22 */
+  int64_t nsamp;            /* samples per detector, 16 .. 2^22: a power of two, or
+                               2^a 3^b 5^c (mixed-radix FFT: the one-kernel filter
+                               up to nsamp/2 = 8192, beyond that a four-step with
+                               rows 2^l and the factors 3 and 5 in columns of at
+                               most 8192); correlated noise and boresight
+                               pointing need a power of two */
   double  fsample;          /* sample rate in Hz (reporting only) */
   const int32_t* pix;       /* [ndet][nsamp] pixel id, -1 = off-map (zero row
                                of P); NULL with MM_POINT_BORESIGHT.  BORROWED:
@@ -110,7 +115,8 @@ typedef struct {
   int32_t det_group;        /* detectors per filter-pipeline group; 0 = automatic.
                                Bounds the timestream scratch in the workspace. */
   int32_t fft_m1;           /* four-step FFT split (0 = automatic): the packed
-                               complex length nsamp/2 = fft_m1 * (nsamp/2/fft_m1) */
+                               complex length nsamp/2 = fft_m1 * (nsamp/2/fft_m1);
+                               ignored for mixed-radix nsamp */
   double  mask_rcond;       /* I,Q,U activity threshold on lambda_min/lambda_max of
                                the binned block; <= 0 selects 1e-3 */
   int32_t fft_cols;         /* columns per pass-1/3 block of the four-step FFT
@@ -281,8 +287,8 @@ typedef struct {
 } mm_pcg_result;
 
 /* Solves A x = b by PCG (Introduction; textbook PCG with device-resident
- * scalars).  precon: MM_M_NONE, JACOBI, BINNED, CIRCULANT (built) or LEARNED
- * (circulant built and a learned correction attached).  b, x: [ncomp][ny][nx] float64 device arrays; x is overwritten
+ * scalars).  precon: MM_M_NONE, JACOBI, BINNED, CIRCULANT (built), LEARNED
+ * (circulant built and a learned correction attached) or TILED (built).  b, x: [ncomp][ny][nx] float64 device arrays; x is overwritten
  * with the solution.  Synchronises `stream`.  Returns MM_OK, MM_ENOCONV or
  * MM_EBREAKDOWN (with res filled in all three cases). */
 mm_status mm_pcg_solve(mm_scan scan, int32_t precon, const double* b, double* x,
