@@ -423,6 +423,11 @@ typedef struct {
 } mm_profile;
 
 mm_status mm_profile_enable(mm_scan scan, int32_t enable);
+/* Restricts the timing to the stages whose bit (1 << stage) is set in mask
+ * (default: every stage); the others record no events, so a benchmark can
+ * time one kernel without the event overhead on the rest.  Kept across
+ * mm_profile_enable calls. */
+mm_status mm_profile_stages(mm_scan scan, uint32_t mask);
 mm_status mm_profile_read(mm_scan scan, mm_profile* out /*[host]*/);
 
 /* Thread-local message describing the last non-OK status ("" if none). */

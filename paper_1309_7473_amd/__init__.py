@@ -183,6 +183,12 @@ def mm_profile_enable(h, enable=True):
     check(lib.mm_profile_enable(h, 1 if enable else 0), "mm_profile_enable")
 
 
+def mm_profile_stages(h, stages=None):
+    """Time only the named stages (PROFILE_STAGES names); None: every stage."""
+    mask = 0xFFFFFFFF if stages is None else sum(1 << PROFILE_STAGES.index(n) for n in stages)
+    check(lib.mm_profile_stages(h, mask), "mm_profile_stages")
+
+
 def mm_profile_read(h):
     """Synchronises the timed launches; returns {stage: (ms, launches, samples)}."""
     p = mm_profile()

@@ -118,6 +118,7 @@ SIGNATURES = {
     "mm_apply_precon_learned": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mm_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "mm_profile_read": (C.c_int, [C.c_void_p, C.POINTER(mm_profile)]),
+    "mm_profile_stages": (C.c_int, [C.c_void_p, C.c_uint32]),
     "mm_last_error": (C.c_char_p, []),
 }
 

@@ -429,6 +429,12 @@ mm_status mm_profile_enable(mm_scan scan, int32_t enable) {
   return profile_enable(s, enable != 0);
 }
 
+mm_status mm_profile_stages(mm_scan scan, uint32_t mask) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  return profile_stages(s, mask);
+}
+
 mm_status mm_profile_read(mm_scan scan, mm_profile* out) {
   ScanImpl* s = get(scan);
   if (!s || !out) return fail(MM_EINVAL, "invalid scan handle or out");

@@ -1177,7 +1177,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
     hipEvent_t tok;
     if (pl.single) {
       const size_t lds = size_t(M) * sizeof(Cx<T>);
-      prof_begin(s, st, &tok);
+      prof_begin(s, st, &tok, kProfSingle);
       auto single = [&](auto csr, auto mix) {
         constexpr bool C_ = decltype(csr)::value, X_ = decltype(mix)::value;
         raise_lds_limit(k_single<T, S, NC, SRC, C_, X_>, lds);
@@ -1195,7 +1195,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       }
       prof_end(s, st, tok, kProfSingle, gs);
       if (pl.csr) {
-        prof_begin(s, st, &tok);
+        prof_begin(s, st, &tok, kProfReduce);
         launch_reduce<T, S, NC>(s, a, st);
         prof_end(s, st, tok, kProfReduce, gs);
       }
@@ -1207,7 +1207,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const size_t lds2 =
           (size_t(2) * M2 + (size_t(2) * M2 >> kPad2) + M2 + 2 * (M2 / JL) + 2 * JL) * sizeof(Cx<T>);
       const bool e16 = size_t(C) * M1 > size_t(8) * kNT13;   // 16 elements per thread
-      prof_begin(s, st, &tok);
+      prof_begin(s, st, &tok, kProfPass1);
       using TT = std::true_type;
       using FF = std::false_type;
       auto pass1 = [&](auto e, auto mix) {
@@ -1235,7 +1235,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
           mix1 ? pass1(E8{}, TT{}) : pass1(E8{}, FF{});
       }
       prof_end(s, st, tok, kProfPass1, gs);
-      prof_begin(s, st, &tok);
+      prof_begin(s, st, &tok, kProfPass2);
       const dim3 g2(gd * (M1 / 2));
       // one row pair per block: two waves
       constexpr int PB = 1;
@@ -1255,10 +1255,10 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
         c.ndet = gd;
         launch_pass2w<T, S, 1>(M2, g2w, lds2w, st, a, c);
         prof_end(s, st, tok, kProfPass2, gs);
-        prof_begin(s, st, &tok);
+        prof_begin(s, st, &tok, kProfCorr);
         launch_corr_t<T, S>(M, st, a, c);
         prof_end(s, st, tok, kProfCorr, gs);
-        prof_begin(s, st, &tok);
+        prof_begin(s, st, &tok, kProfPass2);
         launch_pass2w<T, S, 2>(M2, g2w, lds2w, st, a, c);
       } else if (wave_rows && M2 == 512) {
         raise_lds_limit(k_pass2w<T, S, 8, PB, 0>, lds2w);
@@ -1280,7 +1280,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
         hipLaunchKernelGGL((k_pass2<T, S, 32>), g2, dim3(kNT), lds2, st, a);
       }
       prof_end(s, st, tok, kProfPass2, gs);
-      prof_begin(s, st, &tok);
+      prof_begin(s, st, &tok, kProfPass3);
       const dim3 g13(gd * (M2 / C));
       auto pass3 = [&](auto csr, auto e, auto mix) {
         constexpr bool C_ = decltype(csr)::value, X_ = decltype(mix)::value;
@@ -1300,7 +1300,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       if (!e16) pass3e(E8{});
       prof_end(s, st, tok, kProfPass3, gs);
       if (pl.csr) {
-        prof_begin(s, st, &tok);
+        prof_begin(s, st, &tok, kProfReduce);
         launch_reduce<T, S, NC>(s, a, st);
         prof_end(s, st, tok, kProfReduce, gs);
       }
@@ -1331,7 +1331,7 @@ mm_status filter_pipeline(ScanImpl* s, int src, const void* tod, const double* x
   const int32_t* mask = s->at<int32_t>(s->lay.mask);
   double* acc = s->at<double>(s->lay.acc);
   hipEvent_t tok;
-  prof_begin(s, st, &tok);
+  prof_begin(s, st, &tok, kProfApplyA);
   if (src == 0) {
     const dim3 grd1((npix + 1 + 255) / 256);   // npix + 1: the zero entry too
     if (s->plan.f64)

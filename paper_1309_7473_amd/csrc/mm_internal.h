@@ -125,6 +125,7 @@ struct ScanImpl {
   int circ_sym = 1;
   int maxdyn_lds = 65536;
   Profiler* prof = nullptr;
+  uint32_t prof_mask = ~0u;   // stages timed while profiling is enabled
   bool capturing = false;   // launches are being recorded into a graph
   mm_learned learned = nullptr;
 
@@ -172,9 +173,10 @@ mm_status pcg_solve_batch(ScanImpl* const* scans, int n, int precon, const doubl
                           mm_status* status, hipStream_t st);
 mm_status fill_zero(void* p, size_t bytes, hipStream_t st);
 mm_status apply_precon(ScanImpl* s, int precon, const double* r, double* z, hipStream_t st);
-void prof_begin(ScanImpl* s, hipStream_t st, hipEvent_t* tok);
+void prof_begin(ScanImpl* s, hipStream_t st, hipEvent_t* tok, int stage);
 void prof_end(ScanImpl* s, hipStream_t st, hipEvent_t tok, int stage, int64_t samples);
 mm_status profile_enable(ScanImpl* s, int enable);
+mm_status profile_stages(ScanImpl* s, uint32_t mask);
 mm_status profile_read(ScanImpl* s, mm_profile* out);
 void profile_free(ScanImpl* s);
 // learned correction (learned.hip)

@@ -240,7 +240,7 @@ static mm_status apply_precon_inner(ScanImpl* s, int precon, const double* r, do
 
 mm_status apply_precon(ScanImpl* s, int precon, const double* r, double* z, hipStream_t st) {
   hipEvent_t tok;
-  prof_begin(s, st, &tok);
+  prof_begin(s, st, &tok, kProfPrecon);
   const mm_status rc = apply_precon_inner(s, precon, r, z, st);
   prof_end(s, st, tok, kProfPrecon, int64_t(s->nc) * s->npix);
   return rc;

@@ -45,9 +45,10 @@ struct Profiler {
   }
 };
 
-void prof_begin(ScanImpl* s, hipStream_t st, hipEvent_t* tok) {
+void prof_begin(ScanImpl* s, hipStream_t st, hipEvent_t* tok, int stage) {
   *tok = nullptr;
   if (!s->prof || s->capturing) return;   // no timing inside a captured graph
+  if (!((s->prof_mask >> stage) & 1u)) return;   // stage not selected: no events
   if (s->prof->used > 32768) s->prof->flush();
   hipEvent_t e = s->prof->take();
   if (e && hipEventRecord(e, st) == hipSuccess) *tok = e;
@@ -65,6 +66,11 @@ mm_status profile_enable(ScanImpl* s, int enable) {
     delete s->prof;
     s->prof = nullptr;
   }
+  return MM_OK;
+}
+
+mm_status profile_stages(ScanImpl* s, uint32_t mask) {
+  s->prof_mask = mask;
   return MM_OK;
 }
 
