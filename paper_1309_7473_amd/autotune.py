@@ -39,14 +39,15 @@ def shape_key(inputs, tod_dtype, acc):
 def candidates(nsamp, ndet, tod_dtype="f32"):
     """Candidate plans for a four-step shape: every split the library accepts
     with M1 from 2^max(2, logM-12) to 2^min(9, logM-5), 8 or 16 columns, and
-    the automatic detector group or half of it."""
+    the automatic detector group (about 512 MiB of pass buffer), half of it
+    or a quarter."""
     M = nsamp // 2
     if M <= ONE_KERNEL_MAX_M:
         return []
     logM = int(round(math.log2(M)))
     cxb = {"f32": 8, "bf16": 4, "f64": 16}[tod_dtype]
-    g_auto = max(1, min(ndet, (256 << 20) // (M * cxb)))
-    groups = sorted({g_auto, max(1, g_auto // 2)})
+    g_auto = max(1, min(ndet, (512 << 20) // (M * cxb)))
+    groups = sorted({g_auto, max(1, g_auto // 2), max(1, g_auto // 4)})
     out = []
     for l1 in range(max(2, logM - 12), min(9, logM - 5) + 1):
         for cols in (8, 16):

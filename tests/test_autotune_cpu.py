@@ -20,9 +20,9 @@ def test_candidates_follow_the_plan_rules():
     l1s = sorted({int(math.log2(p["fft_m1"])) for p in c})
     assert l1s == list(range(max(2, logM - 12), min(9, logM - 5) + 1))
     assert {p["fft_cols"] for p in c} == {8, 16}
-    # automatic group ~256 MiB of pass buffer, and half of it
-    assert {p["det_group"] for p in c} == {32, 16}
-    assert {p["det_group"] for p in at.candidates(2**21, 256, "bf16")} == {64, 32}
+    # automatic group ~512 MiB of pass buffer, half and a quarter of it
+    assert {p["det_group"] for p in c} == {64, 32, 16}
+    assert {p["det_group"] for p in at.candidates(2**21, 256, "bf16")} == {128, 64, 32}
 
 
 def test_tune_picks_the_fastest_and_caches(tmp_path):
