@@ -344,6 +344,10 @@ constexpr int kNT13 = 1024;  // threads per pass-1/3 block
 #define MM_UB 1
 #endif
 constexpr int UB = MM_UB;     // sample groups in flight per thread with boresight pointing
+#ifndef MM_U0
+#define MM_U0 2
+#endif
+constexpr int U0 = MM_U0;     // ... with stored pointing
 // complex elements per thread: 8 (C * M1 <= 8192) or 16 (C * M1 <= 16384,
 // float math only: 128 KB of LDS per block)
 constexpr int kPad2 = 3;     // pass-2 LDS padding: one slot per 8 elements
@@ -515,7 +519,7 @@ __global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
   const int nq = (C * M1) >> 1;  // groups of 4 samples
   // U groups per thread per trip, every load of a trip issued before the
   // first use; a group past the end re-reads group e40 and is not stored.
-  constexpr int U = (SRC == 2) ? UB : 4;
+  constexpr int U = (SRC == 2) ? UB : U0;
   for (int e40 = threadIdx.x; e40 < nq; e40 += U * kNT13) {
     T v[U][4];
 #pragma unroll
@@ -672,7 +676,14 @@ __device__ __forceinline__ int pad_e(int i) {
 // place in natural order.  MODE 2: load the filtered spectrum Y, repack,
 // inverse FFT.
 template <typename T, typename S, int E, int PB, int MODE>
-__global__ void __launch_bounds__(128 * PB) k_pass2w(PassArgs<T, S> a, CorrArgs c) {
+#ifndef MM_P2W_WAVES
+#define MM_P2W_WAVES 0
+#endif
+__global__ void __launch_bounds__(128 * PB)
+#if MM_P2W_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(MM_P2W_WAVES)))
+#endif
+k_pass2w(PassArgs<T, S> a, CorrArgs c) {
   constexpr int LOGE = (E == 8) ? 3 : (E == 16) ? 4 : 5;
   constexpr int L = 64 * E;              // = M2
   constexpr int LOGL = LOGE + 6;
