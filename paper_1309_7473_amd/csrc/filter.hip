@@ -1040,12 +1040,20 @@ __device__ __forceinline__ void entry_weights(const PassArgs<T, S>& a, int k, in
   }
 }
 
+#ifndef MM_LPP
+#define MM_LPP 16
+#endif
+#ifndef MM_RUNROLL
+#define MM_RUNROLL 4
+#endif
+constexpr int kReduceLanes = MM_LPP;   // lanes per pixel in the gather
+
 template <typename T, typename S, int NC, bool CF, bool OTF>
 __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
-  constexpr int LPP = 16;
+  constexpr int LPP = kReduceLanes;
   const int sub = threadIdx.x / LPP;
   const int l = threadIdx.x % LPP;
-  // 16-pixel chunks: each XCD (blocks i mod 8) takes a contiguous eighth of
+  // chunks of 256/LPP pixels: each XCD (blocks i mod 8) takes a contiguous eighth of
   // them, so a line of the pass buffer shared by neighbouring pixels is
   // fetched into one L2 (266 -> 256 us per 64-detector launch)
   int chunk = blockIdx.x;
@@ -1059,7 +1067,7 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
   const int b = a.csr_off[p], e = a.csr_off[p + 1];
   if constexpr (!CF) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll 4
+#pragma unroll MM_RUNROLL
     for (int k = b + l; k < e; k += LPP) {
       const int ik = a.csr_idx[k];
       const double uu = double(Sto<T, S>::ldr(u + ik));
@@ -1159,7 +1167,8 @@ static void launch_pass2w(int M2, dim3 g, size_t lds, hipStream_t st, const Pass
 
 template <typename T, typename S, int NC>
 static void launch_reduce(ScanImpl* s, const PassArgs<T, S>& a, hipStream_t st) {
-  const dim3 grid((s->npix + 15) / 16);   // 16 pixels of 16 lanes per block
+  constexpr int PPB = 256 / kReduceLanes;   // pixels per 256-thread block
+  const dim3 grid((s->npix + PPB - 1) / PPB);
   const bool otf = !s->plan.csr_w && NC == 3;
   if (s->plan.acc32) {
     if (otf)
