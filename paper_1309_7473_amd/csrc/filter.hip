@@ -499,8 +499,18 @@ __device__ __forceinline__ void col_block(int logNB, int* g, int* cb) {
 }
 
 // MIX: the column length M1 is mixed-radix (lds_fft_mx on the columns).
+// Blocks of at most 8 elements a thread (C * M1 <= 8192, 68 KB of LDS) can
+// run two to a CU when a thread holds at most 64 VGPRs (eight waves a SIMD):
+// ask for that; the larger tiles fit one block a CU anyway.
+template <typename T, int E13>
+constexpr int pass1_waves() {
+  return (E13 == 8 && sizeof(T) == 4) ? 8 : 1;
+}
+
 template <typename T, typename S, int NC, int SRC, int E13, bool MIX>
-__global__ void __launch_bounds__(kNT13) k_pass1(PassArgs<T, S> a) {
+__global__ void __launch_bounds__(kNT13)
+__attribute__((amdgpu_waves_per_eu(pass1_waves<T, E13>())))
+k_pass1(PassArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* buf = reinterpret_cast<Cx<T>*>(smem);
   T* bufr = reinterpret_cast<T*>(smem);
