@@ -355,6 +355,9 @@ constexpr int kPad2 = 3;     // pass-2 LDS padding: one slot per 8 elements
 #ifndef MM_NT
 #define MM_NT 1
 #endif
+#ifndef MM_P3_BATCH
+#define MM_P3_BATCH 1
+#endif
 #ifndef MM_RED_XCD
 #define MM_RED_XCD 1
 #endif
@@ -1002,11 +1005,29 @@ __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
   else
     stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
   const auto* w = a.work + int64_t(g) * a.Mi;
-  for (int e = threadIdx.x; e < C * M1; e += kNT13) {
+  // all of a thread's (at most E13) loads in flight before the LDS writes
+  const int ntile = C * M1;
+#if MM_P3_BATCH
+  for (int e0 = threadIdx.x; e0 < ntile; e0 += E13 * kNT13) {
+    Cx<T> v[E13];
+#pragma unroll
+    for (int i = 0; i < E13; ++i) {
+      const int e = e0 + i * kNT13;
+      if (e < ntile) v[i] = Sto<T, S>::ld(w + int64_t(e >> a.logC) * M2 + j20 + (e & (C - 1)));
+    }
+#pragma unroll
+    for (int i = 0; i < E13; ++i) {
+      const int e = e0 + i * kNT13;
+      if (e < ntile) buf[e] = v[i];
+    }
+  }
+#else
+  for (int e = threadIdx.x; e < ntile; e += kNT13) {
     const int k1 = e >> a.logC;
     const int c = e & (C - 1);
     buf[e] = Sto<T, S>::ld(w + int64_t(k1) * M2 + j20 + c);
   }
+#endif
   __syncthreads();
   FftShape sh{a.logM1, a.logC, C, 1, true, a.logM1};
   if constexpr (MIX)
