@@ -397,6 +397,11 @@ typedef struct {
   int32_t single_pass;      /* 1 if each detector's filter runs in one kernel */
   int32_t csr;              /* 1 if P^T runs as a per-pixel gather */
   size_t  workspace_bytes;  /* bytes used */
+  int32_t gather_weights;   /* how the P^T gather gets the I,Q,U weights: 0 float32
+                               pairs stored with the index, 1 computed from the
+                               boresight model, 2 stored as 4-byte angles (stored
+                               weights of unit norm on the float32 and bfloat16
+                               paths; decoded to within 1e-7), -1 no gather or I only */
 } mm_scan_info;
 
 mm_status mm_get_info(mm_scan scan, mm_scan_info* out /*[host]*/);

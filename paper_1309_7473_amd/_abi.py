@@ -62,7 +62,8 @@ class mm_pcg_result(C.Structure):
 class mm_scan_info(C.Structure):
     _fields_ = [("n_active", C.c_int32), ("ref_pixel", C.c_int32), ("n_floored", C.c_int32),
                 ("det_group", C.c_int32), ("fft_m1", C.c_int32), ("fft_m2", C.c_int32),
-                ("fft_cols", C.c_int32), ("single_pass", C.c_int32), ("csr", C.c_int32), ("workspace_bytes", C.c_size_t)]
+                ("fft_cols", C.c_int32), ("single_pass", C.c_int32), ("csr", C.c_int32), ("workspace_bytes", C.c_size_t),
+                ("gather_weights", C.c_int32)]
 
 
 class mm_profile(C.Structure):

@@ -327,6 +327,7 @@ mm_status mm_get_info(mm_scan scan, mm_scan_info* out) {
   out->single_pass = s->plan.single ? 1 : 0;
   out->csr = s->plan.csr ? 1 : 0;
   out->workspace_bytes = s->lay.total;
+  out->gather_weights = (!s->plan.csr || s->nc != 3) ? -1 : !s->plan.csr_w ? 1 : s->csr_ang ? 2 : 0;
   return MM_OK;
 }
 

@@ -132,7 +132,9 @@ __global__ void __launch_bounds__(256) k_binned_accum(const int32_t* __restrict_
 template <int NC>
 __global__ void __launch_bounds__(256) k_binned_gather(const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ idx,
-                                                       const float2* __restrict__ w, Bore bo,
+                                                       const float2* __restrict__ w,
+                                                       const float* __restrict__ c2,
+                                                       const float* __restrict__ s2, Bore bo,
                                                        const double* __restrict__ detw,
                                                        int ngroups, int G, int n, int npix,
                                                        double* __restrict__ hits,
@@ -163,6 +165,9 @@ __global__ void __launch_bounds__(256) k_binned_gather(const int32_t* __restrict
           const float2 cs = w[int64_t(g) * gsz + k];
           c = double(cs.x);
           sn = double(cs.y);
+        } else if (c2) {   // the stored time-major weights, sample g G n + ik
+          c = double(c2[int64_t(g) * gsz + ik]);
+          sn = double(s2[int64_t(g) * gsz + ik]);
         } else {
           bore_weights_at(bo, d, ik % n, &c, &sn);
         }
@@ -343,16 +348,20 @@ mm_status binned_setup(ScanImpl* s, hipStream_t st) {
     // build the pixel-major index first, then sum through it
     if ((r = csr_setup(s, st)) != MM_OK) return r;
     const int G = s->plan.G, ngroups = (s->ndet + G - 1) / G;
-    // boresight pointing: float64 weights from the model, not the index's float32 copy
-    const float2* w = s->plan.csr_w && !s->plan.otf ? s->at<float2>(L.csr_w) : nullptr;
+    // boresight pointing: float64 weights from the model, not the index's float32
+    // copy; angle-coded index: the stored time-major weights themselves
+    const float2* w = s->plan.csr_w && !s->plan.otf && !s->csr_ang ? s->at<float2>(L.csr_w)
+                                                                   : nullptr;
+    const float* c2 = s->csr_ang ? s->d.cos2psi : nullptr;
+    const float* s2 = s->csr_ang ? s->d.sin2psi : nullptr;
     const dim3 gg((npix + 15) / 16);
     if (s->nc == 3)
       hipLaunchKernelGGL(k_binned_gather<3>, gg, dim3(256), 0, st, s->at<int32_t>(L.csr_off),
-                         s->at<int32_t>(L.csr_idx), w, bo, s->at<double>(L.detw), ngroups, G,
+                         s->at<int32_t>(L.csr_idx), w, c2, s2, bo, s->at<double>(L.detw), ngroups, G,
                          int(s->n), npix, s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
     else
       hipLaunchKernelGGL(k_binned_gather<1>, gg, dim3(256), 0, st, s->at<int32_t>(L.csr_off),
-                         s->at<int32_t>(L.csr_idx), w, bo, s->at<double>(L.detw), ngroups, G,
+                         s->at<int32_t>(L.csr_idx), w, c2, s2, bo, s->at<double>(L.detw), ngroups, G,
                          int(s->n), npix, s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
   } else if (s->nc == 3)
     hipLaunchKernelGGL(k_binned_accum<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,

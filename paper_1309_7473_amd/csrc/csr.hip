@@ -86,6 +86,29 @@ __global__ void __launch_bounds__(1024) k_csr_scan(int32_t* __restrict__ cnt,
   if (threadIdx.x == nt - 1) o[npix] = int32_t(part[nt - 1]);
 }
 
+// Counts on-map samples whose stored weights are not of unit norm
+// (|c^2 + s^2 - 1| > 1e-6 in float64, or not finite).
+__global__ void k_unit_weights(const int32_t* __restrict__ pix, const float* __restrict__ c2,
+                               const float* __restrict__ s2, int64_t total, int npix,
+                               int* __restrict__ bad) {
+  int cnt = 0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total; i += stride) {
+    if (unsigned(pix[i]) >= unsigned(npix)) continue;
+    const double c = c2[i], s = s2[i];
+    const double r = c * c + s * s - 1.0;
+    cnt += (r <= 1e-6 && r >= -1e-6) ? 0 : 1;
+  }
+  if (cnt) atomicAdd(bad, cnt);
+}
+
+// The weights (c, s) = (cos, sin)(theta) as u = theta 2^32 / 2pi mod 2^32.
+__device__ __forceinline__ uint32_t weight_angle(float c, float s) {
+  const double t = atan2(double(s), double(c)) * (4294967296.0 / 6.283185307179586476925);
+  const int64_t q = int64_t(llrint(t));          // |t| <= 2^31
+  return uint32_t(q & 0xFFFFFFFFll);
+}
+
 template <int NC>
 __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pix, Bore bo,
                                                   const float* __restrict__ c2,
@@ -93,7 +116,8 @@ __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pi
                                                   int64_t total, int G, int npix,
                                                   int32_t* __restrict__ cursor,
                                                   int32_t* __restrict__ idx,
-                                                  float2* __restrict__ w) {
+                                                  float2* __restrict__ w,
+                                                  uint32_t* __restrict__ ang) {
   const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -115,7 +139,9 @@ __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pi
       const int64_t e = g * gsz + slot0 + (lane - h);
       idx[e] = int32_t(i - g * gsz);
       if constexpr (NC == 3) {
-        if (w) {   // NULL: the gather computes the weights from the boresight model
+        if (ang) {           // unit-norm stored weights: 4 B a sample
+          ang[e] = weight_angle(c2[i], s2[i]);
+        } else if (w) {      // NULL: the gather computes the weights from the boresight model
           double c, sn;
           sample_weights(c2, s2, bo, i, &c, &sn);
           w[e] = make_float2(float(c), float(sn));
@@ -124,6 +150,11 @@ __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pi
     }
   }
 }
+
+#ifndef MM_ANGLE_WEIGHTS
+#define MM_ANGLE_WEIGHTS 1
+#endif
+constexpr bool kAngleWeights = MM_ANGLE_WEIGHTS != 0;
 
 mm_status csr_setup(ScanImpl* s, hipStream_t st) {
   const Layout& L = s->lay;
@@ -141,15 +172,32 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
                      total, G, npix, cnt);
   hipLaunchKernelGGL(k_csr_scan, dim3(ngroups), dim3(1024), 0, st, cnt, s->at<int32_t>(L.csr_off),
                      npix);
+  // stored float32 weights of unit norm (the float32 and bfloat16 paths) go
+  // into the index as 4-byte angles instead of 8-byte pairs
+  s->csr_ang = false;
+  if (s->nc == 3 && s->plan.csr_w && !s->plan.otf && !s->plan.f64 && kAngleWeights) {
+    int* bad = s->at<int>(L.misc);
+    if ((r = fill_zero(bad, 4, st)) != MM_OK) return r;
+    hipLaunchKernelGGL(k_unit_weights, dim3(2048), dim3(256), 0, st, s->d.pix, s->d.cos2psi,
+                       s->d.sin2psi, total, npix, bad);
+    MM_HIP(hipGetLastError());
+    int h = 0;
+    MM_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, st));
+    MM_HIP(hipStreamSynchronize(st));
+    s->csr_ang = h == 0;
+  }
   if (s->nc == 3)
     hipLaunchKernelGGL(k_csr_fill<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->n, total, G, npix, cnt,
                        s->at<int32_t>(L.csr_idx),
-                       s->plan.csr_w ? s->at<float2>(L.csr_w) : static_cast<float2*>(nullptr));
+                       s->plan.csr_w && !s->csr_ang ? s->at<float2>(L.csr_w)
+                                                    : static_cast<float2*>(nullptr),
+                       s->csr_ang ? s->at<uint32_t>(L.csr_w) : static_cast<uint32_t*>(nullptr));
   else
     hipLaunchKernelGGL(k_csr_fill<1>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->n, total, G, npix, cnt,
-                       s->at<int32_t>(L.csr_idx), static_cast<float2*>(nullptr));
+                       s->at<int32_t>(L.csr_idx), static_cast<float2*>(nullptr),
+                       static_cast<uint32_t*>(nullptr));
   MM_HIP(hipGetLastError());
   return MM_OK;
 }

@@ -91,6 +91,8 @@ struct PassArgs {
   const int32_t* csr_off;  // group [npix+1]
   const int32_t* csr_idx;  // group entries
   const float2* csr_w;     // group entries (I,Q,U weights)
+  const uint32_t* csr_ang; // group entries: the weights as a fixed-point angle (see below)
+  const float2* ang_tab;   // (cos, sin)(2 pi k / 256), k < 256
   const int32_t* mask;
   const float* iNt;        // group base [G][M+1], four-step order
   const Cx<T>* tw2;        // W_{2 M2}^k2, k2 < M2
@@ -1082,14 +1084,32 @@ __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
 // P^T for one detector group as a per-pixel gather: 16 lanes per pixel walk
 // its CSR entries, each lane summing a fixed stride of them, then a fixed
 // xor-tree; acc[p] += (sum u, sum c u, sum s u).  No atomics.
-// Weights of gather entry ik (group-relative sample d_local * n + t): stored
-// with the index, or from the boresight model.
-template <typename T, typename S, int NC, bool OTF>
-__device__ __forceinline__ void entry_weights(const PassArgs<T, S>& a, int k, int ik, double* c,
+// Weights of gather entry ik (group-relative sample d_local * n + t).
+// WM 0: stored with the index as float32 (cos 2psi, sin 2psi); WM 1: from the
+// boresight model; WM 2: stored as the angle u = 2psi * 2^32 / 2pi (mod 2^32)
+// when every sample's weights have unit norm, which halves the bytes: with
+// k = u >> 24 and d = (u mod 2^24) 2pi / 2^32 < 2pi/256, (cos, sin)(2psi) is
+// the table entry k turned by d, whose cos and sin are Taylor polynomials to
+// d^4 and d^5 (truncation below 1e-12); a few float32 roundings in all.
+__device__ __forceinline__ void angle_weights(uint32_t u, const float2* tab, double* c,
                                               double* sn) {
-  if constexpr (OTF) {
+  const float2 t = tab[u >> 24];
+  const float d = float(u & 0xFFFFFFu) * 1.4629180792671596e-09f;   // 2 pi / 2^32
+  const float d2 = d * d;
+  const float cd = 1.0f - d2 * (0.5f - d2 * (1.0f / 24.0f));
+  const float sd = d * (1.0f - d2 * (1.0f / 6.0f - d2 * (1.0f / 120.0f)));
+  *c = double(t.x * cd - t.y * sd);
+  *sn = double(t.y * cd + t.x * sd);
+}
+
+template <typename T, typename S, int NC, int WM>
+__device__ __forceinline__ void entry_weights(const PassArgs<T, S>& a, const float2* tab, int k,
+                                              int ik, double* c, double* sn) {
+  if constexpr (WM == 1) {
     const int d = a.det0 + (ik >> a.bo.logn);
     bore_weights_at(a.bo, d, ik & ((1 << a.bo.logn) - 1), c, sn);
+  } else if constexpr (WM == 2) {
+    angle_weights(a.csr_ang[k], tab, c, sn);
   } else {
     const float2 cs = a.csr_w[k];
     *c = double(cs.x);
@@ -1105,11 +1125,16 @@ __device__ __forceinline__ void entry_weights(const PassArgs<T, S>& a, int k, in
 #endif
 constexpr int kReduceLanes = MM_LPP;   // lanes per pixel in the gather
 
-template <typename T, typename S, int NC, bool CF, bool OTF>
+template <typename T, typename S, int NC, bool CF, int WM>
 __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
   constexpr int LPP = kReduceLanes;
   const int sub = threadIdx.x / LPP;
   const int l = threadIdx.x % LPP;
+  __shared__ float2 tab[WM == 2 ? 256 : 1];
+  if constexpr (WM == 2) {
+    tab[threadIdx.x] = a.ang_tab[threadIdx.x];   // blockDim.x == 256
+    __syncthreads();
+  }
   // chunks of 256/LPP pixels: each XCD (blocks i mod 8) takes a contiguous eighth of
   // them, so a line of the pass buffer shared by neighbouring pixels is
   // fetched into one L2 (266 -> 256 us per 64-detector launch)
@@ -1131,7 +1156,7 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
       s0 += uu;
       if constexpr (NC == 3) {
         double c, sn;
-        entry_weights<T, S, NC, OTF>(a, k, ik, &c, &sn);
+        entry_weights<T, S, NC, WM>(a, tab, k, ik, &c, &sn);
         s1 += c * uu;
         s2 += sn * uu;
       }
@@ -1167,7 +1192,7 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
       f2_acc(s0, uu.hi, uu.lo);
       if constexpr (NC == 3) {
         double c, sn;
-        entry_weights<T, S, NC, OTF>(a, k, ik, &c, &sn);
+        entry_weights<T, S, NC, WM>(a, tab, k, ik, &c, &sn);
         f2_fma_acc(s1, float(c), uu);
         f2_fma_acc(s2, float(sn), uu);
       }
@@ -1226,18 +1251,28 @@ template <typename T, typename S, int NC>
 static void launch_reduce(ScanImpl* s, const PassArgs<T, S>& a, hipStream_t st) {
   constexpr int PPB = 256 / kReduceLanes;   // pixels per 256-thread block
   const dim3 grid((s->npix + PPB - 1) / PPB);
-  const bool otf = !s->plan.csr_w && NC == 3;
-  if (s->plan.acc32) {
-    if (otf)
-      hipLaunchKernelGGL((k_csr_reduce<T, S, NC, true, true>), grid, dim3(256), 0, st, a);
+  // weights: 1 from the boresight model, 2 as stored angles, 0 as stored floats
+  const int wm = NC != 3 ? 0 : !s->plan.csr_w ? 1 : s->csr_ang ? 2 : 0;
+  auto go = [&](auto cf, auto w) {
+    constexpr bool CF_ = decltype(cf)::value;
+    constexpr int WM_ = decltype(w)::value;
+    hipLaunchKernelGGL((k_csr_reduce<T, S, NC, CF_, WM_>), grid, dim3(256), 0, st, a);
+  };
+  using W0 = std::integral_constant<int, 0>;
+  using W1 = std::integral_constant<int, 1>;
+  using W2 = std::integral_constant<int, 2>;
+  auto by_w = [&](auto cf) {
+    if (wm == 1)
+      go(cf, W1{});
+    else if (wm == 2)
+      go(cf, W2{});
     else
-      hipLaunchKernelGGL((k_csr_reduce<T, S, NC, true, false>), grid, dim3(256), 0, st, a);
-  } else {
-    if (otf)
-      hipLaunchKernelGGL((k_csr_reduce<T, S, NC, false, true>), grid, dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_csr_reduce<T, S, NC, false, false>), grid, dim3(256), 0, st, a);
-  }
+      go(cf, W0{});
+  };
+  if (s->plan.acc32)
+    by_w(std::true_type{});
+  else
+    by_w(std::false_type{});
 }
 
 template <typename T, typename S, int NC, int SRC>
@@ -1283,7 +1318,11 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const int gi = d0 / G;
       a.csr_off = s->at<int32_t>(s->lay.csr_off) + int64_t(gi) * (s->npix + 1);
       a.csr_idx = s->at<int32_t>(s->lay.csr_idx) + int64_t(gi) * G * s->n;
-      a.csr_w = pl.csr_w ? s->at<float2>(s->lay.csr_w) + int64_t(gi) * G * s->n : nullptr;
+      a.csr_w = pl.csr_w && !s->csr_ang ? s->at<float2>(s->lay.csr_w) + int64_t(gi) * G * s->n
+                                        : nullptr;
+      // stored angles live in the first half of the weights' region
+      a.csr_ang = s->csr_ang ? s->at<uint32_t>(s->lay.csr_w) + int64_t(gi) * G * s->n : nullptr;
+      a.ang_tab = s->at<float2>(s->lay.ang_tab);
     }
     const int64_t gs = int64_t(gd) * s->n;
     hipEvent_t tok;
@@ -1680,6 +1719,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   // float64 path, whose gather computes float64 weights from the model
   pl->csr_w = nc == 3 && !(pl->otf && pl->f64);
   L->csr_w = take(pl->csr_w ? csr_n * 8 : 0);
+  L->ang_tab = take(256 * 8);
   L->total = off;
   return MM_OK;
 }
@@ -1726,6 +1766,14 @@ static mm_status upload_t(ScanImpl* s, hipStream_t st) {
   }
   MM_HIP(hipMemcpyAsync(s->ws + s->lay.wn_hi, hi.data(), hi.size() * sizeof(Cx<T>),
                         hipMemcpyHostToDevice, st));
+  std::vector<float> at(512);   // (cos, sin)(2 pi k / 256), for angle-coded weights
+  for (int k = 0; k < 256; ++k) {
+    const long double ang = 2.0L * 3.14159265358979323846264338327950288L * k / 256.0L;
+    at[2 * k] = float(std::cos(double(ang)));
+    at[2 * k + 1] = float(std::sin(double(ang)));
+  }
+  MM_HIP(hipMemcpyAsync(s->ws + s->lay.ang_tab, at.data(), at.size() * 4, hipMemcpyHostToDevice,
+                        st));
   MM_HIP(hipMemcpyAsync(s->ws + s->lay.wn_lo, lo.data(), lo.size() * sizeof(Cx<T>),
                         hipMemcpyHostToDevice, st));
   std::vector<Cx<double>> tm;

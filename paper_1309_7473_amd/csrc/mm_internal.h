@@ -79,7 +79,8 @@ struct Layout {
   size_t csr_cnt;    // ngroups * npix int32 (counts, then fill cursors)
   size_t csr_off;    // ngroups * (npix+1) int32
   size_t csr_idx;    // ngroups * G * n int32 (group-relative sample index)
-  size_t csr_w;      // ngroups * G * n float2 (cos 2psi, sin 2psi)
+  size_t csr_w;      // ngroups * G * n float2 (cos 2psi, sin 2psi), or uint32 angles
+  size_t ang_tab;    // 256 float2: (cos, sin)(2 pi k / 256)
   size_t total;
 };
 
@@ -119,6 +120,7 @@ struct ScanImpl {
   int n_floored = 0;
   int n_active = 0;
   bool circ_built = false;
+  bool csr_ang = false;       // the index's weights are stored as fixed-point angles
   bool tiled_built = false;   // tiled preconditioner
   int tiled_T = 0;
   char* tiled_ws = nullptr;   // caller-owned workspace of the tiled preconditioner

@@ -204,3 +204,30 @@ def test_apply_parity_wide_column_tiles(dt):
     e = rel(pair.A_gpu(x), pair.A_oracle(x))
     print(f"[apply wide tiles {dt}] rel err {e:.3e}", flush=True)
     assert e <= (TOL32_WHITE if dt == "f32" else 2.0**-8)
+
+
+def test_gather_weight_encodings():
+    """Unit-norm stored weights go into the pixel index as 4-byte angles on the
+    float32 path; other weights, the float64 path, boresight pointing and I
+    only keep their own encodings; every encoding matches the oracle."""
+    import dataclasses
+    from synth import boresight_only
+    inp = raster_scan(ncomp=3, ny=32, nx=32, ndet=4, nsamp=2**15, fsample=100.0,
+                      layout="hex", hex_diameter_px=6.0, sigma_scatter=0.1,
+                      fknee=(0.5, 2.0), drift_deg=10.0, seed=(78, 1))
+    scaled = dataclasses.replace(inp, cos2psi=(inp.cos2psi * np.float32(0.95)),
+                                 sin2psi=(inp.sin2psi * np.float32(0.95)))
+    cases = [("unit f32", inp, "f32", 2, TOL32_WHITE),
+             ("unit bf16", inp, "bf16", 2, 4e-3),
+             ("efficiency 0.95 f32", scaled, "f32", 0, TOL32_WHITE),
+             ("unit f64", inp, "f64", 0, TOL64),
+             ("boresight f32", boresight_only(inp), "f32", 0, TOL32_WHITE)]
+    for label, data, dt, code, tol in cases:
+        pair = Pair(data, tod_dtype=dt)
+        info = pair.g.info()
+        assert info["gather_weights"] == code, (label, info)
+        e = _check_apply(pair, tol, seed=3, label=f"weights {label}")
+        print(f"[gather weights {label}] code {code} rel {e:.2e}", flush=True)
+    pair = Pair(raster_scan(ncomp=1, ny=16, nx=16, ndet=3, nsamp=2**15, fsample=100.0,
+                            seed=(78, 2)), tod_dtype="f32")
+    assert pair.g.info()["gather_weights"] == -1
