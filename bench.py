@@ -37,6 +37,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 # float64 accumulator are cache resident and not counted.  apply_A is the
 # whole operator's minimum: pointing twice, the timestream written and read
 # once, 1/N(f) once (34 B).
+# With unit-norm weights the gather's index stores them as 4-byte angles:
+# the reduce then reads 12 B a sample (alg["reduce"] below).
 ALG_BYTES = {"pass1": 16.0, "pass2": 10.0, "pass3": 16.0, "pass3_csr": 8.0, "reduce": 16.0,
              "single": 26.0, "apply_A": 34.0}
 
@@ -522,7 +524,10 @@ def main():
     tot_ms, nl, ns = prof[dom]
     avg_s = tot_ms * 1e-3 / nl
     key = "pass3_csr" if (dom == "pass3" and info["csr"]) else dom
-    bytes_per_launch = ALG_BYTES[key] * ns / nl
+    alg = dict(ALG_BYTES)
+    if info.get("gather_weights") == 2:   # weights stored as 4-byte angles
+        alg["reduce"] = 12.0
+    bytes_per_launch = alg[key] * ns / nl
     achieved = bytes_per_launch / avg_s / 1e9
     src_hash = kernel_source_hash()
     traffic = load_traffic(dom, src_hash)
