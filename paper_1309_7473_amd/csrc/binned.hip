@@ -352,8 +352,8 @@ mm_status binned_setup(ScanImpl* s, hipStream_t st) {
     // copy; angle-coded index: the stored time-major weights themselves
     const float2* w = s->plan.csr_w && !s->plan.otf && !s->csr_ang ? s->at<float2>(L.csr_w)
                                                                    : nullptr;
-    const float* c2 = s->csr_ang ? s->d.cos2psi : nullptr;
-    const float* s2 = s->csr_ang ? s->d.sin2psi : nullptr;
+    const float* c2 = s->csr_ang && !s->plan.otf ? s->d.cos2psi : nullptr;
+    const float* s2 = s->csr_ang && !s->plan.otf ? s->d.sin2psi : nullptr;
     const dim3 gg((npix + 15) / 16);
     if (s->nc == 3)
       hipLaunchKernelGGL(k_binned_gather<3>, gg, dim3(256), 0, st, s->at<int32_t>(L.csr_off),

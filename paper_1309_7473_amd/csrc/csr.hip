@@ -86,16 +86,17 @@ __global__ void __launch_bounds__(1024) k_csr_scan(int32_t* __restrict__ cnt,
   if (threadIdx.x == nt - 1) o[npix] = int32_t(part[nt - 1]);
 }
 
-// Counts on-map samples whose stored weights are not of unit norm
-// (|c^2 + s^2 - 1| > 1e-6 in float64, or not finite).
-__global__ void k_unit_weights(const int32_t* __restrict__ pix, const float* __restrict__ c2,
-                               const float* __restrict__ s2, int64_t total, int npix,
-                               int* __restrict__ bad) {
+// Counts on-map samples whose weights (stored, or from the boresight model)
+// are not of unit norm (|c^2 + s^2 - 1| > 1e-6 in float64, or not finite).
+__global__ void k_unit_weights(const int32_t* __restrict__ pix, Bore bo,
+                               const float* __restrict__ c2, const float* __restrict__ s2,
+                               int64_t total, int npix, int* __restrict__ bad) {
   int cnt = 0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total; i += stride) {
-    if (unsigned(pix[i]) >= unsigned(npix)) continue;
-    const double c = c2[i], s = s2[i];
+    if (unsigned(sample_pixel(pix, bo, i)) >= unsigned(npix)) continue;
+    double c, s;
+    sample_weights(c2, s2, bo, i, &c, &s);
     const double r = c * c + s * s - 1.0;
     cnt += (r <= 1e-6 && r >= -1e-6) ? 0 : 1;
   }
@@ -103,8 +104,8 @@ __global__ void k_unit_weights(const int32_t* __restrict__ pix, const float* __r
 }
 
 // The weights (c, s) = (cos, sin)(theta) as u = theta 2^32 / 2pi mod 2^32.
-__device__ __forceinline__ uint32_t weight_angle(float c, float s) {
-  const double t = atan2(double(s), double(c)) * (4294967296.0 / 6.283185307179586476925);
+__device__ __forceinline__ uint32_t weight_angle(double c, double s) {
+  const double t = atan2(s, c) * (4294967296.0 / 6.283185307179586476925);
   const int64_t q = int64_t(llrint(t));          // |t| <= 2^31
   return uint32_t(q & 0xFFFFFFFFll);
 }
@@ -139,8 +140,10 @@ __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pi
       const int64_t e = g * gsz + slot0 + (lane - h);
       idx[e] = int32_t(i - g * gsz);
       if constexpr (NC == 3) {
-        if (ang) {           // unit-norm stored weights: 4 B a sample
-          ang[e] = weight_angle(c2[i], s2[i]);
+        if (ang) {           // unit-norm weights: 4 B a sample
+          double c, sn;
+          sample_weights(c2, s2, bo, i, &c, &sn);
+          ang[e] = weight_angle(c, sn);
         } else if (w) {      // NULL: the gather computes the weights from the boresight model
           double c, sn;
           sample_weights(c2, s2, bo, i, &c, &sn);
@@ -172,14 +175,14 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
                      total, G, npix, cnt);
   hipLaunchKernelGGL(k_csr_scan, dim3(ngroups), dim3(1024), 0, st, cnt, s->at<int32_t>(L.csr_off),
                      npix);
-  // stored float32 weights of unit norm (the float32 and bfloat16 paths) go
-  // into the index as 4-byte angles instead of 8-byte pairs
+  // weights of unit norm on the float32 and bfloat16 paths go into the index
+  // as 4-byte angles instead of 8-byte float32 pairs
   s->csr_ang = false;
-  if (s->nc == 3 && s->plan.csr_w && !s->plan.otf && !s->plan.f64 && kAngleWeights) {
+  if (s->nc == 3 && s->plan.csr_w && !s->plan.f64 && kAngleWeights) {
     int* bad = s->at<int>(L.misc);
     if ((r = fill_zero(bad, 4, st)) != MM_OK) return r;
-    hipLaunchKernelGGL(k_unit_weights, dim3(2048), dim3(256), 0, st, s->d.pix, s->d.cos2psi,
-                       s->d.sin2psi, total, npix, bad);
+    hipLaunchKernelGGL(k_unit_weights, dim3(2048), dim3(256), 0, st, s->d.pix, bo,
+                       s->d.cos2psi, s->d.sin2psi, total, npix, bad);
     MM_HIP(hipGetLastError());
     int h = 0;
     MM_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, st));

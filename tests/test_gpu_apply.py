@@ -207,9 +207,10 @@ def test_apply_parity_wide_column_tiles(dt):
 
 
 def test_gather_weight_encodings():
-    """Unit-norm stored weights go into the pixel index as 4-byte angles on the
-    float32 path; other weights, the float64 path, boresight pointing and I
-    only keep their own encodings; every encoding matches the oracle."""
+    """Unit-norm weights (stored, or from the boresight model) go into the
+    pixel index as 4-byte angles on the float32 and bfloat16 paths; other
+    weights keep float32 pairs, the float64 path pairs or (boresight) model
+    weights, I only none; every encoding matches the oracle."""
     import dataclasses
     from synth import boresight_only
     inp = raster_scan(ncomp=3, ny=32, nx=32, ndet=4, nsamp=2**15, fsample=100.0,
@@ -221,7 +222,8 @@ def test_gather_weight_encodings():
              ("unit bf16", inp, "bf16", 2, 4e-3),
              ("efficiency 0.95 f32", scaled, "f32", 0, TOL32_WHITE),
              ("unit f64", inp, "f64", 0, TOL64),
-             ("boresight f32", boresight_only(inp), "f32", 0, TOL32_WHITE)]
+             ("boresight f32", boresight_only(inp), "f32", 2, TOL32_WHITE),
+             ("boresight f64", boresight_only(inp), "f64", 1, TOL64)]
     for label, data, dt, code, tol in cases:
         pair = Pair(data, tod_dtype=dt)
         info = pair.g.info()
