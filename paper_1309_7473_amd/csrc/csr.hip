@@ -110,6 +110,13 @@ __device__ __forceinline__ uint32_t weight_angle(double c, double s) {
   return uint32_t(q & 0xFFFFFFFFll);
 }
 
+__global__ void k_angles_t(const float* __restrict__ c2, const float* __restrict__ s2,
+                           int64_t total, uint32_t* __restrict__ ang) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total; i += stride)
+    ang[i] = weight_angle(c2[i], s2[i]);
+}
+
 template <int NC>
 __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pix, Bore bo,
                                                   const float* __restrict__ c2,
@@ -188,6 +195,14 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
     MM_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, st));
     MM_HIP(hipStreamSynchronize(st));
     s->csr_ang = h == 0;
+  }
+  // a time-major copy of the angles for pass 1 (8 B of pointing a sample)
+  s->ang_t_ready = false;
+  if (s->csr_ang && !s->plan.otf && !s->plan.f64) {   // the region plan_and_layout sized
+    hipLaunchKernelGGL(k_angles_t, dim3(2048), dim3(256), 0, st, s->d.cos2psi, s->d.sin2psi,
+                       total, s->at<uint32_t>(L.ang_t));
+    MM_HIP(hipGetLastError());
+    s->ang_t_ready = true;
   }
   if (s->nc == 3)
     hipLaunchKernelGGL(k_csr_fill<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,

@@ -93,6 +93,7 @@ struct PassArgs {
   const float2* csr_w;     // group entries (I,Q,U weights)
   const uint32_t* csr_ang; // group entries: the weights as a fixed-point angle (see below)
   const float2* ang_tab;   // (cos, sin)(2 pi k / 256), k < 256
+  const uint32_t* ang_t;   // group base [G][n]: the weights as angles, time-major
   const int32_t* mask;
   const float* iNt;        // group base [G][M+1], four-step order
   const Cx<T>* tw2;        // W_{2 M2}^k2, k2 < M2
@@ -119,7 +120,24 @@ struct CorrArgs {
   int rank, ndet;
 };
 
+// Weights (cos, sin)(theta) coded as u = theta 2^32 / 2pi (mod 2^32): with
+// k = u >> 24 and d = (u mod 2^24) 2pi / 2^32 < 2pi/256, they are the table
+// entry (cos, sin)(2pi k / 256) turned by d, whose cos and sin are Taylor
+// polynomials to d^4 and d^5 (truncation below 1e-12); within one float32
+// ulp of the weights the angle was made from.
+__device__ __forceinline__ void angle_cs(uint32_t u, const float2* tab, float* c, float* sn) {
+  const float2 t = tab[u >> 24];
+  const float d = float(u & 0xFFFFFFu) * 1.4629180792671596e-09f;   // 2 pi / 2^32
+  const float d2 = d * d;
+  const float cd = 1.0f - d2 * (0.5f - d2 * (1.0f / 24.0f));
+  const float sd = d * (1.0f - d2 * (1.0f / 6.0f - d2 * (1.0f / 120.0f)));
+  *c = t.x * cd - t.y * sd;
+  *sn = t.y * cd + t.x * sd;
+}
+
 // --------------------------------------------------------------- samples
+// SRC 0: stored pointing; 1: a timestream; 2: the boresight model; 3: stored
+// pixels with the weights as angles (a time-major copy made at set-up).
 template <typename T, typename S, int NC, int SRC>
 __device__ __forceinline__ T source_sample(const PassArgs<T, S>& a, int64_t s) {
   if constexpr (SRC == 1) {
@@ -137,6 +155,12 @@ __device__ __forceinline__ T source_sample(const PassArgs<T, S>& a, int64_t s) {
     } else {
       return m.x;
     }
+  } else if constexpr (SRC == 3) {
+    const int p = a.pix[s];
+    const V4<T> m = a.gmap[unsigned(p) < unsigned(a.npix) ? p : a.npix];
+    float c, sn;
+    angle_cs(a.ang_t[s], a.ang_tab, &c, &sn);
+    return m.x + T(c) * m.y + T(sn) * m.z;
   } else {
     const int p = a.pix[s];
     // off-map samples read the zero entry gmap[npix]: no branch around the gather
@@ -398,7 +422,8 @@ __device__ __forceinline__ void ld4d(const double* p, double (&v)[4]) {
 
 // Four consecutive samples s..s+3 (s a multiple of 4) with 16-byte loads.
 template <typename T, typename S, int NC, int SRC>
-__device__ __forceinline__ void source4(const PassArgs<T, S>& a, int64_t s, T (&v)[4]) {
+__device__ __forceinline__ void source4(const PassArgs<T, S>& a, int64_t s, T (&v)[4],
+                                        const float2* tab = nullptr) {
   if constexpr (SRC == 1) {
     if constexpr (std::is_same<S, Bf16>::value) {
       const uint2 t = *reinterpret_cast<const uint2*>(a.tod + s);
@@ -440,6 +465,19 @@ __device__ __forceinline__ void source4(const PassArgs<T, S>& a, int64_t s, T (&
       const int p = bore_pixel(yb[i], xb[i], cp[i], sp[i], dy, dx, a.bo.ny, a.bo.nx);
       const V4<T> m = a.gmap[p >= 0 ? p : a.npix];
       v[i] = (NC == 3) ? m.x + T(cc[i]) * m.y + T(ss[i]) * m.z : m.x;
+    }
+  } else if constexpr (SRC == 3) {
+    // stored pixels and angle-coded weights: 8 B a sample instead of 12
+    const int4 p4 = ld_stream(reinterpret_cast<const int4*>(a.pix + s));
+    const int4 u4 = ld_stream(reinterpret_cast<const int4*>(a.ang_t + s));
+    const int pp[4] = {p4.x, p4.y, p4.z, p4.w};
+    const uint32_t uu[4] = {uint32_t(u4.x), uint32_t(u4.y), uint32_t(u4.z), uint32_t(u4.w)};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float c, sn;
+      angle_cs(uu[i], tab, &c, &sn);
+      const V4<T> m = a.gmap[unsigned(pp[i]) < unsigned(a.npix) ? pp[i] : a.npix];
+      v[i] = m.x + T(c) * m.y + T(sn) * m.z;
     }
   } else {
     const int4 p4 = ld_stream(reinterpret_cast<const int4*>(a.pix + s));
@@ -534,6 +572,11 @@ k_pass1(PassArgs<T, S> a) {
     for (int m = threadIdx.x; m < M1; m += kNT13) stw[m] = a.twm[m];
   else
     stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
+  __shared__ float2 angtab[SRC == 3 ? 256 : 1];   // angle-coded weights' table
+  if constexpr (SRC == 3) {
+    if (threadIdx.x < 256) angtab[threadIdx.x] = a.ang_tab[threadIdx.x];
+    __syncthreads();
+  }
   const int nq = (C * M1) >> 1;  // groups of 4 samples
   // U groups per thread per trip, every load of a trip issued before the
   // first use; a group past the end re-reads group e40 and is not stored.
@@ -546,7 +589,7 @@ k_pass1(PassArgs<T, S> a) {
       const int e = (e4 < nq ? e4 : e40) << 2;
       const int j1 = e >> (a.logC + 1);
       const int q = e & (2 * C - 1);
-      source4<T, S, NC, SRC>(a, base + 2 * (int64_t(j1) * M2 + j20) + q, v[u]);
+      source4<T, S, NC, SRC>(a, base + 2 * (int64_t(j1) * M2 + j20) + q, v[u], angtab);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1093,13 +1136,10 @@ __global__ void __launch_bounds__(kNT13) k_pass3(PassArgs<T, S> a) {
 // d^4 and d^5 (truncation below 1e-12); a few float32 roundings in all.
 __device__ __forceinline__ void angle_weights(uint32_t u, const float2* tab, double* c,
                                               double* sn) {
-  const float2 t = tab[u >> 24];
-  const float d = float(u & 0xFFFFFFu) * 1.4629180792671596e-09f;   // 2 pi / 2^32
-  const float d2 = d * d;
-  const float cd = 1.0f - d2 * (0.5f - d2 * (1.0f / 24.0f));
-  const float sd = d * (1.0f - d2 * (1.0f / 6.0f - d2 * (1.0f / 120.0f)));
-  *c = double(t.x * cd - t.y * sd);
-  *sn = double(t.y * cd + t.x * sd);
+  float cf, sf;
+  angle_cs(u, tab, &cf, &sf);
+  *c = double(cf);
+  *sn = double(sf);
 }
 
 template <typename T, typename S, int NC, int WM>
@@ -1303,11 +1343,13 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
   a.mask = s->at<int32_t>(s->lay.mask);
   a.tw2 = s->at<Cx<T>>(s->lay.tw2);
   a.bo = scan_bore(s);
+  a.ang_tab = s->at<float2>(s->lay.ang_tab);
   const int G = pl.G;
   for (int d0 = 0; d0 < s->ndet; d0 += G) {
     const int gd = (s->ndet - d0 < G) ? (s->ndet - d0) : G;
     const int64_t off = int64_t(d0) * s->n;
     a.det0 = d0;
+    a.ang_t = s->ang_t_ready ? s->at<uint32_t>(s->lay.ang_t) + off : nullptr;
     a.pix = s->d.pix ? s->d.pix + off : nullptr;
     a.c2 = s->d.cos2psi ? s->d.cos2psi + off : nullptr;
     a.s2 = s->d.sin2psi ? s->d.sin2psi + off : nullptr;
@@ -1322,7 +1364,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
                                         : nullptr;
       // stored angles live in the first half of the weights' region
       a.csr_ang = s->csr_ang ? s->at<uint32_t>(s->lay.csr_w) + int64_t(gi) * G * s->n : nullptr;
-      a.ang_tab = s->at<float2>(s->lay.ang_tab);
+
     }
     const int64_t gs = int64_t(gd) * s->n;
     hipEvent_t tok;
@@ -1467,9 +1509,10 @@ template <typename T, typename S>
 static mm_status run_pipeline(ScanImpl* s, int src, const void* tod, hipStream_t st) {
   const bool otf = s->plan.otf;
   if (s->nc == 3)
-    return src   ? run_pipeline_t<T, S, 3, 1>(s, tod, st)
-           : otf ? run_pipeline_t<T, S, 3, 2>(s, tod, st)
-                 : run_pipeline_t<T, S, 3, 0>(s, tod, st);
+    return src               ? run_pipeline_t<T, S, 3, 1>(s, tod, st)
+           : otf             ? run_pipeline_t<T, S, 3, 2>(s, tod, st)
+           : s->ang_t_ready  ? run_pipeline_t<T, S, 3, 3>(s, tod, st)
+                             : run_pipeline_t<T, S, 3, 0>(s, tod, st);
   return src   ? run_pipeline_t<T, S, 1, 1>(s, tod, st)
          : otf ? run_pipeline_t<T, S, 1, 2>(s, tod, st)
                : run_pipeline_t<T, S, 1, 0>(s, tod, st);
@@ -1720,6 +1763,8 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   pl->csr_w = nc == 3 && !(pl->otf && pl->f64);
   L->csr_w = take(pl->csr_w ? csr_n * 8 : 0);
   L->ang_tab = take(256 * 8);
+  // time-major angle-coded weights for pass 1 (stored pointing, float paths)
+  L->ang_t = take(nc == 3 && pl->csr && !pl->f64 && !pl->otf ? size_t(d->ndet) * size_t(n) * 4 : 0);
   L->total = off;
   return MM_OK;
 }

@@ -81,6 +81,7 @@ struct Layout {
   size_t csr_idx;    // ngroups * G * n int32 (group-relative sample index)
   size_t csr_w;      // ngroups * G * n float2 (cos 2psi, sin 2psi), or uint32 angles
   size_t ang_tab;    // 256 float2: (cos, sin)(2 pi k / 256)
+  size_t ang_t;      // ndet * n uint32: the weights as angles, time-major (pass 1)
   size_t total;
 };
 
@@ -121,6 +122,7 @@ struct ScanImpl {
   int n_active = 0;
   bool circ_built = false;
   bool csr_ang = false;       // the index's weights are stored as fixed-point angles
+  bool ang_t_ready = false;   // pass 1 reads the time-major angles (SRC 3)
   bool tiled_built = false;   // tiled preconditioner
   int tiled_T = 0;
   char* tiled_ws = nullptr;   // caller-owned workspace of the tiled preconditioner
