@@ -527,6 +527,7 @@ def main():
     alg = dict(ALG_BYTES)
     if info.get("gather_weights") == 2:   # weights stored as 4-byte angles
         alg["reduce"] = 12.0
+        alg["pass1"] = 12.0                # pixels 4 + angles 4 + timestream write 4
     bytes_per_launch = alg[key] * ns / nl
     achieved = bytes_per_launch / avg_s / 1e9
     src_hash = kernel_source_hash()

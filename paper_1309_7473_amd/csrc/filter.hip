@@ -387,6 +387,9 @@ constexpr int kPad2 = 3;     // pass-2 LDS padding: one slot per 8 elements
 #ifndef MM_P2_BATCH
 #define MM_P2_BATCH 1
 #endif
+#ifndef MM_P2_CHUNK
+#define MM_P2_CHUNK 4
+#endif
 #ifndef MM_RED_XCD
 #define MM_RED_XCD 1
 #endif
@@ -918,25 +921,29 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
       const float* ia = iN + int64_t(ra) * L;
       const float* ib = iN + int64_t(rb) * L;
 #if MM_P2_BATCH
-      // every global load of the pair loop in flight before the first use
+      // the pair loop's global loads in flight in chunks of NC2 before use
       constexpr int NP = L / 128;
-      T ga[NP], gb[NP];
-      Cx<T> tw[NP];
+      constexpr int NC2 = NP < MM_P2_CHUNK ? NP : MM_P2_CHUNK;
 #pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        const int k2 = tp + 128 * i;
-        ga[i] = gain(ia, k2);
-        gb[i] = gain(ib, L - 1 - k2);
-        tw[i] = a.tw2[k2];
-      }
+      for (int i0c = 0; i0c < NP; i0c += NC2) {
+        T ga[NC2], gb[NC2];
+        Cx<T> tw[NC2];
 #pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        const int k2 = tp + 128 * i;
-        const int i0 = pad_e<LOGE>(k2), i1 = pad_e<LOGE>(L - 1 - k2);
-        Cx<T> zk = Ra[i0], zm = Rb[i1];
-        pair_op(zk, zm, wa * tw[i], ga[i], gb[i]);
-        Ra[i0] = zk;
-        Rb[i1] = zm;
+        for (int i = 0; i < NC2; ++i) {
+          const int k2 = tp + 128 * (i0c + i);
+          ga[i] = gain(ia, k2);
+          gb[i] = gain(ib, L - 1 - k2);
+          tw[i] = a.tw2[k2];
+        }
+#pragma unroll
+        for (int i = 0; i < NC2; ++i) {
+          const int k2 = tp + 128 * (i0c + i);
+          const int i0 = pad_e<LOGE>(k2), i1 = pad_e<LOGE>(L - 1 - k2);
+          Cx<T> zk = Ra[i0], zm = Rb[i1];
+          pair_op(zk, zm, wa * tw[i], ga[i], gb[i]);
+          Ra[i0] = zk;
+          Rb[i1] = zm;
+        }
       }
 #else
       for (int k2 = tp; k2 < L; k2 += 128) {
