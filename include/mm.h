@@ -125,7 +125,8 @@ typedef struct {
                                (four-step) pipeline: MM_SCATTER_AUTO = per-pixel
                                gather through a pixel-major index built at
                                creation (no atomics; 12 B/sample of workspace for
-                               I,Q,U, 4 B for I); MM_SCATTER_ATOMIC = float64
+                               I,Q,U plus 4 B of time-major angle-coded weights on
+                               the float32 and bfloat16 paths, 4 B for I); MM_SCATTER_ATOMIC = float64
                                atomic scatter (no index).  The one-kernel path
                                scatters atomically unless acc = MM_ACC_F32X2. */
   int32_t acc;              /* mm_acc of the P^T accumulation and the PCG inner
