@@ -144,7 +144,7 @@ mm_status mm_create_scan(const mm_scan_desc* desc, void* stream, mm_scan* out) {
   // binned_setup validates the inputs, builds the pixel-major index (when
   // the plan has one) and the binned blocks
   if ((r = upload_tables(&s, st)) != MM_OK || (r = binned_setup(&s, st)) != MM_OK ||
-      (r = permute_inverse_spectrum(&s, st)) != MM_OK) {
+      (r = bore_setup(&s, st)) != MM_OK || (r = permute_inverse_spectrum(&s, st)) != MM_OK) {
     h->magic = 0;
     delete h;
     return r;

@@ -103,13 +103,6 @@ __global__ void k_unit_weights(const int32_t* __restrict__ pix, Bore bo,
   if (cnt) atomicAdd(bad, cnt);
 }
 
-// The weights (c, s) = (cos, sin)(theta) as u = theta 2^32 / 2pi mod 2^32.
-__device__ __forceinline__ uint32_t weight_angle(double c, double s) {
-  const double t = atan2(s, c) * (4294967296.0 / 6.283185307179586476925);
-  const int64_t q = int64_t(llrint(t));          // |t| <= 2^31
-  return uint32_t(q & 0xFFFFFFFFll);
-}
-
 __global__ void k_angles_t(const float* __restrict__ c2, const float* __restrict__ s2,
                            int64_t total, uint32_t* __restrict__ ang) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;

@@ -94,6 +94,10 @@ struct PassArgs {
   const uint32_t* csr_ang; // group entries: the weights as a fixed-point angle (see below)
   const float2* ang_tab;   // (cos, sin)(2 pi k / 256), k < 256
   const uint32_t* ang_t;   // group base [G][n]: the weights as angles, time-major
+  const float4* bore_f;    // boresight in float32: [n] (y_b - c_y, x_b - c_x, cos phi, sin phi)
+  const uint32_t* bore_a;  // [n] angle of (cos 2phi, sin 2phi)
+  const float2* det_f;     // [ndet] (dy, dx) in float32
+  const uint32_t* det_a;   // [ndet] angle of (cos 2psi, sin 2psi)
   const int32_t* mask;
   const float* iNt;        // group base [G][M+1], four-step order
   const Cx<T>* tw2;        // W_{2 M2}^k2, k2 < M2
@@ -137,12 +141,14 @@ __device__ __forceinline__ void angle_cs(uint32_t u, const float2* tab, float* c
 
 // --------------------------------------------------------------- samples
 // SRC 0: stored pointing; 1: a timestream; 2: the boresight model; 3: stored
-// pixels with the weights as angles (a time-major copy made at set-up).
+// pixels with the weights as angles (a time-major copy made at set-up); 4:
+// the boresight model from float32 copies (pass 1 of the float paths; the
+// float64 definition decides the pixels the float32 evaluation cannot).
 template <typename T, typename S, int NC, int SRC>
 __device__ __forceinline__ T source_sample(const PassArgs<T, S>& a, int64_t s) {
   if constexpr (SRC == 1) {
     return Sto<T, S>::ldr(a.tod + s);
-  } else if constexpr (SRC == 2) {
+  } else if constexpr (SRC == 2 || SRC == 4) {
     // pointing from the boresight model: s = d_local * n + t
     const int d = a.det0 + int(s >> a.bo.logn);
     const int64_t t = s & ((int64_t(1) << a.bo.logn) - 1);
@@ -387,6 +393,10 @@ constexpr int kPad2 = 3;     // pass-2 LDS padding: one slot per 8 elements
 #ifndef MM_P2_BATCH
 #define MM_P2_BATCH 1
 #endif
+#ifndef MM_BORE_FAST
+#define MM_BORE_FAST 1
+#endif
+constexpr bool kBoreFast = MM_BORE_FAST != 0;
 #ifndef MM_P2_CHUNK
 #define MM_P2_CHUNK 4
 #endif
@@ -468,6 +478,30 @@ __device__ __forceinline__ void source4(const PassArgs<T, S>& a, int64_t s, T (&
       const int p = bore_pixel(yb[i], xb[i], cp[i], sp[i], dy, dx, a.bo.ny, a.bo.nx);
       const V4<T> m = a.gmap[p >= 0 ? p : a.npix];
       v[i] = (NC == 3) ? m.x + T(cc[i]) * m.y + T(ss[i]) * m.z : m.x;
+    }
+  } else if constexpr (SRC == 4) {
+    // boresight model, float32 copies: 20 B per time sample shared by every
+    // detector; the float64 definition where float32 cannot decide the pixel
+    const int d = a.det0 + int(s >> a.bo.logn);
+    const int64_t n = int64_t(1) << a.bo.logn;
+    const int64_t t = s & (n - 1);
+    const float2 df = a.det_f[d];
+    const uint32_t ad = a.det_a[d];
+    const int4 au = *reinterpret_cast<const int4*>(a.bore_a + t);
+    const uint32_t aa[4] = {uint32_t(au.x), uint32_t(au.y), uint32_t(au.z), uint32_t(au.w)};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float4 b = a.bore_f[t + i];
+      int p = bore_pixel_f32(b.x, b.y, b.z, b.w, df.x, df.y, a.bo.ny, a.bo.nx);
+      if (p == -2) p = bore_pixel_slow(a.bo, d, t + i);
+      const V4<T> m = a.gmap[p >= 0 ? p : a.npix];
+      if constexpr (NC == 3) {
+        float c, sn;
+        angle_cs(ad + aa[i], tab, &c, &sn);
+        v[i] = m.x + T(c) * m.y + T(sn) * m.z;
+      } else {
+        v[i] = m.x;
+      }
     }
   } else if constexpr (SRC == 3) {
     // stored pixels and angle-coded weights: 8 B a sample instead of 12
@@ -565,7 +599,7 @@ k_pass1(PassArgs<T, S> a) {
   T* bufr = reinterpret_cast<T*>(smem);
   const int logNB = a.logM2 - a.logC;
   int g, cb;
-  col_block<SRC == 2>(logNB, &g, &cb);
+  col_block<SRC == 2 || SRC == 4>(logNB, &g, &cb);
   const int C = 1 << a.logC;
   const int M1 = a.M1i, M2 = 1 << a.logM2;
   Cx<T>* stw = buf + C * M1;
@@ -575,15 +609,15 @@ k_pass1(PassArgs<T, S> a) {
     for (int m = threadIdx.x; m < M1; m += kNT13) stw[m] = a.twm[m];
   else
     stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
-  __shared__ float2 angtab[SRC == 3 ? 256 : 1];   // angle-coded weights' table
-  if constexpr (SRC == 3) {
+  __shared__ float2 angtab[SRC == 3 || SRC == 4 ? 256 : 1];   // angle-coded weights' table
+  if constexpr (SRC == 3 || SRC == 4) {
     if (threadIdx.x < 256) angtab[threadIdx.x] = a.ang_tab[threadIdx.x];
     __syncthreads();
   }
   const int nq = (C * M1) >> 1;  // groups of 4 samples
   // U groups per thread per trip, every load of a trip issued before the
   // first use; a group past the end re-reads group e40 and is not stored.
-  constexpr int U = (SRC == 2) ? UB : U0;
+  constexpr int U = (SRC == 2 || SRC == 4) ? UB : U0;
   for (int e40 = threadIdx.x; e40 < nq; e40 += U * kNT13) {
     T v[U][4];
 #pragma unroll
@@ -1351,6 +1385,12 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
   a.tw2 = s->at<Cx<T>>(s->lay.tw2);
   a.bo = scan_bore(s);
   a.ang_tab = s->at<float2>(s->lay.ang_tab);
+  if (s->bore_fast) {
+    a.bore_f = s->at<float4>(s->lay.bore_f);
+    a.bore_a = s->at<uint32_t>(s->lay.bore_a);
+    a.det_f = s->at<float2>(s->lay.det_f);
+    a.det_a = s->at<uint32_t>(s->lay.det_a);
+  }
   const int G = pl.G;
   for (int d0 = 0; d0 < s->ndet; d0 += G) {
     const int gd = (s->ndet - d0 < G) ? (s->ndet - d0) : G;
@@ -1385,7 +1425,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       };
       using TT = std::true_type;
       using FF = std::false_type;
-      if constexpr (SRC == 2) {   // boresight pointing: gather, powers of two
+      if constexpr (SRC == 2 || SRC == 4) {   // boresight pointing: gather, powers of two
         single(TT{}, FF{});
       } else {
         if (pl.csr)
@@ -1422,14 +1462,14 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const bool mix1 = pl.mix_code != 0;
       if constexpr (sizeof(T) == 4) {
         if (e16) {
-          if constexpr (SRC == 2)
+          if constexpr (SRC == 2 || SRC == 4)
             pass1(E16{}, FF{});
           else
             mix1 ? pass1(E16{}, TT{}) : pass1(E16{}, FF{});
         }
       }
       if (!e16) {
-        if constexpr (SRC == 2)
+        if constexpr (SRC == 2 || SRC == 4)
           pass1(E8{}, FF{});
         else
           mix1 ? pass1(E8{}, TT{}) : pass1(E8{}, FF{});
@@ -1517,11 +1557,13 @@ static mm_status run_pipeline(ScanImpl* s, int src, const void* tod, hipStream_t
   const bool otf = s->plan.otf;
   if (s->nc == 3)
     return src               ? run_pipeline_t<T, S, 3, 1>(s, tod, st)
-           : otf             ? run_pipeline_t<T, S, 3, 2>(s, tod, st)
+           : otf             ? (s->bore_fast ? run_pipeline_t<T, S, 3, 4>(s, tod, st)
+                                             : run_pipeline_t<T, S, 3, 2>(s, tod, st))
            : s->ang_t_ready  ? run_pipeline_t<T, S, 3, 3>(s, tod, st)
                              : run_pipeline_t<T, S, 3, 0>(s, tod, st);
   return src   ? run_pipeline_t<T, S, 1, 1>(s, tod, st)
-         : otf ? run_pipeline_t<T, S, 1, 2>(s, tod, st)
+         : otf ? (s->bore_fast ? run_pipeline_t<T, S, 1, 4>(s, tod, st)
+                               : run_pipeline_t<T, S, 1, 2>(s, tod, st))
                : run_pipeline_t<T, S, 1, 0>(s, tod, st);
 }
 
@@ -1770,6 +1812,12 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   pl->csr_w = nc == 3 && !(pl->otf && pl->f64);
   L->csr_w = take(pl->csr_w ? csr_n * 8 : 0);
   L->ang_tab = take(256 * 8);
+  // float32 copies of the boresight model for pass 1 (float paths)
+  const bool bfast = pl->otf && !pl->f64;
+  L->bore_f = take(bfast ? size_t(n) * 16 : 0);
+  L->bore_a = take(bfast ? size_t(n) * 4 : 0);
+  L->det_f = take(bfast ? size_t(d->ndet) * 8 : 0);
+  L->det_a = take(bfast ? size_t(d->ndet) * 4 : 0);
   // time-major angle-coded weights for pass 1 (stored pointing, float paths)
   L->ang_t = take(nc == 3 && pl->csr && !pl->f64 && !pl->otf ? size_t(d->ndet) * size_t(n) * 4 : 0);
   L->total = off;
@@ -1837,6 +1885,47 @@ static mm_status upload_t(ScanImpl* s, hipStream_t st) {
     MM_HIP(hipMemcpyAsync(s->ws + s->lay.corr_edges, s->d.corr_edges,
                           size_t(pl.corr_nbins + 1) * 4, hipMemcpyHostToDevice, st));
   MM_HIP(hipStreamSynchronize(st));
+  return MM_OK;
+}
+
+// Float32 copies of the boresight model and the angles of its weights; counts
+// |cos phi| or |sin phi| above 1 (the float32 pixel's error bound needs them
+// at most 1).
+__global__ void k_bore_prep(const double* __restrict__ b, const double* __restrict__ det,
+                            int64_t n, int ndet, int ny, int nx, float4* __restrict__ bf,
+                            uint32_t* __restrict__ ba, float2* __restrict__ df,
+                            uint32_t* __restrict__ da, int* __restrict__ bad) {
+  const double cy = 0.5 * double(ny - 1), cx = 0.5 * double(nx - 1);
+  int cnt = 0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += stride) {
+    const double c = b[2 * n + t], sn = b[3 * n + t];
+    bf[t] = make_float4(float(b[t] - cy), float(b[n + t] - cx), float(c), float(sn));
+    ba[t] = weight_angle(b[4 * n + t], b[5 * n + t]);
+    cnt += (fabs(c) <= 1.0 && fabs(sn) <= 1.0) ? 0 : 1;
+    if (t < ndet) {
+      df[t] = make_float2(float(det[t]), float(det[ndet + t]));
+      da[t] = weight_angle(det[2 * ndet + t], det[3 * ndet + t]);
+    }
+  }
+  if (cnt) atomicAdd(bad, cnt);
+}
+
+mm_status bore_setup(ScanImpl* s, hipStream_t st) {
+  s->bore_fast = false;
+  if (!s->plan.otf || s->plan.f64 || s->ndet > s->n) return MM_OK;
+  const Layout& L = s->lay;
+  int* bad = s->at<int>(L.misc);
+  mm_status r;
+  if ((r = fill_zero(bad, 4, st)) != MM_OK) return r;
+  hipLaunchKernelGGL(k_bore_prep, dim3(1024), dim3(256), 0, st, s->d.bore, s->d.det_off, s->n,
+                     s->ndet, s->ny, s->nx, s->at<float4>(L.bore_f), s->at<uint32_t>(L.bore_a),
+                     s->at<float2>(L.det_f), s->at<uint32_t>(L.det_a), bad);
+  MM_HIP(hipGetLastError());
+  int h = 0;
+  MM_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, st));
+  MM_HIP(hipStreamSynchronize(st));
+  s->bore_fast = (h == 0) && kBoreFast;
   return MM_OK;
 }
 

@@ -82,6 +82,7 @@ struct Layout {
   size_t csr_w;      // ngroups * G * n float2 (cos 2psi, sin 2psi), or uint32 angles
   size_t ang_tab;    // 256 float2: (cos, sin)(2 pi k / 256)
   size_t ang_t;      // ndet * n uint32: the weights as angles, time-major (pass 1)
+  size_t bore_f, bore_a, det_f, det_a;   // float32 copies of the boresight model
   size_t total;
 };
 
@@ -123,6 +124,7 @@ struct ScanImpl {
   bool circ_built = false;
   bool csr_ang = false;       // the index's weights are stored as fixed-point angles
   bool ang_t_ready = false;   // pass 1 reads the time-major angles (SRC 3)
+  bool bore_fast = false;     // pass 1 evaluates the boresight model in float32 (SRC 4)
   bool tiled_built = false;   // tiled preconditioner
   int tiled_T = 0;
   char* tiled_ws = nullptr;   // caller-owned workspace of the tiled preconditioner
@@ -158,6 +160,7 @@ mm_status filter_pipeline(ScanImpl* s, int src /*0 gather x, 1 timestream*/,
                           const void* tod, const double* x, double* y, hipStream_t st);
 mm_status binned_setup(ScanImpl* s, hipStream_t st);
 mm_status csr_setup(ScanImpl* s, hipStream_t st);
+mm_status bore_setup(ScanImpl* s, hipStream_t st);
 mm_status permute_inverse_spectrum(ScanImpl* s, hipStream_t st);
 mm_status binned_apply(ScanImpl* s, int jacobi, const double* r, double* z, hipStream_t st);
 mm_status circulant_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st);

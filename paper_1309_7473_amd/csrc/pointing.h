@@ -48,6 +48,36 @@ __device__ __forceinline__ void bore_weights(double c2p, double s2p, double c2f,
   *s = s2p * c2f + c2p * s2f;
 }
 
+// Float32 evaluation of the same pixel, for inputs Y = fl32(y_b - c_y),
+// X = fl32(x_b - c_x), c, s, dy, dx rounded to float32 from their float64
+// values.  Each rounding is at most u = 2^-24 relative; propagated through
+// ry, rx, the products and the two sums, |p32 - p64| <= u (|c_p| + 4|rx| +
+// 3|ry| + |X| + |Y| + |dx| + |dy| + |p|) on either axis (the float64
+// definition's own roundings are 2^29 times smaller), plus u|p| for the
+// float32 p + 1/2.  When p + 1/2 lies farther than twice that from an
+// integer on both axes, floor(p32 + 1/2) equals the float64 definition's
+// floor; otherwise the caller evaluates the float64 definition.  Returns
+// the pixel, -1 off the map, or -2 for "not decided".
+__device__ __forceinline__ int bore_pixel_f32(float Y, float X, float c, float s, float dy,
+                                              float dx, int ny, int nx) {
+#pragma clang fp contract(off)
+  const float cy = 0.5f * float(ny - 1), cx = 0.5f * float(nx - 1);
+  const float ry = Y + dy;
+  const float rx = X + dx;
+  const float py = (cy + s * rx) + c * ry;
+  const float px = (cx + c * rx) - s * ry;
+  const float com = 4.0f * (fabsf(rx) + fabsf(ry)) + fabsf(X) + fabsf(Y) + fabsf(dx) + fabsf(dy);
+  const float ty = 1.1920929e-07f * (cy + com + 2.0f * fabsf(py));   // 2u (...)
+  const float tx = 1.1920929e-07f * (cx + com + 2.0f * fabsf(px));
+  const float vy = py + 0.5f, vx = px + 0.5f;
+  const float fy = floorf(vy), fx = floorf(vx);
+  const float dyy = fminf(vy - fy, fy + 1.0f - vy);
+  const float dxx = fminf(vx - fx, fx + 1.0f - vx);
+  if (!(dyy > ty && dxx > tx)) return -2;
+  if (!(fy >= 0.0f && fy < float(ny) && fx >= 0.0f && fx < float(nx))) return -1;
+  return int(fy) * nx + int(fx);
+}
+
 __device__ __forceinline__ int bore_pixel_at(const Bore& bo, int d, int64_t t) {
   const int64_t n = int64_t(1) << bo.logn;
   return bore_pixel(bo.b[t], bo.b[n + t], bo.b[2 * n + t], bo.b[3 * n + t], bo.det[d],
@@ -59,6 +89,20 @@ __device__ __forceinline__ void bore_weights_at(const Bore& bo, int d, int64_t t
   const int64_t n = int64_t(1) << bo.logn;
   bore_weights(bo.det[2 * bo.ndet + d], bo.det[3 * bo.ndet + d], bo.b[4 * n + t],
                bo.b[5 * n + t], c, s);
+}
+
+// The weights (c, s) = (cos, sin)(theta) as u = theta 2^32 / 2pi mod 2^32
+// (angles then add exactly, mod 2^32).
+__device__ __forceinline__ uint32_t weight_angle(double c, double s) {
+  const double t = atan2(s, c) * (4294967296.0 / 6.283185307179586476925);
+  const int64_t q = int64_t(llrint(t));          // |t| <= 2^31
+  return uint32_t(q & 0xFFFFFFFFll);
+}
+
+// The float64 definition as an out-of-line call, for the rare samples the
+// float32 evaluation leaves undecided (keeps the caller's registers low).
+static __device__ __attribute__((noinline)) int bore_pixel_slow(Bore bo, int d, int64_t t) {
+  return bore_pixel_at(bo, d, t);
 }
 
 // Sample i = d * n + t of the whole scan: stored pointing when pix is given.
