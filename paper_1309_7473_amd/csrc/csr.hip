@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pi
                                                   int32_t* __restrict__ cursor,
                                                   int32_t* __restrict__ idx,
                                                   float2* __restrict__ w,
-                                                  uint32_t* __restrict__ ang) {
+                                                  int2* __restrict__ ia) {
   const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -140,10 +140,10 @@ __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pi
       const int64_t e = g * gsz + slot0 + (lane - h);
       idx[e] = int32_t(i - g * gsz);
       if constexpr (NC == 3) {
-        if (ang) {           // unit-norm weights: 4 B a sample
+        if (ia) {            // unit-norm weights: (index, angle) in 8 B
           double c, sn;
           sample_weights(c2, s2, bo, i, &c, &sn);
-          ang[e] = weight_angle(c, sn);
+          ia[e] = make_int2(int32_t(i - g * gsz), int32_t(weight_angle(c, sn)));
         } else if (w) {      // NULL: the gather computes the weights from the boresight model
           double c, sn;
           sample_weights(c2, s2, bo, i, &c, &sn);
@@ -203,12 +203,12 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
                        s->at<int32_t>(L.csr_idx),
                        s->plan.csr_w && !s->csr_ang ? s->at<float2>(L.csr_w)
                                                     : static_cast<float2*>(nullptr),
-                       s->csr_ang ? s->at<uint32_t>(L.csr_w) : static_cast<uint32_t*>(nullptr));
+                       s->csr_ang ? s->at<int2>(L.csr_w) : static_cast<int2*>(nullptr));
   else
     hipLaunchKernelGGL(k_csr_fill<1>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->n, total, G, npix, cnt,
                        s->at<int32_t>(L.csr_idx), static_cast<float2*>(nullptr),
-                       static_cast<uint32_t*>(nullptr));
+                       static_cast<int2*>(nullptr));
   MM_HIP(hipGetLastError());
   return MM_OK;
 }

@@ -91,7 +91,7 @@ struct PassArgs {
   const int32_t* csr_off;  // group [npix+1]
   const int32_t* csr_idx;  // group entries
   const float2* csr_w;     // group entries (I,Q,U weights)
-  const uint32_t* csr_ang; // group entries: the weights as a fixed-point angle (see below)
+  const int2* csr_ia;      // group entries: (index, weights as a fixed-point angle)
   const float2* ang_tab;   // (cos, sin)(2 pi k / 256), k < 256
   const uint32_t* ang_t;   // group base [G][n]: the weights as angles, time-major
   const float4* bore_f;    // boresight in float32: [n] (y_b - c_y, x_b - c_x, cos phi, sin phi)
@@ -1189,8 +1189,6 @@ __device__ __forceinline__ void entry_weights(const PassArgs<T, S>& a, const flo
   if constexpr (WM == 1) {
     const int d = a.det0 + (ik >> a.bo.logn);
     bore_weights_at(a.bo, d, ik & ((1 << a.bo.logn) - 1), c, sn);
-  } else if constexpr (WM == 2) {
-    angle_weights(a.csr_ang[k], tab, c, sn);
   } else {
     const float2 cs = a.csr_w[k];
     *c = double(cs.x);
@@ -1232,12 +1230,23 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll MM_RUNROLL
     for (int k = b + l; k < e; k += LPP) {
-      const int ik = a.csr_idx[k];
+      int ik;
+      uint32_t ua = 0;
+      if constexpr (WM == 2) {   // index and angle in one 8-byte load
+        const int2 r = a.csr_ia[k];
+        ik = r.x;
+        ua = uint32_t(r.y);
+      } else {
+        ik = a.csr_idx[k];
+      }
       const double uu = double(Sto<T, S>::ldr(u + ik));
       s0 += uu;
       if constexpr (NC == 3) {
         double c, sn;
-        entry_weights<T, S, NC, WM>(a, tab, k, ik, &c, &sn);
+        if constexpr (WM == 2)
+          angle_weights(ua, tab, &c, &sn);
+        else
+          entry_weights<T, S, NC, WM>(a, tab, k, ik, &c, &sn);
         s1 += c * uu;
         s2 += sn * uu;
       }
@@ -1263,7 +1272,15 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
     F2 s0{0.f, 0.f}, s1{0.f, 0.f}, s2{0.f, 0.f};
 #pragma unroll 4
     for (int k = b + l; k < e; k += LPP) {
-      const int ik = a.csr_idx[k];
+      int ik;
+      uint32_t ua = 0;
+      if constexpr (WM == 2) {
+        const int2 r = a.csr_ia[k];
+        ik = r.x;
+        ua = uint32_t(r.y);
+      } else {
+        ik = a.csr_idx[k];
+      }
       const T ut = Sto<T, S>::ldr(u + ik);
       F2 uu;
       if constexpr (sizeof(T) == 8)
@@ -1273,7 +1290,10 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
       f2_acc(s0, uu.hi, uu.lo);
       if constexpr (NC == 3) {
         double c, sn;
-        entry_weights<T, S, NC, WM>(a, tab, k, ik, &c, &sn);
+        if constexpr (WM == 2)
+          angle_weights(ua, tab, &c, &sn);
+        else
+          entry_weights<T, S, NC, WM>(a, tab, k, ik, &c, &sn);
         f2_fma_acc(s1, float(c), uu);
         f2_fma_acc(s2, float(sn), uu);
       }
@@ -1410,7 +1430,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       a.csr_w = pl.csr_w && !s->csr_ang ? s->at<float2>(s->lay.csr_w) + int64_t(gi) * G * s->n
                                         : nullptr;
       // stored angles live in the first half of the weights' region
-      a.csr_ang = s->csr_ang ? s->at<uint32_t>(s->lay.csr_w) + int64_t(gi) * G * s->n : nullptr;
+      a.csr_ia = s->csr_ang ? s->at<int2>(s->lay.csr_w) + int64_t(gi) * G * s->n : nullptr;
 
     }
     const int64_t gs = int64_t(gd) * s->n;
