@@ -807,6 +807,14 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
   const int ra = pr;
   const int rb = (pr == 0) ? (M1 >> 1) : (M1 - pr);
   const int myrow = row_of(wave);
+  auto* w = a.work + int64_t(g) * M + int64_t(myrow) * L;
+  // the row's loads are issued before the twiddle tables are built, so the
+  // two latencies overlap
+  Cx<T> v[E];
+  if constexpr (MODE != 2) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = Sto<T, S>::ld(w + lane + 64 * r);
+  }
   for (int t = threadIdx.x; t < NW * E; t += NT)
     tA[t] = a.wn(2 * int64_t(row_of(t / E)) * (int64_t(t % E) << 6));
   for (int t = threadIdx.x; t < NW * 64; t += NT) tB[t] = a.wn(2 * int64_t(row_of(t >> 6)) * (t & 63));
@@ -814,14 +822,12 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
   const int tsh = a.logLmax - LOGL;
   auto twL = [&](int m) { return a.tw[m << tsh]; };   // W_L^m, from the cached table
   Cx<T>* R = rows + wave * RS;
-  auto* w = a.work + int64_t(g) * M + int64_t(myrow) * L;
   const Cx<T> tb = tB[wave * 64 + lane];
   auto twE = [&](int m) { return twL(m << 6); };   // W_E^m = W_L^(64 m)
   // ---------------- forward: radix-E from global, then 2 x radix-8
   if constexpr (MODE != 2) {
-    Cx<T> v[E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) v[r] = Sto<T, S>::ld(w + lane + 64 * r) * (tA[wave * E + r] * tb);
+    for (int r = 0; r < E; ++r) v[r] = v[r] * (tA[wave * E + r] * tb);
     dft_regs<T, E, false>(v, twE);
 #pragma unroll
     for (int r = 0; r < E; ++r) R[pad_e<LOGE>(lane * E + r)] = v[r];
