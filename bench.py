@@ -128,7 +128,7 @@ def summarize(trace_dir, fetch_dir, write_dir, bench_log, out_dir):
     with open(os.path.join(out_dir, "hbm_traffic_iqu256.json"), "w") as fh:
         json.dump(traffic, fh, indent=1)
     lines = ["# Kernel times, iqu_256det PCG iterations (rocprofv3 --kernel-trace --stats)", "",
-             "Command (repo root, GPU box):", "",
+             "Command (from the repository root, on the MI355X):", "",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- "
              "python3 bench.py --steps 10 --warmup 2 --no-solve --no-cpu", "",
              f"Kernel source hash {bench['source_hash']}; plan {json.dumps(bench['config']['plan'])}", "",
