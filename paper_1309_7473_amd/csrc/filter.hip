@@ -774,6 +774,9 @@ __device__ __forceinline__ int pad_e(int i) {
 // place in natural order.  MODE 2: load the filtered spectrum Y, repack,
 // inverse FFT.
 template <typename T, typename S, int E, int PB, int MODE>
+#ifndef MM_P2_REV
+#define MM_P2_REV 1
+#endif
 #ifndef MM_P2W_WAVES
 #define MM_P2W_WAVES 0
 #endif
@@ -797,11 +800,15 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
   const int M = a.Mi;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int half = M1 >> 1;   // row pairs per detector
+  // blocks run from the last detector of the group to the first: pass 1
+  // wrote the last detectors last, so their rows are the likeliest to be
+  // still in the memory-side cache
+  const int bx = MM_P2_REV ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
   auto row_of = [&](int w) {
-    const int prw = (blockIdx.x * PB + (w >> 1)) % half;
+    const int prw = (bx * PB + (w >> 1)) % half;
     return (w & 1) ? ((prw == 0) ? (M1 >> 1) : (M1 - prw)) : prw;
   };
-  const int pair = blockIdx.x * PB + (wave >> 1);
+  const int pair = bx * PB + (wave >> 1);
   const int g = pair / half;
   const int pr = pair % half;
   const int ra = pr;
