@@ -115,8 +115,8 @@ __global__ void k_q_assemble(const int32_t* __restrict__ mask, const double* __r
 }
 
 // ------------------------------------------------------------ 2-D FFT
-template <bool INV>
-__global__ void __launch_bounds__(kNT) k_map_rows(Cx<double>* __restrict__ planes, int logny,
+template <bool INV, int NT, int E>
+__global__ void __launch_bounds__(NT) k_map_rows(Cx<double>* __restrict__ planes, int logny,
                                                   int lognx, int logRB, int logLmax,
                                                   const Cx<double>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -124,15 +124,15 @@ __global__ void __launch_bounds__(kNT) k_map_rows(Cx<double>* __restrict__ plane
   const int nx = 1 << lognx;
   const int cnt = nx << logRB;
   Cx<double>* base = planes + (int64_t(blockIdx.y) << (logny + lognx)) + (int64_t(blockIdx.x) * cnt);
-  for (int e = threadIdx.x; e < cnt; e += kNT) buf[e] = base[e];
+  for (int e = threadIdx.x; e < cnt; e += NT) buf[e] = base[e];
   __syncthreads();
   FftShape sh{lognx, logRB, 1, nx, false, logLmax};
-  lds_fft<double, kNT, kMapE, INV>(buf, sh, tw);
-  for (int e = threadIdx.x; e < cnt; e += kNT) base[e] = buf[e];
+  lds_fft<double, NT, E, INV>(buf, sh, tw);
+  for (int e = threadIdx.x; e < cnt; e += NT) base[e] = buf[e];
 }
 
-template <bool INV>
-__global__ void __launch_bounds__(kNT) k_map_cols(Cx<double>* __restrict__ planes, int logny,
+template <bool INV, int NT, int E>
+__global__ void __launch_bounds__(NT) k_map_cols(Cx<double>* __restrict__ planes, int logny,
                                                   int lognx, int logCB, int logLmax,
                                                   const Cx<double>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -140,14 +140,14 @@ __global__ void __launch_bounds__(kNT) k_map_cols(Cx<double>* __restrict__ plane
   const int nx = 1 << lognx, ny = 1 << logny, CB = 1 << logCB;
   Cx<double>* base = planes + (int64_t(blockIdx.y) << (logny + lognx)) + int64_t(blockIdx.x) * CB;
   const int cnt = CB * ny;
-  for (int e = threadIdx.x; e < cnt; e += kNT) {
+  for (int e = threadIdx.x; e < cnt; e += NT) {
     const int y = e >> logCB, c = e & (CB - 1);
     buf[e] = base[int64_t(y) * nx + c];
   }
   __syncthreads();
   FftShape sh{logny, logCB, CB, 1, true, logLmax};
-  lds_fft<double, kNT, kMapE, INV>(buf, sh, tw);
-  for (int e = threadIdx.x; e < cnt; e += kNT) {
+  lds_fft<double, NT, E, INV>(buf, sh, tw);
+  for (int e = threadIdx.x; e < cnt; e += NT) {
     const int y = e >> logCB, c = e & (CB - 1);
     base[int64_t(y) * nx + c] = buf[e];
   }
@@ -166,11 +166,17 @@ mm_status map_fft(ScanImpl* s, Cx<double>* planes, int nplanes, bool inv, hipStr
   return map_fft_dims(s, planes, ilog2i(s->ny), ilog2i(s->nx), nplanes, inv, st);
 }
 
-// nplanes [2^logny][2^lognx] planes (sides up to the map's)
-static mm_status map_fft_dims(ScanImpl* s, Cx<double>* planes, int logny, int lognx, int nplanes,
-                              bool inv, hipStream_t st) {
+#ifndef MM_MAP_SMALL
+#define MM_MAP_SMALL 2
+#endif
+
+// nplanes [2^logny][2^lognx] planes (sides up to the map's), with blocks of
+// NT threads holding E elements each
+template <int NT, int E>
+static mm_status map_fft_blocks(ScanImpl* s, Cx<double>* planes, int logny, int lognx,
+                                int nplanes, bool inv, hipStream_t st) {
   const int ny = 1 << logny, nx = 1 << lognx;
-  const int cap = kMapE * kNT;  // complex elements per block
+  const int cap = E * NT;  // complex elements per block
   int logRB = ilog2i(cap) - lognx;
   if (logRB > logny) logRB = logny;
   if (logRB < 0) logRB = 0;
@@ -188,15 +194,27 @@ static mm_status map_fft_dims(ScanImpl* s, Cx<double>* planes, int logny, int lo
     const dim3 gr(unsigned(ny >> logRB), unsigned(np));
     const dim3 gc(unsigned(nx >> logCB), unsigned(np));
     if (!inv) {
-      hipLaunchKernelGGL(k_map_rows<false>, gr, dim3(kNT), ldsr, st, pl, logny, lognx, logRB, logL, tw);
-      hipLaunchKernelGGL(k_map_cols<false>, gc, dim3(kNT), ldsc, st, pl, logny, lognx, logCB, logL, tw);
+      hipLaunchKernelGGL((k_map_rows<false, NT, E>), gr, dim3(NT), ldsr, st, pl, logny, lognx, logRB, logL, tw);
+      hipLaunchKernelGGL((k_map_cols<false, NT, E>), gc, dim3(NT), ldsc, st, pl, logny, lognx, logCB, logL, tw);
     } else {
-      hipLaunchKernelGGL(k_map_cols<true>, gc, dim3(kNT), ldsc, st, pl, logny, lognx, logCB, logL, tw);
-      hipLaunchKernelGGL(k_map_rows<true>, gr, dim3(kNT), ldsr, st, pl, logny, lognx, logRB, logL, tw);
+      hipLaunchKernelGGL((k_map_cols<true, NT, E>), gc, dim3(NT), ldsc, st, pl, logny, lognx, logCB, logL, tw);
+      hipLaunchKernelGGL((k_map_rows<true, NT, E>), gr, dim3(NT), ldsr, st, pl, logny, lognx, logRB, logL, tw);
     }
     MM_HIP(hipGetLastError());
   }
   return MM_OK;
+}
+
+static mm_status map_fft_dims(ScanImpl* s, Cx<double>* planes, int logny, int lognx, int nplanes,
+                              bool inv, hipStream_t st) {
+  // sides up to 1024: smaller blocks (16 or 32 KB of LDS) put more of them
+  // on the chip; larger sides need the 64 KB block
+  const int side = (logny > lognx ? logny : lognx);
+  if (MM_MAP_SMALL == 2 && side <= 10)
+    return map_fft_blocks<128, 8>(s, planes, logny, lognx, nplanes, inv, st);
+  if (MM_MAP_SMALL == 1 && side <= 11)
+    return map_fft_blocks<256, 8>(s, planes, logny, lognx, nplanes, inv, st);
+  return map_fft_blocks<kNT, kMapE>(s, planes, logny, lognx, nplanes, inv, st);
 }
 
 // ------------------------------------------------- per-wavenumber inverse
@@ -395,6 +413,141 @@ __global__ void k_circ_post(const Cx<double>* __restrict__ planes, const double*
   }
 }
 
+// ---------------------------------------------- fused apply (sides <= 1024)
+// The seven steps of the apply (Sigma^-T, forward rows, forward columns, K^-1,
+// inverse columns, inverse rows, Sigma^-1) in three kernels whose blocks hold
+// the same pixels of all NC planes: the symmetric Sigma^-1 blocks and the
+// per-wavenumber NC x NC products need every component at a pixel.  The NC
+// planes of a block are transformed together as one batch (padded to NP = 4
+// planes for I,Q,U, so that the batch count stays a power of two; the pad
+// plane is zero and never stored), 128 threads a plane.  The transforms are
+// the same Stockham stages as map_fft's, so the result is the same to the bit.
+constexpr int kFuseE = 8, kFuseCapLog = 10;   // 1024 complex elements a plane a block
+template <int NC>
+struct Fuse {
+  static constexpr int NP = NC == 3 ? 4 : 1, LOGNP = NC == 3 ? 2 : 0;
+  static constexpr int NT = (1 << kFuseCapLog) / kFuseE * NP;
+};
+
+// Sigma^-T r on RB rows, then the forward row transforms.  LDS [NP][RB][nx].
+template <int NC>
+__global__ void __launch_bounds__(Fuse<NC>::NT) k_circ_rows_pre(
+    const double* __restrict__ r, const double* __restrict__ siginv,
+    const int32_t* __restrict__ mask, int logny, int lognx, int logRB, int logLmax,
+    const Cx<double>* __restrict__ tw, Cx<double>* __restrict__ planes) {
+  constexpr int NT = Fuse<NC>::NT, NP = Fuse<NC>::NP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<double>* buf = reinterpret_cast<Cx<double>*>(smem);
+  const int nx = 1 << lognx;
+  const int npix = 1 << (logny + lognx);
+  const int cnt = nx << logRB;
+  const int p0 = blockIdx.x * cnt;
+  for (int e = threadIdx.x; e < cnt; e += NT) {
+    const int p = p0 + e;
+    const double* S = siginv + 6 * int64_t(p);
+    const bool on = mask[p] != 0;
+    if constexpr (NC == 1) {
+      buf[e] = cx(on ? S[0] * r[p] : 0.0, 0.0);
+    } else {
+      const double r0 = on ? r[p] : 0.0, r1 = on ? r[npix + p] : 0.0,
+                   r2 = on ? r[2 * npix + p] : 0.0;
+      buf[e] = cx(S[0] * r0 + S[1] * r1 + S[2] * r2, 0.0);
+      buf[cnt + e] = cx(S[1] * r0 + S[3] * r1 + S[4] * r2, 0.0);
+      buf[2 * cnt + e] = cx(S[2] * r0 + S[4] * r1 + S[5] * r2, 0.0);
+      buf[3 * cnt + e] = cx(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  FftShape sh{lognx, logRB + Fuse<NC>::LOGNP, 1, nx, false, logLmax};
+  lds_fft<double, NT, kFuseE, false>(buf, sh, tw);
+  for (int e = threadIdx.x; e < NC * cnt; e += NT) {
+    const int a = e / cnt, i = e - a * cnt;
+    planes[int64_t(a) * npix + p0 + i] = buf[e];
+  }
+  (void)NP;
+}
+
+// CB columns: forward column transforms, scale * K^-1(k) per wavenumber,
+// inverse column transforms.  LDS [ny][NP][CB]: one batch of NP * CB columns.
+template <int NC>
+__global__ void __launch_bounds__(Fuse<NC>::NT) k_circ_cols_kmul(
+    Cx<double>* __restrict__ planes, const Cx<double>* __restrict__ kinv, int logny, int lognx,
+    int logCB, int logLmax, const Cx<double>* __restrict__ tw, double scale) {
+  constexpr int NT = Fuse<NC>::NT, NP = Fuse<NC>::NP, LOGNP = Fuse<NC>::LOGNP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<double>* buf = reinterpret_cast<Cx<double>*>(smem);
+  const int nx = 1 << lognx, CB = 1 << logCB;
+  const int npix = 1 << (logny + lognx);
+  const int logW = logCB + LOGNP;             // LDS row: NP * CB elements
+  const int tot = 1 << (logny + logW);
+  const int x0 = blockIdx.x * CB;
+  for (int e = threadIdx.x; e < tot; e += NT) {
+    const int y = e >> logW, a = (e >> logCB) & (NP - 1), c = e & (CB - 1);
+    buf[e] = a < NC ? planes[int64_t(a) * npix + int64_t(y) * nx + x0 + c] : cx(0.0, 0.0);
+  }
+  __syncthreads();
+  FftShape sh{logny, logW, 1 << logW, 1, true, logLmax};
+  lds_fft<double, NT, kFuseE, false>(buf, sh, tw);
+  for (int e = threadIdx.x; e < (tot >> LOGNP); e += NT) {
+    const int y = e >> logCB, c = e & (CB - 1);
+    const int64_t k = int64_t(y) * nx + x0 + c;
+    const Cx<double>* Ki = kinv + k * NC * NC;
+    const int b0 = (y << logW) + c;
+    Cx<double> u[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) u[a] = buf[b0 + a * CB];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      Cx<double> t = cx(0.0, 0.0);
+#pragma unroll
+      for (int b = 0; b < NC; ++b) t = t + Ki[a * NC + b] * u[b];
+      buf[b0 + a * CB] = scale * t;
+    }
+  }
+  __syncthreads();
+  lds_fft<double, NT, kFuseE, true>(buf, sh, tw);
+  for (int e = threadIdx.x; e < tot; e += NT) {
+    const int y = e >> logW, a = (e >> logCB) & (NP - 1), c = e & (CB - 1);
+    if (a < NC) planes[int64_t(a) * npix + int64_t(y) * nx + x0 + c] = buf[e];
+  }
+}
+
+// inverse row transforms on RB rows, then Sigma^-1 on the real parts.
+// LDS [NP][RB][nx].
+template <int NC>
+__global__ void __launch_bounds__(Fuse<NC>::NT) k_circ_rows_post(
+    const Cx<double>* __restrict__ planes, const double* __restrict__ siginv,
+    const int32_t* __restrict__ mask, int logny, int lognx, int logRB, int logLmax,
+    const Cx<double>* __restrict__ tw, double* __restrict__ z) {
+  constexpr int NT = Fuse<NC>::NT, NP = Fuse<NC>::NP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<double>* buf = reinterpret_cast<Cx<double>*>(smem);
+  const int nx = 1 << lognx;
+  const int npix = 1 << (logny + lognx);
+  const int cnt = nx << logRB;
+  const int p0 = blockIdx.x * cnt;
+  for (int e = threadIdx.x; e < NP * cnt; e += NT) {
+    const int a = e / cnt, i = e - a * cnt;
+    buf[e] = a < NC ? planes[int64_t(a) * npix + p0 + i] : cx(0.0, 0.0);
+  }
+  __syncthreads();
+  FftShape sh{lognx, logRB + Fuse<NC>::LOGNP, 1, nx, false, logLmax};
+  lds_fft<double, NT, kFuseE, true>(buf, sh, tw);
+  for (int e = threadIdx.x; e < cnt; e += NT) {
+    const int p = p0 + e;
+    const double* S = siginv + 6 * int64_t(p);
+    const bool on = mask[p] != 0;
+    if constexpr (NC == 1) {
+      z[p] = on ? S[0] * buf[e].x : 0.0;
+    } else {
+      const double v0 = buf[e].x, v1 = buf[cnt + e].x, v2 = buf[2 * cnt + e].x;
+      z[p] = on ? S[0] * v0 + S[1] * v1 + S[2] * v2 : 0.0;
+      z[npix + p] = on ? S[1] * v0 + S[3] * v1 + S[4] * v2 : 0.0;
+      z[2 * int64_t(npix) + p] = on ? S[2] * v0 + S[4] * v1 + S[5] * v2 : 0.0;
+    }
+  }
+}
+
 // ------------------------------------------------------------ host
 struct Misc {
   unsigned long long ref_key;
@@ -481,10 +634,38 @@ mm_status circulant_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st) 
   return s->nc == 3 ? build_t<3>(s, o, st) : build_t<1>(s, o, st);
 }
 
+#ifndef MM_CIRC_FUSED
+#define MM_CIRC_FUSED 1
+#endif
+
 template <int NC>
 static mm_status apply_t(ScanImpl* s, const double* r, double* z, hipStream_t st) {
   const Layout& L = s->lay;
   const int npix = s->npix;
+  const int logny = ilog2i(s->ny), lognx = ilog2i(s->nx);
+  constexpr int kCapLog = kFuseCapLog;
+  constexpr int NP = Fuse<NC>::NP, NT = Fuse<NC>::NT;
+  if (MM_CIRC_FUSED && logny <= kCapLog && lognx <= kCapLog && (1 << logny) == s->ny &&
+      (1 << lognx) == s->nx) {
+    const int logRB = (kCapLog - lognx < logny) ? kCapLog - lognx : logny;
+    const int logCB = (kCapLog - logny < lognx) ? kCapLog - logny : lognx;
+    const size_t lds_r = size_t(NP) * (size_t(s->nx) << logRB) * sizeof(Cx<double>);
+    const size_t lds_c = size_t(NP) * (size_t(s->ny) << logCB) * sizeof(Cx<double>);
+    const Cx<double>* tw = s->at<Cx<double>>(L.tw_map);
+    const int logL = s->plan.logMapL;
+    Cx<double>* planes = s->at<Cx<double>>(L.planes);
+    hipLaunchKernelGGL(k_circ_rows_pre<NC>, dim3(unsigned(s->ny >> logRB)), dim3(NT), lds_r,
+                       st, r, s->at<double>(L.siginv), s->at<int32_t>(L.mask), logny, lognx,
+                       logRB, logL, tw, planes);
+    hipLaunchKernelGGL(k_circ_cols_kmul<NC>, dim3(unsigned(s->nx >> logCB)), dim3(NT),
+                       lds_c, st, planes, s->at<Cx<double>>(L.kinv), logny, lognx, logCB, logL,
+                       tw, 1.0 / double(npix));
+    hipLaunchKernelGGL(k_circ_rows_post<NC>, dim3(unsigned(s->ny >> logRB)), dim3(NT),
+                       lds_r, st, planes, s->at<double>(L.siginv), s->at<int32_t>(L.mask), logny,
+                       lognx, logRB, logL, tw, z);
+    MM_HIP(hipGetLastError());
+    return MM_OK;
+  }
   const dim3 g((npix + 255) / 256), b(256);
   Cx<double>* planes = s->at<Cx<double>>(L.planes);
   hipLaunchKernelGGL(k_circ_pre<NC>, g, b, 0, st, r, s->at<double>(L.siginv),
