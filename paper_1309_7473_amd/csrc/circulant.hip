@@ -421,7 +421,8 @@ __global__ void k_circ_post(const Cx<double>* __restrict__ planes, const double*
 // planes of a block are transformed together as one batch (padded to NP = 4
 // planes for I,Q,U, so that the batch count stays a power of two; the pad
 // plane is zero and never stored), 128 threads a plane.  The transforms are
-// the same Stockham stages as map_fft's, so the result is the same to the bit.
+// the same Stockham stages as map_fft's; results agree with the seven-kernel
+// path to rounding (the compiler may fuse multiply-adds differently).
 constexpr int kFuseE = 8, kFuseCapLog = 10;   // 1024 complex elements a plane a block
 template <int NC>
 struct Fuse {
