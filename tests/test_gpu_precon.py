@@ -181,3 +181,25 @@ def test_pcg_reports_noconv_and_breakdown():
     bn[np.flatnonzero(np.tile(pair.mask, 3))[0]] = np.nan
     r = pair.g.pcg("binned", pair.dev(bn), tol=1e-6, maxiter=5)
     assert not r["converged"] and r["status"] == mm.MM_EBREAKDOWN
+
+
+@pytest.mark.parametrize("shape", [(2048, 8), (8, 2048)], ids=["tall", "wide"])
+def test_circulant_apply_long_side(shape):
+    """A map side above 1024 takes the seven-kernel circulant apply (the
+    three-kernel one covers sides up to 1024): both orientations against
+    the oracle, float64 path."""
+    ny, nx = shape
+    inp = small_raster(ncomp=3, ny=ny, nx=nx, ndet=3, sweeps=8 if ny < nx else None,
+                       diameter=3.0)
+    pair = Pair(inp, tod_dtype="f64")
+    assert pair.mask.sum() > 0
+    Mo = oracle.CirculantPrecon(pair.o, pair.mask, pair.B, sigma_taper=3.0)
+    pair.g.build_precon("circulant", sigma=3.0)
+    info = pair.g.info()
+    assert info["ref_pixel"] == Mo.ref
+    assert info["n_floored"] == Mo.n_floored
+    r = pair.masked_random(11)
+    got = pair.host(pair.g.apply_precon("circulant", pair.dev(r)))
+    e = rel(got, Mo(r))
+    print(f"[circulant {ny}x{nx}] {e:.3e} active={int(pair.mask.sum())}", flush=True)
+    assert e <= 1e-9
