@@ -166,10 +166,6 @@ mm_status map_fft(ScanImpl* s, Cx<double>* planes, int nplanes, bool inv, hipStr
   return map_fft_dims(s, planes, ilog2i(s->ny), ilog2i(s->nx), nplanes, inv, st);
 }
 
-#ifndef MM_MAP_SMALL
-#define MM_MAP_SMALL 2
-#endif
-
 // nplanes [2^logny][2^lognx] planes (sides up to the map's), with blocks of
 // NT threads holding E elements each
 template <int NT, int E>
@@ -210,10 +206,7 @@ static mm_status map_fft_dims(ScanImpl* s, Cx<double>* planes, int logny, int lo
   // sides up to 1024: smaller blocks (16 or 32 KB of LDS) put more of them
   // on the chip; larger sides need the 64 KB block
   const int side = (logny > lognx ? logny : lognx);
-  if (MM_MAP_SMALL == 2 && side <= 10)
-    return map_fft_blocks<128, 8>(s, planes, logny, lognx, nplanes, inv, st);
-  if (MM_MAP_SMALL == 1 && side <= 11)
-    return map_fft_blocks<256, 8>(s, planes, logny, lognx, nplanes, inv, st);
+  if (side <= 10) return map_fft_blocks<128, 8>(s, planes, logny, lognx, nplanes, inv, st);
   return map_fft_blocks<kNT, kMapE>(s, planes, logny, lognx, nplanes, inv, st);
 }
 
