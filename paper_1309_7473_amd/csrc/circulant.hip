@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(Fuse<NC>::NT) k_circ_rows_pre(
     const double* __restrict__ r, const double* __restrict__ siginv,
     const int32_t* __restrict__ mask, int logny, int lognx, int logRB, int logLmax,
     const Cx<double>* __restrict__ tw, Cx<double>* __restrict__ planes) {
-  constexpr int NT = Fuse<NC>::NT, NP = Fuse<NC>::NP;
+  constexpr int NT = Fuse<NC>::NT;
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<double>* buf = reinterpret_cast<Cx<double>*>(smem);
   const int nx = 1 << lognx;
@@ -458,7 +458,6 @@ __global__ void __launch_bounds__(Fuse<NC>::NT) k_circ_rows_pre(
     const int a = e / cnt, i = e - a * cnt;
     planes[int64_t(a) * npix + p0 + i] = buf[e];
   }
-  (void)NP;
 }
 
 // CB columns: forward column transforms, scale * K^-1(k) per wavenumber,
