@@ -167,10 +167,11 @@ mm_status map_fft(ScanImpl* s, Cx<double>* planes, int nplanes, bool inv, hipStr
 }
 
 // nplanes [2^logny][2^lognx] planes (sides up to the map's), with blocks of
-// NT threads holding E elements each
+// NT threads holding E elements each; parts: 1 the row transforms, 2 the
+// column transforms, 3 both
 template <int NT, int E>
 static mm_status map_fft_blocks(ScanImpl* s, Cx<double>* planes, int logny, int lognx,
-                                int nplanes, bool inv, hipStream_t st) {
+                                int nplanes, bool inv, hipStream_t st, int parts = 3) {
   const int ny = 1 << logny, nx = 1 << lognx;
   const int cap = E * NT;  // complex elements per block
   int logRB = ilog2i(cap) - lognx;
@@ -190,11 +191,15 @@ static mm_status map_fft_blocks(ScanImpl* s, Cx<double>* planes, int logny, int 
     const dim3 gr(unsigned(ny >> logRB), unsigned(np));
     const dim3 gc(unsigned(nx >> logCB), unsigned(np));
     if (!inv) {
-      hipLaunchKernelGGL((k_map_rows<false, NT, E>), gr, dim3(NT), ldsr, st, pl, logny, lognx, logRB, logL, tw);
-      hipLaunchKernelGGL((k_map_cols<false, NT, E>), gc, dim3(NT), ldsc, st, pl, logny, lognx, logCB, logL, tw);
+      if (parts & 1)
+        hipLaunchKernelGGL((k_map_rows<false, NT, E>), gr, dim3(NT), ldsr, st, pl, logny, lognx, logRB, logL, tw);
+      if (parts & 2)
+        hipLaunchKernelGGL((k_map_cols<false, NT, E>), gc, dim3(NT), ldsc, st, pl, logny, lognx, logCB, logL, tw);
     } else {
-      hipLaunchKernelGGL((k_map_cols<true, NT, E>), gc, dim3(NT), ldsc, st, pl, logny, lognx, logCB, logL, tw);
-      hipLaunchKernelGGL((k_map_rows<true, NT, E>), gr, dim3(NT), ldsr, st, pl, logny, lognx, logRB, logL, tw);
+      if (parts & 2)
+        hipLaunchKernelGGL((k_map_cols<true, NT, E>), gc, dim3(NT), ldsc, st, pl, logny, lognx, logCB, logL, tw);
+      if (parts & 1)
+        hipLaunchKernelGGL((k_map_rows<true, NT, E>), gr, dim3(NT), ldsr, st, pl, logny, lognx, logRB, logL, tw);
     }
     MM_HIP(hipGetLastError());
   }
@@ -471,6 +476,9 @@ __global__ void __launch_bounds__(Fuse<NC>::NT) k_circ_cols_kmul(
   Cx<double>* buf = reinterpret_cast<Cx<double>*>(smem);
   const int nx = 1 << lognx, CB = 1 << logCB;
   const int npix = 1 << (logny + lognx);
+  // blockIdx.y: one of a batch of NC-plane sets (the tiles of the tiled apply)
+  planes += int64_t(blockIdx.y) * NC * npix;
+  kinv += int64_t(blockIdx.y) * NC * NC * npix;
   const int logW = logCB + LOGNP;             // LDS row: NP * CB elements
   const int tot = 1 << (logny + logW);
   const int x0 = blockIdx.x * CB;
@@ -953,11 +961,24 @@ static mm_status tiled_apply_t(ScanImpl* s, const double* rv, double* z, hipStre
   hipLaunchKernelGGL(k_tile_gather<NC>, gt, b, 0, st, u, ny, nx, logT, ntx, swy, swx, tp);
   MM_HIP(hipGetLastError());
   mm_status r;
-  if ((r = map_fft_dims(s, tp, logT, logT, nt * NC, false, st)) != MM_OK) return r;
-  hipLaunchKernelGGL(k_circ_kmul<NC>, gt, b, 0, st, tp,
-                     reinterpret_cast<const Cx<double>*>(tws + TL.kinv), TT, 1.0);
-  MM_HIP(hipGetLastError());
-  if ((r = map_fft_dims(s, tp, logT, logT, nt * NC, true, st)) != MM_OK) return r;
+  const Cx<double>* kinv_t = reinterpret_cast<const Cx<double>*>(tws + TL.kinv);
+  if (MM_CIRC_FUSED && logT <= kFuseCapLog && nt <= 65535) {
+    // row transforms, then the three-step column kernel of the circulant
+    // apply with one grid row per tile, then the inverse row transforms
+    if ((r = map_fft_blocks<128, 8>(s, tp, logT, logT, nt * NC, false, st, 1)) != MM_OK) return r;
+    const int logCB = (kFuseCapLog - logT < logT) ? kFuseCapLog - logT : logT;
+    const size_t lds_c = size_t(Fuse<NC>::NP) * (size_t(T) << logCB) * sizeof(Cx<double>);
+    hipLaunchKernelGGL(k_circ_cols_kmul<NC>, dim3(unsigned(T >> logCB), unsigned(nt)),
+                       dim3(Fuse<NC>::NT), lds_c, st, tp, kinv_t, logT, logT, logCB,
+                       s->plan.logMapL, s->at<Cx<double>>(s->lay.tw_map), 1.0);
+    MM_HIP(hipGetLastError());
+    if ((r = map_fft_blocks<128, 8>(s, tp, logT, logT, nt * NC, true, st, 1)) != MM_OK) return r;
+  } else {
+    if ((r = map_fft_dims(s, tp, logT, logT, nt * NC, false, st)) != MM_OK) return r;
+    hipLaunchKernelGGL(k_circ_kmul<NC>, gt, b, 0, st, tp, kinv_t, TT, 1.0);
+    MM_HIP(hipGetLastError());
+    if ((r = map_fft_dims(s, tp, logT, logT, nt * NC, true, st)) != MM_OK) return r;
+  }
   hipLaunchKernelGGL(k_tile_post<NC>, g, b, 0, st, tp, s->at<double>(s->lay.siginv),
                      s->at<int32_t>(s->lay.mask), ny, nx, logT, nty, ntx, swy, swx, z);
   MM_HIP(hipGetLastError());
