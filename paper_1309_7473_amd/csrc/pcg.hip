@@ -135,15 +135,28 @@ __global__ void k_mask_vec(double* __restrict__ x, const int32_t* __restrict__ m
   for (int a = 0; a < nc; ++a) x[int64_t(a) * npix + p] = 0.0;
 }
 
-// after s = A p: alpha = rho / p.s
-__global__ void k_fin_ps(const double* __restrict__ part, int nb, PcgDev* st) {
+// alpha = rho / p.s from the p.s partials (every block sums them in the same
+// order, so all agree; block 0 records alpha, or the breakdown), then
+// x += alpha p ; r -= alpha s ; partial r.r into part_rr (a buffer other
+// than part_ps, which the other blocks may still be reading)
+template <bool CF>
+__global__ void __launch_bounds__(256) k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ s, int64_t n,
+                                                   PcgDev* st, const double* part_ps, int nb,
+                                                   double* __restrict__ part_rr) {
+  if (st->done) return;   // uniform: set only by earlier kernels, or below when every block returns
   __shared__ double sm[32];
-  double v[2];
-  sum_partials(part, nb, v, sm, st->cf);
-  if (threadIdx.x == 0 && !st->done) {
-    const double ps = v[0], rho = st->rho;
+  __shared__ double ps_all;
+  double ps2[2];
+  sum_partials(part_ps, nb, ps2, sm, st->cf);   // the total is in thread 0
+  if (threadIdx.x == 0) ps_all = ps2[0];
+  __syncthreads();
+  const double ps = ps_all, rho = st->rho;
+  const bool bad = !(ps > 0.0) || !(rho > 0.0) || !isfinite(ps) || !isfinite(rho);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->ps = ps;
-    if (!(ps > 0.0) || !(rho > 0.0) || !isfinite(ps) || !isfinite(rho)) {
+    if (bad) {
       st->breakdown = 1;
       st->done = 1;
       st->alpha = 0.0;
@@ -151,17 +164,8 @@ __global__ void k_fin_ps(const double* __restrict__ part, int nb, PcgDev* st) {
       st->alpha = rho / ps;
     }
   }
-}
-
-// x += alpha p ; r -= alpha s ; partial r.r
-template <bool CF>
-__global__ void __launch_bounds__(256) k_update_xr(double* __restrict__ x, double* __restrict__ r,
-                                                   const double* __restrict__ p,
-                                                   const double* __restrict__ s, int64_t n,
-                                                   const PcgDev* __restrict__ st,
-                                                   double* __restrict__ part) {
-  if (st->done) return;
-  const double alpha = st->alpha;
+  if (bad) return;
+  const double alpha = rho / ps;
   Acc2<CF> v;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
@@ -170,7 +174,7 @@ __global__ void __launch_bounds__(256) k_update_xr(double* __restrict__ x, doubl
     r[i] = ri;
     v.add_prod(0, ri, ri);
   }
-  v.store(part);
+  v.store(part_rr);
 }
 
 __global__ void k_fin_rr(const double* __restrict__ part, int nb, PcgDev* st, double* hist,
@@ -320,12 +324,14 @@ static mm_status pcg_iteration_launches(ScanImpl* s, int precon, double* x, hipS
   // s = A p
   if ((rc = filter_pipeline(s, 0, nullptr, p, sv, st)) != MM_OK) return rc;
   dot(p, sv);
-  hipLaunchKernelGGL(k_fin_ps, dim3(1), bb, 0, st, part, nb, dev);
+  // alpha is formed inside the update (no separate finalisation launch); its
+  // r.r partials go to the second half of the partials region
+  double* part_rr = part + 2 * kMaxPartials;
   if (cf)
-    hipLaunchKernelGGL(k_update_xr<true>, gb, bb, 0, st, x, r, p, sv, N, dev, part);
+    hipLaunchKernelGGL(k_update_xr<true>, gb, bb, 0, st, x, r, p, sv, N, dev, part, nb, part_rr);
   else
-    hipLaunchKernelGGL(k_update_xr<false>, gb, bb, 0, st, x, r, p, sv, N, dev, part);
-  hipLaunchKernelGGL(k_fin_rr, dim3(1), bb, 0, st, part, nb, dev, hist, kHistCap);
+    hipLaunchKernelGGL(k_update_xr<false>, gb, bb, 0, st, x, r, p, sv, N, dev, part, nb, part_rr);
+  hipLaunchKernelGGL(k_fin_rr, dim3(1), bb, 0, st, part_rr, nb, dev, hist, kHistCap);
   if ((rc = apply_precon(s, precon, r, z, st)) != MM_OK) return rc;
   dot(r, z);
   hipLaunchKernelGGL(k_fin_rz, dim3(1), bb, 0, st, part, nb, dev);
