@@ -6,8 +6,10 @@
 //          stop when ||r|| <= tol ||b||;  z = M r;  rho' = r.z;
 //          beta = rho' / rho;  p = z + beta p
 //
-// Dot products are two-kernel reductions with a fixed summation order (block
-// partials, then one block), so a solve is bit-reproducible.  Under
+// Dot products are two-step reductions with a fixed summation order (block
+// partials, then a 256-thread sum of the partials: in a one-block kernel, or,
+// for p.s, redundantly in every block of the x/r update), so a solve is
+// bit-reproducible.  Under
 // MM_ACC_F32X2 (template CF) the products and sums are compensated float32
 // pairs: each double is split into hi + lo floats, products take their fma
 // error, sums are error-free, and a block partial is stored as (hi, lo) in
