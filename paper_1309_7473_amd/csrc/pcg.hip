@@ -8,8 +8,8 @@
 //
 // Dot products are two-step reductions with a fixed summation order (block
 // partials, then a 256-thread sum of the partials: in a one-block kernel, or,
-// for p.s, redundantly in every block of the x/r update), so a solve is
-// bit-reproducible.  Under
+// for p.s and r.z, redundantly in every block of the x/r and p updates that
+// consume them), so a solve is bit-reproducible.  Under
 // MM_ACC_F32X2 (template CF) the products and sums are compensated float32
 // pairs: each double is split into hi + lo floats, products take their fma
 // error, sums are error-free, and a block partial is stored as (hi, lo) in
@@ -127,7 +127,7 @@ __global__ void k_fin_rho0(const double* __restrict__ part, int nb, PcgDev* st) 
   __shared__ double sm[32];
   double v[2];
   sum_partials(part, nb, v, sm, st->cf);
-  if (threadIdx.x == 0) st->rho = v[0];
+  if (threadIdx.x == 0) st->rho = st->rz = v[0];
 }
 
 __global__ void k_mask_vec(double* __restrict__ x, const int32_t* __restrict__ mask, int npix,
@@ -154,10 +154,12 @@ __global__ void __launch_bounds__(256) k_update_xr(double* __restrict__ x, doubl
   sum_partials(part_ps, nb, ps2, sm, st->cf);   // the total is in thread 0
   if (threadIdx.x == 0) ps_all = ps2[0];
   __syncthreads();
-  const double ps = ps_all, rho = st->rho;
+  // rho of this iteration: the last r.z (set by the p update or the start)
+  const double ps = ps_all, rho = st->rz;
   const bool bad = !(ps > 0.0) || !(rho > 0.0) || !isfinite(ps) || !isfinite(rho);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->ps = ps;
+    st->rho = rho;   // read by the history and by the p update's beta
     if (bad) {
       st->breakdown = 1;
       st->done = 1;
@@ -204,24 +206,26 @@ __global__ void k_fin_rr(const double* __restrict__ part, int nb, PcgDev* st, do
   }
 }
 
-// rho' = r.z ; beta = rho'/rho
-__global__ void k_fin_rz(const double* __restrict__ part, int nb, PcgDev* st) {
-  if (st->done) return;
-  __shared__ double sm[32];
-  double v[2];
-  sum_partials(part, nb, v, sm, st->cf);
-  if (threadIdx.x == 0) {
-    const double rz = v[0];
-    st->rz = rz;
-    st->beta = rz / st->rho;
-    st->rho = rz;
-  }
-}
-
+// rho' = r.z from the r.z partials (every block sums them in the same order),
+// beta = rho' / rho, p = z + beta p.  Block 0 records rho' in rz and beta; rho
+// itself is left for the next x/r update to set, since the other blocks read
+// it here.
 __global__ void __launch_bounds__(256) k_update_p(double* __restrict__ p, const double* __restrict__ z,
-                                                  int64_t n, const PcgDev* __restrict__ st) {
-  if (st->done) return;
-  const double beta = st->beta;
+                                                  int64_t n, PcgDev* st, const double* part_rz,
+                                                  int nb) {
+  if (st->done) return;   // uniform: set only by earlier kernels
+  __shared__ double sm[32];
+  __shared__ double rz_all;
+  double v[2];
+  sum_partials(part_rz, nb, v, sm, st->cf);   // the total is in thread 0
+  if (threadIdx.x == 0) rz_all = v[0];
+  __syncthreads();
+  const double rz = rz_all;
+  const double beta = rz / st->rho;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rz = rz;
+    st->beta = beta;
+  }
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x)
     p[i] = z[i] + beta * p[i];
@@ -336,8 +340,7 @@ static mm_status pcg_iteration_launches(ScanImpl* s, int precon, double* x, hipS
   hipLaunchKernelGGL(k_fin_rr, dim3(1), bb, 0, st, part_rr, nb, dev, hist, kHistCap);
   if ((rc = apply_precon(s, precon, r, z, st)) != MM_OK) return rc;
   dot(r, z);
-  hipLaunchKernelGGL(k_fin_rz, dim3(1), bb, 0, st, part, nb, dev);
-  hipLaunchKernelGGL(k_update_p, gb, bb, 0, st, p, z, N, dev);
+  hipLaunchKernelGGL(k_update_p, gb, bb, 0, st, p, z, N, dev, part, nb);
   MM_HIP(hipGetLastError());
   return MM_OK;
 }
