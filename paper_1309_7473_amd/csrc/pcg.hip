@@ -7,9 +7,10 @@
 //          beta = rho' / rho;  p = z + beta p
 //
 // Dot products are two-step reductions with a fixed summation order (block
-// partials, then a 256-thread sum of the partials: in a one-block kernel, or,
-// for p.s and r.z, redundantly in every block of the x/r and p updates that
-// consume them), so a solve is bit-reproducible.  Under
+// partials, then a 256-thread sum of the partials: for p.s and r.z
+// redundantly in every block of the x/r and p updates that consume them, for
+// ||r||^2 in block 0 of the next dot kernel, at the start in one-block
+// kernels), so a solve is bit-reproducible.  Under
 // MM_ACC_F32X2 (template CF) the products and sums are compensated float32
 // pairs: each double is split into hi + lo floats, products take their fma
 // error, sums are error-free, and a block partial is stored as (hi, lo) in
@@ -181,9 +182,11 @@ __global__ void __launch_bounds__(256) k_update_xr(double* __restrict__ x, doubl
   v.store(part_rr);
 }
 
-__global__ void k_fin_rr(const double* __restrict__ part, int nb, PcgDev* st, double* hist,
-                         int hist_cap) {
-  if (st->done) return;
+// ||r||^2 from the x/r update's partials: the iteration count, the history
+// and the convergence test.  Run by one block (all its threads).
+__device__ __forceinline__ void fin_rr(const double* part, int nb, PcgDev* st, double* hist,
+                                       int hist_cap) {
+  if (st->done) return;   // read by every thread before thread 0 can change it
   __shared__ double sm[32];
   double v[2];
   sum_partials(part, nb, v, sm, st->cf);
@@ -204,6 +207,22 @@ __global__ void k_fin_rr(const double* __restrict__ part, int nb, PcgDev* st, do
       st->done = 1;
     }
   }
+}
+
+// r.z partials of the p update, with block 0 first finishing ||r||^2 (the
+// iteration's bookkeeping) from the x/r update's partials
+template <bool CF>
+__global__ void __launch_bounds__(256) k_dot_rz(const double* __restrict__ r,
+                                                const double* __restrict__ z, int64_t n,
+                                                double* __restrict__ part, PcgDev* st,
+                                                const double* part_rr, int nb, double* hist,
+                                                int hist_cap) {
+  if (blockIdx.x == 0) fin_rr(part_rr, nb, st, hist, hist_cap);
+  Acc2<CF> v;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    v.add_prod(0, r[i], z[i]);
+  v.store(part);
 }
 
 // rho' = r.z from the r.z partials (every block sums them in the same order),
@@ -337,9 +356,15 @@ static mm_status pcg_iteration_launches(ScanImpl* s, int precon, double* x, hipS
     hipLaunchKernelGGL(k_update_xr<true>, gb, bb, 0, st, x, r, p, sv, N, dev, part, nb, part_rr);
   else
     hipLaunchKernelGGL(k_update_xr<false>, gb, bb, 0, st, x, r, p, sv, N, dev, part, nb, part_rr);
-  hipLaunchKernelGGL(k_fin_rr, dim3(1), bb, 0, st, part_rr, nb, dev, hist, kHistCap);
   if ((rc = apply_precon(s, precon, r, z, st)) != MM_OK) return rc;
-  dot(r, z);
+  // r.z, with ||r||^2's bookkeeping in its block 0 (nothing between the x/r
+  // update and here reads it)
+  if (cf)
+    hipLaunchKernelGGL(k_dot_rz<true>, gb, bb, 0, st, r, z, N, part, dev, part_rr, nb, hist,
+                       kHistCap);
+  else
+    hipLaunchKernelGGL(k_dot_rz<false>, gb, bb, 0, st, r, z, N, part, dev, part_rr, nb, hist,
+                       kHistCap);
   hipLaunchKernelGGL(k_update_p, gb, bb, 0, st, p, z, N, dev, part, nb);
   MM_HIP(hipGetLastError());
   return MM_OK;
