@@ -112,6 +112,8 @@ struct PassArgs {
   int npix;
   int logM, logM1, logM2, logC, logLmax;
   T scale;              // 1/M
+  double* y_out;        // non-null on the last group's gather: write acc + this
+                        // group's sums to y ([ncomp][npix], zeros off the mask)
 };
 
 // Inter-detector correlated inverse noise (pass 2 in three steps).
@@ -1235,7 +1237,11 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
     chunk = (blockIdx.x & 7) * int(gridDim.x >> 3) + (blockIdx.x >> 3);
   const int p = chunk * (256 / LPP) + sub;
   if (p >= a.npix) return;            // whole 16-lane groups leave together
-  if (!a.mask[p]) return;
+  if (!a.mask[p]) {
+    if (a.y_out && l == 0)
+      for (int c = 0; c < NC; ++c) a.y_out[int64_t(c) * a.npix + p] = 0.0;
+    return;
+  }
   // the pass buffer read as packed reals: sample 2j is Re z[j], 2j+1 is Im z[j]
   const auto* u = reinterpret_cast<const typename Sto<T, S>::R*>(a.work);
   const int b = a.csr_off[p], e = a.csr_off[p + 1];
@@ -1274,10 +1280,18 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
     }
     if (l == 0) {
       double* d = a.acc + 4 * int64_t(p);
-      d[0] += s0;
-      if constexpr (NC == 3) {
-        d[1] += s1;
-        d[2] += s2;
+      if (a.y_out) {
+        a.y_out[p] = d[0] + s0;
+        if constexpr (NC == 3) {
+          a.y_out[a.npix + int64_t(p)] = d[1] + s1;
+          a.y_out[2 * int64_t(a.npix) + p] = d[2] + s2;
+        }
+      } else {
+        d[0] += s0;
+        if constexpr (NC == 3) {
+          d[1] += s1;
+          d[2] += s2;
+        }
       }
     }
   } else {
@@ -1395,6 +1409,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
   const Plan& pl = s->plan;
   const int M = int(s->n / 2);
   A a;
+  a.y_out = nullptr;
   a.Mi = M;
   a.M1i = pl.M1;
   a.mix_code = pl.mix_code;
@@ -1444,7 +1459,9 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
                                         : nullptr;
       // stored angles live in the first half of the weights' region
       a.csr_ia = s->csr_ang ? s->at<int2>(s->lay.csr_w) + int64_t(gi) * G * s->n : nullptr;
-
+      // the last group's gather writes the result itself (float64 sums only)
+      a.y_out = (d0 + G >= s->ndet && !pl.acc32) ? s->fuse_y : nullptr;
+      if (a.y_out) s->fused_y = true;
     }
     const int64_t gs = int64_t(gd) * s->n;
     hipEvent_t tok;
@@ -1620,11 +1637,16 @@ mm_status filter_pipeline(ScanImpl* s, int src, const void* tod, const double* x
     hipLaunchKernelGGL(k_zero_acc, grd, blk, 0, st, acc, npix);
   }
   MM_HIP(hipGetLastError());
+  s->fuse_y = y;
+  s->fused_y = false;
   mm_status r = s->plan.f64    ? run_pipeline<double, double>(s, src, tod, st)
                 : s->plan.bf16 ? run_pipeline<float, Bf16>(s, src, tod, st)
                                : run_pipeline<float, float>(s, src, tod, st);
+  s->fuse_y = nullptr;
   if (r != MM_OK) return r;
-  hipLaunchKernelGGL(k_epilogue, grd, blk, 0, st, acc, mask, y, npix, s->nc, s->plan.acc32 ? 1 : 0);
+  if (!s->fused_y)   // otherwise the last group's gather wrote y
+    hipLaunchKernelGGL(k_epilogue, grd, blk, 0, st, acc, mask, y, npix, s->nc,
+                       s->plan.acc32 ? 1 : 0);
   MM_HIP(hipGetLastError());
   prof_end(s, st, tok, kProfApplyA, int64_t(s->ndet) * s->n);
   return MM_OK;

@@ -124,6 +124,8 @@ struct ScanImpl {
   bool circ_built = false;
   bool csr_ang = false;       // the index's weights are stored as fixed-point angles
   bool ang_t_ready = false;   // pass 1 reads the time-major angles (SRC 3)
+  double* fuse_y = nullptr;   // output map the last group's gather may write directly
+  bool fused_y = false;       // set when it did (the epilogue is then skipped)
   bool bore_fast = false;     // pass 1 evaluates the boresight model in float32 (SRC 4)
   bool tiled_built = false;   // tiled preconditioner
   int tiled_T = 0;
