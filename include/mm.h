@@ -225,6 +225,15 @@ typedef struct {
                                and kept alive (unchanged) while the preconditioner
                                is used */
   size_t  tiled_workspace_bytes;
+  int32_t probe_sets;       /* 0: each tile's reference pixel is probed on its own
+                               (ncomp A-applies per tile: the definition).
+                               s >= 2: tiles whose tile row and column agree
+                               modulo s share one A-apply per component (s^2
+                               probe sets, same-set references >= s T/2 pixels
+                               apart); cheaper, but each q_t then also holds the
+                               other references' responses at its displacements,
+                               damped only by distance and the taper.  1 is
+                               rejected. */
 } mm_precon_opts;
 
 /* Builds a preconditioner on `stream`.  JACOBI, BINNED: per-pixel inverse
@@ -248,7 +257,7 @@ mm_status mm_apply_precon_circulant(mm_scan scan, const double* r, double* z,
 
 /* Bytes of device workspace the tiled preconditioner (Summary section) needs
  * for tile side `tile` on this scan's map: the per-tile inverse kernels
- * (ntiles T^2 ncomp^2 complex float64), the tile planes, four probe responses
+ * (ntiles T^2 ncomp^2 complex float64), the tile planes, one probe response
  * and small tables, with ntiles = (2 ny/T - 1)(2 nx/T - 1).  0 if the tile
  * size is invalid (not a power of two in [8, min(ny, nx)], or more than 65535
  * tiles). */
@@ -274,6 +283,16 @@ typedef struct {
                                updates) into a HIP graph on a private stream
                                forked from the caller's, and replay it; results
                                are those of the eager loop */
+  int32_t flexible;         /* 1: beta = z_{k+1}.(r_{k+1} - r_k) / r_k.z_k (flexible,
+                               Polak-Ribiere form; keeps consecutive directions
+                               A-conjugate for a nearly symmetric M); always used
+                               with MM_M_LEARNED.  0: beta = r_{k+1}.z_{k+1} / r_k.z_k */
+  int32_t refine;           /* >= 0: after convergence of the recursive residual,
+                               compute b - A x (one more A-apply) and, while
+                               ||b - A x|| > tol ||b||, restart PCG from x with the
+                               iterations left, at most `refine` times */
+  int32_t true_residual;    /* 1: report ||b - A x|| / ||b|| (one more A-apply)
+                               even with refine = 0 */
 } mm_pcg_opts;
 
 typedef struct {
@@ -285,6 +304,15 @@ typedef struct {
                                k = 0..iters, array of at least maxiter+1 */
   double* alpha;            /* [host] optional: alpha_k, k = 0..iters-1 */
   double* rho;              /* [host] optional: r_k.z_k, k = 0..iters-1 */
+  double  t_setup_s;        /* wall time of the solve's set-up (r0, z0, p0, rho0 and
+                               the graph capture), included in t_solve_s; the
+                               preconditioner's own build time is
+                               mm_scan_info.t_build_s */
+  double  true_rel_resid;   /* ||b - A x|| / ||b|| of the returned x if computed
+                               (refine > 0 or true_residual), else -1 */
+  int32_t restarts;         /* restarts taken by `refine`; iters counts the
+                               A-applies of every segment, history[k] at a restart
+                               holds the true residual it started from */
 } mm_pcg_result;
 
 /* Solves A x = b by PCG (Introduction; textbook PCG with device-resident
@@ -403,6 +431,7 @@ typedef struct {
                                boresight model, 2 stored as 4-byte angles (stored
                                weights of unit norm on the float32 and bfloat16
                                paths; decoded to within 1e-7), -1 no gather or I only */
+  double  t_build_s;        /* wall time of the last mm_build_precon on this handle */
 } mm_scan_info;
 
 mm_status mm_get_info(mm_scan scan, mm_scan_info* out /*[host]*/);

@@ -6,6 +6,12 @@ satisfies ||r||_2 <= tol ||b||_2; the iteration count is the number of
 A-applies inside the loop.  Breakdown (p.Ap <= 0 or r.z <= 0, or a non-finite
 scalar) stops the solve with the last good iterate.
 
+flexible=True takes the Polak-Ribiere form of beta, z_{k+1}.(r_{k+1} - r_k) /
+r_k.z_k, in place of r_{k+1}.z_{k+1} / r_k.z_k.  The two agree in exact
+arithmetic when M is symmetric; the flexible form keeps the search directions
+conjugate when M is only nearly symmetric (a preconditioner evaluated in
+reduced precision), at the price of one more inner product.
+
 Also the error A-norm estimate quoted with the residual A-norm figure in the
 Results section: ||x_k - x||_A^2 ~ sum_{j=k}^{k+d-1} alpha_j r_j.z_j, d = 4
 (with preconditioning r_j.z_j takes the place of ||r_j||^2).
@@ -28,7 +34,8 @@ class PCGResult:
     iterates: list | None = None
 
 
-def pcg(apply_A, apply_M, b, tol=1e-6, maxiter=5000, x0=None, keep_iterates=False):
+def pcg(apply_A, apply_M, b, tol=1e-6, maxiter=5000, x0=None, keep_iterates=False,
+        flexible=False):
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
     r = b - apply_A(x) if x0 is not None else b.copy()
@@ -54,6 +61,7 @@ def pcg(apply_A, apply_M, b, tol=1e-6, maxiter=5000, x0=None, keep_iterates=Fals
             break
         alpha = rho / ps
         x = x + alpha * p
+        r_old = r
         r = r - alpha * s
         res.iters = it
         res.alphas.append(alpha)
@@ -65,7 +73,7 @@ def pcg(apply_A, apply_M, b, tol=1e-6, maxiter=5000, x0=None, keep_iterates=Fals
             break
         z = apply_M(r)
         rho_new = float(r @ z)
-        beta = rho_new / rho
+        beta = (float(z @ (r - r_old)) if flexible else rho_new) / rho
         p = z + beta * p
         rho = rho_new
         res.rhos.append(rho)

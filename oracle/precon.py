@@ -124,17 +124,28 @@ class CirculantPrecon:
         self.q = q
         qhat = np.fft.fft2(q, axes=(0, 1))                   # (ky, kx, a, b)
         K = np.conj(qhat)
+        self.K = K
         self.n_floored = 0
         if symmetrize:
-            lam, V = np.linalg.eigh(K)
-            floor = eig_floor_rel * lam.max()
-            self.n_floored = int(np.count_nonzero(lam < floor))
-            lam = np.maximum(lam, floor)
-            self.lam = lam
-            self.Kinv = np.einsum("...ij,...j,...kj->...ik", V, 1.0 / lam, np.conj(V))
+            self.Kinv, self.lam, self.n_floored = self.floored_inverse(K, eig_floor_rel)
         else:
             self.lam = None
             self.Kinv = np.linalg.inv(K)
+
+    @staticmethod
+    def floored_inverse(K, eig_floor_rel):
+        """Positive definite inverse of the Hermitian blocks K(k) (reading of
+        the Implementation section, which needs Q invertible): every
+        eigenvalue of every block is raised to at least eig_floor_rel times
+        the largest eigenvalue over ALL wavenumbers (the largest eigenvalue of
+        the whole block-circulant Q), then K^-1 = V diag(1/lam) V^H.
+        Returns (K^-1, the floored eigenvalues, how many were raised)."""
+        lam, V = np.linalg.eigh(K)
+        floor = eig_floor_rel * lam.max()
+        n_floored = int(np.count_nonzero(lam < floor))
+        lam = np.maximum(lam, floor)
+        Kinv = np.einsum("...ij,...j,...kj->...ik", V, 1.0 / lam, np.conj(V))
+        return Kinv, lam, n_floored
 
     def __call__(self, rvec):
         nc, ny, nx, npix = self.nc, self.ny, self.nx, self.npix

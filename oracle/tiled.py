@@ -17,23 +17,22 @@ constant-correlation preconditioner to each tile, merge.  Readings:
 * Tile t's reference pixel is the active pixel of the tile nearest its
   centre (o + T/2 on each axis), smallest id on ties; a tile without active
   pixels contributes nothing.
-* Probing: the tiles fall into four interleaved sets by the parity of their
-  tile row and column; one A-apply per component and set probes every
-  reference pixel of the set at once (same-set references are a whole tile
-  apart, so their responses overlap only at long, tapered distances), and
-  each tile reads its column from its set's response.
+* Probing: each tile's constant-correlation kernel comes from the rows of A
+  at that tile's own reference pixel (eq. 6): ncomp A-applies per tile, one
+  unit vector at a time, exactly as for M_C.
 * K_t is built exactly like M_C's K but on the tile's own periodic T x T
   displacement grid: q_t(d) = Sigma_r^-T C_(r+d) Sigma_(r+d)^-1 with r + d
   taken modulo the map, zero for inactive pixels, Gaussian taper on the
   minimal-image displacement, symmetrised, conj FFT2, Hermitian eigenvalue
-  floor relative to the tile's largest eigenvalue.
+  floor relative to the tile's largest eigenvalue (the same floor as M_C's,
+  applied to the tile's own Q_t).
 With T equal to the map size there is one tile of weight one and M_T = M_C.
 """
 
 import numpy as np
 
 from .operators import apply_A
-from .precon import sym_sqrt, gaussian_taper
+from .precon import CirculantPrecon, sym_sqrt, gaussian_taper
 
 
 def tile_origins(n, T):
@@ -92,21 +91,16 @@ class TiledCirculantPrecon:
                 W = np.outer(wys[iy], wxs[ix])
                 ref = tile_reference(mask, nx, oy, ox, T)
                 self.tiles.append(dict(iy=iy, ix=ix, oy=oy, ox=ox, W=W, ref=ref, Kinv=None))
-        # interleaved probe sets
+        # the rows of A at every tile's own reference pixel (eq. 6)
         C = {}
-        for py in (0, 1):
-            for px in (0, 1):
-                members = [t for t in self.tiles if t["iy"] % 2 == py and t["ix"] % 2 == px
-                           and t["ref"] >= 0]
-                if not members:
-                    continue
-                for g in range(nc):
-                    e = np.zeros((nc, npix))
-                    for t in members:
-                        e[g, t["ref"]] = 1.0
-                    resp = apply_A(scan, e, mask).reshape(nc, npix)
-                    for t in members:
-                        C.setdefault(id(t), np.zeros((nc, nc, npix)))[g] = resp
+        for t in self.tiles:
+            if t["ref"] < 0:
+                continue
+            C[id(t)] = np.zeros((nc, nc, npix))
+            for g in range(nc):
+                e = np.zeros((nc, npix))
+                e[g, t["ref"]] = 1.0
+                C[id(t)][g] = apply_A(scan, e, mask).reshape(nc, npix)
         taper = gaussian_taper(T, T, sigma_taper)
         d = np.arange(T)
         dmi = np.where(d > T // 2, d - T, d)              # minimal image on the tile
@@ -121,13 +115,13 @@ class TiledCirculantPrecon:
             Cj = np.transpose(C[id(t)], (2, 0, 1))[j]       # (T, T, g, b)
             q = np.einsum("ga,yxgb,yxbc->yxac", self.Siginv[r], Cj, self.Siginv[j])
             q[~mask[j]] = 0.0
+            t["q_raw"] = q.copy()
             q *= taper[:, :, None, None]
             qm = q[(-d) % T][:, (-d) % T]
             q = 0.5 * (q + np.transpose(qm, (0, 1, 3, 2)))
+            t["q"] = q
             K = np.conj(np.fft.fft2(q, axes=(0, 1)))
-            lam, V = np.linalg.eigh(K)
-            lam = np.maximum(lam, eig_floor_rel * lam.max())
-            t["Kinv"] = np.einsum("...ij,...j,...kj->...ik", V, 1.0 / lam, np.conj(V))
+            t["Kinv"], _, t["n_floored"] = CirculantPrecon.floored_inverse(K, eig_floor_rel)
 
     def __call__(self, rvec):
         nc, ny, nx, npix, T = self.nc, self.ny, self.nx, self.npix, self.T

@@ -101,6 +101,17 @@ def mm_apply_precon_tiled(h, r, z, stream=None):
           "mm_apply_precon_tiled")
 
 
+def _pcg_opts(tol, maxiter, check_every=1, x0=False, graph=False, flexible=False, refine=0,
+              true_residual=False):
+    o = mm_pcg_opts()
+    o.tol, o.maxiter, o.check_every, o.use_x0 = float(tol), int(maxiter), int(check_every), int(x0)
+    o.graph = 1 if graph else 0
+    o.flexible = 1 if flexible else 0
+    o.refine = int(refine)
+    o.true_residual = 1 if true_residual else 0
+    return o
+
+
 def mm_pcg_solve(h, precon, b, x, opts, stream=None, history_len=0):
     """Returns (status, result dict).  MM_ENOCONV is returned, not raised."""
     res = mm_pcg_result()
@@ -117,8 +128,7 @@ def mm_pcg_solve(h, precon, b, x, opts, stream=None, history_len=0):
                           _stream(stream))
     if st not in (MM_OK, MM_ENOCONV, MM_EBREAKDOWN):
         check(st, "mm_pcg_solve")
-    out = dict(status=st, iters=res.iters, converged=bool(res.converged),
-               rel_resid=res.rel_resid, t_solve_s=res.t_solve_s)
+    out = _result_dict(res, st)
     if history_len:
         n = min(res.iters, history_len)
         out["history"] = np.array(hist[: n + 1])
@@ -140,9 +150,14 @@ def mm_pcg_solve_batch(handles, precon, bs, xs, opts, stream=None):
     st = lib.mm_pcg_solve_batch(H, n, int(precon), B, X, C.byref(opts), res, sts, _stream(stream))
     if st not in (MM_OK, MM_ENOCONV, MM_EBREAKDOWN):
         check(st, "mm_pcg_solve_batch")
-    out = [dict(status=int(sts[i]), iters=res[i].iters, converged=bool(res[i].converged),
-                rel_resid=res[i].rel_resid, t_solve_s=res[i].t_solve_s) for i in range(n)]
+    out = [_result_dict(res[i], int(sts[i])) for i in range(n)]
     return st, out
+
+
+def _result_dict(res, st):
+    return dict(status=st, iters=res.iters, converged=bool(res.converged),
+                rel_resid=res.rel_resid, t_solve_s=res.t_solve_s, t_setup_s=res.t_setup_s,
+                true_rel_resid=res.true_rel_resid, restarts=res.restarts)
 
 
 def mm_map_spectra(h, x, pixel_arcmin, dell, nbins, ncomp, stream=None):
@@ -393,9 +408,10 @@ class Scan:
         return b
 
     def build_precon(self, name, ref=None, sigma=0.0, symmetrize=True, eig_floor_rel=0.0,
-                     tile=0, stream=None):
+                     tile=0, probe_sets=0, stream=None):
         """tile: side of the tiles of the "tiled" preconditioner; its device
-        workspace is allocated here and held by this object."""
+        workspace is allocated here and held by this object.  probe_sets: 0
+        probes every tile alone, s >= 2 shares probes among tiles s apart."""
         o = mm_precon_opts()
         o.ref_y, o.ref_x = (-1, -1) if ref is None else (int(ref[0]), int(ref[1]))
         o.gauss_sigma_px = float(sigma) if sigma else 0.0
@@ -409,6 +425,7 @@ class Scan:
             o.tile = int(tile)
             o.tiled_workspace = self._tiled_ws.data_ptr()
             o.tiled_workspace_bytes = nb
+            o.probe_sets = int(probe_sets)
         mm_build_precon(self.handle, PRECON[name], o, stream)
 
     def apply_precon(self, name, r, z=None, stream=None):
@@ -424,11 +441,10 @@ class Scan:
         return z
 
     def pcg(self, name, b, x=None, tol=1e-6, maxiter=5000, check_every=1, x0=False,
-            history=True, snapshots=None, snap_every=0, graph=False, stream=None):
+            history=True, snapshots=None, snap_every=0, graph=False, flexible=False, refine=0,
+            true_residual=False, stream=None):
         x = self.new_map() if x is None else x
-        o = mm_pcg_opts()
-        o.tol, o.maxiter, o.check_every, o.use_x0 = float(tol), int(maxiter), int(check_every), int(x0)
-        o.graph = 1 if graph else 0
+        o = _pcg_opts(tol, maxiter, check_every, x0, graph, flexible, refine, true_residual)
         if snapshots is not None:
             o.snapshots = _ptr(snapshots, torch.float64, name="snapshots").value
             o.snap_every = int(snap_every)
@@ -498,21 +514,13 @@ class Learned:
         except Exception:
             pass
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
 
 def pcg_batch(scans, name, bs, xs=None, tol=1e-6, maxiter=5000, check_every=8, graph=True,
-              stream=None):
+              refine=0, true_residual=False, stream=None):
     """Solve several scans together (mm_pcg_solve_batch); returns the result
     dicts, each with its solution under "x"."""
     xs = [sc.new_map() for sc in scans] if xs is None else xs
-    o = mm_pcg_opts()
-    o.tol, o.maxiter, o.check_every = float(tol), int(maxiter), int(check_every)
-    o.graph = 1 if graph else 0
+    o = _pcg_opts(tol, maxiter, check_every, False, graph, False, refine, true_residual)
     _, out = mm_pcg_solve_batch([sc.handle for sc in scans], PRECON[name], bs, xs, o, stream)
     for r, x in zip(out, xs):
         r["x"] = x

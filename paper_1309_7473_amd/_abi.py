@@ -38,13 +38,14 @@ class mm_precon_opts(C.Structure):
     _fields_ = [("ref_y", C.c_int32), ("ref_x", C.c_int32), ("gauss_sigma_px", C.c_double),
                 ("symmetrize", C.c_int32), ("eig_floor_rel", C.c_double),
                 ("tile", C.c_int32), ("tiled_workspace", C.c_void_p),
-                ("tiled_workspace_bytes", C.c_size_t)]
+                ("tiled_workspace_bytes", C.c_size_t), ("probe_sets", C.c_int32)]
 
 
 class mm_pcg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int32), ("check_every", C.c_int32),
                 ("use_x0", C.c_int32), ("snap_every", C.c_int32), ("max_snaps", C.c_int32),
-                ("snapshots", C.c_void_p), ("graph", C.c_int32)]
+                ("snapshots", C.c_void_p), ("graph", C.c_int32), ("flexible", C.c_int32),
+                ("refine", C.c_int32), ("true_residual", C.c_int32)]
 
 
 class mm_train_opts(C.Structure):
@@ -56,14 +57,16 @@ class mm_train_opts(C.Structure):
 class mm_pcg_result(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rel_resid", C.c_double),
                 ("t_solve_s", C.c_double), ("history", C.POINTER(C.c_double)),
-                ("alpha", C.POINTER(C.c_double)), ("rho", C.POINTER(C.c_double))]
+                ("alpha", C.POINTER(C.c_double)), ("rho", C.POINTER(C.c_double)),
+                ("t_setup_s", C.c_double), ("true_rel_resid", C.c_double),
+                ("restarts", C.c_int32)]
 
 
 class mm_scan_info(C.Structure):
     _fields_ = [("n_active", C.c_int32), ("ref_pixel", C.c_int32), ("n_floored", C.c_int32),
                 ("det_group", C.c_int32), ("fft_m1", C.c_int32), ("fft_m2", C.c_int32),
                 ("fft_cols", C.c_int32), ("single_pass", C.c_int32), ("csr", C.c_int32), ("workspace_bytes", C.c_size_t),
-                ("gather_weights", C.c_int32)]
+                ("gather_weights", C.c_int32), ("t_build_s", C.c_double)]
 
 
 class mm_profile(C.Structure):

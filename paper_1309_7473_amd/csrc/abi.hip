@@ -2,6 +2,7 @@
 // (before anything is enqueued), handle lifetime and the thread-local error
 // message.  The compute lives in filter.hip, binned.hip, circulant.hip and
 // pcg.hip.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -194,7 +195,10 @@ mm_status mm_build_precon(mm_scan scan, int32_t precon, const mm_precon_opts* op
         if ((opts->ref_y >= 0) != (opts->ref_x >= 0) || opts->ref_y >= s->ny || opts->ref_x >= s->nx)
           return fail(MM_EINVAL, "ref_y/ref_x out of range");
       }
-      return circulant_build(s, opts, static_cast<hipStream_t>(stream));
+      const auto t0 = std::chrono::steady_clock::now();
+      const mm_status rc = circulant_build(s, opts, static_cast<hipStream_t>(stream));
+      s->t_build_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      return rc;
     }
     case MM_M_TILED: {
       s->tiled_built = false;   // a previous build's workspace may be gone
@@ -205,7 +209,12 @@ mm_status mm_build_precon(mm_scan scan, int32_t precon, const mm_precon_opts* op
         return fail(MM_EINVAL, "tiled_workspace must be a 256-byte aligned device pointer");
       if (opts->tiled_workspace_bytes < tiled_workspace_bytes(s, opts->tile))
         return fail(MM_ENOMEM, "tiled_workspace_bytes below mm_tiled_workspace_bytes");
-      return tiled_build(s, opts, static_cast<hipStream_t>(stream));
+      if (opts->probe_sets < 0 || opts->probe_sets == 1)
+        return fail(MM_EINVAL, "probe_sets must be 0 (each tile alone) or >= 2");
+      const auto t0 = std::chrono::steady_clock::now();
+      const mm_status rc = tiled_build(s, opts, static_cast<hipStream_t>(stream));
+      s->t_build_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      return rc;
     }
     default:
       return fail(MM_EINVAL, "unknown preconditioner");
@@ -328,6 +337,7 @@ mm_status mm_get_info(mm_scan scan, mm_scan_info* out) {
   out->csr = s->plan.csr ? 1 : 0;
   out->workspace_bytes = s->lay.total;
   out->gather_weights = (!s->plan.csr || s->nc != 3) ? -1 : !s->plan.csr_w ? 1 : s->csr_ang ? 2 : 0;
+  out->t_build_s = s->t_build_s;
   return MM_OK;
 }
 

@@ -288,18 +288,36 @@ __global__ void k_kinv_floor(const Cx<double>* __restrict__ qhat, int npix,
   double R[2 * NC][2 * NC], V[2 * NC][2 * NC];
   embed_K<NC>(qhat, npix, k, R);
   jacobi_eig<2 * NC>(R, V);
+  // The real embedding holds every eigenvalue of the Hermitian K twice; in
+  // ascending order the copies are neighbours (ranks 2m and 2m+1).  Each
+  // pair is taken as one eigenvalue (the mean of its two rounded copies),
+  // floored as one and counted once, so both copies always get the same
+  // 1/lambda and the floored count is that of K itself.
+  int rank[2 * NC];
+#pragma unroll
+  for (int i = 0; i < 2 * NC; ++i) {
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < 2 * NC; ++j)
+      c += (R[j][j] < R[i][i] || (R[j][j] == R[i][i] && j < i)) ? 1 : 0;
+    rank[i] = c;
+  }
   double f[2 * NC];
   int nf = 0;
 #pragma unroll
   for (int i = 0; i < 2 * NC; ++i) {
-    double l = R[i][i];
+    double partner = R[i][i];
+#pragma unroll
+    for (int j = 0; j < 2 * NC; ++j)
+      if (rank[j] == (rank[i] ^ 1)) partner = R[j][j];
+    double l = 0.5 * (R[i][i] + partner);
     if (l < floor_v) {
       l = floor_v;
-      ++nf;
+      nf += (rank[i] & 1) ? 0 : 1;
     }
     f[i] = 1.0 / l;
   }
-  if (nf) atomicAdd(nfloor, nf);  // every eigenvalue of K is counted twice
+  if (nf) atomicAdd(nfloor, nf);
 #pragma unroll
   for (int a = 0; a < NC; ++a)
 #pragma unroll
@@ -624,7 +642,7 @@ static mm_status build_t(ScanImpl* s, const mm_precon_opts* o, hipStream_t st) {
   }
   MM_HIP(hipStreamSynchronize(st));
   if (sym && h.lmax_bits == 0) return fail(MM_EINVAL, "circulant kernel has no positive eigenvalue");
-  s->n_floored = sym ? h.nfloor / 2 : 0;
+  s->n_floored = sym ? h.nfloor : 0;
   s->circ_built = true;
   s->circ_sym = sym;
   return MM_OK;
@@ -696,12 +714,17 @@ mm_status circulant_apply(ScanImpl* s, const double* r, double* z, hipStream_t s
 // K but from a probe at the tile's reference pixel and on the tile's own
 // periodic T x T displacement grid, merged by a sin^2 partition of unity:
 //   M_T r = Sigma^-1 [ sum_t sqrt(W_t) F_t^-1 K_t^-1 F_t sqrt(W_t) ] Sigma^-T r.
-// Tiles fall into four interleaved probe sets by the parity of their tile row
-// and column; one A-apply per component and set probes all references of
-// the set at once.
+// By default every tile's reference pixel is probed on its own (ncomp
+// A-applies per tile), which is the definition.  With probe_sets = s >= 2 the
+// tiles whose tile row and column agree modulo s share one A-apply per
+// component (s^2 sets, same-set references at least s T/2 pixels apart): a
+// cheaper set-up whose q_t also picks up the other references' responses,
+// damped only by their distance and the taper.  Each probe response is cut
+// down at once to the T x T window of displacements each of its tiles uses
+// (held in the K^-1 area until the inverses are formed).
 
 struct TiledLayout {
-  size_t kinv, planes, probes, tref, tset, swy, swx, lmax, nfloor, total;
+  size_t kinv, planes, probes, tref, tlist, swy, swx, lmax, nfloor, total;
 };
 
 static TiledLayout tiled_layout(const ScanImpl* s, int T) {
@@ -717,9 +740,9 @@ static TiledLayout tiled_layout(const ScanImpl* s, int T) {
   };
   L.kinv = take(nt * TT * nc * nc * 16);
   L.planes = take(nt * TT * nc * nc * 16);
-  L.probes = take(size_t(4) * nc * nc * s->npix * 8);
+  L.probes = take(size_t(nc) * s->npix * 8);   // one probe response
   L.tref = take(nt * 4);
-  L.tset = take(nt * 4);
+  L.tlist = take(nt * 4);
   L.swy = take(size_t(nty) * T * 8);
   L.swx = take(size_t(ntx) * T * 8);
   L.lmax = take(nt * 8);
@@ -747,17 +770,67 @@ static double tile_sqrt_weight(int i, int nt, int T, int u) {
   return std::fabs(sn);
 }
 
-__global__ void k_set_units(double* __restrict__ e, const int32_t* __restrict__ idx, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) e[idx[i]] = 1.0;
+// The T x T window of one probe response around each listed tile's
+// reference pixel: win[t][g*NC+b][y][x] = resp[b][r_t + d] with d the
+// minimal image of (y, x) on the tile, r_t + d taken modulo the map.
+template <int NC>
+__global__ void k_tile_window(const double* __restrict__ resp, int ny, int nx, int logT,
+                              const int32_t* __restrict__ tref, const int32_t* __restrict__ tlist,
+                              int g, double* __restrict__ win) {
+  const int T = 1 << logT, TT = T * T;
+  const int t = tlist[blockIdx.y];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= TT) return;
+  const int ref = tref[t];
+  const int y = e >> logT, x = e & (T - 1);
+  const int my = y > T / 2 ? y - T : y, mx = x > T / 2 ? x - T : x;
+  const int jy = (ref / nx + my + ny) % ny, jx = (ref % nx + mx + nx) % nx;
+  const int64_t j = int64_t(jy) * nx + jx, npix = int64_t(ny) * nx;
+#pragma unroll
+  for (int b = 0; b < NC; ++b)
+    win[(int64_t(t) * NC * NC + g * NC + b) * TT + e] = resp[b * npix + j];
+}
+
+// q_t(d) = Sigma_r^-T C(d) Sigma_j^-1 from a tile's probe window (zero if
+// the pixel j = r + d is inactive)
+template <int NC>
+__device__ __forceinline__ void q_window(const double* win, int TT, int e, int64_t j,
+                                         const double (&Sr)[NC][NC], const int32_t* mask,
+                                         const double* siginv, double (&q)[NC][NC]) {
+#pragma unroll
+  for (int a = 0; a < NC; ++a)
+#pragma unroll
+    for (int b = 0; b < NC; ++b) q[a][b] = 0.0;
+  if (!mask[j]) return;
+  double Sj[NC][NC], Cm[NC][NC];
+  if constexpr (NC == 3) {
+    unpack_sym3(siginv + 6 * j, Sj);
+  } else {
+    Sj[0][0] = siginv[6 * j];
+  }
+#pragma unroll
+  for (int g = 0; g < NC; ++g)
+#pragma unroll
+    for (int b = 0; b < NC; ++b) Cm[g][b] = win[int64_t(g * NC + b) * TT + e];
+#pragma unroll
+  for (int a = 0; a < NC; ++a)
+#pragma unroll
+    for (int b = 0; b < NC; ++b) {
+      double s = 0.0;
+#pragma unroll
+      for (int g = 0; g < NC; ++g)
+#pragma unroll
+        for (int h = 0; h < NC; ++h) s += Sr[g][a] * Cm[g][h] * Sj[h][b];
+      q[a][b] = s;
+    }
 }
 
 // planes[t][a*NC+b][y][x] = taper * sym q_t(d), d the minimal image of (y, x) on the tile
 template <int NC>
-__global__ void k_tq_assemble(const int32_t* __restrict__ mask, const double* __restrict__ probes,
+__global__ void k_tq_assemble(const int32_t* __restrict__ mask, const double* __restrict__ win,
                               const double* __restrict__ siginv, int ny, int nx, int logT,
-                              const int32_t* __restrict__ tref, const int32_t* __restrict__ tset,
-                              double sigma, Cx<double>* __restrict__ planes) {
+                              const int32_t* __restrict__ tref, double sigma,
+                              Cx<double>* __restrict__ planes) {
   const int T = 1 << logT, TT = T * T;
   const int t = blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -769,23 +842,36 @@ __global__ void k_tq_assemble(const int32_t* __restrict__ mask, const double* __
     for (int i = 0; i < NC * NC; ++i) out[int64_t(i) * TT] = cx(0.0, 0.0);
     return;
   }
-  const int npix = ny * nx;
-  const double* probe = probes + int64_t(tset[t]) * NC * NC * npix;
+  win += int64_t(t) * NC * NC * TT;
   const int y = e >> logT, x = e & (T - 1);
-  // minimal images on the tile of d and of -d (both T/2 at the Nyquist index)
+  // d and -d on the tile's grid (both T/2 at the Nyquist index)
   const int ym = (T - y) & (T - 1), xm = (T - x) & (T - 1);
+  const int em = (ym << logT) | xm;
   const int my = y > T / 2 ? y - T : y, mx = x > T / 2 ? x - T : x;
   const int mym = ym > T / 2 ? ym - T : ym, mxm = xm > T / 2 ? xm - T : xm;
   const int ry = ref / nx, rx = ref % nx;
+  const int64_t j = int64_t((ry + my + ny) % ny) * nx + (rx + mx + nx) % nx;
+  const int64_t jm = int64_t((ry + mym + ny) % ny) * nx + (rx + mxm + nx) % nx;
+  double Sr[NC][NC];
+  if constexpr (NC == 3) {
+    unpack_sym3(siginv + 6 * int64_t(ref), Sr);
+  } else {
+    Sr[0][0] = siginv[6 * int64_t(ref)];
+  }
   double q[NC][NC], qm[NC][NC];
-  q_raw<NC>((my + ny) % ny, (mx + nx) % nx, ry, rx, ny, nx, mask, probe, siginv, q);
-  q_raw<NC>((mym + ny) % ny, (mxm + nx) % nx, ry, rx, ny, nx, mask, probe, siginv, qm);
+  q_window<NC>(win, TT, e, j, Sr, mask, siginv, q);
+  q_window<NC>(win, TT, em, jm, Sr, mask, siginv, qm);
   double g = 1.0;
   if (sigma > 0.0) g = exp(-double(my * my + mx * mx) / (2.0 * sigma * sigma));
 #pragma unroll
   for (int a = 0; a < NC; ++a)
 #pragma unroll
     for (int b = 0; b < NC; ++b) out[int64_t(a * NC + b) * TT] = cx(g * 0.5 * (q[a][b] + qm[b][a]), 0.0);
+}
+
+__global__ void k_set_units(double* __restrict__ e, const int32_t* __restrict__ idx, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) e[idx[i]] = 1.0;
 }
 
 // tile planes[t][a][y][x] = sqrt(W_t) * u_a(oy + y, ox + x), u = Sigma^-T r (global planes)
@@ -860,6 +946,9 @@ static mm_status tiled_build_t(ScanImpl* s, const mm_precon_opts* o, hipStream_t
   MM_HIP(hipMemcpyAsync(mask.data(), s->at<int32_t>(s->lay.mask), size_t(npix) * 4,
                         hipMemcpyDeviceToHost, st));
   MM_HIP(hipStreamSynchronize(st));
+  // probe sets: 0 = every tile alone (the definition); s >= 2 = tiles whose
+  // tile row and column agree modulo s
+  const int ps = o->probe_sets;
   std::vector<int32_t> tref(nt, -1), tset(nt);
   for (int iy = 0; iy < nty; ++iy)
     for (int ix = 0; ix < ntx; ++ix) {
@@ -877,48 +966,53 @@ static mm_status tiled_build_t(ScanImpl* s, const mm_precon_opts* o, hipStream_t
           }
         }
       tref[iy * ntx + ix] = best;
-      tset[iy * ntx + ix] = 2 * (iy & 1) + (ix & 1);
+      tset[iy * ntx + ix] = ps >= 2 ? (iy % ps) * ps + (ix % ps) : iy * ntx + ix;
     }
+  const int nsets = ps >= 2 ? ps * ps : nt;
   std::vector<double> swy(size_t(nty) * T), swx(size_t(ntx) * T);
   for (int i = 0; i < nty; ++i)
     for (int u = 0; u < T; ++u) swy[size_t(i) * T + u] = tile_sqrt_weight(i, nty, T, u);
   for (int i = 0; i < ntx; ++i)
     for (int u = 0; u < T; ++u) swx[size_t(i) * T + u] = tile_sqrt_weight(i, ntx, T, u);
   MM_HIP(hipMemcpyAsync(at(TL.tref), tref.data(), size_t(nt) * 4, hipMemcpyHostToDevice, st));
-  MM_HIP(hipMemcpyAsync(at(TL.tset), tset.data(), size_t(nt) * 4, hipMemcpyHostToDevice, st));
   MM_HIP(hipMemcpyAsync(at(TL.swy), swy.data(), swy.size() * 8, hipMemcpyHostToDevice, st));
   MM_HIP(hipMemcpyAsync(at(TL.swx), swx.data(), swx.size() * 8, hipMemcpyHostToDevice, st));
-  // probes: per set and component, every reference of the set at once
-  double* probes = reinterpret_cast<double*>(at(TL.probes));
+  // probes: per set and component one A-apply with a unit at every reference
+  // of the set, cut at once into the set's tile windows (in the K^-1 area)
+  double* resp = reinterpret_cast<double*>(at(TL.probes));
+  double* win = reinterpret_cast<double*>(at(TL.kinv));
   double* e = s->at<double>(s->lay.vec) + 4 * int64_t(NC) * npix;   // the spare CG vector
-  mm_status r;
-  if ((r = fill_zero(probes, size_t(4) * NC * NC * npix * 8, st)) != MM_OK) return r;
   int32_t* idx = reinterpret_cast<int32_t*>(at(TL.lmax));   // scratch until the floor
-  for (int set = 0; set < 4; ++set) {
-    std::vector<int32_t> refs;
-    for (int t = 0; t < nt; ++t)
-      if (tset[t] == set && tref[t] >= 0) refs.push_back(tref[t]);
-    if (refs.empty()) continue;
+  int32_t* tlist = reinterpret_cast<int32_t*>(at(TL.tlist));
+  mm_status r;
+  std::vector<std::vector<int32_t>> members(nsets);
+  for (int t = 0; t < nt; ++t)
+    if (tref[t] >= 0) members[tset[t]].push_back(t);
+  for (int set = 0; set < nsets; ++set) {
+    const std::vector<int32_t>& mt = members[set];
+    if (mt.empty()) continue;
+    MM_HIP(hipMemcpyAsync(tlist, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, st));
     for (int g = 0; g < NC; ++g) {
-      std::vector<int32_t> units(refs.size());
-      for (size_t i = 0; i < refs.size(); ++i) units[i] = g * npix + refs[i];
+      std::vector<int32_t> units(mt.size());
+      for (size_t i = 0; i < mt.size(); ++i) units[i] = g * npix + tref[mt[i]];
       if ((r = fill_zero(e, size_t(NC) * npix * 8, st)) != MM_OK) return r;
       MM_HIP(hipMemcpyAsync(idx, units.data(), units.size() * 4, hipMemcpyHostToDevice, st));
       hipLaunchKernelGGL(k_set_units, dim3(unsigned((units.size() + 255) / 256)), dim3(256), 0, st,
                          e, idx, int(units.size()));
       MM_HIP(hipGetLastError());
-      if ((r = filter_pipeline(s, 0, nullptr, e, probes + (int64_t(set) * NC + g) * NC * npix, st)) !=
-          MM_OK)
-        return r;
-      MM_HIP(hipStreamSynchronize(st));   // idx is reused by the next set
+      if ((r = filter_pipeline(s, 0, nullptr, e, resp, st)) != MM_OK) return r;
+      hipLaunchKernelGGL(k_tile_window<NC>, dim3(unsigned((TT + 255) / 256), unsigned(mt.size())),
+                         dim3(256), 0, st, resp, ny, nx, logT,
+                         reinterpret_cast<const int32_t*>(at(TL.tref)), tlist, g, win);
+      MM_HIP(hipGetLastError());
+      MM_HIP(hipStreamSynchronize(st));   // idx (and tlist) are reused by the next probe
     }
   }
   Cx<double>* planes = reinterpret_cast<Cx<double>*>(at(TL.planes));
   const dim3 gt((TT + 255) / 256, nt), b(256);
-  hipLaunchKernelGGL(k_tq_assemble<NC>, gt, b, 0, st, s->at<int32_t>(s->lay.mask), probes,
+  hipLaunchKernelGGL(k_tq_assemble<NC>, gt, b, 0, st, s->at<int32_t>(s->lay.mask), win,
                      s->at<double>(s->lay.siginv), ny, nx, logT,
-                     reinterpret_cast<const int32_t*>(at(TL.tref)),
-                     reinterpret_cast<const int32_t*>(at(TL.tset)), o->gauss_sigma_px, planes);
+                     reinterpret_cast<const int32_t*>(at(TL.tref)), o->gauss_sigma_px, planes);
   MM_HIP(hipGetLastError());
   if ((r = map_fft_dims(s, planes, logT, logT, nt * NC * NC, false, st)) != MM_OK) return r;
   double eps = o->eig_floor_rel;

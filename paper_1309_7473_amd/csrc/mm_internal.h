@@ -41,10 +41,12 @@ struct PcgDev {
   double rz;       // new r.z
   double alpha, beta;
   double tol2;
+  double true_rr;  // ||b - A x||^2 over the active entries (true-residual check)
   int iters;
   int done;
   int breakdown;
   int cf;          // reductions in compensated float32 pairs
+  int flex;        // Polak-Ribiere beta = -alpha (s.z') / rho
 };
 
 // Offsets of the sub-buffers inside the caller's workspace.
@@ -120,6 +122,7 @@ struct ScanImpl {
   char* ws;
   int ref_pixel = -1;
   int n_floored = 0;
+  double t_build_s = 0.0;   // wall time of the last mm_build_precon
   int n_active = 0;
   bool circ_built = false;
   bool csr_ang = false;       // the index's weights are stored as fixed-point angles

@@ -6,6 +6,15 @@
 //          stop when ||r|| <= tol ||b||;  z = M r;  rho' = r.z;
 //          beta = rho' / rho;  p = z + beta p
 //
+// The flexible (Polak-Ribiere) variant takes beta = z.(r' - r) / rho =
+// -alpha (s.z) / rho instead, which keeps consecutive directions
+// A-conjugate when M is only nearly symmetric (the learned correction, whose
+// convolutions round to bfloat16); s.z is the second sum of the r.z kernel.
+// On request the loop is followed by the true residual b - A x (one more
+// A-apply) and, while that misses the tolerance, by restarts from x (at most
+// opts->refine of them): the recursive residual drifts from the true one by
+// the rounding of the updates.
+//
 // Dot products are two-step reductions with a fixed summation order (block
 // partials, then a 256-thread sum of the partials: for p.s and r.z
 // redundantly in every block of the x/r and p updates that consume them, for
@@ -123,6 +132,14 @@ __global__ void k_fin_init(const double* __restrict__ part, int nb, PcgDev* st, 
   }
 }
 
+// ||b - A x||^2 of the true-residual check
+__global__ void k_fin_true(const double* __restrict__ part, int nb, PcgDev* st) {
+  __shared__ double sm[32];
+  double v[2];
+  sum_partials(part, nb, v, sm, st->cf);
+  if (threadIdx.x == 0) st->true_rr = v[0];
+}
+
 // rho0 = r0.z0
 __global__ void k_fin_rho0(const double* __restrict__ part, int nb, PcgDev* st) {
   __shared__ double sm[32];
@@ -213,15 +230,18 @@ __device__ __forceinline__ void fin_rr(const double* part, int nb, PcgDev* st, d
 // iteration's bookkeeping) from the x/r update's partials
 template <bool CF>
 __global__ void __launch_bounds__(256) k_dot_rz(const double* __restrict__ r,
-                                                const double* __restrict__ z, int64_t n,
+                                                const double* __restrict__ z,
+                                                const double* __restrict__ s, int64_t n,
                                                 double* __restrict__ part, PcgDev* st,
                                                 const double* part_rr, int nb, double* hist,
                                                 int hist_cap) {
   if (blockIdx.x == 0) fin_rr(part_rr, nb, st, hist, hist_cap);
   Acc2<CF> v;
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x)
+       i += int64_t(gridDim.x) * blockDim.x) {
     v.add_prod(0, r[i], z[i]);
+    if (s) v.add_prod(1, s[i], z[i]);   // flexible beta: s.z as the second sum
+  }
   v.store(part);
 }
 
@@ -234,13 +254,16 @@ __global__ void __launch_bounds__(256) k_update_p(double* __restrict__ p, const 
                                                   int nb) {
   if (st->done) return;   // uniform: set only by earlier kernels
   __shared__ double sm[32];
-  __shared__ double rz_all;
+  __shared__ double rz_all, sz_all;
   double v[2];
-  sum_partials(part_rz, nb, v, sm, st->cf);   // the total is in thread 0
-  if (threadIdx.x == 0) rz_all = v[0];
+  sum_partials(part_rz, nb, v, sm, st->cf);   // the totals are in thread 0
+  if (threadIdx.x == 0) {
+    rz_all = v[0];
+    sz_all = v[1];
+  }
   __syncthreads();
   const double rz = rz_all;
-  const double beta = rz / st->rho;
+  const double beta = st->flex ? -st->alpha * sz_all / st->rho : rz / st->rho;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->rz = rz;
     st->beta = beta;
@@ -314,7 +337,12 @@ struct PcgRun {
   mm_pcg_result* res = nullptr;
   hipStream_t st = nullptr;
   int it = 0;
+  bool flex = false;
   bool finished = false;
+  int offset = 0;        // iterations of the earlier segments (restarts)
+  int restarts = 0;
+  double true_rel = -1.0;
+  double t_setup = 0.0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   PcgDev h{};
@@ -327,7 +355,8 @@ struct PcgRun {
 
 // the launches of one iteration (no host synchronisation, no memset/memcpy:
 // safe to capture)
-static mm_status pcg_iteration_launches(ScanImpl* s, int precon, double* x, hipStream_t st) {
+static mm_status pcg_iteration_launches(ScanImpl* s, int precon, bool flex, double* x,
+                                        hipStream_t st) {
   const Layout& L = s->lay;
   const int64_t N = int64_t(s->nc) * s->npix;
   double* vec = s->at<double>(L.vec);
@@ -359,11 +388,12 @@ static mm_status pcg_iteration_launches(ScanImpl* s, int precon, double* x, hipS
   if ((rc = apply_precon(s, precon, r, z, st)) != MM_OK) return rc;
   // r.z, with ||r||^2's bookkeeping in its block 0 (nothing between the x/r
   // update and here reads it)
+  const double* sz = flex ? sv : nullptr;
   if (cf)
-    hipLaunchKernelGGL(k_dot_rz<true>, gb, bb, 0, st, r, z, N, part, dev, part_rr, nb, hist,
+    hipLaunchKernelGGL(k_dot_rz<true>, gb, bb, 0, st, r, z, sz, N, part, dev, part_rr, nb, hist,
                        kHistCap);
   else
-    hipLaunchKernelGGL(k_dot_rz<false>, gb, bb, 0, st, r, z, N, part, dev, part_rr, nb, hist,
+    hipLaunchKernelGGL(k_dot_rz<false>, gb, bb, 0, st, r, z, sz, N, part, dev, part_rr, nb, hist,
                        kHistCap);
   hipLaunchKernelGGL(k_update_p, gb, bb, 0, st, p, z, N, dev, part, nb);
   MM_HIP(hipGetLastError());
@@ -378,7 +408,7 @@ static mm_status pcg_poll(PcgRun& R) {
 }
 
 static mm_status pcg_start(PcgRun& R) {
-  R.t0 = std::chrono::steady_clock::now();
+  if (R.offset == 0) R.t0 = std::chrono::steady_clock::now();
   ScanImpl* s = R.s;
   hipStream_t st = R.st;
   const Layout& L = s->lay;
@@ -402,6 +432,7 @@ static mm_status pcg_start(PcgRun& R) {
   PcgDev init{};
   init.tol2 = R.o.tol * R.o.tol;
   init.cf = cf ? 1 : 0;
+  init.flex = R.flex ? 1 : 0;
   MM_HIP(hipMemcpyAsync(dev, &init, sizeof(PcgDev), hipMemcpyHostToDevice, st));
   // r = b - A x0  (or b), x0 = 0 unless use_x0
   if (R.o.use_x0) {
@@ -430,17 +461,19 @@ static mm_status pcg_start(PcgRun& R) {
   MM_HIP(hipGetLastError());
   if ((rc = pcg_poll(R)) != MM_OK) return rc;
   R.it = R.h.done ? R.o.maxiter : 0;
-  if (R.o.graph && R.it < R.o.maxiter) {
+  if (R.o.graph && R.it < R.o.maxiter && !R.exec) {
     // capture one iteration; every later iteration is one graph launch
     s->capturing = true;
     MM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    rc = pcg_iteration_launches(s, R.precon, R.x, st);
+    rc = pcg_iteration_launches(s, R.precon, R.flex, R.x, st);
     const hipError_t ec = hipStreamEndCapture(st, &R.graph);
     s->capturing = false;
     if (rc != MM_OK) return rc;
     MM_HIP(ec);
     MM_HIP(hipGraphInstantiateWithFlags(&R.exec, R.graph, 0));
   }
+  if (R.offset == 0)
+    R.t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - R.t0).count();
   return MM_OK;
 }
 
@@ -449,7 +482,7 @@ static mm_status pcg_iterate(PcgRun& R) {
   if (R.exec) {
     MM_HIP(hipGraphLaunch(R.exec, R.st));
   } else {
-    const mm_status rc = pcg_iteration_launches(R.s, R.precon, R.x, R.st);
+    const mm_status rc = pcg_iteration_launches(R.s, R.precon, R.flex, R.x, R.st);
     if (rc != MM_OK) return rc;
   }
   ++R.it;
@@ -462,6 +495,9 @@ static mm_status pcg_iterate(PcgRun& R) {
   return MM_OK;
 }
 
+// Reads the state of the segment that just ended and appends its history
+// (entry 0 of a restarted segment, the true residual at the restart,
+// replaces the last entry of the segment before).
 static mm_status pcg_finish(PcgRun& R) {
   mm_status rc;
   if ((rc = pcg_poll(R)) != MM_OK) return rc;
@@ -474,17 +510,21 @@ static mm_status pcg_finish(PcgRun& R) {
   const bool converged = h.done && !h.breakdown;
   if (R.res) {
     mm_pcg_result* res = R.res;
-    res->iters = iters;
+    const int off = R.offset;
+    res->iters = off + iters;
     res->converged = converged ? 1 : 0;
     res->rel_resid = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
     if (iters == 0) res->rel_resid = h.bb > 0 ? hh[0] : 0.0;
     res->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - R.t0).count();
+    res->t_setup_s = R.t_setup;
+    res->true_rel_resid = R.true_rel;
+    res->restarts = R.restarts;
     if (res->history)
-      for (int k = 0; k <= nh; ++k) res->history[k] = hh[k];
+      for (int k = 0; k <= nh; ++k) res->history[off + k] = hh[k];
     if (res->alpha)
-      for (int k = 0; k < nh; ++k) res->alpha[k] = hh[(kHistCap + 1) + k];
+      for (int k = 0; k < nh; ++k) res->alpha[off + k] = hh[(kHistCap + 1) + k];
     if (res->rho)
-      for (int k = 0; k < nh; ++k) res->rho[k] = hh[2 * (kHistCap + 1) + k];
+      for (int k = 0; k < nh; ++k) res->rho[off + k] = hh[2 * (kHistCap + 1) + k];
   }
   if (h.breakdown) return fail(MM_EBREAKDOWN, "PCG breakdown (p.Ap <= 0, r.z <= 0 or non-finite)");
   if (!converged) {
@@ -492,6 +532,75 @@ static mm_status pcg_finish(PcgRun& R) {
     return MM_ENOCONV;
   }
   return MM_OK;
+}
+
+// ||b - A x|| / ||b|| over the active entries (one A-apply; z and s are free
+// once the loop has stopped)
+static mm_status pcg_true_residual(PcgRun& R, double* out) {
+  ScanImpl* s = R.s;
+  hipStream_t st = R.st;
+  const Layout& L = s->lay;
+  const int64_t N = int64_t(s->nc) * s->npix;
+  double* vec = s->at<double>(L.vec);
+  double *z = vec + N, *sv = vec + 3 * N;
+  double* part = s->at<double>(L.partials);
+  PcgDev* dev = s->at<PcgDev>(L.pcg);
+  const int nb = red_blocks(N);
+  const dim3 gb(nb), bb(256);
+  const double* none = nullptr;
+  mm_status rc;
+  if ((rc = filter_pipeline(s, 0, nullptr, R.x, sv, st)) != MM_OK) return rc;
+  hipLaunchKernelGGL(k_axpby, gb, bb, 0, st, z, R.b, 1.0, sv, -1.0, N);
+  hipLaunchKernelGGL(k_mask_vec, dim3((s->npix + 255) / 256), bb, 0, st, z,
+                     s->at<int32_t>(L.mask), s->npix, s->nc);
+  if (s->plan.acc32)
+    hipLaunchKernelGGL(k_dot_partial<true>, gb, bb, 0, st, z, z, none, none, N, part);
+  else
+    hipLaunchKernelGGL(k_dot_partial<false>, gb, bb, 0, st, z, z, none, none, N, part);
+  hipLaunchKernelGGL(k_fin_true, dim3(1), bb, 0, st, part, nb, dev);
+  MM_HIP(hipGetLastError());
+  if ((rc = pcg_poll(R)) != MM_OK) return rc;
+  *out = R.h.bb > 0 ? std::sqrt(R.h.true_rr / R.h.bb) : 0.0;
+  return MM_OK;
+}
+
+static mm_status pcg_loop(PcgRun& R, int every) {
+  mm_status rc;
+  while (R.it < R.o.maxiter) {
+    if ((rc = pcg_iterate(R)) != MM_OK) return rc;
+    if (R.it % every == 0 || R.it == R.o.maxiter) {
+      if ((rc = pcg_poll(R)) != MM_OK) return rc;
+      if (R.h.done) break;
+    }
+  }
+  return MM_OK;
+}
+
+// After a converged segment: the true residual (opts->true_residual or
+// refine > 0) and, while it misses the tolerance, restarts from x with the
+// iterations left, at most opts->refine times.  Returns the status of the
+// last segment.
+static mm_status pcg_check_and_refine(PcgRun& R, const mm_pcg_opts* o, mm_status rc) {
+  const int every = o->check_every > 0 ? o->check_every : 1;
+  while (rc == MM_OK && (o->true_residual || o->refine > 0)) {
+    mm_status r2;
+    if ((r2 = pcg_true_residual(R, &R.true_rel)) != MM_OK) return r2;
+    if (R.res) R.res->true_rel_resid = R.true_rel;
+    const int done_iters = R.offset + R.h.iters;
+    if (R.true_rel <= o->tol || R.restarts >= o->refine || done_iters >= o->maxiter) break;
+    // restart from x: r = b - A x, z = M r, p = z
+    ++R.restarts;
+    R.offset = done_iters;
+    R.o.use_x0 = 1;
+    R.o.maxiter = o->maxiter - done_iters;
+    R.o.snapshots = nullptr;   // snapshots number the first segment's iterations only
+    R.it = 0;
+    R.finished = false;
+    if ((r2 = pcg_start(R)) != MM_OK) return r2;
+    if ((r2 = pcg_loop(R, every)) != MM_OK) return r2;
+    rc = pcg_finish(R);
+  }
+  return rc;
 }
 
 // run on a private stream forked from / joined to the caller's (a captured
@@ -532,6 +641,7 @@ mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const m
   R.o = *o;
   R.res = res;
   R.st = st;
+  R.flex = precon == MM_M_LEARNED || o->flexible != 0;
   mm_status rc;
   if (o->graph) {
     if ((rc = fs.open()) != MM_OK) return rc;
@@ -539,14 +649,8 @@ mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const m
   }
   if ((rc = pcg_start(R)) != MM_OK) return rc;
   const int every = o->check_every > 0 ? o->check_every : 1;
-  while (R.it < o->maxiter) {
-    if ((rc = pcg_iterate(R)) != MM_OK) return rc;
-    if (R.it % every == 0 || R.it == o->maxiter) {
-      if ((rc = pcg_poll(R)) != MM_OK) return rc;
-      if (R.h.done) break;
-    }
-  }
-  rc = pcg_finish(R);
+  if ((rc = pcg_loop(R, every)) != MM_OK) return rc;
+  rc = pcg_check_and_refine(R, o, pcg_finish(R));
   if (o->graph) {
     const mm_status rj = fs.join();
     if (rj != MM_OK) return rj;
@@ -575,6 +679,7 @@ mm_status pcg_solve_batch(ScanImpl* const* scans, int n, int precon, const doubl
     R[i].o.snap_every = 0;
     R[i].res = res ? &res[i] : nullptr;
     R[i].st = fs.back()->st;
+    R[i].flex = precon == MM_M_LEARNED || o->flexible != 0;
   }
   for (int i = 0; i < n; ++i)
     if ((rc = pcg_start(R[i])) != MM_OK) return rc;
@@ -595,7 +700,7 @@ mm_status pcg_solve_batch(ScanImpl* const* scans, int n, int precon, const doubl
   // first error of any run, else MM_ENOCONV if one did not converge
   mm_status worst = MM_OK;
   for (int i = 0; i < n; ++i) {
-    const mm_status ri = pcg_finish(R[i]);
+    const mm_status ri = pcg_check_and_refine(R[i], o, pcg_finish(R[i]));
     if (status) status[i] = ri;
     if (ri < 0 && worst >= 0) worst = ri;
     if (ri == MM_ENOCONV && worst == MM_OK) worst = MM_ENOCONV;

@@ -21,6 +21,15 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def relmax(a, b):
+    """Element-wise gate: max |a - b| over max |b|.  A relative L2 error can
+    hide a large error confined to a few entries; this cannot."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    mb = np.abs(b).max() if b.size else 0.0
+    return np.abs(a - b).max() / (mb if mb > 0 else 1.0) if a.size else 0.0
+
+
 class Pair:
     """The same seeded inputs seen by the oracle and by the GPU library."""
 

@@ -233,3 +233,39 @@ def test_mixed_radix_lengths(mm):
     edges = np.array([0, 100, 501], np.int32)
     d = _desc(mm, nsamp=1000, corr_rank=1, corr_nbins=2, corr_edges=edges.ctypes.data)
     assert mm.mm_scan_workspace_bytes(d) == 0 and "power of two" in mm.mm_last_error()
+
+
+STRUCTS = ["mm_scan_desc", "mm_precon_opts", "mm_pcg_opts", "mm_pcg_result", "mm_scan_info",
+           "mm_train_opts", "mm_profile"]
+
+
+def test_struct_layouts_match_the_header(mm, tmp_path):
+    """Every struct the binding declares has the header's size and field
+    offsets (compiled with the system C compiler from include/mm.h)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mm.h"', "int main(void) {"]
+    for s in STRUCTS:
+        cls = getattr(mm, s)
+        lines.append(f'printf("{s} size %zu\\n", sizeof({s}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{s} {f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            s, f, v = ln.split()
+            got[(s, f)] = int(v)
+    for s in STRUCTS:
+        cls = getattr(mm, s)
+        assert C.sizeof(cls) == got[(s, "size")], s
+        for f, _ in cls._fields_:
+            assert getattr(cls, f).offset == got[(s, f)], (s, f)

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from conftest import small_raster
-from gpu_common import Pair, rel, need_gpu
+from gpu_common import Pair, rel, relmax, need_gpu
 from synth import make_workload, raster_scan
 
 pytestmark = pytest.mark.gpu
@@ -27,9 +27,9 @@ def _check_apply(pair, tol, seed=0, label=""):
     assert pair.mask.sum() > 0, "no active pixel: the comparison would be vacuous"
     x = pair.masked_random(seed)
     got, want = pair.A_gpu(x), pair.A_oracle(x)
-    e = rel(got, want)
-    print(f"[apply {label}] rel err random map = {e:.3e}", flush=True)
-    assert e <= tol, e
+    e, emax = rel(got, want), relmax(got, want)
+    print(f"[apply {label}] rel err random map = {e:.3e} max {emax:.3e}", flush=True)
+    assert e <= tol and emax <= tol, (e, emax)
     # inactive pixels are zero
     assert np.all(got.reshape(pair.nc, -1)[:, ~pair.mask] == 0)
     return e
@@ -77,9 +77,11 @@ def test_apply_A_parity(case, scatter):
     sky = make_sky(nc, ny, nx) * pair.mask.reshape(1, ny, nx)
     want = pair.A_oracle(sky.ravel())
     assert np.linalg.norm(want) > 0
-    e = rel(pair.A_gpu(sky.ravel()), want)
-    print(f"[apply {label}] rel err sky map = {e:.3e}", flush=True)
-    assert e <= (TOL64 if dt == "f64" else TOL32_SKY), e
+    got = pair.A_gpu(sky.ravel())
+    e, emax = rel(got, want), relmax(got, want)
+    print(f"[apply {label}] rel err sky map = {e:.3e} max {emax:.3e}", flush=True)
+    tol = TOL64 if dt == "f64" else TOL32_SKY
+    assert e <= tol and emax <= tol, (e, emax)
 
 
 def make_sky(nc, ny, nx):

@@ -8,16 +8,17 @@ taper.  The oracle's A-apply on the whole scan takes seconds in NumPy, so
 every pixel of each output is compared, not a sample.  Tolerances as in the
 smaller parity tests: A-apply 2e-6 relative L2 for a white random map and
 2e-5 for the smooth sky; circulant apply 1e-4 (its probe rows come from the
-float32 A-apply); the PCG solution's true residual under the oracle's float64
-A at most 2.1e-5: 1e-6 from the solve plus |(A_gpu - A) x| / |b|, which the
-sky tolerance of the A-apply bounds by 2e-5 since A x ~ b.
+float32 A-apply); every output is also held element-wise to the same
+tolerance times its largest entry.  The PCG solution (tolerance 1e-6, with the
+library's true-residual check and restarts) must meet 1e-6 in the true
+residual ||b - A x|| / ||b|| under the oracle's float64 A.
 """
 
 import numpy as np
 import pytest
 
 import oracle
-from gpu_common import need_gpu, rel
+from gpu_common import need_gpu, rel, relmax
 from synth import make_workload
 
 pytestmark = pytest.mark.gpu
@@ -60,9 +61,9 @@ def test_iqu256_full_size_apply(full):
     for label, x, tol in (("random", rnd, TOL32_WHITE), ("sky", sky, TOL32_SKY)):
         got = _to_host(torch, g.apply_A(torch.from_numpy(x).cuda()))
         want = oracle.apply_A(o, x, mask)
-        e = rel(got, want)
-        print(f"[full size] {label} map rel err {e:.3e}", flush=True)
-        assert e <= tol, e
+        e, emax = rel(got, want), relmax(got, want)
+        print(f"[full size] {label} map rel err {e:.3e} max {emax:.3e}", flush=True)
+        assert e <= tol and emax <= tol, (e, emax)
         assert np.all(got.reshape(nc, -1)[:, ~mask] == 0)
 
 
@@ -76,15 +77,18 @@ def test_iqu256_full_size_circulant_and_pcg(full):
     assert info["n_floored"] == Mo.n_floored
     r = (np.random.default_rng(6).standard_normal((nc, npix)) * mask).ravel()
     got = _to_host(torch, g.apply_precon("circulant", torch.from_numpy(r).cuda()))
-    e = rel(got, Mo(r))
-    print(f"[full size] circulant apply rel err {e:.3e} floored={info['n_floored']}", flush=True)
-    assert e <= 1e-4, e
+    want = Mo(r)
+    e, emax = rel(got, want), relmax(got, want)
+    print(f"[full size] circulant apply rel err {e:.3e} max {emax:.3e} "
+          f"floored={info['n_floored']}", flush=True)
+    assert e <= 1e-4 and emax <= 1e-4, (e, emax)
     # PCG to 1e-6 on b = A m_sky (oracle), checked under the oracle's A
     b = oracle.apply_A(o, (inp.sky.reshape(nc, npix) * mask).ravel(), mask)
-    res = g.pcg("circulant", torch.from_numpy(b).cuda(), tol=1e-6, maxiter=2000)
+    res = g.pcg("circulant", torch.from_numpy(b).cuda(), tol=1e-6, maxiter=2000, refine=2)
     x = _to_host(torch, res["x"])
     tr = np.linalg.norm(b - oracle.apply_A(o, x, mask)) / np.linalg.norm(b)
     print(f"[full size] circulant PCG iters={res['iters']} rel={res['rel_resid']:.2e} "
-          f"true={tr:.2e}", flush=True)
-    assert res["converged"]
-    assert tr <= 1e-6 + TOL32_SKY, tr
+          f"gpu true={res['true_rel_resid']:.2e} restarts={res['restarts']} "
+          f"oracle true={tr:.2e}", flush=True)
+    assert res["converged"] and res["true_rel_resid"] <= 1e-6
+    assert tr <= 1e-6, tr

@@ -2,9 +2,12 @@
 accumulation) against the FP64 oracle.
 
 Tolerances: one convolution layer 1e-2 relative L2 (bf16 inputs and weights:
-2^-9 relative rounding each); the four-layer H^T H and the weight gradients
-3e-2; M_L applied to a residual 1e-2 (the correction is a small part of
-M_L r); training pairs built in float64 and stored as float32: 1e-6.
+2^-9 relative rounding each); the four-layer H^T H 3e-2; the weight
+gradients 2e-2 (each gradient is a sum over pixels of products of two bf16
+activations, whose errors partly cancel; measured a few 1e-3); M_L applied to
+a residual 1e-2 (the correction is a small part of M_L r); training pairs
+built in float64 and stored as float32: 1e-6.  PCG with M_L takes the
+flexible beta, in the library and in the oracle.
 """
 
 import numpy as np
@@ -73,7 +76,7 @@ def test_gradients_match_oracle():
     print(f"[grad] loss {loss:.6g} vs {lo:.6g}; g1 {rel(g1, go1):.2e} g2 {rel(g2, go2):.2e}",
           flush=True)
     assert abs(loss - lo) <= 1e-2 * abs(lo)
-    assert rel(g1, go1) <= 3e-2 and rel(g2, go2) <= 3e-2
+    assert rel(g1, go1) <= 2e-2 and rel(g2, go2) <= 2e-2
     # the hook leaves the weights unchanged
     w1, w2 = lrn.weights()
     assert np.array_equal(w1, W1.astype(np.float32)) and np.array_equal(w2, W2.astype(np.float32))
@@ -133,10 +136,17 @@ def test_zero_weights_give_circulant_and_apply_parity():
     s = pair.masked_random(4)
     zs = pair.host(pair.g.apply_precon("learned", pair.dev(s)))
     a, b = s @ zl, r @ zs
+    asym = abs(a - b) / (np.linalg.norm(s) * np.linalg.norm(zl - zc))
+    print(f"[M_L] symmetry |s.M r - r.M s| / (|s| |M_L r - M_C r|) = {asym:.2e}", flush=True)
     assert abs(a - b) <= 3e-2 * np.linalg.norm(s) * np.linalg.norm(zl - zc) + 1e-9 * abs(a)
     bb = pair.A_oracle(pair.masked_random(5))
     res = pair.g.pcg("learned", pair.dev(bb), tol=1e-8, maxiter=500)
     assert res["converged"]
+    # the flexible beta of the library against the oracle's, M_L in float64
+    ro = oracle.pcg(pair.A_oracle, Mo, bb, tol=1e-8, maxiter=500, flexible=True)
+    print(f"[M_L PCG] iterations gpu {res['iters']} oracle (flexible) {ro.iters}", flush=True)
+    assert ro.converged
+    assert abs(res["iters"] - ro.iters) <= max(1, 0.05 * ro.iters)
 
 
 def test_training_pairs_match_oracle():

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from conftest import small_raster
-from gpu_common import Pair, rel
+from gpu_common import Pair, rel, relmax
 from synth import make_workload, crosslinked_torus_scan
 
 pytestmark = pytest.mark.gpu
@@ -60,6 +60,52 @@ def test_circulant_apply(case):
     e = rel(got, Mo(r))
     print(f"[circulant {label}] {e:.3e} floored={info['n_floored']}", flush=True)
     assert e <= tol
+
+
+FLOOR = [
+    # label, nc, sigma, eps: None = the default 1e-6 with the negative
+    # eigenvalues of an untapered strongly 1/f scan; a float = the fraction of
+    # eigenvalues to floor, eps put half way into a gap of the oracle's spectrum
+    ("I-untapered", 1, 0.0, None),
+    ("IQU-untapered", 3, 0.0, None),
+    ("IQU-taper-gap", 3, 3.0, 0.3),
+]
+
+
+@pytest.mark.parametrize("case", FLOOR, ids=[c[0] for c in FLOOR])
+def test_circulant_active_floor(case):
+    """The eigenvalue floor engaged: the same eigenvalues of K(k) are raised
+    (count per Hermitian eigenvalue) and M_C r agrees to 1e-9 in float64."""
+    label, nc, sigma, frac = case
+    inp = small_raster(ncomp=nc, ny=16, nx=16, ndet=5, sweeps=64, fknee=(2.0, 4.0))
+    pair = Pair(inp, tod_dtype="f64")
+    Mo0 = oracle.CirculantPrecon(pair.o, pair.mask, pair.B, sigma_taper=sigma or None)
+    lam = np.sort(np.linalg.eigvalsh(Mo0.K).ravel())
+    lmax = lam[-1]
+    if frac is None:
+        eps = 1e-6
+    else:
+        i = int(frac * lam.size)
+        while lam[i + 1] - lam[i] < 1e-6 * lmax:
+            i += 1
+        eps = 0.5 * (lam[i] + lam[i + 1]) / lmax
+    # no eigenvalue within rounding of the floor: the count is decided the same way
+    assert np.abs(lam - eps * lmax).min() > 1e-6 * lmax
+    Mo = oracle.CirculantPrecon(pair.o, pair.mask, pair.B, sigma_taper=sigma or None,
+                                eig_floor_rel=eps)
+    assert Mo.n_floored > 0
+    pair.g.build_precon("circulant", sigma=sigma, eig_floor_rel=eps)
+    info = pair.g.info()
+    print(f"[floor {label}] eps={eps:.3e} floored gpu={info['n_floored']} "
+          f"oracle={Mo.n_floored}", flush=True)
+    assert info["n_floored"] == Mo.n_floored
+    for seed in (6, 7):
+        r = pair.masked_random(seed)
+        want = Mo(r)
+        got = pair.host(pair.g.apply_precon("circulant", pair.dev(r)))
+        e, emax = rel(got, want), relmax(got, want)
+        print(f"[floor {label}] seed={seed} rel {e:.3e} max {emax:.3e}", flush=True)
+        assert e <= 1e-9 and emax <= 1e-9
 
 
 def test_circulant_reference_pixel_override_and_inactive_centre():
@@ -128,14 +174,17 @@ def test_pcg_intensity_small_matches_oracle(precon):
     else:
         M = lambda v: v * np.tile(pair.mask, inp.ncomp)  # noqa: E731
     ro = oracle.pcg(pair.A_oracle, M, b, tol=1e-6, maxiter=3000)
-    rg = pair.g.pcg(precon, pair.dev(b), tol=1e-6, maxiter=3000)
+    rg = pair.g.pcg(precon, pair.dev(b), tol=1e-6, maxiter=3000, refine=2)
     x = pair.host(rg["x"])
     tr = _true_resid(pair, x, b)
     print(f"[pcg intensity_small {precon}] oracle iters={ro.iters} gpu iters={rg['iters']} "
-          f"true resid={tr:.2e}", flush=True)
+          f"true resid={tr:.2e} (gpu {rg['true_rel_resid']:.2e}, restarts {rg['restarts']})",
+          flush=True)
     assert ro.converged and rg["converged"]
     assert abs(rg["iters"] - ro.iters) <= max(1, 0.05 * ro.iters)
-    assert tr <= 2e-6
+    assert tr <= 1e-6
+    # float64 path: the library's own true residual is the oracle's to rounding
+    assert abs(rg["true_rel_resid"] - tr) <= 1e-6 * tr
     # history and scalars agree with the oracle's iteration by iteration
     k = min(len(ro.history), len(rg["history"]), 20)
     np.testing.assert_allclose(rg["history"][:k], ro.history[:k], rtol=1e-6)
@@ -203,3 +252,33 @@ def test_circulant_apply_long_side(shape):
     e = rel(got, Mo(r))
     print(f"[circulant {ny}x{nx}] {e:.3e} active={int(pair.mask.sum())}", flush=True)
     assert e <= 1e-9
+
+
+def test_pcg_true_residual_restarts():
+    """refine: after the recursive residual meets tol, b - A x is recomputed
+    and PCG restarts from x while it misses tol.  With the float32 timestream
+    the true residual stalls near the float32 rounding of A while the
+    recursive one keeps falling, so a tolerance of 1e-9 uses up every
+    restart; each restart's history entry is the true residual it starts from."""
+    inp = small_raster(ncomp=3, ny=16, nx=16, ndet=5, sweeps=64)
+    pair = Pair(inp, tod_dtype="f32")
+    b = pair.A_oracle(pair.masked_random(12))
+    pair.g.build_precon("circulant", sigma=4.0)
+    r1 = pair.g.pcg("circulant", pair.dev(b), tol=1e-9, maxiter=3000, true_residual=True)
+    assert r1["converged"] and r1["restarts"] == 0
+    tr1 = _true_resid(pair, pair.host(r1["x"]), b)
+    print(f"[refine] no restart: iters {r1['iters']} rel {r1['rel_resid']:.2e} "
+          f"true gpu {r1['true_rel_resid']:.2e} oracle {tr1:.2e}", flush=True)
+    assert r1["true_rel_resid"] > 1e-9          # the stall the restarts are for
+    assert abs(r1["true_rel_resid"] - tr1) <= 0.1 * tr1
+    r2 = pair.g.pcg("circulant", pair.dev(b), tol=1e-9, maxiter=3000, refine=2)
+    print(f"[refine] iters {r2['iters']} restarts {r2['restarts']} "
+          f"true {r2['true_rel_resid']:.2e}", flush=True)
+    assert r2["restarts"] == 2 and r2["iters"] > r1["iters"]
+    assert len(r2["history"]) == r2["iters"] + 1
+    # the first segment is the solve without restarts, iteration for iteration
+    np.testing.assert_array_equal(r2["history"][:r1["iters"]], r1["history"][:r1["iters"]])
+    # a reachable tolerance needs no restart and is met by the true residual
+    r3 = pair.g.pcg("circulant", pair.dev(b), tol=1e-6, maxiter=3000, refine=2)
+    assert r3["converged"] and r3["true_rel_resid"] <= 1e-6
+    assert _true_resid(pair, pair.host(r3["x"]), b) <= 1e-6

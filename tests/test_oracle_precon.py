@@ -276,3 +276,42 @@ def test_anorm_estimate_tracks_true_error(rng):
     # expansion, up to rounding) that tracks the truth within a modest factor
     assert np.all(est <= true * (1 + 1e-6) + 1e-12 * true[0])
     assert np.median(est / true) > 0.2
+
+
+def test_flexible_beta_equals_standard_for_symmetric_M(rng):
+    # with a symmetric M, r_{k+1}.M r_k = 0, so the Polak-Ribiere beta is the
+    # standard one: the same iterates up to rounding
+    inp = small_raster(ncomp=3, ny=8, nx=8, ndet=4)
+    sc, B, mask, A = _setup(inp)
+    M = oracle.CirculantPrecon(sc, mask, B, sigma_taper=3.0)
+    b = _signal_rhs(sc, mask, A, rng)
+    r1 = oracle.pcg(A, M, b, tol=1e-9, maxiter=200, keep_iterates=True)
+    r2 = oracle.pcg(A, M, b, tol=1e-9, maxiter=200, keep_iterates=True, flexible=True)
+    assert r1.iters == r2.iters
+    for a, c in zip(r1.iterates, r2.iterates):
+        np.testing.assert_allclose(c, a, rtol=1e-7, atol=1e-9 * np.abs(a).max())
+
+
+def test_flexible_beta_keeps_consecutive_directions_conjugate(rng):
+    # for ANY M, beta = z'.(r' - r)/rho = -alpha z'.s/rho makes p_{k+1}.A p_k = 0;
+    # the directions are the steps x_{k+1} - x_k.  The standard beta loses this
+    # when M is not symmetric.
+    inp = small_raster(ncomp=3, ny=8, nx=8, ndet=4)
+    sc, B, mask, A = _setup(inp)
+    Mb = oracle.BinnedPrecon(B, mask)
+    n = 3 * 64
+    G = np.random.default_rng(2).standard_normal((n, n)) * np.tile(mask, 3)[:, None]
+    G *= np.tile(mask, 3)[None, :]
+    Mns = lambda v: Mb(v) + 0.02 * Mb(G @ v)  # noqa: E731  (not symmetric)
+    b = _signal_rhs(sc, mask, A, rng)
+
+    def worst(res):
+        xs = [np.zeros(n)] + res.iterates
+        d = [xs[k + 1] - xs[k] for k in range(len(xs) - 1)]
+        return max(abs(d[k + 1] @ A(d[k])) / np.sqrt((d[k + 1] @ A(d[k + 1])) * (d[k] @ A(d[k])))
+                   for k in range(min(8, len(d) - 1)))
+
+    rf = oracle.pcg(A, Mns, b, tol=1e-12, maxiter=12, keep_iterates=True, flexible=True)
+    rs = oracle.pcg(A, Mns, b, tol=1e-12, maxiter=12, keep_iterates=True)
+    assert worst(rf) <= 1e-10, worst(rf)
+    assert worst(rs) > 1e-4, worst(rs)

@@ -56,3 +56,41 @@ def test_symmetric_positive_definite(rng):
     # it differs from the single circulant (the tiles see different columns)
     Mc = oracle.CirculantPrecon(sc, mask, B, sigma_taper=3.0)
     assert np.linalg.norm(Mt(x) - Mc(x)) > 1e-3 * np.linalg.norm(Mc(x))
+
+
+def test_tile_kernels_are_rows_of_A_at_each_tiles_reference(rng):
+    # Each tile's q_t(d) is Sigma_r^-T A_(r, r+d) Sigma_(r+d)^-1 at that tile's
+    # OWN reference pixel r (eq. 6, eq. 10 per tile), read off the dense A:
+    # a probe shared between tiles would add the other references' rows.
+    sc, B, mask = _setup(ny=16, nx=16, ndet=5)
+    Mt = TiledCirculantPrecon(sc, mask, B, tile=8, sigma_taper=None)
+    assert len(Mt.tiles) == 9
+    n = 3 * sc.npix
+    A = lambda v: oracle.apply_A(sc, v, mask)  # noqa: E731
+    Ad = oracle.dense_operator(A, n).reshape(3, sc.npix, 3, sc.npix)
+    d = np.arange(8)
+    dmi = np.where(d > 4, d - 8, d)
+    for t in Mt.tiles:
+        r = t["ref"]
+        assert r >= 0
+        ry, rx = divmod(r, 16)
+        for iy in range(8):
+            for ix in range(8):
+                jy, jx = (ry + dmi[iy]) % 16, (rx + dmi[ix]) % 16
+                j = jy * 16 + jx
+                want = Mt.Siginv[r].T @ Ad[:, r, :, j] @ Mt.Siginv[j] if mask[j] else 0.0
+                np.testing.assert_allclose(t["q_raw"][iy, ix], want, rtol=1e-10,
+                                           atol=1e-12 * np.abs(t["q_raw"]).max())
+
+
+def test_tile_floor_is_relative_to_the_tile(rng):
+    # an eps that floors part of one tile's spectrum floors the count the
+    # tile's own eigenvalues give (the floor of M_C applied to Q_t)
+    sc, B, mask = _setup(ny=16, nx=16, ndet=5)
+    M0 = TiledCirculantPrecon(sc, mask, B, tile=8, sigma_taper=2.0)
+    M1 = TiledCirculantPrecon(sc, mask, B, tile=8, sigma_taper=2.0, eig_floor_rel=0.45)
+    for t0, t1 in zip(M0.tiles, M1.tiles):
+        K = np.conj(np.fft.fft2(t0["q"], axes=(0, 1)))
+        lam = np.linalg.eigvalsh(K)
+        assert t1["n_floored"] == np.count_nonzero(lam < 0.45 * lam.max())
+    assert sum(t["n_floored"] for t in M1.tiles) > 0
