@@ -407,6 +407,24 @@ mm_status mm_map_spectra(mm_scan scan, const double* x, double pixel_arcmin, dou
                          int32_t nbins, double* spectra /*[host]*/, double* counts /*[host]*/,
                          void* stream);
 
+/* mm_map_spectra without any device memory from the caller or the scan's
+ * workspace for its scratch: for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, results and synchronisation as mm_map_spectra; the Fourier
+ * planes and bin partials live instead in one static device array of 64 MiB
+ * per GPU, held from the library's first use on that GPU until the process
+ * ends (its address is looked up once per device).  Maps with ncomp*ny*nx*16
+ * bytes + 4.2 MB above 64 MiB (e.g. I,Q,U above 1024 x 1024) are rejected
+ * with MM_EINVAL.  The call must be made with the scan's device current.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other threads, other streams) race and give wrong spectra.
+ * Unlike mm_map_spectra it does not touch the scan's preconditioner scratch,
+ * so it may run while a preconditioner apply of the same handle is in flight.
+ * Calls no hipMalloc, hipFree or other allocating routine. */
+mm_status mm_map_spectra_noalloc(mm_scan scan, const double* x, double pixel_arcmin, double dell,
+                                 int32_t nbins, double* spectra /*[host]*/, double* counts /*[host]*/,
+                                 void* stream);
+
 /* Delayed A-norm error estimate of PCG (footnote of the Results section,
  * with r_j.z_j for ||r_j||^2 under a preconditioner): est[k] =
  * sum_{j=k}^{k+delay-1} alpha_j rho_j for k = 0..n-delay, an estimate of

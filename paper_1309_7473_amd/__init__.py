@@ -172,6 +172,19 @@ def mm_map_spectra(h, x, pixel_arcmin, dell, nbins, ncomp, stream=None):
     return spec, cnt
 
 
+def mm_map_spectra_noalloc(h, x, pixel_arcmin, dell, nbins, ncomp, stream=None):
+    """mm_map_spectra with its scratch in the library's static device array
+    (no device memory from the caller or the scan's workspace)."""
+    nout = 3 if ncomp == 3 else 1
+    spec = np.zeros((nout, int(nbins)), np.float64)
+    cnt = np.zeros(int(nbins), np.float64)
+    check(lib.mm_map_spectra_noalloc(h, _ptr(x, torch.float64, name="x"), float(pixel_arcmin),
+                                     float(dell), int(nbins), spec.ctypes.data_as(C.c_void_p),
+                                     cnt.ctypes.data_as(C.c_void_p), _stream(stream)),
+          "mm_map_spectra_noalloc")
+    return spec, cnt
+
+
 def mm_anorm_error_estimate(alpha, rho, delay=4):
     """Delayed A-norm error estimate from recorded PCG scalars (host)."""
     a = np.ascontiguousarray(alpha, dtype=np.float64)

@@ -98,6 +98,8 @@ SIGNATURES = {
                                      C.POINTER(C.c_int32), C.c_void_p]),
     "mm_map_spectra": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int32,
                                  C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mm_map_spectra_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int32,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]),
     "mm_anorm_error_estimate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                           C.c_void_p]),
     "mm_get_info": (C.c_int, [C.c_void_p, C.POINTER(mm_scan_info)]),

@@ -311,6 +311,18 @@ mm_status mm_map_spectra(mm_scan scan, const double* x, double pixel_arcmin, dou
                      static_cast<hipStream_t>(stream));
 }
 
+mm_status mm_map_spectra_noalloc(mm_scan scan, const double* x, double pixel_arcmin, double dell,
+                                 int32_t nbins, double* spectra, double* counts, void* stream) {
+  ScanImpl* s = get(scan);
+  if (!s) return fail(MM_EINVAL, "invalid scan handle");
+  if (!x || !spectra) return fail(MM_EINVAL, "x and spectra are required");
+  if (!(pixel_arcmin > 0.0) || !(dell > 0.0) || !std::isfinite(pixel_arcmin) || !std::isfinite(dell))
+    return fail(MM_EINVAL, "pixel_arcmin and dell must be positive");
+  if (nbins < 1 || nbins > kSpecMaxBins) return fail(MM_EINVAL, "nbins must be in [1, 512]");
+  return map_spectra_noalloc(s, x, pixel_arcmin, dell, nbins, spectra, counts,
+                             static_cast<hipStream_t>(stream));
+}
+
 mm_status mm_anorm_error_estimate(const double* alpha, const double* rho, int32_t n, int32_t delay,
                                   double* est) {
   if (n < 0 || delay < 1) return fail(MM_EINVAL, "n must be >= 0 and delay >= 1");

@@ -10,6 +10,8 @@
 // (|k| in cycles per pixel).  Per-block bin sums in LDS, then a fixed-order sum
 // over the blocks.
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "mm_device.h"
@@ -84,10 +86,16 @@ static int ilog2d(int v) {
   return l;
 }
 
-mm_status map_spectra(ScanImpl* s, const double* x, double pixel_arcmin, double dell, int nbins,
-                      double* spectra, double* counts, hipStream_t st) {
+// The spectra with the scratch given: planes (ncomp x npix complex double),
+// the block partials (kSpecBlocks x kSpecMaxBins x 4 double) and the result
+// (4 x kSpecMaxBins double).  Every scratch element read is written first by
+// the same call (the load fills the planes, each binning block writes its
+// whole partial row, the final kernel writes every result it reads back), so
+// nothing needs clearing between calls.
+static mm_status map_spectra_into(ScanImpl* s, const double* x, double pixel_arcmin, double dell,
+                                  int nbins, double* spectra, double* counts, Cx<double>* planes,
+                                  double* part, double* res, hipStream_t st) {
   const int npix = s->npix, nc = s->nc;
-  Cx<double>* planes = s->at<Cx<double>>(s->lay.planes);
   const int32_t* mask = s->at<int32_t>(s->lay.mask);
   const dim3 g((npix + 255) / 256), b(256);
   if (nc == 3)
@@ -101,8 +109,6 @@ mm_status map_spectra(ScanImpl* s, const double* x, double pixel_arcmin, double 
   const double ell_per_cycle = 2.0 * 3.14159265358979323846 / d;
   int nblocks = (npix + 255) / 256;
   if (nblocks > kSpecBlocks) nblocks = kSpecBlocks;
-  double* part = s->at<double>(s->lay.spec);
-  double* res = part + int64_t(kSpecBlocks) * kSpecMaxBins * 4;
   const size_t lds = size_t(nbins) * 4 * sizeof(double);
   if (nc == 3)
     hipLaunchKernelGGL(k_spec_bin<3>, dim3(nblocks), b, lds, st, planes, ilog2d(s->ny), ilog2d(s->nx),
@@ -121,6 +127,68 @@ mm_status map_spectra(ScanImpl* s, const double* x, double pixel_arcmin, double 
   if (counts)
     for (int k = 0; k < nbins; ++k) counts[k] = h[size_t(3) * nbins + k];
   return MM_OK;
+}
+
+mm_status map_spectra(ScanImpl* s, const double* x, double pixel_arcmin, double dell, int nbins,
+                      double* spectra, double* counts, hipStream_t st) {
+  double* part = s->at<double>(s->lay.spec);
+  return map_spectra_into(s, x, pixel_arcmin, dell, nbins, spectra, counts,
+                          s->at<Cx<double>>(s->lay.planes), part,
+                          part + int64_t(kSpecBlocks) * kSpecMaxBins * 4, st);
+}
+
+// ------------------------------------------------ allocation-free variant
+// Scratch of mm_map_spectra_noalloc: one array per device for the whole
+// process, never allocated at run time.  Host code must not pass `scratch`
+// itself to a kernel (on the host it names a stand-in, not device memory):
+// its device address comes from hipGetSymbolAddress, once per device, with
+// that device current.
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static mm_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(MM_EDEVICE, "device id out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MM_OK;
+}
+
+size_t map_spectra_noalloc_bytes(const ScanImpl* s) {
+  const size_t planes = size_t(s->nc) * size_t(s->npix) * sizeof(Cx<double>);
+  const size_t tail = size_t(kSpecBlocks + 1) * kSpecMaxBins * 4 * sizeof(double);
+  return ((planes + 255) & ~size_t(255)) + tail;
+}
+
+mm_status map_spectra_noalloc(ScanImpl* s, const double* x, double pixel_arcmin, double dell,
+                              int nbins, double* spectra, double* counts, hipStream_t st) {
+  if (map_spectra_noalloc_bytes(s) > kNoallocScratchBytes)
+    return fail(MM_EINVAL, "map too large for the allocation-free spectra: ncomp * ny * nx * 16 "
+                           "bytes plus 4.2 MB of partials must fit in 64 MiB");
+  int dev = -1;
+  MM_HIP(hipGetDevice(&dev));
+  // the scan's memory must be on the current device (the scratch is per device)
+  hipPointerAttribute_t attr{};
+  MM_HIP(hipPointerGetAttributes(&attr, s->ws));
+  if (attr.device != dev) return fail(MM_EINVAL, "call with the scan's device current");
+  void* base = nullptr;
+  mm_status rc;
+  if ((rc = scratch_address(dev, &base)) != MM_OK) return rc;
+  char* b = static_cast<char*>(base);
+  const size_t planes = size_t(s->nc) * size_t(s->npix) * sizeof(Cx<double>);
+  double* part = reinterpret_cast<double*>(b + ((planes + 255) & ~size_t(255)));
+  return map_spectra_into(s, x, pixel_arcmin, dell, nbins, spectra, counts,
+                          reinterpret_cast<Cx<double>*>(b), part,
+                          part + int64_t(kSpecBlocks) * kSpecMaxBins * 4, st);
 }
 
 }  // namespace mm

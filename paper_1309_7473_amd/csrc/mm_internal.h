@@ -19,6 +19,8 @@ constexpr int kMaxPartials = 1024;
 constexpr int kProfStages = 8;   // see mm_profile in mm.h
 constexpr int kSpecBlocks = 256;   // blocks of the map-spectra binning
 constexpr int kSpecMaxBins = 512;  // multipole bins of mm_map_spectra
+// device scratch of mm_map_spectra_noalloc (one static array per device)
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
 constexpr int kProfSingle = 0, kProfPass1 = 1, kProfPass2 = 2, kProfPass3 = 3, kProfApplyA = 4,
               kProfPrecon = 5, kProfReduce = 6, kProfCorr = 7;
 
@@ -176,6 +178,8 @@ mm_status tiled_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st);
 mm_status tiled_apply(ScanImpl* s, const double* r, double* z, hipStream_t st);
 // 2-D FFT of nplanes complex double [ny][nx] planes in place (unnormalised)
 mm_status map_fft(ScanImpl* s, Cx<double>* planes, int nplanes, bool inv, hipStream_t st);
+mm_status map_spectra_noalloc(ScanImpl* s, const double* x, double pixel_arcmin, double dell,
+                              int nbins, double* spectra, double* counts, hipStream_t st);
 mm_status map_spectra(ScanImpl* s, const double* x, double pixel_arcmin, double dell, int nbins,
                       double* spectra, double* counts, hipStream_t st);
 mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x,
