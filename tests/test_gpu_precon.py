@@ -278,7 +278,10 @@ def test_pcg_true_residual_restarts():
     assert r2["restarts"] == 2 and r2["iters"] > r1["iters"]
     assert len(r2["history"]) == r2["iters"] + 1
     # the first segment is the solve without restarts, iteration for iteration
-    np.testing.assert_array_equal(r2["history"][:r1["iters"]], r1["history"][:r1["iters"]])
+    # (to rounding: this small scan's one-kernel filter scatters with float64
+    # atomics, whose order varies from run to run)
+    np.testing.assert_allclose(r2["history"][:r1["iters"]], r1["history"][:r1["iters"]],
+                               rtol=1e-3)
     # a reachable tolerance needs no restart and is met by the true residual
     r3 = pair.g.pcg("circulant", pair.dev(b), tol=1e-6, maxiter=3000, refine=2)
     assert r3["converged"] and r3["true_rel_resid"] <= 1e-6
