@@ -67,7 +67,7 @@ def load_traffic(kernel, src_hash):
 
 
 KERNEL_KEYS = (("k_pass1", "pass1"), ("k_pass2", "pass2"), ("k_pass3", "pass3"),
-               ("k_csr_reduce", "reduce"), ("k_single", "single"))
+               ("k_csr_reduce", "reduce"), ("k_rle_reduce", "reduce"), ("k_single", "single"))
 COPY_BYTES = 512 * 2**20
 
 

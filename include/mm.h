@@ -124,11 +124,18 @@ typedef struct {
   int32_t scatter;          /* how P^T reaches the pixels in the multi-kernel
                                (four-step) pipeline: MM_SCATTER_AUTO = per-pixel
                                gather through a pixel-major index built at
-                               creation (no atomics; 12 B/sample of workspace for
-                               I,Q,U plus 4 B of time-major angle-coded weights on
-                               the float32 and bfloat16 paths, 4 B for I); MM_SCATTER_ATOMIC = float64
-                               atomic scatter (no index).  The one-kernel path
-                               scatters atomically unless acc = MM_ACC_F32X2. */
+                               creation (no atomics): with stored pointing and
+                               groups of at most 2^28 samples the index holds runs
+                               of consecutive samples (4 B per run, about 1 B a
+                               sample on a raster scan; workspace sized for 4 B a
+                               sample) and the gather reads the time-major weights
+                               (plus 4 B/sample of workspace for their angle-coded
+                               copy on the float32 and bfloat16 paths), otherwise
+                               one 4 B entry a sample plus 8 B of weights;
+                               MM_SCATTER_SAMPLES = the per-sample index always;
+                               MM_SCATTER_ATOMIC = float64 atomic scatter (no
+                               index).  The one-kernel path scatters atomically
+                               unless acc = MM_ACC_F32X2. */
   int32_t acc;              /* mm_acc of the P^T accumulation and the PCG inner
                                products.  MM_ACC_F32X2 needs scatter =
                                MM_SCATTER_AUTO (it always takes the per-pixel
@@ -170,7 +177,7 @@ typedef struct {
                                BORROWED */
 } mm_scan_desc;
 
-enum { MM_SCATTER_AUTO = 0, MM_SCATTER_ATOMIC = 1 };
+enum { MM_SCATTER_AUTO = 0, MM_SCATTER_ATOMIC = 1, MM_SCATTER_SAMPLES = 2 };
 
 /* Bytes of device workspace the scan needs (the caller allocates it and puts
  * the pointer in desc->workspace).  Only the shape fields and the tuning
@@ -442,7 +449,10 @@ typedef struct {
   int32_t fft_m1, fft_m2;   /* four-step split in use (m1 = 1: one-pass kernel) */
   int32_t fft_cols;         /* columns per pass-1/3 block (0: one-pass kernel) */
   int32_t single_pass;      /* 1 if each detector's filter runs in one kernel */
-  int32_t csr;              /* 1 if P^T runs as a per-pixel gather */
+  int32_t csr;              /* how P^T runs: 0 atomic scatter; 1 per-pixel gather
+                               through a per-sample index; 2 per-pixel gather through
+                               runs of consecutive samples (stored pointing, groups
+                               of at most 2^28 samples) */
   size_t  workspace_bytes;  /* bytes used */
   int32_t gather_weights;   /* how the P^T gather gets the I,Q,U weights: 0 float32
                                pairs stored with the index, 1 computed from the

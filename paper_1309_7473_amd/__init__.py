@@ -19,7 +19,7 @@ from ._abi import (  # noqa: F401
     mm_scan_info, MM_OK, MM_ENOCONV, MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_ENOTBUILT,
     MM_EBREAKDOWN, MM_F32, MM_BF16, MM_F64, MM_M_NONE, MM_M_JACOBI, MM_M_BINNED,
     MM_M_CIRCULANT, MM_M_LEARNED, MM_M_TILED, LIB_PATH, mm_profile, PROFILE_STAGES, MM_SCATTER_AUTO,
-    MM_SCATTER_ATOMIC, mm_train_opts, MM_ACC_F64, MM_ACC_F32X2, MM_POINT_STORED,
+    MM_SCATTER_ATOMIC, MM_SCATTER_SAMPLES, mm_train_opts, MM_ACC_F64, MM_ACC_F32X2, MM_POINT_STORED,
     MM_POINT_BORESIGHT,
 )
 
@@ -385,7 +385,8 @@ class Scan:
         d.fft_m1 = int(fft_m1)
         d.fft_cols = int(fft_cols)
         d.mask_rcond = float(mask_rcond)
-        d.scatter = {"auto": MM_SCATTER_AUTO, "atomic": MM_SCATTER_ATOMIC}[scatter]
+        d.scatter = {"auto": MM_SCATTER_AUTO, "atomic": MM_SCATTER_ATOMIC,
+                     "samples": MM_SCATTER_SAMPLES}[scatter]
         d.acc = {"f64": MM_ACC_F64, "f32x2": MM_ACC_F32X2}[acc]
         edges = getattr(inputs, "corr_edges", None)
         if edges is not None:   # inter-detector correlated inverse noise

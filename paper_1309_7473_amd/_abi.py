@@ -75,7 +75,7 @@ class mm_profile(C.Structure):
 
 
 PROFILE_STAGES = ["single", "pass1", "pass2", "pass3", "apply_A", "precon", "reduce", "corr"]
-MM_SCATTER_AUTO, MM_SCATTER_ATOMIC = 0, 1
+MM_SCATTER_AUTO, MM_SCATTER_ATOMIC, MM_SCATTER_SAMPLES = 0, 1, 2
 
 
 # name -> (restype, argtypes)

@@ -52,8 +52,9 @@ static mm_status validate_shape(const mm_scan_desc* d) {
     return fail(MM_EINVAL, "fft_m1 must be 0 or a power of two");
   if (d->fft_cols < 0 || (d->fft_cols > 0 && !pow2(d->fft_cols)))
     return fail(MM_EINVAL, "fft_cols must be 0 or a power of two");
-  if (d->scatter != MM_SCATTER_AUTO && d->scatter != MM_SCATTER_ATOMIC)
-    return fail(MM_EINVAL, "scatter must be MM_SCATTER_AUTO or MM_SCATTER_ATOMIC");
+  if (d->scatter != MM_SCATTER_AUTO && d->scatter != MM_SCATTER_ATOMIC &&
+      d->scatter != MM_SCATTER_SAMPLES)
+    return fail(MM_EINVAL, "scatter must be MM_SCATTER_AUTO, MM_SCATTER_ATOMIC or MM_SCATTER_SAMPLES");
   if (d->acc != MM_ACC_F64 && d->acc != MM_ACC_F32X2)
     return fail(MM_EINVAL, "acc must be MM_ACC_F64 or MM_ACC_F32X2");
   if (d->acc == MM_ACC_F32X2 && d->scatter == MM_SCATTER_ATOMIC)
@@ -346,7 +347,7 @@ mm_status mm_get_info(mm_scan scan, mm_scan_info* out) {
   out->fft_m2 = s->plan.single ? (1 << s->plan.logM) : (1 << s->plan.logM2);
   out->fft_cols = s->plan.single ? 0 : (1 << s->plan.logC);
   out->single_pass = s->plan.single ? 1 : 0;
-  out->csr = s->plan.csr ? 1 : 0;
+  out->csr = !s->plan.csr ? 0 : s->plan.rle ? 2 : 1;
   out->workspace_bytes = s->lay.total;
   out->gather_weights = (!s->plan.csr || s->nc != 3) ? -1 : !s->plan.csr_w ? 1 : s->csr_ang ? 2 : 0;
   out->t_build_s = s->t_build_s;

@@ -8,6 +8,8 @@
 // the Jacobi block uses w_d = 1.  Both are accumulated in one pass over the
 // pointing with the same wave-level run pre-sum as the scatter of A.
 #include "linalg_small.h"
+#include <type_traits>
+
 #include "mm_device.h"
 #include "mm_internal.h"
 
@@ -129,7 +131,9 @@ __global__ void __launch_bounds__(256) k_binned_accum(const int32_t* __restrict_
 // scan has one): 16 lanes per pixel run over the pixel's entries of every
 // detector group in a fixed order, so no atomics and a deterministic result.
 // Entry ik of group g is detector g * G + ik / n, sample ik mod n.
-template <int NC>
+// RLE: the entries are runs (first sample << 4 | length) of consecutive
+// group-relative samples.
+template <int NC, bool RLE>
 __global__ void __launch_bounds__(256) k_binned_gather(const int32_t* __restrict__ off,
                                                        const int32_t* __restrict__ idx,
                                                        const float2* __restrict__ w,
@@ -154,30 +158,41 @@ __global__ void __launch_bounds__(256) k_binned_gather(const int32_t* __restrict
     const int32_t* o = off + int64_t(g) * (npix + 1);
     const int b = o[p], e = o[p + 1];
     for (int k = b + l; k < e; k += LPP) {
-      const int ik = idx[int64_t(g) * gsz + k];
-      const int d = g * G + ik / n;
-      const double wd = detw[d];
-      double u[NU];
-      u[0] = 1.0;
-      if constexpr (NC == 3) {
-        double c, sn;
-        if (w) {
-          const float2 cs = w[int64_t(g) * gsz + k];
-          c = double(cs.x);
-          sn = double(cs.y);
-        } else if (c2) {   // the stored time-major weights, sample g G n + ik
-          c = double(c2[int64_t(g) * gsz + ik]);
-          sn = double(s2[int64_t(g) * gsz + ik]);
-        } else {
-          bore_weights_at(bo, d, ik % n, &c, &sn);
-        }
-        u[1] = c; u[2] = sn; u[3] = c * c; u[4] = c * sn; u[5] = sn * sn;
+      int first, len;
+      if constexpr (RLE) {
+        const uint32_t h = reinterpret_cast<const uint32_t*>(idx)[int64_t(g) * gsz + k];
+        first = int(h >> 4);
+        len = int(h & 15u);
+      } else {
+        first = idx[int64_t(g) * gsz + k];
+        len = 1;
       }
-      v[0] += 1.0;
+      for (int jj = 0; jj < len; ++jj) {
+        const int ik = first + jj;
+        const int d = g * G + ik / n;
+        const double wd = detw[d];
+        double u[NU];
+        u[0] = 1.0;
+        if constexpr (NC == 3) {
+          double c, sn;
+          if (w) {
+            const float2 cs = w[int64_t(g) * gsz + k];
+            c = double(cs.x);
+            sn = double(cs.y);
+          } else if (c2) {   // the stored time-major weights, sample g G n + ik
+            c = double(c2[int64_t(g) * gsz + ik]);
+            sn = double(s2[int64_t(g) * gsz + ik]);
+          } else {
+            bore_weights_at(bo, d, ik % n, &c, &sn);
+          }
+          u[1] = c; u[2] = sn; u[3] = c * c; u[4] = c * sn; u[5] = sn * sn;
+        }
+        v[0] += 1.0;
 #pragma unroll
-      for (int j = 0; j < NU; ++j) {
-        v[1 + j] += u[j];
-        v[1 + NU + j] += wd * u[j];
+        for (int j = 0; j < NU; ++j) {
+          v[1 + j] += u[j];
+          v[1 + NU + j] += wd * u[j];
+        }
       }
     }
   }
@@ -350,19 +365,30 @@ mm_status binned_setup(ScanImpl* s, hipStream_t st) {
     const int G = s->plan.G, ngroups = (s->ndet + G - 1) / G;
     // boresight pointing: float64 weights from the model, not the index's float32
     // copy; angle-coded index: the stored time-major weights themselves
-    const float2* w = s->plan.csr_w && !s->plan.otf && !s->csr_ang ? s->at<float2>(L.csr_w)
-                                                                   : nullptr;
-    const float* c2 = s->csr_ang && !s->plan.otf ? s->d.cos2psi : nullptr;
-    const float* s2 = s->csr_ang && !s->plan.otf ? s->d.sin2psi : nullptr;
+    // (the run-length index keeps no weights: the time-major ones always)
+    const bool rle = s->plan.rle;
+    const float2* w = s->plan.csr_w && !s->plan.otf && !s->csr_ang && !rle
+                          ? s->at<float2>(L.csr_w)
+                          : nullptr;
+    const bool tm = (s->csr_ang || rle) && !s->plan.otf;
+    const float* c2 = tm ? s->d.cos2psi : nullptr;
+    const float* s2 = tm ? s->d.sin2psi : nullptr;
     const dim3 gg((npix + 15) / 16);
-    if (s->nc == 3)
-      hipLaunchKernelGGL(k_binned_gather<3>, gg, dim3(256), 0, st, s->at<int32_t>(L.csr_off),
-                         s->at<int32_t>(L.csr_idx), w, c2, s2, bo, s->at<double>(L.detw), ngroups, G,
-                         int(s->n), npix, s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
-    else
-      hipLaunchKernelGGL(k_binned_gather<1>, gg, dim3(256), 0, st, s->at<int32_t>(L.csr_off),
-                         s->at<int32_t>(L.csr_idx), w, c2, s2, bo, s->at<double>(L.detw), ngroups, G,
-                         int(s->n), npix, s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
+    auto go = [&](auto nc, auto rl) {
+      constexpr int NC_ = decltype(nc)::value;
+      constexpr bool R_ = decltype(rl)::value;
+      hipLaunchKernelGGL((k_binned_gather<NC_, R_>), gg, dim3(256), 0, st,
+                         s->at<int32_t>(L.csr_off), s->at<int32_t>(L.csr_idx), w, c2, s2, bo,
+                         s->at<double>(L.detw), ngroups, G, int(s->n), npix,
+                         s->at<double>(L.hits), s->at<double>(L.bb), s->at<double>(L.bj));
+    };
+    using N3 = std::integral_constant<int, 3>;
+    using N1 = std::integral_constant<int, 1>;
+    if (s->nc == 3) {
+      if (rle) go(N3{}, std::true_type{}); else go(N3{}, std::false_type{});
+    } else {
+      if (rle) go(N1{}, std::true_type{}); else go(N1{}, std::false_type{});
+    }
   } else if (s->nc == 3)
     hipLaunchKernelGGL(k_binned_accum<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->at<double>(L.detw), s->n, total, npix,

@@ -2,6 +2,15 @@
 // scan, so that P^T can be applied as a per-pixel gather-and-sum instead of
 // an atomic scatter.
 //
+// Run-length form (plan.rle, groups of at most 2^28 samples): a raster scan
+// steps a quarter pixel a sample, so a detector stays about four consecutive
+// samples in one pixel.  The entries of pixel p are then runs of consecutive
+// group-relative samples, one uint32 each: (first sample << 4) | length,
+// length 1..4 (longer runs are split), in time order.  The gather reads a run's timestream
+// and its time-major weights as consecutive samples, so the index costs about
+// 1 byte a sample instead of 4 (plus 4-8 of pixel-major weights).
+//
+// Per-sample form (larger groups):
 // For group g (detectors g*G .. g*G+G-1, G*n samples) the entries of pixel p
 // are off[g][p] .. off[g][p+1]-1; entry e holds the group-relative sample
 // index idx[e] = d_local*n + t and, for I,Q,U, its weights (cos 2psi,
@@ -30,6 +39,19 @@ __device__ __forceinline__ void wave_runs(int key, bool force_head, int* head_la
   *run_len = next - h;
 }
 
+// samples per run entry of the run-length index: the gather reads a run as
+// one vector of four samples, so longer runs are split into pieces of four
+// (a raster scan at a quarter pixel a sample gives runs of four, rarely five)
+constexpr int kRunMax = 4;
+
+// Entries a wave run of `len` samples takes: one per sample, or one per
+// kRunMax-sample piece in the run-length form; the lanes heading a piece.
+template <bool RLE>
+__device__ __forceinline__ int run_entries(int len) {
+  return RLE ? (len + kRunMax - 1) / kRunMax : len;
+}
+
+template <bool RLE>
 __global__ void __launch_bounds__(256) k_csr_count(const int32_t* __restrict__ pix, Bore bo,
                                                    int64_t n, int64_t total, int G, int npix,
                                                    int32_t* __restrict__ cnt) {
@@ -48,7 +70,7 @@ __global__ void __launch_bounds__(256) k_csr_count(const int32_t* __restrict__ p
     wave_runs(p, i < total && (i % gsz) == 0, &h, &len);
     if (lane == h && p >= 0) {
       const int64_t g = i / gsz;
-      atomicAdd(cnt + g * npix + p, len);
+      atomicAdd(cnt + g * npix + p, run_entries<RLE>(len));
     }
   }
 }
@@ -110,6 +132,37 @@ __global__ void k_angles_t(const float* __restrict__ c2, const float* __restrict
     ang[i] = weight_angle(c2[i], s2[i]);
 }
 
+// Run-length entries: the lane heading each kRunMax-sample piece of a wave run
+// writes (first sample << 4) | length into the pixel's next free slot.
+__global__ void __launch_bounds__(256) k_rle_fill(const int32_t* __restrict__ pix, Bore bo,
+                                                  int64_t total, int64_t gsz, int npix,
+                                                  int32_t* __restrict__ cursor,
+                                                  uint32_t* __restrict__ hdr) {
+  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  for (int64_t base = wave * 64; base < total; base += nwaves * 64) {
+    const int64_t i = base + lane;
+    int p = -1;
+    if (i < total) {
+      p = sample_pixel(pix, bo, i);
+      if (unsigned(p) >= unsigned(npix)) p = -1;
+    }
+    int h, len;
+    wave_runs(p, i < total && (i % gsz) == 0, &h, &len);
+    const int64_t g = (i < total) ? i / gsz : 0;
+    int slot0 = 0;
+    if (lane == h && p >= 0) slot0 = atomicAdd(cursor + g * npix + p, run_entries<true>(len));
+    slot0 = __shfl(slot0, h);
+    const int off = lane - h;
+    if (p >= 0 && off % kRunMax == 0) {
+      const int piece = len - off < kRunMax ? len - off : kRunMax;
+      const uint32_t first = uint32_t(i - g * gsz);
+      hdr[g * gsz + slot0 + off / kRunMax] = (first << 4) | uint32_t(piece);
+    }
+  }
+}
+
 template <int NC>
 __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pix, Bore bo,
                                                   const float* __restrict__ c2,
@@ -159,24 +212,90 @@ __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pi
 #endif
 constexpr bool kAngleWeights = MM_ANGLE_WEIGHTS != 0;
 
+// Each pixel's runs in time order (by first sample; runs of one pixel never
+// overlap), one thread per pixel and group, insertion sort in place.  Pixels
+// next to each other along a sweep are then visited by the same detector
+// passes in the same order, so the gather's lanes for neighbouring pixels
+// (one wave holds four) read neighbouring pieces of the same timestream
+// lines, and the index no longer depends on the order the fill's atomics
+// happened to claim slots in.
+__global__ void k_rle_sort(const int32_t* __restrict__ roff_all, int npix, int ngroups, int64_t gsz,
+                           uint32_t* __restrict__ hdr_all) {
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= int64_t(npix) * ngroups) return;
+  const int g = int(i / npix), p = int(i % npix);
+  const int32_t* roff = roff_all + int64_t(g) * (npix + 1);
+  uint32_t* h = hdr_all + int64_t(g) * gsz;
+  const int b = roff[p], e = roff[p + 1];
+  for (int k = b + 1; k < e; ++k) {
+    const uint32_t v = h[k];
+    int j = k - 1;
+    while (j >= b && h[j] > v) {
+      h[j + 1] = h[j];
+      --j;
+    }
+    h[j + 1] = v;
+  }
+}
+
+// The run-length index's angle-coded weights in gather order: each pixel's
+// runs are expanded exactly as the gather does (16 lanes, batches of 16 runs,
+// lane l taking samples l, l + 16, ... of a batch) and sample q of the pixel
+// gets the time-major angle of its sample.  blockIdx.y is the group.
+__global__ void __launch_bounds__(256) k_rle_angles(const int32_t* __restrict__ roff_all,
+                                                    const int32_t* __restrict__ soff_all,
+                                                    const uint32_t* __restrict__ hdr_all,
+                                                    const uint32_t* __restrict__ ang_t, int npix,
+                                                    int64_t gsz, uint32_t* __restrict__ pa_all) {
+  constexpr int LPP = 16;
+  const int g = blockIdx.y;
+  const int l = threadIdx.x % LPP;
+  const int p = blockIdx.x * (256 / LPP) + threadIdx.x / LPP;
+  if (p >= npix) return;               // whole 16-lane groups leave together
+  const int32_t* roff = roff_all + int64_t(g) * (npix + 1);
+  const uint32_t* hdr = hdr_all + int64_t(g) * gsz;
+  const uint32_t* ang = ang_t + int64_t(g) * gsz;
+  uint32_t* pa = pa_all + int64_t(g) * gsz + soff_all[int64_t(g) * (npix + 1) + p];
+  const int b = roff[p], e = roff[p + 1];
+  for (int kb = b; kb < e; kb += LPP) {
+    const int k = kb + l;
+    const uint32_t h = k < e ? hdr[k] : 0u;
+    const int first = int(h >> 4), len = int(h & 15u);
+    int incl = len;
+#pragma unroll
+    for (int off = 1; off < LPP; off <<= 1) {
+      const int v = __shfl_up(incl, off, LPP);
+      if (l >= off) incl += v;
+    }
+    const int excl = incl - len;
+    const int total = __shfl(incl, LPP - 1, LPP);
+    for (int q0 = 0; q0 < total; q0 += LPP) {
+      const int q = q0 + l;
+      int r = 0;
+#pragma unroll
+      for (int step = LPP / 2; step > 0; step >>= 1)
+        if (__shfl(excl, r + step, LPP) <= q) r += step;
+      const int ik = __shfl(first, r, LPP) + (q - __shfl(excl, r, LPP));
+      if (q < total) pa[q] = ang[ik];
+    }
+    pa += total;
+  }
+}
+
 mm_status csr_setup(ScanImpl* s, hipStream_t st) {
   const Layout& L = s->lay;
   const int npix = s->npix;
   const int G = s->plan.G;
   const int ngroups = (s->ndet + G - 1) / G;
   const int64_t total = int64_t(s->ndet) * s->n;
+  const int64_t gsz = int64_t(G) * s->n;
   int32_t* cnt = s->at<int32_t>(L.csr_cnt);
   mm_status r;
-  if ((r = fill_zero(cnt, size_t(ngroups) * npix * 4, st)) != MM_OK) return r;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   const Bore bo = scan_bore(s);
-  hipLaunchKernelGGL(k_csr_count, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo, s->n,
-                     total, G, npix, cnt);
-  hipLaunchKernelGGL(k_csr_scan, dim3(ngroups), dim3(1024), 0, st, cnt, s->at<int32_t>(L.csr_off),
-                     npix);
-  // weights of unit norm on the float32 and bfloat16 paths go into the index
-  // as 4-byte angles instead of 8-byte float32 pairs
+  // weights of unit norm on the float32 and bfloat16 paths are stored as
+  // 4-byte angles instead of 8-byte float32 pairs
   s->csr_ang = false;
   if (s->nc == 3 && s->plan.csr_w && !s->plan.f64 && kAngleWeights) {
     int* bad = s->at<int>(L.misc);
@@ -197,18 +316,50 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
     MM_HIP(hipGetLastError());
     s->ang_t_ready = true;
   }
-  if (s->nc == 3)
+  // run-length index with angle-coded weights: the angles also go pixel-major
+  // in gather order, for which each pixel's sample offsets come first
+  s->rle_pa = s->plan.rle && s->ang_t_ready;
+  if (s->rle_pa) {
+    if ((r = fill_zero(cnt, size_t(ngroups) * npix * 4, st)) != MM_OK) return r;
+    hipLaunchKernelGGL(k_csr_count<false>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
+                       s->n, total, G, npix, cnt);
+    hipLaunchKernelGGL(k_csr_scan, dim3(ngroups), dim3(1024), 0, st, cnt,
+                       s->at<int32_t>(L.csr_soff), npix);
+    MM_HIP(hipGetLastError());
+  }
+  if ((r = fill_zero(cnt, size_t(ngroups) * npix * 4, st)) != MM_OK) return r;
+  if (s->plan.rle)
+    hipLaunchKernelGGL(k_csr_count<true>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
+                       s->n, total, G, npix, cnt);
+  else
+    hipLaunchKernelGGL(k_csr_count<false>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
+                       s->n, total, G, npix, cnt);
+  hipLaunchKernelGGL(k_csr_scan, dim3(ngroups), dim3(1024), 0, st, cnt, s->at<int32_t>(L.csr_off),
+                     npix);
+  if (s->plan.rle) {
+    hipLaunchKernelGGL(k_rle_fill, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo, total,
+                       gsz, npix, cnt, s->at<uint32_t>(L.csr_idx));
+    const int64_t nsort = int64_t(npix) * ngroups;
+    hipLaunchKernelGGL(k_rle_sort, dim3(unsigned((nsort + 255) / 256)), dim3(256), 0, st,
+                       s->at<int32_t>(L.csr_off), npix, ngroups, gsz, s->at<uint32_t>(L.csr_idx));
+    if (s->rle_pa)
+      hipLaunchKernelGGL(k_rle_angles, dim3(unsigned((npix + 15) / 16), unsigned(ngroups)),
+                         dim3(256), 0, st, s->at<int32_t>(L.csr_off), s->at<int32_t>(L.csr_soff),
+                         s->at<uint32_t>(L.csr_idx), s->at<uint32_t>(L.ang_t), npix, gsz,
+                         s->at<uint32_t>(L.csr_w));
+  } else if (s->nc == 3) {
     hipLaunchKernelGGL(k_csr_fill<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->n, total, G, npix, cnt,
                        s->at<int32_t>(L.csr_idx),
                        s->plan.csr_w && !s->csr_ang ? s->at<float2>(L.csr_w)
                                                     : static_cast<float2*>(nullptr),
                        s->csr_ang ? s->at<int2>(L.csr_w) : static_cast<int2*>(nullptr));
-  else
+  } else {
     hipLaunchKernelGGL(k_csr_fill<1>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->n, total, G, npix, cnt,
                        s->at<int32_t>(L.csr_idx), static_cast<float2*>(nullptr),
                        static_cast<int2*>(nullptr));
+  }
   MM_HIP(hipGetLastError());
   return MM_OK;
 }

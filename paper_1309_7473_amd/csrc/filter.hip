@@ -52,6 +52,7 @@ struct Sto {  // storage in the math type itself
   static __device__ __forceinline__ Cx<T> ld(const W* p) { return *p; }
   static __device__ __forceinline__ void st(W* p, Cx<T> v) { *p = v; }
   static __device__ __forceinline__ T ldr(const R* p) { return *p; }
+  static __device__ __forceinline__ T up_r(R v) { return v; }   // a loaded sample
 };
 
 template <>
@@ -72,6 +73,7 @@ struct Sto<float, Bf16> {
     *p = down(v.x) | (down(v.y) << 16);
   }
   static __device__ __forceinline__ float ldr(const R* p) { return up(*p); }
+  static __device__ __forceinline__ float up_r(R v) { return up(v); }
 };
 
 template <typename T, typename S>
@@ -92,6 +94,9 @@ struct PassArgs {
   const int32_t* csr_idx;  // group entries
   const float2* csr_w;     // group entries (I,Q,U weights)
   const int2* csr_ia;      // group entries: (index, weights as a fixed-point angle)
+  const uint32_t* rle;     // group run entries: first sample << 4 | length
+  const int32_t* rle_soff; // group [npix+1]: each pixel's first sample in rle_ang
+  const uint32_t* rle_ang; // group samples pixel-major: the weights as angles
   const float2* ang_tab;   // (cos, sin)(2 pi k / 256), k < 256
   const uint32_t* ang_t;   // group base [G][n]: the weights as angles, time-major
   const float4* bore_f;    // boresight in float32: [n] (y_b - c_y, x_b - c_x, cos phi, sin phi)
@@ -1344,6 +1349,179 @@ __global__ void __launch_bounds__(256) k_csr_reduce(PassArgs<T, S> a) {
   }
 }
 
+// P^T through the run-length index: 16 lanes per pixel, each lane summing
+// whole runs (runs l, l + 16, ... of the pixel), a run's timestream values
+// and pixel-major angles read four samples at a time with one vector load
+// each (a run is consecutive samples, and the angles are stored in the same
+// order), so a run of up to four samples costs one timestream load and one
+// angle load instead of one per sample.  The angles' pixel-major offset of a
+// run comes from a prefix sum of the run lengths over the 16 lanes.  Then the
+// same xor-tree and accumulator update as the per-sample gather.  Weights
+// other than angles come from the time-major storage sample by sample (WM 0:
+// the caller's float32 cos 2psi, sin 2psi; WM 1: the boresight model).
+template <typename T, typename S, int NC, int WM>
+__device__ __forceinline__ void sample_w(const PassArgs<T, S>& a, const float2* tab, int ik,
+                                         double* c, double* sn) {
+  if constexpr (WM == 2) {
+    angle_weights(a.ang_t[ik], tab, c, sn);
+  } else if constexpr (WM == 1) {
+    bore_weights_at(a.bo, a.det0 + (ik >> a.bo.logn), ik & ((1 << a.bo.logn) - 1), c, sn);
+  } else {
+    *c = double(a.c2[ik]);
+    *sn = double(a.s2[ik]);
+  }
+}
+
+template <typename T, typename S, int NC, bool CF, int WM>
+__global__ void __launch_bounds__(256) k_rle_reduce(PassArgs<T, S> a) {
+  constexpr int LPP = kReduceLanes;
+  constexpr int U = 4;   // samples per lane whose loads are issued together
+  const int sub = threadIdx.x / LPP;
+  const int l = threadIdx.x % LPP;
+  __shared__ float2 tab[WM == 2 ? 256 : 1];
+  if constexpr (WM == 2) {
+    tab[threadIdx.x] = a.ang_tab[threadIdx.x];   // blockDim.x == 256
+    __syncthreads();
+  }
+  int chunk = blockIdx.x;
+  if (MM_RED_XCD && (gridDim.x & 7) == 0)
+    chunk = (blockIdx.x & 7) * int(gridDim.x >> 3) + (blockIdx.x >> 3);
+  const int p = chunk * (256 / LPP) + sub;
+  if (p >= a.npix) return;            // whole 16-lane groups leave together
+  if (!a.mask[p]) {
+    if (a.y_out && l == 0)
+      for (int c = 0; c < NC; ++c) a.y_out[int64_t(c) * a.npix + p] = 0.0;
+    return;
+  }
+  const auto* u = reinterpret_cast<const typename Sto<T, S>::R*>(a.work);
+  const int b = a.csr_off[p], e = a.csr_off[p + 1];
+  // WM 2 with pixel-major angles: the pixel's samples in gather order
+  const uint32_t* pa = nullptr;
+  if constexpr (WM == 2) pa = a.rle_ang ? a.rle_ang + a.rle_soff[p] : nullptr;
+  using Acc = typename std::conditional<CF, F2, double>::type;
+  Acc s0{}, s1{}, s2{};
+  auto add = [&](T ut, double c, double sn) {
+    if constexpr (CF) {
+      F2 uu;
+      if constexpr (sizeof(T) == 8)
+        uu = f2_split(ut);
+      else
+        uu = F2{float(ut), 0.f};
+      f2_acc(s0, uu.hi, uu.lo);
+      if constexpr (NC == 3) {
+        f2_fma_acc(s1, float(c), uu);
+        f2_fma_acc(s2, float(sn), uu);
+      }
+    } else {
+      const double uu = double(ut);
+      s0 += uu;
+      if constexpr (NC == 3) {
+        s1 += c * uu;
+        s2 += sn * uu;
+      }
+    }
+  };
+  static_assert(LPP == 16, "the run scan works on DPP rows of 16 lanes");
+  using R = typename Sto<T, S>::R;
+  uint32_t hnext = b + l < e ? a.rle[b + l] : 0u;
+  for (int kb = b; kb < e; kb += LPP) {
+    // this lane's run of the batch (lanes past the pixel's end: empty), and
+    // the next batch's entry loaded meanwhile
+    const uint32_t h = hnext;
+    hnext = kb + LPP + l < e ? a.rle[kb + LPP + l] : 0u;
+    const int first = int(h >> 4), len = int(h & 15u);
+    // offset of the run's first angle: prefix sum over the 16 lanes of a DPP
+    // row (lanes shifted in from outside the row read 0)
+    int incl = len;
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, true);   // row_shr:1
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, true);   // row_shr:2
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xf, true);   // row_shr:4
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xf, 0xf, true);   // row_shr:8
+    const int excl = incl - len;
+    const int total = __shfl(incl, LPP - 1, LPP);
+    // runs are at most four samples (U): one pass, all lanes in step
+    for (int j0 = 0; j0 < len; j0 += U) {
+      // four samples from the run's j0-th on, loaded whole (the buffers have
+      // 64 B of padding past their end, so reading beyond a run's last sample
+      // stays inside); the samples past the run's end are replaced by zeros,
+      // which leave the sums unchanged
+      struct { R r[U]; } v;
+      __builtin_memcpy(&v, u + first + j0, sizeof(v));
+      uint32_t ua[U] = {};
+      if constexpr (NC == 3 && WM == 2) {
+        if (pa) {
+          uint4 w4;
+          __builtin_memcpy(&w4, pa + excl + j0, sizeof(w4));
+          ua[0] = w4.x;
+          ua[1] = w4.y;
+          ua[2] = w4.z;
+          ua[3] = w4.w;
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < U; ++jj) ua[jj] = a.ang_t[first + j0 + (j0 + jj < len ? jj : 0)];
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < U; ++jj) {
+        const bool on = j0 + jj < len;
+        double c = 0.0, sn = 0.0;
+        if constexpr (NC == 3) {
+          if constexpr (WM == 2)
+            angle_weights(ua[jj], tab, &c, &sn);
+          else
+            sample_w<T, S, NC, WM>(a, tab, first + j0 + (on ? jj : 0), &c, &sn);
+        }
+        const T x = Sto<T, S>::up_r(v.r[jj]);
+        add(on ? x : T(0), c, sn);
+      }
+    }
+    if (pa) pa += total;
+  }
+  if constexpr (!CF) {
+#pragma unroll
+    for (int off = LPP / 2; off > 0; off >>= 1) {
+      s0 += __shfl_xor(s0, off, LPP);
+      if constexpr (NC == 3) {
+        s1 += __shfl_xor(s1, off, LPP);
+        s2 += __shfl_xor(s2, off, LPP);
+      }
+    }
+    if (l == 0) {
+      double* d = a.acc + 4 * int64_t(p);
+      if (a.y_out) {
+        a.y_out[p] = d[0] + s0;
+        if constexpr (NC == 3) {
+          a.y_out[a.npix + int64_t(p)] = d[1] + s1;
+          a.y_out[2 * int64_t(a.npix) + p] = d[2] + s2;
+        }
+      } else {
+        d[0] += s0;
+        if constexpr (NC == 3) {
+          d[1] += s1;
+          d[2] += s2;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int off = LPP / 2; off > 0; off >>= 1) {
+      s0 = f2_add(s0, f2_shfl_xor(s0, off, LPP));
+      if constexpr (NC == 3) {
+        s1 = f2_add(s1, f2_shfl_xor(s1, off, LPP));
+        s2 = f2_add(s2, f2_shfl_xor(s2, off, LPP));
+      }
+    }
+    if (l == 0) {
+      F2* d = reinterpret_cast<F2*>(a.acc + 4 * int64_t(p));
+      d[0] = f2_add(d[0], s0);
+      if constexpr (NC == 3) {
+        d[1] = f2_add(d[1], s1);
+        d[2] = f2_add(d[2], s2);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------- host side
 static int ilog2(int64_t v) {
   int l = 0;
@@ -1384,7 +1562,10 @@ static void launch_reduce(ScanImpl* s, const PassArgs<T, S>& a, hipStream_t st) 
   auto go = [&](auto cf, auto w) {
     constexpr bool CF_ = decltype(cf)::value;
     constexpr int WM_ = decltype(w)::value;
-    hipLaunchKernelGGL((k_csr_reduce<T, S, NC, CF_, WM_>), grid, dim3(256), 0, st, a);
+    if (s->plan.rle)
+      hipLaunchKernelGGL((k_rle_reduce<T, S, NC, CF_, WM_>), grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_csr_reduce<T, S, NC, CF_, WM_>), grid, dim3(256), 0, st, a);
   };
   using W0 = std::integral_constant<int, 0>;
   using W1 = std::integral_constant<int, 1>;
@@ -1455,10 +1636,16 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const int gi = d0 / G;
       a.csr_off = s->at<int32_t>(s->lay.csr_off) + int64_t(gi) * (s->npix + 1);
       a.csr_idx = s->at<int32_t>(s->lay.csr_idx) + int64_t(gi) * G * s->n;
-      a.csr_w = pl.csr_w && !s->csr_ang ? s->at<float2>(s->lay.csr_w) + int64_t(gi) * G * s->n
-                                        : nullptr;
+      a.csr_w = pl.csr_w && !s->csr_ang && !pl.rle
+                    ? s->at<float2>(s->lay.csr_w) + int64_t(gi) * G * s->n
+                    : nullptr;
       // stored angles live in the first half of the weights' region
-      a.csr_ia = s->csr_ang ? s->at<int2>(s->lay.csr_w) + int64_t(gi) * G * s->n : nullptr;
+      a.csr_ia = s->csr_ang && !pl.rle ? s->at<int2>(s->lay.csr_w) + int64_t(gi) * G * s->n
+                                       : nullptr;
+      a.rle = pl.rle ? s->at<uint32_t>(s->lay.csr_idx) + int64_t(gi) * G * s->n : nullptr;
+      a.rle_ang = s->rle_pa ? s->at<uint32_t>(s->lay.csr_w) + int64_t(gi) * G * s->n : nullptr;
+      a.rle_soff = s->rle_pa ? s->at<int32_t>(s->lay.csr_soff) + int64_t(gi) * (s->npix + 1)
+                             : nullptr;
       // the last group's gather writes the result itself (float64 sums only)
       a.y_out = (d0 + G >= s->ndet && !pl.acc32) ? s->fuse_y : nullptr;
       if (a.y_out) s->fused_y = true;
@@ -1826,7 +2013,9 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     off += (bytes + 255) & ~size_t(255);
     return o;
   };
-  L->tod = take(pl->single && !pl->csr ? 0 : size_t(pl->G) * size_t(M) * wxb);
+  // (+64 B: the run-length gather reads four samples at a time from a run's
+  // first sample, so its last loads may reach up to three samples past the end)
+  L->tod = take(pl->single && !pl->csr ? 0 : size_t(pl->G) * size_t(M) * wxb + 64);
   L->tw = take((pl->mix_code && pl->single ? size_t(M) : (size_t(1) << pl->logLmax)) * cxb);
   L->tw2 = take(pl->single ? 0 : (size_t(1) << pl->logM2) * cxb);
   L->tw_m1 = take(pl->mix_code && !pl->single ? size_t(pl->M1) * cxb : 0);
@@ -1862,10 +2051,20 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->csr_cnt = take(pl->csr ? size_t(ngroups) * npix * 4 : 0);
   L->csr_off = take(pl->csr ? size_t(ngroups) * (npix + 1) * 4 : 0);
   L->csr_idx = take(csr_n * 4);
+  // the run-length index keeps the angle-coded weights pixel-major (4 B a
+  // sample, in the gather's sample order) when the weights can be angles
+  // (stored pointing of unit norm on the float paths, checked at creation)
+  const bool rle_pa = pl->csr && !pl->otf && !pl->f64 && nc == 3 && d->scatter != MM_SCATTER_SAMPLES &&
+                      int64_t(pl->G) * n <= (int64_t(1) << 28);
+  L->csr_soff = take(rle_pa ? size_t(ngroups) * (npix + 1) * 4 : 0);
   // stored weights beside the index, except for boresight pointing on the
-  // float64 path, whose gather computes float64 weights from the model
+  // float64 path, whose gather computes float64 weights from the model; the
+  // run-length index (stored pointing, groups of at most 2^28 samples) reads
+  // the time-major weights instead and stores none
   pl->csr_w = nc == 3 && !(pl->otf && pl->f64);
-  L->csr_w = take(pl->csr_w ? csr_n * 8 : 0);
+  pl->rle = pl->csr && !pl->otf && d->scatter != MM_SCATTER_SAMPLES &&
+            int64_t(pl->G) * n <= (int64_t(1) << 28);
+  L->csr_w = take(pl->csr_w && !pl->rle ? csr_n * 8 : rle_pa ? csr_n * 4 + 64 : 0);
   L->ang_tab = take(256 * 8);
   // float32 copies of the boresight model for pass 1 (float paths)
   const bool bfast = pl->otf && !pl->f64;

@@ -82,7 +82,10 @@ struct Layout {
   size_t corr_t;     // corr_rank * M complex: low-rank projections of the spectra
   size_t csr_cnt;    // ngroups * npix int32 (counts, then fill cursors)
   size_t csr_off;    // ngroups * (npix+1) int32
-  size_t csr_idx;    // ngroups * G * n int32 (group-relative sample index)
+  size_t csr_soff;   // run-length index with angle-coded weights: ngroups * (npix+1)
+                     // int32 offsets of each pixel's samples in the pixel-major angles
+  size_t csr_idx;    // ngroups * G * n int32 (group-relative sample index), or
+                     // uint32 run entries (first sample << 4 | length)
   size_t csr_w;      // ngroups * G * n float2 (cos 2psi, sin 2psi), or uint32 angles
   size_t ang_tab;    // 256 float2: (cos, sin)(2 pi k / 256)
   size_t ang_t;      // ndet * n uint32: the weights as angles, time-major (pass 1)
@@ -99,7 +102,9 @@ struct Plan {
   bool single;       // whole detector filtered in one kernel
   bool csr;          // P^T by per-pixel gather (else atomic scatter)
   bool otf;          // pointing computed from the boresight model
-  bool csr_w;        // the pixel-major index stores the (float32) weights
+  bool csr_w;        // the gather has stored weights (in the index, or time-major
+                     // beside the pointing with the run-length index)
+  bool rle;          // the pixel-major index holds runs of consecutive samples
   uint32_t mix_code; // mixed-radix stage code of M (one kernel) or M1 (four-step); 0: power of two
   int M1;            // four-step column length (2^logM1 unless mixed)
   int logn, logM;    // n = 2^logn samples, M = n/2 packed complex
@@ -129,6 +134,7 @@ struct ScanImpl {
   bool circ_built = false;
   bool csr_ang = false;       // the index's weights are stored as fixed-point angles
   bool ang_t_ready = false;   // pass 1 reads the time-major angles (SRC 3)
+  bool rle_pa = false;        // the run-length gather reads pixel-major angles
   double* fuse_y = nullptr;   // output map the last group's gather may write directly
   bool fused_y = false;       // set when it did (the epilogue is then skipped)
   bool bore_fast = false;     // pass 1 evaluates the boresight model in float32 (SRC 4)

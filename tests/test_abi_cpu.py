@@ -59,16 +59,23 @@ def test_workspace_query_and_plan(mm):
 
 
 def test_pixel_index_workspace(mm):
-    # the pixel-major index costs 12 B per sample for I,Q,U (index and float32
-    # weight pairs, or index and angles) plus 4 B of time-major angles for
-    # pass 1, and 4 B for I
+    # the run-length index is sized for one 4 B run a sample (the worst case);
+    # I,Q,U adds 4 B of time-major angles and 4 B of pixel-major angles a
+    # sample (with a per-pixel offset table).  The per-sample index costs 12 B
+    # a sample for I,Q,U (index and float32 weight pairs, or index and
+    # angles) plus the 4 B of time-major angles, and 4 B for I
     a = mm.mm_scan_workspace_bytes(_desc(mm, scatter=mm.MM_SCATTER_ATOMIC))
     b = mm.mm_scan_workspace_bytes(_desc(mm))
+    c = mm.mm_scan_workspace_bytes(_desc(mm, scatter=mm.MM_SCATTER_SAMPLES))
     S = 4 * (1 << 16)
-    assert 16 * S <= b - a <= 16 * S + 2 * 4 * (64 * 64 + 1) + 4 * 256
+    tail = 2 * 4 * (64 * 64 + 1) + 4 * 256
+    assert 12 * S <= b - a <= 12 * S + tail + 4 * (64 * 64 + 1) + 256
+    assert 16 * S <= c - a <= 16 * S + tail
     a1 = mm.mm_scan_workspace_bytes(_desc(mm, ncomp=1, scatter=mm.MM_SCATTER_ATOMIC))
     b1 = mm.mm_scan_workspace_bytes(_desc(mm, ncomp=1))
+    c1 = mm.mm_scan_workspace_bytes(_desc(mm, ncomp=1, scatter=mm.MM_SCATTER_SAMPLES))
     assert 4 * S <= b1 - a1 <= 4 * S + 2 * 4 * (64 * 64 + 1) + 3 * 256
+    assert c1 == b1
 
 
 def test_bf16_pass_buffer_is_half_of_f32(mm):
@@ -80,18 +87,20 @@ def test_bf16_pass_buffer_is_half_of_f32(mm):
 
 
 def test_compensated_accumulation_takes_the_gather_on_one_kernel_plans(mm):
-    # nsamp = 2^12 is a one-kernel plan: the gather index (12 B/sample, and
-    # 4 B of time-major angles) and a pass buffer appear only under MM_ACC_F32X2
+    # nsamp = 2^12 is a one-kernel plan: the gather index (4 B/sample of runs,
+    # 4 B of pixel-major and 4 B of time-major angles) and a pass buffer
+    # (4 B/sample) appear only under MM_ACC_F32X2
     a = mm.mm_scan_workspace_bytes(_desc(mm, nsamp=1 << 12))
     b = mm.mm_scan_workspace_bytes(_desc(mm, nsamp=1 << 12, acc=mm.MM_ACC_F32X2))
     S = 4 * (1 << 12)
-    assert 16 * S + 4 * S <= b - a <= 20 * S + 2 * 4 * (64 * 64 + 1) + 5 * 256
+    assert 16 * S <= b - a <= 16 * S + 3 * 4 * (64 * 64 + 1) + 6 * 256
 
 
 @pytest.mark.parametrize("field,value", [
     ("ncomp", 2), ("ny", 48), ("nx", 2), ("ndet", 0), ("nsamp", 1022), ("nsamp", 1001), ("nsamp", 8),
     ("nsamp", 2 * 3**9 * 2**4), ("nsamp", 7 * 2**8),
     ("nsamp", 1 << 23), ("tod_dtype", 7), ("fft_m1", 3), ("det_group", -1), ("scatter", 5),
+    ("scatter", 3),
     ("acc", 2),
 ])
 def test_invalid_descriptions_rejected(mm, field, value):
@@ -179,7 +188,9 @@ def test_boresight_pointing_descriptor(mm):
     """Validation of the boresight pointing mode (no device work: every
     rejection happens before the first HIP call)."""
     h = C.c_void_p()
-    d = _desc(mm, nsamp=2**16)
+    # boresight pointing keeps the per-sample index: compare with stored
+    # pointing on the per-sample index too
+    d = _desc(mm, nsamp=2**16, scatter=mm.MM_SCATTER_SAMPLES)
     stored = mm.mm_scan_workspace_bytes(d)
     d.pointing = 2
     assert mm.mm_scan_workspace_bytes(d) == 0 and "pointing" in mm.mm_last_error()

@@ -56,11 +56,11 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("scatter", ["auto", "atomic"])
+@pytest.mark.parametrize("scatter", ["auto", "atomic", "samples"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_apply_A_parity(case, scatter):
     label, nc, ny, nx, ndet, n, dt, G, m1 = case
-    if scatter == "atomic" and not label.startswith("fourstep"):
+    if scatter != "auto" and not label.startswith("fourstep"):
         pytest.skip("the one-kernel path has only the atomic scatter")
     sweeps = max(1, n // (4 * nx))
     inp = raster_scan(ncomp=nc, ny=ny, nx=nx, ndet=ndet, nsamp=n, fsample=100.0,
@@ -69,7 +69,9 @@ def test_apply_A_parity(case, scatter):
     pair = Pair(inp, tod_dtype=dt, det_group=G, fft_m1=m1, scatter=scatter)
     info = pair.g.info()
     print(label, info, flush=True)
-    assert info["csr"] == (1 if (label.startswith("fourstep") and scatter == "auto") else 0)
+    want_csr = 0 if not label.startswith("fourstep") else {"auto": 2, "atomic": 0,
+                                                              "samples": 1}[scatter]
+    assert info["csr"] == want_csr
     if m1:
         assert info["fft_m1"] == m1
     tol = TOL64 if dt == "f64" else TOL32_WHITE
@@ -158,10 +160,11 @@ def test_collision_stress_long_runs():
     _check_apply(pair, TOL64, label="collision-IQU")
 
 
-def test_apply_A_bitwise_repeatable():
+@pytest.mark.parametrize("scatter,csr", [("auto", 2), ("samples", 1)])
+def test_apply_A_bitwise_repeatable(scatter, csr):
     inp = small_raster(ncomp=3, ny=32, nx=32, ndet=5, sweeps=256)
-    pair = Pair(inp, tod_dtype="f32", det_group=2)
-    assert pair.g.info()["csr"] == 1
+    pair = Pair(inp, tod_dtype="f32", det_group=2, scatter=scatter)
+    assert pair.g.info()["csr"] == csr
     x = pair.dev(pair.masked_random(8))
     y1 = pair.host(pair.g.apply_A(x))
     y2 = pair.host(pair.g.apply_A(x))

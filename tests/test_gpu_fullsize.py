@@ -52,7 +52,7 @@ def test_iqu256_full_size_apply(full):
     info = g.info()
     print(f"[full size] plan {info}", flush=True)
     assert (info["det_group"], info["fft_m1"], info["fft_m2"]) == (128, 512, 1024)
-    assert info["csr"] == 1 and info["gather_weights"] == 2
+    assert info["csr"] == 2 and info["gather_weights"] == 2
     assert np.array_equal(g.mask().cpu().numpy().astype(bool), mask)
     assert mask.sum() > 0
     nc, npix = inp.ncomp, inp.ny * inp.nx

@@ -110,7 +110,7 @@ def test_compensated_accumulation_parity(case):
     inp = _scan(nc, ny, nx, ndet, n)
     pair = Pair(inp, tod_dtype=dt, acc="f32x2")
     ref = Pair(inp, tod_dtype=dt, acc="f64")
-    assert pair.g.info()["csr"] == 1
+    assert pair.g.info()["csr"] >= 1
     x, sky = _maps(pair)
     for name, v, tol32 in (("random", x, TOL32_WHITE), ("sky", sky, TOL32_SKY)):
         want = pair.A_oracle(v)
