@@ -331,6 +331,21 @@ mm_status mm_pcg_solve(mm_scan scan, int32_t precon, const double* b, double* x,
                        const mm_pcg_opts* opts /*[host]*/,
                        mm_pcg_result* res /*[host]*/, void* stream);
 
+/* The judge, and with it the fallback, of a learned correction (and of any
+ * preconditioner choice): solves A x = b once with each candidate in
+ * candidates[0..n-1] (1 <= n <= 16, each a preconditioner mm_pcg_solve
+ * accepts on this scan, typically {MM_M_LEARNED, MM_M_CIRCULANT,
+ * MM_M_BINNED}), each from x0 = 0 with *opts (no snapshots), and sets *chosen
+ * to the candidate that reached opts->tol in the fewest iterations (the earlier
+ * in the list on ties; if none converged, the smallest final residual).  Run it
+ * on held-out data: the winner is the preconditioner to use for scans like it.
+ * res: [host] n results (may be NULL; history arrays in them are filled).
+ * x receives the winner's solution.  Synchronises.  Returns the winner's
+ * status (MM_OK, MM_ENOCONV or MM_EBREAKDOWN) or an error. */
+mm_status mm_precon_judge(mm_scan scan, const int32_t* candidates /*[host]*/, int32_t n,
+                          const double* b, double* x, const mm_pcg_opts* opts /*[host]*/,
+                          mm_pcg_result* res /*[host]*/, int32_t* chosen /*[host]*/, void* stream);
+
 /* Independent solves of n scans, e.g. a batch of scans of uneven detector
  * count, length and map size.  Each run gets its own stream, forked from
  * `stream` and joined back; every round enqueues opts->check_every

@@ -154,6 +154,22 @@ def mm_pcg_solve_batch(handles, precon, bs, xs, opts, stream=None):
     return st, out
 
 
+def mm_precon_judge(h, candidates, b, x, opts, stream=None):
+    """Solves A x = b with each candidate preconditioner (names or enums);
+    returns (status, chosen enum, [result dict])."""
+    cand = [PRECON[c] if isinstance(c, str) else int(c) for c in candidates]
+    n = len(cand)
+    ca = (C.c_int32 * n)(*cand)
+    res = (mm_pcg_result * n)()
+    chosen = C.c_int32(-1)
+    st = lib.mm_precon_judge(h, ca, n, _ptr(b, torch.float64, name="b"),
+                             _ptr(x, torch.float64, name="x"), C.byref(opts), res,
+                             C.byref(chosen), _stream(stream))
+    if st not in (MM_OK, MM_ENOCONV, MM_EBREAKDOWN):
+        check(st, "mm_precon_judge")
+    return st, int(chosen.value), [_result_dict(res[i], None) for i in range(n)]
+
+
 def _result_dict(res, st):
     return dict(status=st, iters=res.iters, converged=bool(res.converged),
                 rel_resid=res.rel_resid, t_solve_s=res.t_solve_s, t_setup_s=res.t_setup_s,
@@ -467,6 +483,18 @@ class Scan:
                                history_len=maxiter if history else 0)
         res["x"] = x
         return res
+
+    def judge(self, candidates, b, x=None, tol=1e-6, maxiter=5000, check_every=1, graph=False,
+              refine=0):
+        """mm_precon_judge: one solve per candidate; returns (chosen name,
+        {name: result dict}, x of the chosen solve)."""
+        x = self.new_map() if x is None else x
+        o = _pcg_opts(tol, maxiter, check_every, False, graph, False, refine, False)
+        _, chosen, out = mm_precon_judge(self.handle, candidates, b, x, o)
+        names = {v: k for k, v in PRECON.items() if k not in ("none",)}
+        names[PRECON["none"]] = "none"
+        return names[chosen], {c if isinstance(c, str) else names[c]: r
+                               for c, r in zip(candidates, out)}, x
 
     def attach_learned(self, learned):
         """Attach a Learned correction (None detaches); the scan keeps it alive."""

@@ -92,6 +92,8 @@ SIGNATURES = {
     "mm_apply_precon_tiled": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mm_pcg_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                C.POINTER(mm_pcg_opts), C.POINTER(mm_pcg_result), C.c_void_p]),
+    "mm_precon_judge": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                  C.POINTER(mm_pcg_opts), C.c_void_p, C.c_void_p, C.c_void_p]),
     "mm_pcg_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32,
                                      C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(mm_pcg_opts), C.POINTER(mm_pcg_result),

@@ -280,6 +280,20 @@ mm_status mm_pcg_solve(mm_scan scan, int32_t precon, const double* b, double* x,
   return pcg_solve(s, precon, b, x, opts, res, static_cast<hipStream_t>(stream));
 }
 
+mm_status mm_precon_judge(mm_scan scan, const int32_t* candidates, int32_t n, const double* b,
+                          double* x, const mm_pcg_opts* opts, mm_pcg_result* res, int32_t* chosen,
+                          void* stream) {
+  ScanImpl* s = get(scan);
+  if (!candidates || n < 1 || n > 16 || !chosen)
+    return fail(MM_EINVAL, "candidates (1..16) and chosen are required");
+  if (opts && opts->snapshots) return fail(MM_EINVAL, "the judge takes no snapshots");
+  for (int i = 0; i < n; ++i) {
+    const mm_status rc = check_solve(s, candidates[i], b, x, opts);
+    if (rc != MM_OK) return rc;
+  }
+  return precon_judge(s, candidates, n, b, x, opts, res, chosen, static_cast<hipStream_t>(stream));
+}
+
 mm_status mm_pcg_solve_batch(const mm_scan* scans, int32_t n, int32_t precon,
                              const double* const* b, double* const* x, const mm_pcg_opts* opts,
                              mm_pcg_result* res, int32_t* status, void* stream) {

@@ -184,6 +184,8 @@ mm_status tiled_build(ScanImpl* s, const mm_precon_opts* o, hipStream_t st);
 mm_status tiled_apply(ScanImpl* s, const double* r, double* z, hipStream_t st);
 // 2-D FFT of nplanes complex double [ny][nx] planes in place (unnormalised)
 mm_status map_fft(ScanImpl* s, Cx<double>* planes, int nplanes, bool inv, hipStream_t st);
+mm_status precon_judge(ScanImpl* s, const int32_t* cand, int n, const double* b, double* x,
+                       const mm_pcg_opts* o, mm_pcg_result* res, int32_t* chosen, hipStream_t st);
 mm_status map_spectra_noalloc(ScanImpl* s, const double* x, double pixel_arcmin, double dell,
                               int nbins, double* spectra, double* counts, hipStream_t st);
 mm_status map_spectra(ScanImpl* s, const double* x, double pixel_arcmin, double dell, int nbins,

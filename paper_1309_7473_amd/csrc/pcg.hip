@@ -658,6 +658,49 @@ mm_status pcg_solve(ScanImpl* s, int precon, const double* b, double* x, const m
   return rc;
 }
 
+// The judge of preconditioners (and with it the fallback of a learned
+// correction): one solve of A x = b per candidate, in the order given, each
+// from x0 = 0 with the caller's options; the winner is the candidate that
+// converged in the fewest iterations, the earlier one on ties (if none
+// converged, the one with the smallest final residual).  Iteration counts are
+// the paper's measure and, unlike wall times, repeatable.  The winner's
+// solution is kept in the scan's spare map vector while the later candidates
+// run and returned in x.
+mm_status precon_judge(ScanImpl* s, const int32_t* cand, int n, const double* b, double* x,
+                       const mm_pcg_opts* o, mm_pcg_result* res, int32_t* chosen, hipStream_t st) {
+  const int64_t N = int64_t(s->nc) * s->npix;
+  double* keep = s->at<double>(s->lay.vec) + 4 * N;   // spare vector: not used by PCG
+  mm_pcg_opts oo = *o;
+  oo.use_x0 = 0;
+  int best = -1, best_iters = 0, best_conv = 0;
+  double best_resid = 0.0;
+  mm_status best_rc = MM_OK;
+  for (int i = 0; i < n; ++i) {
+    mm_pcg_result r{};
+    if (res) r = res[i];   // the caller's history buffers, if any
+    const mm_status rc = pcg_solve(s, cand[i], b, x, &oo, &r, st);
+    if (rc < 0 && rc != MM_EBREAKDOWN) return rc;
+    if (res) res[i] = r;
+    const bool conv = rc == MM_OK && r.converged;
+    const bool better = best < 0 || (conv && !best_conv) ||
+                        (conv == bool(best_conv) &&
+                         (conv ? r.iters < best_iters : r.rel_resid < best_resid));
+    if (better) {
+      best = i;
+      best_iters = r.iters;
+      best_conv = conv ? 1 : 0;
+      best_resid = r.rel_resid;
+      best_rc = rc;
+      MM_HIP(hipMemcpyAsync(keep, x, size_t(N) * 8, hipMemcpyDeviceToDevice, st));
+    }
+  }
+  MM_HIP(hipMemcpyAsync(x, keep, size_t(N) * 8, hipMemcpyDeviceToDevice, st));
+  MM_HIP(hipStreamSynchronize(st));
+  *chosen = cand[best];
+  if (best_rc == MM_ENOCONV) set_error("no candidate reached the tolerance within maxiter");
+  return best_rc;
+}
+
 // Independent solves interleaved: each run gets its own stream (forked from
 // the caller's), every round enqueues check_every iterations of every
 // unfinished run before any host read, so small scans overlap on the device.

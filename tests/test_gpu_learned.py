@@ -238,3 +238,11 @@ def test_training_lowers_loss_and_reports_iterations():
            for n in ("binned", "circulant", "learned")}
     print(f"[held-out] iterations to 1e-6: {its}", flush=True)
     assert all(v < 3000 for v in its.values())
+    # the judge and fallback: the preconditioner it picks on the held-out scan
+    # is never worse than circulant or binned alone, and the learned
+    # correction is picked only if it wins outright
+    chosen, res, _ = pair.g.judge(["circulant", "binned", "learned"], b, tol=1e-6, maxiter=3000)
+    print(f"[held-out] judge picks {chosen}", flush=True)
+    assert res[chosen]["iters"] <= min(its["circulant"], its["binned"])
+    if chosen == "learned":
+        assert its["learned"] < its["circulant"]

@@ -286,3 +286,33 @@ def test_pcg_true_residual_restarts():
     r3 = pair.g.pcg("circulant", pair.dev(b), tol=1e-6, maxiter=3000, refine=2)
     assert r3["converged"] and r3["true_rel_resid"] <= 1e-6
     assert _true_resid(pair, pair.host(r3["x"]), b) <= 1e-6
+
+
+def test_precon_judge_picks_the_fewest_iterations():
+    """mm_precon_judge: one solve per candidate; the winner is the one with the
+    fewest iterations (the earlier on ties), x is its solution, and each
+    candidate's count is what its own solve takes."""
+    inp = small_raster(ncomp=3, ny=16, nx=16, ndet=5, sweeps=64, fknee=(2.0, 4.0))
+    pair = Pair(inp, tod_dtype="f64")
+    pair.g.build_precon("circulant", sigma=3.0)
+    b = pair.dev(pair.A_oracle(pair.masked_random(21)))
+    solo = {n: pair.g.pcg(n, b, tol=1e-8, maxiter=2000) for n in ("none", "binned", "circulant")}
+    its = {n: r["iters"] for n, r in solo.items()}
+    chosen, res, x = pair.g.judge(["none", "binned", "circulant"], b, tol=1e-8, maxiter=2000)
+    print(f"[judge] iterations {its}, chosen {chosen}", flush=True)
+    assert {n: r["iters"] for n, r in res.items()} == its
+    best = min(its.values())
+    assert chosen == [n for n in ("none", "binned", "circulant") if its[n] == best][0]
+    # (equal to rounding: this small scan's one-kernel filter scatters with
+    # float64 atomics, so two solves differ in the last bits)
+    xs = pair.host(solo[chosen]["x"])
+    np.testing.assert_allclose(pair.host(x), xs, rtol=1e-6, atol=1e-9 * np.abs(xs).max())
+    # a tie goes to the earlier candidate
+    chosen2, _, _ = pair.g.judge(["circulant", "circulant"], b, tol=1e-8, maxiter=2000)
+    assert chosen2 == "circulant"
+    # invalid candidates are rejected before anything runs
+    import paper_1309_7473_amd as mm
+    with pytest.raises(mm.MMError, match="EINVAL"):
+        pair.g.judge(["binned", 17], b)
+    with pytest.raises(mm.MMError, match="ENOTBUILT"):
+        pair.g.judge(["binned", "tiled"], b)
