@@ -230,7 +230,11 @@ def learned_leg(mm, train_scans, eval_scans, taper, pairs_per_scan=24, epochs=10
     lrn = mm.Learned(sc0.ncomp, sc0.ny, sc0.nx, batch, W1, W2)
     l0 = lrn.loss(RW, T, E2)
     t1 = time.perf_counter()
-    hist = lrn.train(RW, T, E2, epochs=epochs, batch=batch, lr=lr, seed=seed + 1)
+    hist = []
+    for ep in range(epochs):   # one call an epoch (Adam's state carries over)
+        hist += list(lrn.train(RW, T, E2, epochs=1, batch=batch, lr=lr, seed=seed + 1 + ep))
+        print(json.dumps({"learned_epoch": ep, "loss": round(float(hist[-1]), 5)}),
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     w1, w2 = lrn.weights()
@@ -584,48 +588,92 @@ def cpu_baseline(inp, small_taper, ndet_sample=128, reps=2):
     return out
 
 
+def _oracle_binned_part(rng_):
+    """Partial binned blocks and hits of detectors d0..d1 (forked worker)."""
+    import oracle
+    from types import SimpleNamespace
+    d0, d1 = rng_
+    inp = _CPU_SHARE["inp"]
+    sub = SimpleNamespace(ncomp=inp.ncomp, ny=inp.ny, nx=inp.nx, pix=inp.pix[d0:d1],
+                          cos2psi=inp.cos2psi[d0:d1], sin2psi=inp.sin2psi[d0:d1],
+                          inv_noise=inp.inv_noise[d0:d1])
+    o = oracle.OracleScan(sub)
+    return oracle.binned_blocks(o, oracle.detector_weights(o))
+
+
+def _oracle_rhs_apply_part(rng_):
+    """b and A x of detectors d0..d1 (forked worker): b from the noiseless
+    d = P m_sky, A x of the shared map; the A-apply is timed."""
+    import oracle
+    from types import SimpleNamespace
+    d0, d1 = rng_
+    inp, mask, x = _CPU_SHARE["inp"], _CPU_SHARE["mask"], _CPU_SHARE["x"]
+    sub = SimpleNamespace(ncomp=inp.ncomp, ny=inp.ny, nx=inp.nx, pix=inp.pix[d0:d1],
+                          cos2psi=inp.cos2psi[d0:d1], sin2psi=inp.sin2psi[d0:d1],
+                          inv_noise=inp.inv_noise[d0:d1])
+    o = oracle.OracleScan(sub)
+    b = oracle.rhs(o, oracle.pointing(o, inp.sky), mask)
+    t0 = time.perf_counter()
+    y = oracle.apply_A(o, x, mask)
+    return b, y, time.perf_counter() - t0
+
+
 def precision_study(args):
-    """Map error per Stokes component of each precision mode on a 128-detector
-    slice of the iqu_1024det workload (2^21 samples, 1024 x 1024 map): the
-    share of one GPU out of eight.  The float64 mode (float64 timestream and
-    accumulation) provides the reference map; every mode forms its own
-    right-hand side from the same noiseless timestream d = P m_sky (rounded
-    to its storage type) and solves to 1e-6 with the binned preconditioner."""
+    """Config 3 at full size on one GPU: the iqu_1024det workload (1024
+    detectors x 2^21 samples, 1024 x 1024 I,Q,U map), noiseless d = P m_sky,
+    each precision mode (timestream storage float64 / float32 / bfloat16,
+    sums float64 or compensated float32) solving to 1e-6 with the circulant
+    preconditioner (80 px taper, the one frozen on iqu_256det's training scan:
+    same scan pattern and pixel size).  The float64 GPU solve is the reference
+    map; the map error of every mode per Stokes component, its true residual
+    under the float64 GPU operator and its A-apply throughput are reported.
+    The CPU leg runs the FP64 oracle on all cores over the whole scan: its
+    A-apply time, and the reference map's true residual under the oracle's A
+    (with b from the oracle), which ties the reference to the oracle at this
+    size.  Prints one JSON line per mode and a summary line."""
     import numpy as np
     import torch
     import paper_1309_7473_amd as mm
     from synth import make_workload
     t0 = time.time()
-    inp = make_workload("iqu_1024det", ndet=args.precision_ndet)
+
+    def prog(done, n):
+        print(json.dumps({"generating": f"{done}/{n} detectors", "t_s": round(time.time() - t0, 1)}),
+              file=sys.stderr, flush=True)
+
+    inp = make_workload("iqu_1024det", ndet=args.precision_ndet, progress=prog)
     nc, npix = inp.ncomp, inp.ny * inp.nx
+    S = inp.ndet * inp.nsamp
     sky = inp.sky.reshape(nc, npix)
-    tod = sky[0][np.maximum(inp.pix, 0)]
-    if nc == 3:
-        tod = tod + inp.cos2psi * sky[1][np.maximum(inp.pix, 0)] + \
-            inp.sin2psi * sky[2][np.maximum(inp.pix, 0)]
-    tod = np.where(inp.pix >= 0, tod, 0.0)
-    tod_dev = torch.from_numpy(tod).cuda()            # float64 on the device
-    del tod
+    # d = P m_sky, built on the host 32 detectors at a time into a device array
+    tod_dev = torch.empty((inp.ndet, inp.nsamp), dtype=torch.float64, device="cuda")
+    for d0 in range(0, inp.ndet, 32):
+        d1 = min(d0 + 32, inp.ndet)
+        p = inp.pix[d0:d1]
+        pc = np.maximum(p, 0)
+        t = sky[0][pc] + inp.cos2psi[d0:d1] * sky[1][pc] + inp.sin2psi[d0:d1] * sky[2][pc]
+        tod_dev[d0:d1] = torch.from_numpy(np.where(p >= 0, t, 0.0))
     t_gen = time.time() - t0
+    print(json.dumps({"generated": True, "t_s": round(t_gen, 1)}), file=sys.stderr, flush=True)
     modes = [("f64", "f64"), ("f32", "f64"), ("f32", "f32x2"), ("bf16", "f64"), ("bf16", "f32x2")]
-    ref = None
-    A64 = None
+    alg = {"f64": 46.0, "f32": 34.0, "bf16": 30.0}   # pointing 24 + timestream 2x + 1/N(f)
+    taper = 80.0
+    ref = x_ref_host = b64 = A64 = None
     out = []
+    sk = torch.from_numpy(sky).cuda()
     for dt, acc in modes:
         scan = mm.Scan(inp, tod_dtype=dt, acc=acc)
-        scan.build_precon("binned")
+        scan.build_precon("circulant", sigma=taper)
         b = scan.rhs(tod_dev)
         torch.cuda.synchronize()
-        r = scan.pcg("binned", b, tol=1e-6, maxiter=5000, check_every=10, history=False)
+        r = scan.pcg("circulant", b, tol=1e-6, maxiter=5000, check_every=10, history=False)
         x = r["x"]
-        mask = scan.mask().bool().repeat(nc)
         if ref is None:
             ref, b64, A64 = x.clone(), b.clone(), scan
-        ax = A64.apply_A(x)
-        true_res = float(torch.linalg.norm((ax - b64)[mask]) / torch.linalg.norm(b64[mask]))
-        xs, xr = x.view(nc, npix), ref.view(nc, npix)
+            x_ref_host = ref.cpu().numpy()
+        true_res = true_resid(A64, b64, x)
         m1 = scan.mask().bool()
-        sk = torch.from_numpy(sky).cuda()
+        xs, xr = x.view(nc, npix), ref.view(nc, npix)
         err_ref = [float(torch.linalg.norm((xs[k] - xr[k])[m1]) / torch.linalg.norm(xr[k][m1]))
                    for k in range(nc)]
         err_sky = [float(torch.linalg.norm((xs[k] - sk[k])[m1]) / torch.linalg.norm(sk[k][m1]))
@@ -640,18 +688,163 @@ def precision_study(args):
             scan.apply_A(x, y)
         e1.record()
         torch.cuda.synchronize()
+        a_ms = e0.elapsed_time(e1) / 5
         out.append({"tod": dt, "acc": acc, "iters": r["iters"], "converged": r["converged"],
                     "rel_resid": r["rel_resid"], "true_resid_f64": true_res,
                     "map_err_vs_f64_IQU": err_ref, "map_err_vs_sky_IQU": err_sky,
-                    "apply_ms": round(e0.elapsed_time(e1) / 5, 3), "solve_s": round(r["t_solve_s"], 3)})
+                    "apply_ms": round(a_ms, 3), "samples_per_s": S / (a_ms * 1e-3),
+                    "roofline_frac": round(alg[dt] * S / (a_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                    "alg_bytes_per_sample": alg[dt], "solve_s": round(r["t_solve_s"], 3),
+                    "workspace_GiB": round(scan.workspace.numel() / 2**30, 2)})
         print(json.dumps({"mode": out[-1]}), flush=True)
         if scan is not A64:
             scan.close()
+    # the oracle on the host cores: mask, b and A x_ref over the whole scan
+    cpu = None
+    if not args.no_cpu:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        import oracle
+        ncores = max(1, min(len(os.sched_getaffinity(0)), 16))
+        chunks = [(d, min(d + 16, inp.ndet)) for d in range(0, inp.ndet, 16)]
+        _CPU_SHARE.update(inp=inp)
+        with cf.ProcessPoolExecutor(ncores, mp_context=mp.get_context("fork")) as ex:
+            B = sum(ex.map(_oracle_binned_part, chunks))
+        mask = oracle.active_mask(SimpleNamespaceScan(inp), B)
+        _CPU_SHARE.update(mask=mask, x=x_ref_host.reshape(nc, npix) * mask)
+        t1 = time.perf_counter()
+        with cf.ProcessPoolExecutor(ncores, mp_context=mp.get_context("fork")) as ex:
+            parts = list(ex.map(_oracle_rhs_apply_part, chunks))
+        wall = time.perf_counter() - t1
+        bo = sum(p[0] for p in parts)
+        yo = sum(p[1] for p in parts)
+        t_apply = sum(p[2] for p in parts)
+        gmask = A64.mask().cpu().numpy().astype(bool)
+        ax64 = A64.apply_A(ref).cpu().numpy()
+        cpu = {"kind": "oracle", "cores": ncores, "cpu_model": _cpu_model(),
+               "apply_samples_per_s_all_cores": S / (t_apply / ncores),
+               "sample": f"the whole scan in {len(chunks)} chunks of 16 detectors over {ncores} "
+                         f"worker processes ({wall:.1f} s wall for b and A x)",
+               "mask_equal": bool(np.array_equal(mask, gmask)),
+               "ref_true_resid_oracle": float(np.linalg.norm(bo - yo) / np.linalg.norm(bo)),
+               "gpu_f64_apply_vs_oracle": float(np.linalg.norm(ax64 - yo) / np.linalg.norm(yo))}
+    A64.close()
     print(json.dumps({"precision_study": {
-        "workload": f"iqu_1024det slice: {inp.ndet} of 1024 detectors x {inp.nsamp} samples, "
-                    f"{inp.ny}x{inp.nx} I,Q,U map",
+        "workload": f"iqu_1024det: {inp.ndet} detectors x {inp.nsamp} samples, "
+                    f"{inp.ny}x{inp.nx} I,Q,U map, noiseless d = P m_sky",
         "reference": "float64 timestream and accumulation on the GPU",
-        "precon": "binned", "tol": 1e-6, "gen_s": round(t_gen, 1), "modes": out}}), flush=True)
+        "precon": f"circulant, {taper:g} px taper", "tol": 1e-6, "gen_s": round(t_gen, 1),
+        "modes": out, "cpu_oracle": cpu}}), flush=True)
+
+
+def batch_study(args):
+    """Config 4: the 64 scans of batch_64scans (detectors U{32..512}, 2^16-2^21
+    samples, maps 128^2-1024^2) with the detector counts divided by
+    args.batch_shrink (the full draw, 1.45e10 samples, needs ~350 GB of
+    pointing and index; lengths, maps and the scan pattern stay as drawn).
+    Plans come from the autotuner.  Reports the aggregate A-apply throughput
+    (each scan's apply timed alone), the aggregate throughput of batched,
+    graph-replayed PCG iterations (mm_pcg_solve_batch: every scan on its own
+    stream), and every scan solved to 1e-6 in one batch with the binned
+    preconditioner (restarts while a scan's own true residual misses the
+    tolerance).  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_1309_7473_amd as mm
+    from paper_1309_7473_amd import autotune
+    from synth import make_workload, batch_scan_spec
+    t0 = time.time()
+    cache = os.path.join(ROOT, "gpurun_out", "autotune_batch.json")
+    scans, bs, shapes, plans = [], [], [], []
+    for sid in range(64):
+        sp = batch_scan_spec(sid)
+        nd = max(1, sp["ndet"] // args.batch_shrink)
+        inp = make_workload("batch_64scans", sid, ndet=nd)
+        plan = autotune.tune(inp, tod_dtype="f32", reps=2, cache_path=cache)
+        sc = mm.Scan(inp, tod_dtype="f32", **plan)
+        sc.build_precon("binned")
+        bs.append(sc.apply_A(torch.from_numpy(inp.sky.ravel().copy()).cuda()))
+        scans.append(sc)
+        shapes.append((inp.ndet, inp.nsamp, inp.ny))
+        plans.append(plan)
+        del inp
+        print(json.dumps({"scan": sid, "ndet": nd, "nsamp": sp["nsamp"], "side": sp["ny"],
+                          "plan": plan, "t_s": round(time.time() - t0, 1)}),
+              file=sys.stderr, flush=True)
+    t_gen = time.time() - t0
+    S = np.array([n * m for n, m, _ in shapes], dtype=np.float64)
+    # each scan's A-apply alone
+    t_apply = []
+    for sc in scans:
+        x = torch.ones(sc.ncomp * sc.npix, dtype=torch.float64, device="cuda")
+        y = sc.new_map()
+        sc.apply_A(x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            sc.apply_A(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        t_apply.append(e0.elapsed_time(e1) * 1e-3 / 5)
+    t_apply = np.array(t_apply)
+    # K batched PCG iterations of every scan at once (tol 0: none stops)
+    K = 20
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    out0 = mm.pcg_batch(scans, "binned", bs, tol=0.0, maxiter=K, check_every=K, graph=True)
+    torch.cuda.synchronize()
+    w_iter = time.perf_counter() - w0
+    # (a tiny scan may reach an exact zero residual, a breakdown, before K)
+    it0 = np.array([r["iters"] for r in out0], dtype=np.float64)
+    # every scan to 1e-6
+    w0 = time.perf_counter()
+    out = mm.pcg_batch(scans, "binned", bs, tol=TOL32, maxiter=5000, check_every=8, graph=True,
+                       refine=2, true_residual=True)
+    torch.cuda.synchronize()
+    w_solve = time.perf_counter() - w0
+    # the same solves one scan after another (graph replay, no other scan
+    # in flight): what the interleaving on forked streams buys
+    w0 = time.perf_counter()
+    seq = [sc.pcg("binned", b, tol=TOL32, maxiter=5000, check_every=8, graph=True, refine=2,
+                  history=False) for sc, b in zip(scans, bs)]
+    torch.cuda.synchronize()
+    w_seq = time.perf_counter() - w0
+    same = all(a["iters"] == r["iters"] for a, r in zip(seq, out))
+    per_scan = [{"ndet": n, "nsamp": m, "side": side, "iters": r["iters"],
+                 "converged": r["converged"], "true_resid": r["true_rel_resid"],
+                 "apply_ms": round(t * 1e3, 4)}
+                for (n, m, side), r, t in zip(shapes, out, t_apply)]
+    tot = float(S.sum())
+    res = {"workload": f"batch_64scans, detectors / {args.batch_shrink} (lengths, maps and "
+                       "pattern as drawn)",
+           "samples": tot, "gen_s": round(t_gen, 1),
+           "apply_sequential": {"samples_per_s": tot / float(t_apply.sum()),
+                                "roofline_frac": round(34.0 * tot / float(t_apply.sum()) /
+                                                       (HBM_PEAK_GBS * 1e9), 4)},
+           "pcg_batched_iterations": {"iters": K, "scans_short_of_K": int((it0 < K).sum()),
+                                      "wall_s": round(w_iter, 4),
+                                      "samples_per_s": float((S * it0).sum()) / w_iter,
+                                      "roofline_frac": round(34.0 * float((S * it0).sum()) /
+                                                             w_iter / (HBM_PEAK_GBS * 1e9), 4)},
+           "solve_to_1e-6": {"precon": "binned", "tol": TOL32, "wall_s": round(w_solve, 3),
+                             "sequential_wall_s": round(w_seq, 3),
+                             "sequential_same_iters": same,
+                             "all_converged": all(r["converged"] for r in out),
+                             "max_true_resid": max(r["true_rel_resid"] for r in out),
+                             "iters_total": int(sum(r["iters"] for r in out))},
+           "per_scan": per_scan}
+    for sc in scans:
+        sc.close()
+    print(json.dumps({"batch_study": res}), flush=True)
+
+
+class SimpleNamespaceScan:
+    """The fields the oracle's mask reads (shape and pixel indices)."""
+
+    def __init__(self, inp):
+        self.ncomp, self.ny, self.nx = inp.ncomp, inp.ny, inp.nx
+        self.npix = inp.ny * inp.nx
+        self.pix = inp.pix
 
 
 def learned_protocol(args, n_train=8, pairs_per_scan=250, epochs=10, batch=16,
@@ -727,6 +920,9 @@ def main():
     ap.add_argument("--precision-ndet", type=int, default=1024, help=argparse.SUPPRESS)
     ap.add_argument("--learned-protocol", action="store_true",
                     help="run the full learned-preconditioner protocol instead of the benchmark")
+    ap.add_argument("--batch", action="store_true",
+                    help="run the 64-scan batch study instead of the benchmark")
+    ap.add_argument("--batch-shrink", type=int, default=8, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.summarize:
         summarize(*args.summarize)
@@ -741,6 +937,9 @@ def main():
         return
     if args.learned_protocol:
         learned_protocol(args)
+        return
+    if args.batch:
+        batch_study(args)
         return
 
     import numpy as np

@@ -98,7 +98,7 @@ def raster_boresight(nsamp, ny, nx, samples_per_px=4):
     return y, x
 
 
-def _pointing_rows(ny, nx, yb, xb, dy, dx, phi, psi, ncomp):
+def _pointing_rows(ny, nx, yb, xb, dy, dx, phi, psi, ncomp, progress=None):
     cy, cx = (ny - 1) / 2.0, (nx - 1) / 2.0
     ndet, nsamp = len(dy), len(yb)
     pix = np.empty((ndet, nsamp), np.int32)
@@ -118,13 +118,15 @@ def _pointing_rows(ny, nx, yb, xb, dy, dx, phi, psi, ncomp):
             ang = 2.0 * (psi[d] + phi)
             cos2[d] = np.cos(ang)
             sin2[d] = np.sin(ang)
+        if progress and (d + 1) % 128 == 0:
+            progress(d + 1, ndet)
     return pix, cos2, sin2
 
 
 def raster_scan(*, ncomp, ny, nx, ndet, nsamp, fsample, layout="hex",
                 hex_diameter_px=60.0, sigma=1.0, sigma_scatter=0.0,
                 fknee=(1.0, 1.0), alpha=-3.0, drift_deg=0.0, seed=(0, 0),
-                white=False, with_sky=True):
+                white=False, with_sky=True, progress=None):
     """A seeded raster scan.
 
     layout: "line" puts detector d at cross-scan offset d px (no along-scan
@@ -132,6 +134,7 @@ def raster_scan(*, ncomp, ny, nx, ndet, nsamp, fsample, layout="hex",
     sigma_scatter: sigma_d = sigma * exp(sigma_scatter * N(0, 1)).
     fknee: (lo, hi), f_knee,d ~ U(lo, hi).  drift_deg: total scan-angle drift
     is U(-drift_deg, drift_deg) degrees over the scan.  white: pure white noise.
+    progress: optional callable(done, ndet), called every 128 detectors.
     """
     from .noise import noise_spectrum, inverse_spectrum, white_inverse_spectrum
     from .sky import grf_sky
@@ -159,7 +162,7 @@ def raster_scan(*, ncomp, ny, nx, ndet, nsamp, fsample, layout="hex",
     yb, xb = raster_boresight(nsamp, ny, nx)
     t = np.arange(nsamp, dtype=np.float64)
     phi = dphi * (t / nsamp - 0.5)
-    pix, cos2, sin2 = _pointing_rows(ny, nx, yb, xb, dy, dx, phi, psi, ncomp)
+    pix, cos2, sin2 = _pointing_rows(ny, nx, yb, xb, dy, dx, phi, psi, ncomp, progress)
     bore = np.stack([yb, xb, np.cos(phi), np.sin(phi), np.cos(2 * phi), np.sin(2 * phi)])
     det_off = np.stack([dy, dx, np.cos(2 * psi), np.sin(2 * psi)])
 
