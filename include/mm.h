@@ -455,6 +455,24 @@ mm_status mm_map_spectra_noalloc(mm_scan scan, const double* x, double pixel_arc
 mm_status mm_anorm_error_estimate(const double* alpha /*[host]*/, const double* rho /*[host]*/,
                                   int32_t n, int32_t delay, double* est /*[host]*/);
 
+/* Error of a spectrum in cosmic-variance units (the Results section's
+ * convergence measure): err[c][b] = |c_iter[c][b] - c_input[c][b]| / sigma_b
+ * with sigma_b = c_input[c][b] sqrt(2 / N_b), N_b = counts[b] / 2 (a real
+ * map's independent modes); NaN where the bin is empty or c_input <= 0.
+ * All arrays [host], [ncomp][nbins] (counts [nbins]).  Host only. */
+mm_status mm_spectrum_cv_error(const double* c_iter, const double* c_input, const double* counts,
+                               int32_t ncomp, int32_t nbins, double* err /*[host]*/);
+
+/* The CG step at which a per-bin error first reaches `threshold` once the
+ * errors of n recorded steps are averaged over consecutive blocks of `block`
+ * steps: linear interpolation between the centres of the last block above
+ * and the first block at or below the threshold (the first block's centre if
+ * that one is already below).  *found = 0 (and *step unchanged) if no block
+ * reaches it.  steps, errors: [host] n values.  Host only. */
+mm_status mm_cv_crossing_step(const double* steps, const double* errors, int32_t n,
+                              double threshold, int32_t block, double* step /*[host]*/,
+                              int32_t* found /*[host]*/);
+
 /* Diagnostics of a scan handle. */
 typedef struct {
   int32_t n_active;         /* active pixels */

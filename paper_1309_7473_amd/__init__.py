@@ -213,6 +213,33 @@ def mm_anorm_error_estimate(alpha, rho, delay=4):
     return est
 
 
+def mm_spectrum_cv_error(c_iter, c_input, counts):
+    """Per-bin spectrum error in cosmic-variance units (host, libmm)."""
+    ci = np.ascontiguousarray(c_iter, dtype=np.float64)
+    cn = np.ascontiguousarray(np.broadcast_to(c_input, ci.shape), dtype=np.float64)
+    cnt = np.ascontiguousarray(counts, dtype=np.float64)
+    nb = cnt.size
+    if ci.size % nb:
+        raise ValueError("c_iter must be [ncomp][nbins]")
+    err = np.empty(ci.shape, np.float64)
+    check(lib.mm_spectrum_cv_error(ci.ctypes.data_as(C.c_void_p), cn.ctypes.data_as(C.c_void_p),
+                                   cnt.ctypes.data_as(C.c_void_p), ci.size // nb, nb,
+                                   err.ctypes.data_as(C.c_void_p)), "mm_spectrum_cv_error")
+    return err
+
+
+def mm_cv_crossing_step(steps, errors, threshold=0.1, block=50):
+    """CG step at which block-averaged errors first reach threshold, or None."""
+    st = np.ascontiguousarray(steps, dtype=np.float64)
+    er = np.ascontiguousarray(errors, dtype=np.float64)
+    out = C.c_double(0.0)
+    found = C.c_int32(0)
+    check(lib.mm_cv_crossing_step(st.ctypes.data_as(C.c_void_p), er.ctypes.data_as(C.c_void_p),
+                                  min(st.size, er.size), float(threshold), int(block),
+                                  C.byref(out), C.byref(found)), "mm_cv_crossing_step")
+    return float(out.value) if found.value else None
+
+
 def mm_get_info(h):
     info = mm_scan_info()
     check(lib.mm_get_info(h, C.byref(info)), "mm_get_info")

@@ -104,6 +104,10 @@ SIGNATURES = {
                                  C.c_void_p, C.c_void_p, C.c_void_p]),
     "mm_anorm_error_estimate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                           C.c_void_p]),
+    "mm_spectrum_cv_error": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                       C.c_void_p]),
+    "mm_cv_crossing_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int32,
+                                      C.c_void_p, C.c_void_p]),
     "mm_get_info": (C.c_int, [C.c_void_p, C.POINTER(mm_scan_info)]),
     "mm_get_mask": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "mm_learned_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),

@@ -350,6 +350,54 @@ mm_status mm_anorm_error_estimate(const double* alpha, const double* rho, int32_
   return MM_OK;
 }
 
+mm_status mm_spectrum_cv_error(const double* c_iter, const double* c_input, const double* counts,
+                               int32_t ncomp, int32_t nbins, double* err) {
+  if (ncomp < 1 || nbins < 1) return fail(MM_EINVAL, "ncomp and nbins must be >= 1");
+  if (!c_iter || !c_input || !counts || !err)
+    return fail(MM_EINVAL, "c_iter, c_input, counts and err are required");
+  for (int c = 0; c < ncomp; ++c)
+    for (int b = 0; b < nbins; ++b) {
+      const int i = c * nbins + b;
+      const double half = 0.5 * counts[b];
+      if (half > 0.0 && c_input[i] > 0.0)
+        err[i] = std::fabs(c_iter[i] - c_input[i]) / (c_input[i] * std::sqrt(2.0 / half));
+      else
+        err[i] = std::nan("");
+    }
+  return MM_OK;
+}
+
+mm_status mm_cv_crossing_step(const double* steps, const double* errors, int32_t n,
+                              double threshold, int32_t block, double* step, int32_t* found) {
+  if (n < 0 || block < 1) return fail(MM_EINVAL, "n must be >= 0 and block >= 1");
+  if (!found || !step || (n > 0 && (!steps || !errors)))
+    return fail(MM_EINVAL, "steps, errors, step and found are required");
+  *found = 0;
+  double prev_c = 0.0, prev_v = 0.0;
+  for (int b0 = 0, j = 0; b0 < n; b0 += block, ++j) {
+    const int b1 = b0 + block < n ? b0 + block : n;
+    double cs = 0.0, vs = 0.0;
+    for (int i = b0; i < b1; ++i) {
+      cs += steps[i];
+      vs += errors[i];
+    }
+    const double cen = cs / (b1 - b0), val = vs / (b1 - b0);
+    if (val <= threshold) {
+      if (j == 0) {
+        *step = cen;
+      } else {
+        const double t = (prev_v - threshold) / (prev_v - val);
+        *step = prev_c + t * (cen - prev_c);
+      }
+      *found = 1;
+      return MM_OK;
+    }
+    prev_c = cen;
+    prev_v = val;
+  }
+  return MM_OK;
+}
+
 mm_status mm_get_info(mm_scan scan, mm_scan_info* out) {
   ScanImpl* s = get(scan);
   if (!s || !out) return fail(MM_EINVAL, "invalid scan handle or out");

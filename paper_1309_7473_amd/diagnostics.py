@@ -3,8 +3,9 @@ per multipole bin, the error of a PCG iterate's TT/EE/BB spectrum against the
 input map's spectrum in units of cosmic variance, and the CG step at which it
 falls to a threshold (0.1 cosmic variance), with the errors averaged over
 blocks of CG steps (about 50 in the paper) and linearly interpolated between
-block centres.  The spectra come from mm_map_spectra on the GPU; what is left
-here is bookkeeping on a few hundred numbers per iterate.
+block centres.  The spectra come from mm_map_spectra on the GPU, the errors
+and crossing steps from the library's host functions; this module only
+sequences the calls.
 
 Cosmic variance of a bin: sigma_b = C_b(input) sqrt(2 / N_b), N_b = half the
 modes of the bin (a real map's independent modes).
@@ -14,33 +15,18 @@ import numpy as np
 
 
 def cv_error(c_iter, c_input, counts):
-    """|C(iterate) - C(input)| / sigma_cv per bin, nan for empty bins."""
-    half = np.asarray(counts, dtype=np.float64) * 0.5
-    c_input = np.asarray(c_input, dtype=np.float64)
-    out = np.full(np.broadcast(np.asarray(c_iter), c_input).shape, np.nan)
-    good = (half > 0) & (c_input > 0)
-    sigma = np.where(good, c_input * np.sqrt(2.0 / np.where(half > 0, half, 1.0)), 1.0)
-    diff = np.abs(np.asarray(c_iter, dtype=np.float64) - c_input)
-    np.divide(diff, sigma, out=out, where=np.broadcast_to(good, out.shape))
-    return out
+    """|C(iterate) - C(input)| / sigma_cv per bin, nan for empty bins
+    (mm_spectrum_cv_error)."""
+    from . import mm_spectrum_cv_error
+    c_iter = np.asarray(c_iter, dtype=np.float64)
+    return mm_spectrum_cv_error(c_iter, np.broadcast_to(c_input, c_iter.shape), counts)
 
 
 def crossing_step(steps, errors, threshold=0.1, block=50):
     """CG step where the block-averaged error first reaches `threshold`
-    (interpolated between block centres), or None."""
-    steps = np.asarray(steps, dtype=np.float64)
-    errors = np.asarray(errors, dtype=np.float64)
-    nblk = (len(steps) + block - 1) // block
-    cen = np.array([steps[i * block:(i + 1) * block].mean() for i in range(nblk)])
-    val = np.array([errors[i * block:(i + 1) * block].mean() for i in range(nblk)])
-    below = np.nonzero(val <= threshold)[0]
-    if below.size == 0:
-        return None
-    j = int(below[0])
-    if j == 0:
-        return float(cen[0])
-    t = (val[j - 1] - threshold) / (val[j - 1] - val[j])
-    return float(cen[j - 1] + t * (cen[j] - cen[j - 1]))
+    (interpolated between block centres), or None (mm_cv_crossing_step)."""
+    from . import mm_cv_crossing_step
+    return mm_cv_crossing_step(steps, errors, threshold, block)
 
 
 def ps_convergence(scan, precon, b, x_input, pixel_arcmin=0.5, dell=100.0, nbins=200,
