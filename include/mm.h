@@ -100,7 +100,8 @@ typedef struct {
                                pointing need a power of two */
   double  fsample;          /* sample rate in Hz (reporting only) */
   const int32_t* pix;       /* [ndet][nsamp] pixel id, -1 = off-map (zero row
-                               of P); NULL with MM_POINT_BORESIGHT.  BORROWED:
+                               of P); NULL with MM_POINT_BORESIGHT.  pix, cos2psi
+                               and sin2psi are 16-byte aligned.  BORROWED:
                                must stay valid and unchanged until
                                mm_destroy_scan. */
   const float* cos2psi;     /* [ndet][nsamp] weight of Q; NULL iff ncomp == 1. BORROWED */
@@ -175,13 +176,28 @@ typedef struct {
   const double* det_off;    /* device [4][ndet] float64: dy, dx (offsets from the
                                boresight before the turn), cos 2psi, sin 2psi.
                                BORROWED */
+  int32_t pointing_code;    /* pass 1's copy of stored I,Q,U pointing whose weights
+                               are angles (float32 and bfloat16 four-step paths,
+                               nsamp a multiple of 64): MM_PTC_AUTO = chunk-coded
+                               when every 64-sample chunk of every detector fits
+                               (on-map pixels within 65534 of the chunk's smallest;
+                               weight angles, as 2 psi 2^32 / 2 pi, less than 2^15
+                               off the line through the chunk's first and last
+                               on-map samples), 4 B a sample plus 16 B a chunk of
+                               workspace, decoded to exactly the stored pixel and
+                               angle; otherwise, and with MM_PTC_OFF, pass 1 reads
+                               the stored pixels and the time-major angles (8 B a
+                               sample) */
 } mm_scan_desc;
+
+enum { MM_PTC_AUTO = 0, MM_PTC_OFF = 1 };
 
 enum { MM_SCATTER_AUTO = 0, MM_SCATTER_ATOMIC = 1, MM_SCATTER_SAMPLES = 2 };
 
 /* Bytes of device workspace the scan needs (the caller allocates it and puts
  * the pointer in desc->workspace).  Only the shape fields and the tuning
- * fields (det_group, fft_m1, tod_dtype) are read.  Returns 0 and sets
+ * fields (det_group, fft_m1, fft_cols, scatter, pointing, pointing_code,
+ * tod_dtype, acc) are read.  Returns 0 and sets
  * mm_last_error() on an invalid description. */
 size_t mm_scan_workspace_bytes(const mm_scan_desc* desc /*[host]*/);
 
@@ -492,6 +508,10 @@ typedef struct {
                                boresight model, 2 stored as 4-byte angles (stored
                                weights of unit norm on the float32 and bfloat16
                                paths; decoded to within 1e-7), -1 no gather or I only */
+  int32_t pass1_pointing;   /* what pass 1 reads for the pointing: 0 stored pixels and
+                               weights (or I only, or a timestream), 1 the boresight
+                               model, 2 stored pixels and time-major angles, 3 the
+                               chunk-coded pixels and angles (pointing_code) */
   double  t_build_s;        /* wall time of the last mm_build_precon on this handle */
 } mm_scan_info;
 

@@ -20,7 +20,7 @@ from ._abi import (  # noqa: F401
     MM_EBREAKDOWN, MM_F32, MM_BF16, MM_F64, MM_M_NONE, MM_M_JACOBI, MM_M_BINNED,
     MM_M_CIRCULANT, MM_M_LEARNED, MM_M_TILED, LIB_PATH, mm_profile, PROFILE_STAGES, MM_SCATTER_AUTO,
     MM_SCATTER_ATOMIC, MM_SCATTER_SAMPLES, mm_train_opts, MM_ACC_F64, MM_ACC_F32X2, MM_POINT_STORED,
-    MM_POINT_BORESIGHT,
+    MM_POINT_BORESIGHT, MM_PTC_AUTO, MM_PTC_OFF,
 )
 
 PRECON = {"none": MM_M_NONE, "jacobi": MM_M_JACOBI, "binned": MM_M_BINNED,
@@ -369,11 +369,13 @@ class Scan:
 
     def __init__(self, inputs, tod_dtype="f32", det_group=0, fft_m1=0, fft_cols=0,
                  mask_rcond=0.0, scatter="auto", acc="f64", pointing="auto", device="cuda",
-                 stream=None):
+                 stream=None, pointing_code="auto"):
         """pointing: "stored" (inputs.pix, cos2psi, sin2psi), "boresight"
         (inputs.bore [6][nsamp] and inputs.det_off [4][ndet], float64: each
         sample's pointing is computed on the GPU when it is needed), or "auto"
-        (stored when inputs.pix is given)."""
+        (stored when inputs.pix is given).  pointing_code: "auto" lets pass 1
+        read a chunk-coded copy of stored pointing when every chunk fits,
+        "off" keeps the stored pixels and time-major angles."""
         self.device = torch.device(device)
         dev = self.device
 
@@ -431,6 +433,7 @@ class Scan:
         d.scatter = {"auto": MM_SCATTER_AUTO, "atomic": MM_SCATTER_ATOMIC,
                      "samples": MM_SCATTER_SAMPLES}[scatter]
         d.acc = {"f64": MM_ACC_F64, "f32x2": MM_ACC_F32X2}[acc]
+        d.pointing_code = {"auto": MM_PTC_AUTO, "off": MM_PTC_OFF}[pointing_code]
         edges = getattr(inputs, "corr_edges", None)
         if edges is not None:   # inter-detector correlated inverse noise
             self.corr_edges = np.ascontiguousarray(edges, dtype=np.int32)   # host, copied at create

@@ -30,7 +30,7 @@ class mm_scan_desc(C.Structure):
         ("fft_cols", C.c_int32), ("scatter", C.c_int32), ("acc", C.c_int32),
         ("corr_rank", C.c_int32), ("corr_nbins", C.c_int32), ("corr_edges", C.c_void_p),
         ("corr_V", C.c_void_p), ("pointing", C.c_int32), ("bore", C.c_void_p),
-        ("det_off", C.c_void_p),
+        ("det_off", C.c_void_p), ("pointing_code", C.c_int32),
     ]
 
 
@@ -66,7 +66,8 @@ class mm_scan_info(C.Structure):
     _fields_ = [("n_active", C.c_int32), ("ref_pixel", C.c_int32), ("n_floored", C.c_int32),
                 ("det_group", C.c_int32), ("fft_m1", C.c_int32), ("fft_m2", C.c_int32),
                 ("fft_cols", C.c_int32), ("single_pass", C.c_int32), ("csr", C.c_int32), ("workspace_bytes", C.c_size_t),
-                ("gather_weights", C.c_int32), ("t_build_s", C.c_double)]
+                ("gather_weights", C.c_int32), ("pass1_pointing", C.c_int32),
+                ("t_build_s", C.c_double)]
 
 
 class mm_profile(C.Structure):
@@ -76,6 +77,7 @@ class mm_profile(C.Structure):
 
 PROFILE_STAGES = ["single", "pass1", "pass2", "pass3", "apply_A", "precon", "reduce", "corr"]
 MM_SCATTER_AUTO, MM_SCATTER_ATOMIC, MM_SCATTER_SAMPLES = 0, 1, 2
+MM_PTC_AUTO, MM_PTC_OFF = 0, 1
 
 
 # name -> (restype, argtypes)

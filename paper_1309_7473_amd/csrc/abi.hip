@@ -57,6 +57,8 @@ static mm_status validate_shape(const mm_scan_desc* d) {
     return fail(MM_EINVAL, "scatter must be MM_SCATTER_AUTO, MM_SCATTER_ATOMIC or MM_SCATTER_SAMPLES");
   if (d->acc != MM_ACC_F64 && d->acc != MM_ACC_F32X2)
     return fail(MM_EINVAL, "acc must be MM_ACC_F64 or MM_ACC_F32X2");
+  if (d->pointing_code != MM_PTC_AUTO && d->pointing_code != MM_PTC_OFF)
+    return fail(MM_EINVAL, "pointing_code must be MM_PTC_AUTO or MM_PTC_OFF");
   if (d->acc == MM_ACC_F32X2 && d->scatter == MM_SCATTER_ATOMIC)
     return fail(MM_EINVAL, "acc = MM_ACC_F32X2 needs scatter = MM_SCATTER_AUTO");
   if (d->pointing != MM_POINT_STORED && d->pointing != MM_POINT_BORESIGHT)
@@ -118,6 +120,11 @@ mm_status mm_create_scan(const mm_scan_desc* desc, void* stream, mm_scan* out) {
       return fail(MM_EINVAL, "cos2psi/sin2psi must be given iff ncomp == 3");
     if (desc->ncomp == 1 && (desc->cos2psi || desc->sin2psi))
       return fail(MM_EINVAL, "cos2psi/sin2psi must be NULL when ncomp == 1");
+    // the timestream kernels read four samples at a time
+    if (reinterpret_cast<uintptr_t>(desc->pix) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(desc->cos2psi) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(desc->sin2psi) % 16 != 0)
+      return fail(MM_EINVAL, "pix, cos2psi and sin2psi must be 16-byte aligned");
   }
   if (desc->corr_rank > 0 && !desc->corr_V) return fail(MM_EINVAL, "corr_V is required");
   Plan pl;
@@ -412,6 +419,7 @@ mm_status mm_get_info(mm_scan scan, mm_scan_info* out) {
   out->csr = !s->plan.csr ? 0 : s->plan.rle ? 2 : 1;
   out->workspace_bytes = s->lay.total;
   out->gather_weights = (!s->plan.csr || s->nc != 3) ? -1 : !s->plan.csr_w ? 1 : s->csr_ang ? 2 : 0;
+  out->pass1_pointing = s->plan.otf ? 1 : s->ptc_ready ? 3 : s->ang_t_ready ? 2 : 0;
   out->t_build_s = s->t_build_s;
   return MM_OK;
 }

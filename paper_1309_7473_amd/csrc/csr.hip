@@ -132,6 +132,68 @@ __global__ void k_angles_t(const float* __restrict__ c2, const float* __restrict
     ang[i] = weight_angle(c2[i], s2[i]);
 }
 
+// Chunk-coded pointing for pass 1, one thread per kPtcChunk-sample chunk of
+// one detector.  Header: the smallest on-map pixel of the chunk (0 if none),
+// and the chunk's angle trend u0 + slope * i through its first and last
+// on-map samples (i the sample's place in the chunk; slope 0 with fewer than
+// two), stored as base = u0 - 2^15 and slope.  Each sample is (pixel - lowest)
+// | (angle - base - slope * i) << 16 (mod 2^32), with 0xFFFF in the low half
+// for a sample off the map (pixel outside [0, npix)).  Pass 1 decodes exactly
+// the stored pixel and angle.  A chunk whose on-map pixels span more than
+// 65534 ids, or whose on-map angles stray 2^15 or more from the trend, sets
+// *bad, and the scan keeps the uncoded form.
+__global__ void __launch_bounds__(256) k_ptc_encode(const int32_t* __restrict__ pix,
+                                                    const uint32_t* __restrict__ ang,
+                                                    int64_t nchunks, int npix,
+                                                    int4* __restrict__ hdr,
+                                                    uint32_t* __restrict__ code,
+                                                    int* __restrict__ bad) {
+  constexpr int K = kPtcChunk;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < nchunks; c += stride) {
+    const int32_t* p = pix + c * K;
+    const uint32_t* u = ang + c * K;
+    int lo = npix, hi = -1, i0 = -1, i1 = -1;
+    for (int i = 0; i < K; ++i) {
+      const int q = p[i];
+      if (unsigned(q) < unsigned(npix)) {
+        lo = q < lo ? q : lo;
+        hi = q > hi ? q : hi;
+        if (i0 < 0) i0 = i;
+        i1 = i;
+      }
+    }
+    if (hi < 0) lo = 0;
+    // the trend: a signed angle step per sample, rounded to the nearest
+    int32_t slope = 0;
+    uint32_t u0 = 0;
+    if (i0 >= 0) {
+      if (i1 > i0) {
+        const int64_t du = int64_t(int32_t(u[i1] - u[i0]));
+        const int64_t span = i1 - i0;
+        slope = int32_t(du >= 0 ? (du + span / 2) / span : -((-du + span / 2) / span));
+      }
+      u0 = u[i0] - uint32_t(slope) * uint32_t(i0);
+    }
+    const uint32_t ub = u0 - 32768u;
+    bool ok = hi - lo <= 65534;
+    for (int i = 0; i < K; i += 4) {
+      uint32_t w[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int q = p[i + k];
+        const bool on = unsigned(q) < unsigned(npix);
+        const uint32_t r = u[i + k] - ub - uint32_t(slope) * uint32_t(i + k);
+        ok = ok && (!on || r <= 65535u);
+        w[k] = on ? (uint32_t(q - lo) | (r << 16)) : 0xFFFFu;
+      }
+      *reinterpret_cast<uint4*>(code + c * K + i) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    hdr[c] = make_int4(lo, int(ub), slope, 0);
+    if (!ok) atomicOr(bad, 1);
+  }
+}
+
 // Run-length entries: the lane heading each kRunMax-sample piece of a wave run
 // writes (first sample << 4) | length into the pixel's next free slot.
 __global__ void __launch_bounds__(256) k_rle_fill(const int32_t* __restrict__ pix, Bore bo,
@@ -315,6 +377,23 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
                        total, s->at<uint32_t>(L.ang_t));
     MM_HIP(hipGetLastError());
     s->ang_t_ready = true;
+  }
+  // pass 1's chunk-coded copy of the pixels and angles, if every chunk fits
+  s->ptc_ready = false;
+  if (s->ang_t_ready && s->plan.ptc && s->d.pix) {
+    int* bad = s->at<int>(L.misc);
+    if ((r = fill_zero(bad, 4, st)) != MM_OK) return r;
+    const int64_t nchunks = total / kPtcChunk;
+    int64_t cb = (nchunks + 255) / 256;
+    if (cb > 8192) cb = 8192;
+    hipLaunchKernelGGL(k_ptc_encode, dim3(unsigned(cb)), dim3(256), 0, st, s->d.pix,
+                       s->at<uint32_t>(L.ang_t), nchunks, npix, s->at<int4>(L.ptc_h),
+                       s->at<uint32_t>(L.ptc), bad);
+    MM_HIP(hipGetLastError());
+    int h = 0;
+    MM_HIP(hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, st));
+    MM_HIP(hipStreamSynchronize(st));
+    s->ptc_ready = h == 0;
   }
   // run-length index with angle-coded weights: the angles also go pixel-major
   // in gather order, for which each pixel's sample offsets come first

@@ -99,6 +99,8 @@ struct PassArgs {
   const uint32_t* rle_ang; // group samples pixel-major: the weights as angles
   const float2* ang_tab;   // (cos, sin)(2 pi k / 256), k < 256
   const uint32_t* ang_t;   // group base [G][n]: the weights as angles, time-major
+  const int4* ptc_h;       // group base [G][n/64]: chunk-coded pointing, chunk headers
+  const uint32_t* ptc;     // group base [G][n]: chunk-coded pointing, samples
   const float4* bore_f;    // boresight in float32: [n] (y_b - c_y, x_b - c_x, cos phi, sin phi)
   const uint32_t* bore_a;  // [n] angle of (cos 2phi, sin 2phi)
   const float2* det_f;     // [ndet] (dy, dx) in float32
@@ -150,7 +152,8 @@ __device__ __forceinline__ void angle_cs(uint32_t u, const float2* tab, float* c
 // SRC 0: stored pointing; 1: a timestream; 2: the boresight model; 3: stored
 // pixels with the weights as angles (a time-major copy made at set-up); 4:
 // the boresight model from float32 copies (pass 1 of the float paths; the
-// float64 definition decides the pixels the float32 evaluation cannot).
+// float64 definition decides the pixels the float32 evaluation cannot); 5:
+// the pixels and angles of SRC 3 chunk-coded (4 B a sample, 16 B a chunk).
 template <typename T, typename S, int NC, int SRC>
 __device__ __forceinline__ T source_sample(const PassArgs<T, S>& a, int64_t s) {
   if constexpr (SRC == 1) {
@@ -173,6 +176,15 @@ __device__ __forceinline__ T source_sample(const PassArgs<T, S>& a, int64_t s) {
     const V4<T> m = a.gmap[unsigned(p) < unsigned(a.npix) ? p : a.npix];
     float c, sn;
     angle_cs(a.ang_t[s], a.ang_tab, &c, &sn);
+    return m.x + T(c) * m.y + T(sn) * m.z;
+  } else if constexpr (SRC == 5) {
+    const int4 h = a.ptc_h[s / kPtcChunk];
+    const uint32_t w = a.ptc[s];
+    const uint32_t dp = w & 0xFFFFu;
+    const V4<T> m = a.gmap[dp == 0xFFFFu ? a.npix : h.x + int(dp)];
+    float c, sn;
+    const uint32_t i = uint32_t(s & (kPtcChunk - 1));
+    angle_cs(uint32_t(h.y) + uint32_t(h.z) * i + (w >> 16), a.ang_tab, &c, &sn);
     return m.x + T(c) * m.y + T(sn) * m.z;
   } else {
     const int p = a.pix[s];
@@ -510,6 +522,21 @@ __device__ __forceinline__ void source4(const PassArgs<T, S>& a, int64_t s, T (&
         v[i] = m.x;
       }
     }
+  } else if constexpr (SRC == 5) {
+    // chunk-coded pixels and angles: 4 B a sample and the chunk's header
+    const int4 h = a.ptc_h[s / kPtcChunk];
+    const int4 w4 = ld_stream(reinterpret_cast<const int4*>(a.ptc + s));
+    const uint32_t ww[4] = {uint32_t(w4.x), uint32_t(w4.y), uint32_t(w4.z), uint32_t(w4.w)};
+    // the angle trend at the first of the four samples, then one step each
+    const uint32_t t0 = uint32_t(h.y) + uint32_t(h.z) * uint32_t(s & (kPtcChunk - 1));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t dp = ww[i] & 0xFFFFu;
+      float c, sn;
+      angle_cs(t0 + uint32_t(h.z) * uint32_t(i) + (ww[i] >> 16), tab, &c, &sn);
+      const V4<T> m = a.gmap[dp == 0xFFFFu ? a.npix : h.x + int(dp)];
+      v[i] = m.x + T(c) * m.y + T(sn) * m.z;
+    }
   } else if constexpr (SRC == 3) {
     // stored pixels and angle-coded weights: 8 B a sample instead of 12
     const int4 p4 = ld_stream(reinterpret_cast<const int4*>(a.pix + s));
@@ -616,8 +643,8 @@ k_pass1(PassArgs<T, S> a) {
     for (int m = threadIdx.x; m < M1; m += kNT13) stw[m] = a.twm[m];
   else
     stage_twiddles<T, kNT13>(stw, a.tw, a.logM1, a.logLmax);
-  __shared__ float2 angtab[SRC == 3 || SRC == 4 ? 256 : 1];   // angle-coded weights' table
-  if constexpr (SRC == 3 || SRC == 4) {
+  __shared__ float2 angtab[SRC >= 3 ? 256 : 1];   // angle-coded weights' table
+  if constexpr (SRC >= 3) {
     if (threadIdx.x < 256) angtab[threadIdx.x] = a.ang_tab[threadIdx.x];
     __syncthreads();
   }
@@ -1626,6 +1653,8 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
     const int64_t off = int64_t(d0) * s->n;
     a.det0 = d0;
     a.ang_t = s->ang_t_ready ? s->at<uint32_t>(s->lay.ang_t) + off : nullptr;
+    a.ptc = s->ptc_ready ? s->at<uint32_t>(s->lay.ptc) + off : nullptr;
+    a.ptc_h = s->ptc_ready ? s->at<int4>(s->lay.ptc_h) + off / kPtcChunk : nullptr;
     a.pix = s->d.pix ? s->d.pix + off : nullptr;
     a.c2 = s->d.cos2psi ? s->d.cos2psi + off : nullptr;
     a.s2 = s->d.sin2psi ? s->d.sin2psi + off : nullptr;
@@ -1796,6 +1825,7 @@ static mm_status run_pipeline(ScanImpl* s, int src, const void* tod, hipStream_t
     return src               ? run_pipeline_t<T, S, 3, 1>(s, tod, st)
            : otf             ? (s->bore_fast ? run_pipeline_t<T, S, 3, 4>(s, tod, st)
                                              : run_pipeline_t<T, S, 3, 2>(s, tod, st))
+           : s->ptc_ready    ? run_pipeline_t<T, S, 3, 5>(s, tod, st)
            : s->ang_t_ready  ? run_pipeline_t<T, S, 3, 3>(s, tod, st)
                              : run_pipeline_t<T, S, 3, 0>(s, tod, st);
   return src   ? run_pipeline_t<T, S, 1, 1>(s, tod, st)
@@ -2074,6 +2104,12 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->det_a = take(bfast ? size_t(d->ndet) * 4 : 0);
   // time-major angle-coded weights for pass 1 (stored pointing, float paths)
   L->ang_t = take(nc == 3 && pl->csr && !pl->f64 && !pl->otf ? size_t(d->ndet) * size_t(n) * 4 : 0);
+  // chunk-coded pointing for pass 1 (4 B a sample and 16 B per 64 samples;
+  // built from the time-major angles at creation when every chunk fits)
+  pl->ptc = nc == 3 && pl->csr && !pl->f64 && !pl->otf && !pl->single && n % kPtcChunk == 0 &&
+            d->pointing_code == MM_PTC_AUTO;
+  L->ptc_h = take(pl->ptc ? size_t(d->ndet) * size_t(n / kPtcChunk) * 16 : 0);
+  L->ptc = take(pl->ptc ? size_t(d->ndet) * size_t(n) * 4 : 0);
   L->total = off;
   return MM_OK;
 }

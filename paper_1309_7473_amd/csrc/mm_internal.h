@@ -21,6 +21,7 @@ constexpr int kSpecBlocks = 256;   // blocks of the map-spectra binning
 constexpr int kSpecMaxBins = 512;  // multipole bins of mm_map_spectra
 // device scratch of mm_map_spectra_noalloc (one static array per device)
 constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+constexpr int kPtcChunk = 64;    // samples per chunk of the chunk-coded pointing
 constexpr int kProfSingle = 0, kProfPass1 = 1, kProfPass2 = 2, kProfPass3 = 3, kProfApplyA = 4,
               kProfPrecon = 5, kProfReduce = 6, kProfCorr = 7;
 
@@ -89,6 +90,10 @@ struct Layout {
   size_t csr_w;      // ngroups * G * n float2 (cos 2psi, sin 2psi), or uint32 angles
   size_t ang_tab;    // 256 float2: (cos, sin)(2 pi k / 256)
   size_t ang_t;      // ndet * n uint32: the weights as angles, time-major (pass 1)
+  size_t ptc_h;      // ndet * n/kPtcChunk int4: chunk-coded pointing, per chunk
+                     // (smallest on-map pixel, angle base, angle slope, 0)
+  size_t ptc;        // ndet * n uint32: chunk-coded pointing, per sample
+                     // (pixel - smallest | (angle - base - slope * i) << 16)
   size_t bore_f, bore_a, det_f, det_a;   // float32 copies of the boresight model
   size_t total;
 };
@@ -105,6 +110,7 @@ struct Plan {
   bool csr_w;        // the gather has stored weights (in the index, or time-major
                      // beside the pointing with the run-length index)
   bool rle;          // the pixel-major index holds runs of consecutive samples
+  bool ptc;          // pass 1 may read the chunk-coded pointing (sized in the layout)
   uint32_t mix_code; // mixed-radix stage code of M (one kernel) or M1 (four-step); 0: power of two
   int M1;            // four-step column length (2^logM1 unless mixed)
   int logn, logM;    // n = 2^logn samples, M = n/2 packed complex
@@ -134,6 +140,7 @@ struct ScanImpl {
   bool circ_built = false;
   bool csr_ang = false;       // the index's weights are stored as fixed-point angles
   bool ang_t_ready = false;   // pass 1 reads the time-major angles (SRC 3)
+  bool ptc_ready = false;     // pass 1 reads the chunk-coded pointing (SRC 5)
   bool rle_pa = false;        // the run-length gather reads pixel-major angles
   double* fuse_y = nullptr;   // output map the last group's gather may write directly
   bool fused_y = false;       // set when it did (the epilogue is then skipped)

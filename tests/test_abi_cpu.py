@@ -65,8 +65,9 @@ def test_pixel_index_workspace(mm):
     # a sample for I,Q,U (index and float32 weight pairs, or index and
     # angles) plus the 4 B of time-major angles, and 4 B for I
     a = mm.mm_scan_workspace_bytes(_desc(mm, scatter=mm.MM_SCATTER_ATOMIC))
-    b = mm.mm_scan_workspace_bytes(_desc(mm))
-    c = mm.mm_scan_workspace_bytes(_desc(mm, scatter=mm.MM_SCATTER_SAMPLES))
+    b = mm.mm_scan_workspace_bytes(_desc(mm, pointing_code=mm.MM_PTC_OFF))
+    c = mm.mm_scan_workspace_bytes(_desc(mm, scatter=mm.MM_SCATTER_SAMPLES,
+                                         pointing_code=mm.MM_PTC_OFF))
     S = 4 * (1 << 16)
     tail = 2 * 4 * (64 * 64 + 1) + 4 * 256
     assert 12 * S <= b - a <= 12 * S + tail + 4 * (64 * 64 + 1) + 256
@@ -76,6 +77,23 @@ def test_pixel_index_workspace(mm):
     c1 = mm.mm_scan_workspace_bytes(_desc(mm, ncomp=1, scatter=mm.MM_SCATTER_SAMPLES))
     assert 4 * S <= b1 - a1 <= 4 * S + 2 * 4 * (64 * 64 + 1) + 3 * 256
     assert c1 == b1
+
+
+def test_chunk_coded_pointing_workspace(mm):
+    # pass 1's chunk-coded pointing: 4 B a sample and 16 B per 64-sample chunk
+    # for I,Q,U stored pointing on the float32 and bfloat16 four-step paths,
+    # nothing for I only, float64 or pointing_code = MM_PTC_OFF
+    S = 4 * (1 << 16)
+    for kw in ({}, {"scatter": mm.MM_SCATTER_SAMPLES}, {"tod_dtype": mm.MM_BF16}):
+        on = mm.mm_scan_workspace_bytes(_desc(mm, **kw))
+        off = mm.mm_scan_workspace_bytes(_desc(mm, pointing_code=mm.MM_PTC_OFF, **kw))
+        want = 4 * S + 16 * (S // 64)
+        assert want <= on - off <= want + 2 * 256, kw
+    for kw in ({"ncomp": 1}, {"tod_dtype": mm.MM_F64}, {"scatter": mm.MM_SCATTER_ATOMIC},
+               {"nsamp": 1 << 12}):
+        on = mm.mm_scan_workspace_bytes(_desc(mm, **kw))
+        off = mm.mm_scan_workspace_bytes(_desc(mm, pointing_code=mm.MM_PTC_OFF, **kw))
+        assert on == off > 0, kw
 
 
 def test_bf16_pass_buffer_is_half_of_f32(mm):
@@ -101,7 +119,7 @@ def test_compensated_accumulation_takes_the_gather_on_one_kernel_plans(mm):
     ("nsamp", 2 * 3**9 * 2**4), ("nsamp", 7 * 2**8),
     ("nsamp", 1 << 23), ("tod_dtype", 7), ("fft_m1", 3), ("det_group", -1), ("scatter", 5),
     ("scatter", 3),
-    ("acc", 2),
+    ("acc", 2), ("pointing_code", 2), ("pointing_code", -1),
 ])
 def test_invalid_descriptions_rejected(mm, field, value):
     d = _desc(mm, **{field: value})
@@ -190,7 +208,7 @@ def test_boresight_pointing_descriptor(mm):
     h = C.c_void_p()
     # boresight pointing keeps the per-sample index: compare with stored
     # pointing on the per-sample index too
-    d = _desc(mm, nsamp=2**16, scatter=mm.MM_SCATTER_SAMPLES)
+    d = _desc(mm, nsamp=2**16, scatter=mm.MM_SCATTER_SAMPLES, pointing_code=mm.MM_PTC_OFF)
     stored = mm.mm_scan_workspace_bytes(d)
     d.pointing = 2
     assert mm.mm_scan_workspace_bytes(d) == 0 and "pointing" in mm.mm_last_error()
