@@ -178,7 +178,7 @@ __device__ __forceinline__ T source_sample(const PassArgs<T, S>& a, int64_t s) {
     angle_cs(a.ang_t[s], a.ang_tab, &c, &sn);
     return m.x + T(c) * m.y + T(sn) * m.z;
   } else if constexpr (SRC == 5) {
-    const int4 h = a.ptc_h[s / kPtcChunk];
+    const int4 h = a.ptc_h[s >> kPtcLog];
     const uint32_t w = a.ptc[s];
     const uint32_t dp = w & 0xFFFFu;
     const V4<T> m = a.gmap[dp == 0xFFFFu ? a.npix : h.x + int(dp)];
@@ -524,7 +524,7 @@ __device__ __forceinline__ void source4(const PassArgs<T, S>& a, int64_t s, T (&
     }
   } else if constexpr (SRC == 5) {
     // chunk-coded pixels and angles: 4 B a sample and the chunk's header
-    const int4 h = a.ptc_h[s / kPtcChunk];
+    const int4 h = a.ptc_h[s >> kPtcLog];
     const int4 w4 = ld_stream(reinterpret_cast<const int4*>(a.ptc + s));
     const uint32_t ww[4] = {uint32_t(w4.x), uint32_t(w4.y), uint32_t(w4.z), uint32_t(w4.w)};
     // the angle trend at the first of the four samples, then one step each
@@ -564,6 +564,66 @@ __device__ __forceinline__ void source4(const PassArgs<T, S>& a, int64_t s, T (&
     for (int i = 0; i < 4; ++i) {
       const V4<T> m = a.gmap[unsigned(pp[i]) < unsigned(a.npix) ? pp[i] : a.npix];
       v[i] = (NC == 3) ? m.x + T(cc[i]) * m.y + T(ss[i]) * m.z : m.x;
+    }
+  }
+}
+
+// U groups of four samples (sample indices s[u], multiples of 4) from stored
+// pointing with angle-coded weights (SRC 3, or SRC 5 chunk-coded), in three
+// phases so that the memory round trips of the groups overlap: every group's
+// pointing words, then every map gather, then the weights, decoded while the
+// gathers are in flight, and the sums.
+template <typename T, typename S, int SRC, int U>
+__device__ __forceinline__ void stored_groups(const PassArgs<T, S>& a, const int64_t (&s)[U],
+                                              const float2* tab, T (&v)[U][4]) {
+  static_assert(SRC == 3 || SRC == 5, "stored pointing with angle-coded weights");
+  uint32_t pw[U][4], aw[U][4];
+  int4 h[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if constexpr (SRC == 5) {
+      const int4 w4 = ld_stream(reinterpret_cast<const int4*>(a.ptc + s[u]));
+      h[u] = a.ptc_h[s[u] >> kPtcLog];
+      pw[u][0] = uint32_t(w4.x); pw[u][1] = uint32_t(w4.y);
+      pw[u][2] = uint32_t(w4.z); pw[u][3] = uint32_t(w4.w);
+    } else {
+      const int4 p4 = ld_stream(reinterpret_cast<const int4*>(a.pix + s[u]));
+      const int4 u4 = ld_stream(reinterpret_cast<const int4*>(a.ang_t + s[u]));
+      pw[u][0] = uint32_t(p4.x); pw[u][1] = uint32_t(p4.y);
+      pw[u][2] = uint32_t(p4.z); pw[u][3] = uint32_t(p4.w);
+      aw[u][0] = uint32_t(u4.x); aw[u][1] = uint32_t(u4.y);
+      aw[u][2] = uint32_t(u4.z); aw[u][3] = uint32_t(u4.w);
+    }
+  }
+  V4<T> m[U][4];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int p;
+      if constexpr (SRC == 5) {
+        const uint32_t dp = pw[u][i] & 0xFFFFu;
+        p = dp == 0xFFFFu ? a.npix : h[u].x + int(dp);
+      } else {
+        p = pw[u][i] < uint32_t(a.npix) ? int(pw[u][i]) : a.npix;
+      }
+      m[u][i] = a.gmap[p];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      uint32_t ua;
+      if constexpr (SRC == 5) {   // the chunk's angle trend at this sample, plus the residual
+        ua = uint32_t(h[u].y) + uint32_t(h[u].z) * uint32_t((s[u] & (kPtcChunk - 1)) + i) +
+             (pw[u][i] >> 16);
+      } else {
+        ua = aw[u][i];
+      }
+      float c, sn;
+      angle_cs(ua, tab, &c, &sn);
+      v[u][i] = m[u][i].x + T(c) * m[u][i].y + T(sn) * m[u][i].z;
     }
   }
 }
@@ -652,7 +712,26 @@ k_pass1(PassArgs<T, S> a) {
   // U groups per thread per trip, every load of a trip issued before the
   // first use; a group past the end re-reads group e40 and is not stored.
   constexpr int U = (SRC == 2 || SRC == 4) ? UB : U0;
-  for (int e40 = threadIdx.x; e40 < nq; e40 += U * kNT13) {
+  int e40 = threadIdx.x;
+  if constexpr (SRC == 3 || SRC == 5) {
+    // trips whose U groups are all in range, without a branch between the
+    // groups' loads
+    for (; e40 + (U - 1) * kNT13 < nq; e40 += U * kNT13) {
+      T v[U][4];
+      int64_t si[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = (e40 + u * kNT13) << 2;
+        const int j1 = e >> (a.logC + 1);
+        const int q = e & (2 * C - 1);
+        si[u] = base + 2 * (int64_t(j1) * M2 + j20) + q;
+      }
+      stored_groups<T, S, SRC, U>(a, si, angtab, v);
+#pragma unroll
+      for (int u = 0; u < U; ++u) store4(bufr + ((e40 + u * kNT13) << 2), v[u]);
+    }
+  }
+  for (; e40 < nq; e40 += U * kNT13) {
     T v[U][4];
 #pragma unroll
     for (int u = 0; u < U; ++u) {

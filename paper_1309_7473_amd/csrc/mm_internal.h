@@ -21,7 +21,8 @@ constexpr int kSpecBlocks = 256;   // blocks of the map-spectra binning
 constexpr int kSpecMaxBins = 512;  // multipole bins of mm_map_spectra
 // device scratch of mm_map_spectra_noalloc (one static array per device)
 constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
-constexpr int kPtcChunk = 64;    // samples per chunk of the chunk-coded pointing
+constexpr int kPtcLog = 6;
+constexpr int kPtcChunk = 1 << kPtcLog;   // samples per chunk of the chunk-coded pointing
 constexpr int kProfSingle = 0, kProfPass1 = 1, kProfPass2 = 2, kProfPass3 = 3, kProfApplyA = 4,
               kProfPrecon = 5, kProfReduce = 6, kProfCorr = 7;
 
