@@ -166,9 +166,13 @@ typedef struct {
    *   weights cos 2(psi_d + phi) = c2psi c2phi - s2psi s2phi and
    *           sin 2(psi_d + phi) = s2psi c2phi + c2psi s2phi.
    * The pixel-major index of P^T is then always used (scatter must not be
-   * MM_SCATTER_ATOMIC).  On the float64 path (MM_F64) it holds no weights
-   * (4 B/sample of workspace) and the gather computes them in float64; the
-   * float32 and bfloat16 paths keep float32 weights beside it (12 B/sample). */
+   * MM_SCATTER_ATOMIC): with MM_SCATTER_AUTO and groups of at most 2^28
+   * samples the run-length index (4 B/sample of workspace at most) whose
+   * gather computes the float64 weights from the model on the float64 path
+   * and reads them as pixel-major 4-byte angles of the model's weights on
+   * the float32 and bfloat16 paths (4 B/sample more); otherwise the
+   * per-sample index (4 B/sample, plus 4 B/sample of angles on the float
+   * paths). */
   int32_t pointing;         /* mm_pointing */
   const double* bore;       /* device [6][nsamp] float64, 16-byte aligned: y_b, x_b
                                (pixel coordinates), cos phi, sin phi, cos 2phi,

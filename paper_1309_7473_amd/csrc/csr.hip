@@ -303,12 +303,15 @@ __global__ void k_rle_sort(const int32_t* __restrict__ roff_all, int npix, int n
 // The run-length index's angle-coded weights in gather order: each pixel's
 // runs are expanded exactly as the gather does (16 lanes, batches of 16 runs,
 // lane l taking samples l, l + 16, ... of a batch) and sample q of the pixel
-// gets the time-major angle of its sample.  blockIdx.y is the group.
+// gets the time-major angle of its sample (ang_t), or with boresight
+// pointing (ang_t NULL) the angle of the model's float64 weights, as the
+// per-sample index stores it.  blockIdx.y is the group.
 __global__ void __launch_bounds__(256) k_rle_angles(const int32_t* __restrict__ roff_all,
                                                     const int32_t* __restrict__ soff_all,
                                                     const uint32_t* __restrict__ hdr_all,
-                                                    const uint32_t* __restrict__ ang_t, int npix,
-                                                    int64_t gsz, uint32_t* __restrict__ pa_all) {
+                                                    const uint32_t* __restrict__ ang_t, Bore bo,
+                                                    int npix, int64_t gsz,
+                                                    uint32_t* __restrict__ pa_all) {
   constexpr int LPP = 16;
   const int g = blockIdx.y;
   const int l = threadIdx.x % LPP;
@@ -316,7 +319,7 @@ __global__ void __launch_bounds__(256) k_rle_angles(const int32_t* __restrict__ 
   if (p >= npix) return;               // whole 16-lane groups leave together
   const int32_t* roff = roff_all + int64_t(g) * (npix + 1);
   const uint32_t* hdr = hdr_all + int64_t(g) * gsz;
-  const uint32_t* ang = ang_t + int64_t(g) * gsz;
+  const uint32_t* ang = ang_t ? ang_t + int64_t(g) * gsz : nullptr;
   uint32_t* pa = pa_all + int64_t(g) * gsz + soff_all[int64_t(g) * (npix + 1) + p];
   const int b = roff[p], e = roff[p + 1];
   for (int kb = b; kb < e; kb += LPP) {
@@ -338,7 +341,15 @@ __global__ void __launch_bounds__(256) k_rle_angles(const int32_t* __restrict__ 
       for (int step = LPP / 2; step > 0; step >>= 1)
         if (__shfl(excl, r + step, LPP) <= q) r += step;
       const int ik = __shfl(first, r, LPP) + (q - __shfl(excl, r, LPP));
-      if (q < total) pa[q] = ang[ik];
+      if (q < total) {
+        if (ang) {
+          pa[q] = ang[ik];
+        } else {
+          double c, sn;
+          sample_weights(nullptr, nullptr, bo, int64_t(g) * gsz + ik, &c, &sn);
+          pa[q] = weight_angle(c, sn);
+        }
+      }
     }
     pa += total;
   }
@@ -397,7 +408,8 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
   }
   // run-length index with angle-coded weights: the angles also go pixel-major
   // in gather order, for which each pixel's sample offsets come first
-  s->rle_pa = s->plan.rle && s->ang_t_ready;
+  // (boresight pointing: the angles come from the model, no time-major copy)
+  s->rle_pa = s->plan.rle && (s->ang_t_ready || (s->plan.otf && s->csr_ang));
   if (s->rle_pa) {
     if ((r = fill_zero(cnt, size_t(ngroups) * npix * 4, st)) != MM_OK) return r;
     hipLaunchKernelGGL(k_csr_count<false>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
@@ -424,8 +436,9 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
     if (s->rle_pa)
       hipLaunchKernelGGL(k_rle_angles, dim3(unsigned((npix + 15) / 16), unsigned(ngroups)),
                          dim3(256), 0, st, s->at<int32_t>(L.csr_off), s->at<int32_t>(L.csr_soff),
-                         s->at<uint32_t>(L.csr_idx), s->at<uint32_t>(L.ang_t), npix, gsz,
-                         s->at<uint32_t>(L.csr_w));
+                         s->at<uint32_t>(L.csr_idx),
+                         s->ang_t_ready ? s->at<uint32_t>(L.ang_t) : static_cast<uint32_t*>(nullptr),
+                         bo, npix, gsz, s->at<uint32_t>(L.csr_w));
   } else if (s->nc == 3) {
     hipLaunchKernelGGL(k_csr_fill<3>, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo,
                        s->d.cos2psi, s->d.sin2psi, s->n, total, G, npix, cnt,

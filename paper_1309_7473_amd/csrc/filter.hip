@@ -1664,7 +1664,12 @@ static void launch_reduce(ScanImpl* s, const PassArgs<T, S>& a, hipStream_t st) 
   constexpr int PPB = 256 / kReduceLanes;   // pixels per 256-thread block
   const dim3 grid((s->npix + PPB - 1) / PPB);
   // weights: 1 from the boresight model, 2 as stored angles, 0 as stored floats
-  const int wm = NC != 3 ? 0 : !s->plan.csr_w ? 1 : s->csr_ang ? 2 : 0;
+  // (the run-length gather with boresight pointing has no stored floats)
+  const int wm = NC != 3                                           ? 0
+                 : !s->plan.csr_w                                   ? 1
+                 : s->csr_ang                                       ? 2
+                 : (s->plan.rle && s->plan.otf)                     ? 1
+                                                                    : 0;
   auto go = [&](auto cf, auto w) {
     constexpr bool CF_ = decltype(cf)::value;
     constexpr int WM_ = decltype(w)::value;
@@ -2162,16 +2167,18 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
   L->csr_idx = take(csr_n * 4);
   // the run-length index keeps the angle-coded weights pixel-major (4 B a
   // sample, in the gather's sample order) when the weights can be angles
-  // (stored pointing of unit norm on the float paths, checked at creation)
-  const bool rle_pa = pl->csr && !pl->otf && !pl->f64 && nc == 3 && d->scatter != MM_SCATTER_SAMPLES &&
+  // (weights of unit norm on the float paths, checked at creation: stored
+  // ones, or the boresight model's)
+  const bool rle_pa = pl->csr && !pl->f64 && nc == 3 && d->scatter != MM_SCATTER_SAMPLES &&
                       int64_t(pl->G) * n <= (int64_t(1) << 28);
   L->csr_soff = take(rle_pa ? size_t(ngroups) * (npix + 1) * 4 : 0);
   // stored weights beside the index, except for boresight pointing on the
   // float64 path, whose gather computes float64 weights from the model; the
-  // run-length index (stored pointing, groups of at most 2^28 samples) reads
-  // the time-major weights instead and stores none
+  // run-length index (groups of at most 2^28 samples) stores none beside it:
+  // its gather reads the pixel-major angles, the time-major weights or the
+  // boresight model
   pl->csr_w = nc == 3 && !(pl->otf && pl->f64);
-  pl->rle = pl->csr && !pl->otf && d->scatter != MM_SCATTER_SAMPLES &&
+  pl->rle = pl->csr && d->scatter != MM_SCATTER_SAMPLES &&
             int64_t(pl->G) * n <= (int64_t(1) << 28);
   L->csr_w = take(pl->csr_w && !pl->rle ? csr_n * 8 : rle_pa ? csr_n * 4 + 64 : 0);
   L->ang_tab = take(256 * 8);

@@ -41,14 +41,18 @@ def _inputs(nc, ny, nx, ndet, n, seed):
                        fknee=(0.5, 2.0), drift_deg=10.0, seed=(91, seed))
 
 
+@pytest.mark.parametrize("scatter,csr", [("auto", 2), ("samples", 1)])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_boresight_apply_rhs_and_binned(case):
+def test_boresight_apply_rhs_and_binned(case, scatter, csr):
+    # auto: the run-length index (pixel-major angles from the model's weights
+    # on the float paths, the model's float64 weights on the float64 path);
+    # samples: the per-sample index
     label, nc, ny, nx, ndet, n, dt, acc, G, m1 = case
     inp = boresight_only(_inputs(nc, ny, nx, ndet, n, ndet))
-    pair = Pair(inp, tod_dtype=dt, acc=acc, det_group=G, fft_m1=m1)
+    pair = Pair(inp, tod_dtype=dt, acc=acc, det_group=G, fft_m1=m1, scatter=scatter)
     info = pair.g.info()
-    print(f"[boresight {label}] {info}", flush=True)
-    assert info["csr"] == 1
+    print(f"[boresight {label} {scatter}] {info}", flush=True)
+    assert info["csr"] == csr
     # mask: integer decisions, exact
     mask = pair.host(pair.g.mask()).astype(bool)
     assert np.array_equal(mask, pair.mask), "active pixels differ from the oracle's"
