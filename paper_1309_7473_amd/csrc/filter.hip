@@ -2085,7 +2085,7 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
       pl->logM1 = l1;
       pl->logM2 = pl->logM - l1;
       pl->M1 = 1 << l1;
-      if (pl->logM1 < 2 || pl->logM2 < 5 || pl->logM2 > 12 || pl->logM1 > 9)
+      if (pl->logM1 < 2 || pl->logM2 < 5 || pl->logM2 > 12 || pl->logM1 > 10)
         return fail(MM_EINVAL, "fft_m1 gives an unsupported four-step split");
     }
     int lc = d->fft_cols > 0 ? ilog2(d->fft_cols) : 4;

@@ -46,6 +46,7 @@ CASES = [
     ("fourstep-f32-ragged", 3, 32, 32, 5, 2**15, "f32", 2, 0),
     ("fourstep-f32-m1=16", 3, 32, 32, 3, 2**15, "f32", 0, 16),
     ("fourstep-f32-m1=512", 1, 32, 32, 2, 2**18, "f32", 1, 512),
+    ("fourstep-f32-m1=1024", 3, 32, 32, 5, 2**18, "f32", 2, 1024),
     ("fourstep-f64", 3, 32, 32, 3, 2**16, "f64", 2, 0),
     ("fourstep-f64-m1=8", 1, 16, 16, 2, 2**15, "f64", 0, 8),
     # rows of 512, 1024 and 2048 bins take the one-wavefront-per-row pass 2
