@@ -132,7 +132,7 @@ __global__ void k_angles_t(const float* __restrict__ c2, const float* __restrict
     ang[i] = weight_angle(c2[i], s2[i]);
 }
 
-// Chunk-coded pointing for pass 1, one thread per kPtcChunk-sample chunk of
+// Chunk-coded pointing for pass 1, for each kPtcChunk-sample chunk of
 // one detector.  Header: the smallest on-map pixel of the chunk (0 if none),
 // and the chunk's angle trend u0 + slope * i through its first and last
 // on-map samples (i the sample's place in the chunk; slope 0 with fewer than
@@ -148,49 +148,49 @@ __global__ void __launch_bounds__(256) k_ptc_encode(const int32_t* __restrict__ 
                                                     int4* __restrict__ hdr,
                                                     uint32_t* __restrict__ code,
                                                     int* __restrict__ bad) {
-  constexpr int K = kPtcChunk;
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; c < nchunks; c += stride) {
-    const int32_t* p = pix + c * K;
-    const uint32_t* u = ang + c * K;
-    int lo = npix, hi = -1, i0 = -1, i1 = -1;
-    for (int i = 0; i < K; ++i) {
-      const int q = p[i];
-      if (unsigned(q) < unsigned(npix)) {
-        lo = q < lo ? q : lo;
-        hi = q > hi ? q : hi;
-        if (i0 < 0) i0 = i;
-        i1 = i;
-      }
+  // one wavefront per chunk, one lane per sample (coalesced loads and stores;
+  // the chunk's extremes and first and last on-map samples by wave reductions)
+  static_assert(kPtcChunk == 64, "one lane per sample of a chunk");
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
+  for (int64_t c = wave; c < nchunks; c += nwaves) {
+    const int64_t i = c * kPtcChunk + lane;
+    const int q = pix[i];
+    const uint32_t u = ang[i];
+    const bool on = unsigned(q) < unsigned(npix);
+    int lo = on ? q : npix, hi = on ? q : -1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const int lo2 = __shfl_xor(lo, off), hi2 = __shfl_xor(hi, off);
+      lo = lo2 < lo ? lo2 : lo;
+      hi = hi2 > hi ? hi2 : hi;
     }
     if (hi < 0) lo = 0;
+    const unsigned long long onm = __ballot(on);
+    const int i0 = onm ? __ffsll(onm) - 1 : -1;
+    const int i1 = onm ? 63 - __clzll(onm) : -1;
+    const uint32_t ua = __shfl(u, i0 < 0 ? 0 : i0), ue = __shfl(u, i1 < 0 ? 0 : i1);
     // the trend: a signed angle step per sample, rounded to the nearest
     int32_t slope = 0;
     uint32_t u0 = 0;
     if (i0 >= 0) {
       if (i1 > i0) {
-        const int64_t du = int64_t(int32_t(u[i1] - u[i0]));
+        const int64_t du = int64_t(int32_t(ue - ua));
         const int64_t span = i1 - i0;
         slope = int32_t(du >= 0 ? (du + span / 2) / span : -((-du + span / 2) / span));
       }
-      u0 = u[i0] - uint32_t(slope) * uint32_t(i0);
+      u0 = ua - uint32_t(slope) * uint32_t(i0);
     }
     const uint32_t ub = u0 - 32768u;
-    bool ok = hi - lo <= 65534;
-    for (int i = 0; i < K; i += 4) {
-      uint32_t w[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int q = p[i + k];
-        const bool on = unsigned(q) < unsigned(npix);
-        const uint32_t r = u[i + k] - ub - uint32_t(slope) * uint32_t(i + k);
-        ok = ok && (!on || r <= 65535u);
-        w[k] = on ? (uint32_t(q - lo) | (r << 16)) : 0xFFFFu;
-      }
-      *reinterpret_cast<uint4*>(code + c * K + i) = make_uint4(w[0], w[1], w[2], w[3]);
+    const uint32_t r = u - ub - uint32_t(slope) * uint32_t(lane);
+    const bool fits = !on || r <= 65535u;
+    const bool ok = hi - lo <= 65534 && __ballot(!fits) == 0ull;
+    code[i] = on ? (uint32_t(q - lo) | (r << 16)) : 0xFFFFu;
+    if (lane == 0) {
+      hdr[c] = make_int4(lo, int(ub), slope, 0);
+      if (!ok) atomicOr(bad, 1);
     }
-    hdr[c] = make_int4(lo, int(ub), slope, 0);
-    if (!ok) atomicOr(bad, 1);
   }
 }
 
@@ -275,28 +275,57 @@ __global__ void __launch_bounds__(256) k_csr_fill(const int32_t* __restrict__ pi
 constexpr bool kAngleWeights = MM_ANGLE_WEIGHTS != 0;
 
 // Each pixel's runs in time order (by first sample; runs of one pixel never
-// overlap), one thread per pixel and group, insertion sort in place.  Pixels
-// next to each other along a sweep are then visited by the same detector
-// passes in the same order, so the gather's lanes for neighbouring pixels
-// (one wave holds four) read neighbouring pieces of the same timestream
-// lines, and the index no longer depends on the order the fill's atomics
-// happened to claim slots in.
-__global__ void k_rle_sort(const int32_t* __restrict__ roff_all, int npix, int ngroups, int64_t gsz,
-                           uint32_t* __restrict__ hdr_all) {
-  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= int64_t(npix) * ngroups) return;
-  const int g = int(i / npix), p = int(i % npix);
-  const int32_t* roff = roff_all + int64_t(g) * (npix + 1);
-  uint32_t* h = hdr_all + int64_t(g) * gsz;
-  const int b = roff[p], e = roff[p + 1];
-  for (int k = b + 1; k < e; ++k) {
-    const uint32_t v = h[k];
-    int j = k - 1;
-    while (j >= b && h[j] > v) {
-      h[j + 1] = h[j];
-      --j;
+// overlap, so the entries are distinct).  Pixels next to each other along a
+// sweep are then visited by the same detector passes in the same order, so
+// the gather's lanes for neighbouring pixels (one wave holds four) read
+// neighbouring pieces of the same timestream lines, and the index no longer
+// depends on the order the fill's atomics happened to claim slots in.  One
+// wavefront per pixel and group: the entries go to LDS and each is written
+// back at its rank, the number of smaller entries, which the lanes count from
+// LDS.  A pixel with more than kSortCap entries is sorted in place by one lane
+// (insertion sort).
+constexpr int kSortCap = 2048;
+
+__global__ void __launch_bounds__(256) k_rle_sort(const int32_t* __restrict__ roff_all, int npix,
+                                                  int ngroups, int64_t gsz,
+                                                  uint32_t* __restrict__ hdr_all) {
+  __shared__ uint32_t keys[4][kSortCap];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t item = int64_t(blockIdx.x) * 4 + w;
+  const bool valid = item < int64_t(npix) * ngroups;
+  int b = 0, k = 0;
+  uint32_t* h = hdr_all;
+  if (valid) {
+    const int g = int(item / npix), p = int(item % npix);
+    const int32_t* roff = roff_all + int64_t(g) * (npix + 1);
+    h = hdr_all + int64_t(g) * gsz;
+    b = roff[p];
+    k = roff[p + 1] - b;
+  }
+  const bool ranked = k > 1 && k <= kSortCap;
+  if (ranked)
+    for (int t = lane; t < k; t += 64) keys[w][t] = h[b + t];
+  __syncthreads();
+  if (ranked) {
+    for (int t = lane; t < k; t += 64) {
+      const uint32_t v = keys[w][t];
+      int r = 0;
+      for (int j = 0; j < k; ++j) {
+        const uint32_t kj = keys[w][j];
+        r += (kj < v || (kj == v && j < t)) ? 1 : 0;   // ties (none expected) keep their order
+      }
+      h[b + r] = v;
     }
-    h[j + 1] = v;
+  } else if (k > kSortCap && lane == 0) {
+    for (int q = b + 1; q < b + k; ++q) {
+      const uint32_t v = h[q];
+      int j = q - 1;
+      while (j >= b && h[j] > v) {
+        h[j + 1] = h[j];
+        --j;
+      }
+      h[j + 1] = v;
+    }
   }
 }
 
@@ -394,9 +423,9 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
   if (s->ang_t_ready && s->plan.ptc && s->d.pix) {
     int* bad = s->at<int>(L.misc);
     if ((r = fill_zero(bad, 4, st)) != MM_OK) return r;
-    const int64_t nchunks = total / kPtcChunk;
-    int64_t cb = (nchunks + 255) / 256;
-    if (cb > 8192) cb = 8192;
+    const int64_t nchunks = total / kPtcChunk;   // one wavefront each, four a block
+    int64_t cb = (nchunks + 3) / 4;
+    if (cb > 65536) cb = 65536;
     hipLaunchKernelGGL(k_ptc_encode, dim3(unsigned(cb)), dim3(256), 0, st, s->d.pix,
                        s->at<uint32_t>(L.ang_t), nchunks, npix, s->at<int4>(L.ptc_h),
                        s->at<uint32_t>(L.ptc), bad);
@@ -430,8 +459,8 @@ mm_status csr_setup(ScanImpl* s, hipStream_t st) {
   if (s->plan.rle) {
     hipLaunchKernelGGL(k_rle_fill, dim3(unsigned(blocks)), dim3(256), 0, st, s->d.pix, bo, total,
                        gsz, npix, cnt, s->at<uint32_t>(L.csr_idx));
-    const int64_t nsort = int64_t(npix) * ngroups;
-    hipLaunchKernelGGL(k_rle_sort, dim3(unsigned((nsort + 255) / 256)), dim3(256), 0, st,
+    const int64_t nsort = int64_t(npix) * ngroups;   // one wavefront each, four a block
+    hipLaunchKernelGGL(k_rle_sort, dim3(unsigned((nsort + 3) / 4)), dim3(256), 0, st,
                        s->at<int32_t>(L.csr_off), npix, ngroups, gsz, s->at<uint32_t>(L.csr_idx));
     if (s->rle_pa)
       hipLaunchKernelGGL(k_rle_angles, dim3(unsigned((npix + 15) / 16), unsigned(ngroups)),
