@@ -1046,6 +1046,18 @@ def main():
     per_kernel = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1],
                       "share": round(v[0] / max(1, args.warmup) / ms_step, 4)}
                   for k, v in prof_w.items()}
+    # every timestream kernel against the HBM peak on its step's algorithmic
+    # bytes (the headline roofline is the slowest of them, which changes from
+    # run to run when they are close), with the counted traffic when the
+    # committed counter summary matches the kernel source
+    for k, v in prof_w.items():
+        if k not in ("single", "pass1", "pass2", "pass3", "reduce") or v[1] == 0:
+            continue
+        kk = "pass3_csr" if (k == "pass3" and info["csr"]) else k
+        gbs = ALG_BYTES[kk] * v[2] / v[1] / (v[0] * 1e-3 / v[1]) / 1e9
+        per_kernel[k].update({"alg_bytes_per_sample": ALG_BYTES[kk],
+                              "alg_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "traffic": load_traffic(k, src_hash)})
 
     solves = None
     if not args.no_solve:
