@@ -38,7 +38,7 @@ def shape_key(inputs, tod_dtype, acc):
 
 def candidates(nsamp, ndet, tod_dtype="f32"):
     """Candidate plans for a four-step shape: every split the library accepts
-    with M1 from 2^max(2, logM-12) to 2^min(9, logM-5), 8 or 16 columns, and
+    with M1 from 2^max(2, logM-12) to 2^min(10, logM-5), 8 or 16 columns, and
     the automatic detector group (about 512 MiB of pass buffer), half of it
     or a quarter."""
     M = nsamp // 2
@@ -49,7 +49,7 @@ def candidates(nsamp, ndet, tod_dtype="f32"):
     g_auto = max(1, min(ndet, (512 << 20) // (M * cxb)))
     groups = sorted({g_auto, max(1, g_auto // 2), max(1, g_auto // 4)})
     out = []
-    for l1 in range(max(2, logM - 12), min(9, logM - 5) + 1):
+    for l1 in range(max(2, logM - 12), min(10, logM - 5) + 1):
         for cols in (8, 16):
             for g in groups:
                 out.append({"fft_m1": 1 << l1, "fft_cols": cols, "det_group": g})

@@ -2077,8 +2077,13 @@ mm_status plan_and_layout(const mm_scan_desc* d, Plan* pl, Layout* L) {
     } else if (d->fft_m1 > 0) {
       l1 = ilog2(d->fft_m1);
     } else {
+      // columns of at most 512 (two pass-1/3 blocks a CU), unless that leaves
+      // rows longer than 2048 bins, which the one-wavefront pass 2 cannot
+      // take: then columns of 1024 (n = 2^22: 0.72 ms against 1.16 ms an
+      // A-apply at 16 detectors)
       l1 = pl->logM / 2;
       if (l1 > 9) l1 = 9;
+      if (pl->logM - l1 > 11) l1 = pl->logM - 11 < 10 ? pl->logM - 11 : 10;
       if (pl->logM - l1 > 12) l1 = pl->logM - 12;
     }
     if (!mixed) {

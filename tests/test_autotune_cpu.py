@@ -18,7 +18,7 @@ def test_candidates_follow_the_plan_rules():
     c = at.candidates(2**21, 256, "f32")
     logM = 20
     l1s = sorted({int(math.log2(p["fft_m1"])) for p in c})
-    assert l1s == list(range(max(2, logM - 12), min(9, logM - 5) + 1))
+    assert l1s == list(range(max(2, logM - 12), min(10, logM - 5) + 1))
     assert {p["fft_cols"] for p in c} == {8, 16}
     # automatic group ~512 MiB of pass buffer, half and a quarter of it
     assert {p["det_group"] for p in c} == {64, 32, 16}

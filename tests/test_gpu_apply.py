@@ -172,6 +172,19 @@ def test_apply_A_bitwise_repeatable(scatter, csr):
     assert np.array_equal(y1, y2)
 
 
+def test_longest_timestream_takes_wavefront_rows():
+    # nsamp = 2^22: the automatic split is 1024 x 2048 (rows for the
+    # one-wavefront pass 2), not 512 x 4096
+    n = 2**22
+    inp = raster_scan(ncomp=3, ny=32, nx=32, ndet=3, nsamp=n, fsample=400.0, layout="hex",
+                      hex_diameter_px=6.0, sigma_scatter=0.1, fknee=(0.5, 2.0), drift_deg=10.0,
+                      seed=(77, 22))
+    pair = Pair(inp, tod_dtype="f32")
+    info = pair.g.info()
+    assert (info["fft_m1"], info["fft_m2"]) == (1024, 2048), info
+    _check_apply(pair, TOL32_WHITE, label="n=2^22")
+
+
 def test_invalid_pixel_rejected():
     mm = need_gpu()
     inp = small_raster(ncomp=1, ny=8, nx=8, ndet=2)
