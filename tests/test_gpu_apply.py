@@ -49,11 +49,13 @@ CASES = [
     ("fourstep-f32-m1=1024", 3, 32, 32, 5, 2**18, "f32", 2, 1024),
     ("fourstep-f64", 3, 32, 32, 3, 2**16, "f64", 2, 0),
     ("fourstep-f64-m1=8", 1, 16, 16, 2, 2**15, "f64", 0, 8),
-    # rows of 512, 1024 and 2048 bins take the one-wavefront-per-row pass 2
+    # rows of 512 and 1024 bins take one wavefront a row in pass 2, rows
+    # of 2048 bins two
     ("fourstep-f32-m2=512", 3, 32, 32, 3, 2**15, "f32", 0, 32),
     ("fourstep-f32-m2=2048", 3, 32, 32, 3, 2**15, "f32", 3, 8),
     ("fourstep-f64-m2=512", 3, 32, 32, 3, 2**15, "f64", 0, 32),
     ("fourstep-f64-m2=1024", 3, 32, 32, 5, 2**15, "f64", 2, 16),
+    ("fourstep-f64-m2=2048", 3, 32, 32, 3, 2**15, "f64", 0, 8),
 ]
 
 

@@ -59,15 +59,20 @@ BF16_CASES = [
     ("fourstep-IQU-m2=1024", 3, 32, 32, 4, 2**16, "f64"),
     ("fourstep-I-f32x2", 1, 32, 32, 3, 2**15, "f32x2"),
     ("onekernel-gather-IQU", 3, 16, 16, 5, 2**12, "f32x2"),
+    # rows of 2048 bins: two wavefronts a row in pass 2
+    ("fourstep-IQU-m2=2048", 3, 32, 32, 3, 2**15, "f64", 8),
 ]
 
 
 @pytest.mark.parametrize("case", BF16_CASES, ids=[c[0] for c in BF16_CASES])
 def test_bf16_storage_parity(case):
-    label, nc, ny, nx, ndet, n, acc = case
+    label, nc, ny, nx, ndet, n, acc = case[:7]
+    m1 = case[7] if len(case) > 7 else 0
     inp = _scan(nc, ny, nx, ndet, n)
-    pair = Pair(inp, tod_dtype="bf16", acc=acc)
-    ref = Pair(inp, tod_dtype="f32", acc=acc)
+    pair = Pair(inp, tod_dtype="bf16", acc=acc, fft_m1=m1)
+    ref = Pair(inp, tod_dtype="f32", acc=acc, fft_m1=m1)
+    if m1:
+        assert pair.g.info()["fft_m1"] == m1
     x, sky = _maps(pair)
     for name, v in (("random", x), ("sky", sky)):
         want = pair.A_oracle(v)
