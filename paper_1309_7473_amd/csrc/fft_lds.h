@@ -99,6 +99,32 @@ __device__ __forceinline__ void dft_2level(Cx<T> (&v)[A * B], TW tw) {
   }
 }
 
+// W_N^m = exp(-2 pi i m / N) for N dividing 32, from literal constants
+// (cos(pi j / 16), j = 0..8, rounded by the compiler to T), so a DFT in
+// registers needs no table loads and its powers fold into the arithmetic.
+template <typename T, int N>
+struct ConstTw {
+  static_assert(N == 8 || N == 16 || N == 32, "N must divide 32");
+  __device__ __forceinline__ static constexpr double cospi16(int j) {
+    constexpr double c[9] = {1.0,
+                             0.98078528040323044912618223613424,
+                             0.92387953251128675612818318939679,
+                             0.83146961230254523707878837761791,
+                             0.70710678118654752440084436210485,
+                             0.55557023301960222474283081394853,
+                             0.38268343236508977172845998403040,
+                             0.19509032201612826784828486847702,
+                             0.0};
+    j &= 31;
+    if (j > 16) j = 32 - j;            // cos(2 pi - x) = cos(x)
+    return j <= 8 ? c[j] : -c[16 - j];   // cos(pi - x) = -cos(x)
+  }
+  __device__ __forceinline__ Cx<T> operator()(int m) const {
+    const int j = m * (32 / N);        // W_N^m = exp(-i pi j / 16)
+    return cx(T(cospi16(j)), T(-cospi16(8 - j)));
+  }
+};
+
 // In-register DFT of length E in {8, 16, 32}; tw(m) = W_E^m.
 template <typename T, int E, bool INV, typename TW>
 __device__ __forceinline__ void dft_regs(Cx<T> (&v)[E], TW tw) {

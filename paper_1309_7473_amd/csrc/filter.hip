@@ -229,33 +229,36 @@ __device__ __forceinline__ void scatter_sample(const A& a, int64_t s, T u) {
   }
 }
 
-// Filter the Hermitian pair (Z[k], Z[M-k]) in place; W = W_n^k, a = iN[k]/M,
-// b = iN[M-k]/M.
+// Filter the Hermitian pair (Z[k], Z[M-k]) in place; W = W_n^k, a = iN[k]/(4M),
+// b = iN[M-k]/(4M).  The unpack's two factors 1/2 (on the even and odd
+// parts and on the gains' sum and difference) ride in the gains' 1/4: as
+// powers of two they change no rounding, so the result is the same bit for
+// bit as with the halves applied one by one.
 template <typename T>
 __device__ __forceinline__ void pair_filter(Cx<T>& Zk, Cx<T>& Zmk, Cx<T> W, T a, T b) {
-  const T h = T(0.5);
-  const Cx<T> E = cx(h * (Zk.x + Zmk.x), h * (Zk.y - Zmk.y));
-  const Cx<T> D = cx(h * (Zk.x - Zmk.x), h * (Zk.y + Zmk.y));
+  const Cx<T> E = cx(Zk.x + Zmk.x, Zk.y - Zmk.y);
+  const Cx<T> D = cx(Zk.x - Zmk.x, Zk.y + Zmk.y);
   const Cx<T> O = cx(D.y, -D.x);
   const Cx<T> WO = W * O;
-  const T sp = h * (a + b), sm = h * (a - b);
+  const T sp = a + b, sm = a - b;
   const Cx<T> Ep = cx(sp * E.x + sm * WO.x, sp * E.y + sm * WO.y);
   const Cx<T> Op = cx(sm * E.x + sp * WO.x, sm * E.y + sp * WO.y) * conj(W);
   Zk = cx(Ep.x - Op.y, Ep.y + Op.x);
   Zmk = cx(Ep.x + Op.y, Op.x - Ep.y);
 }
 
-// DC / Nyquist bin: Z[0] carries X[0] = Re+Im and X[M] = Re-Im.
+// DC / Nyquist bin: Z[0] carries X[0] = Re+Im and X[M] = Re-Im; gains as in
+// pair_filter, a0 = iN[0]/(4M), aM = iN[M]/(4M).
 template <typename T>
 __device__ __forceinline__ Cx<T> dc_filter(Cx<T> Z0, T a0, T aM) {
   const T y0 = a0 * (Z0.x + Z0.y);
   const T yM = aM * (Z0.x - Z0.y);
-  return cx(T(0.5) * (y0 + yM), T(0.5) * (y0 - yM));
+  return cx(T(2) * (y0 + yM), T(2) * (y0 - yM));
 }
 
 // The two halves of pair_filter, for a filter that mixes detectors:
 // unpack (Z[k], Z[M-k]) into the real-input spectrum (X[k], X[M-k]), and
-// repack a filtered (Y[k], Y[M-k]) into the packed pair.  pair_filter(a, b)
+// repack a filtered (Y[k], Y[M-k]) into the packed pair.  pair_filter(a/4, b/4)
 // equals pair_repack(a X[k], b X[M-k]).
 template <typename T>
 __device__ __forceinline__ void pair_unpack(Cx<T>& Zk, Cx<T>& Zmk, Cx<T> W) {
@@ -362,11 +365,12 @@ __global__ void __launch_bounds__(kNT) k_single(PassArgs<T, S> a) {
     lds_fft<T, kNT, kE, false>(buf, sh, a.tw);
   const float* iN = a.iN + int64_t(g) * (M + 1);
   for (int k = threadIdx.x; k <= M / 2; k += kNT) {
+    const T sq = T(0.25) * a.scale;   // the filter's gains are iN/(4M)
     if (k == 0) {
-      buf[0] = dc_filter(buf[0], a.scale * T(iN[0]), a.scale * T(iN[M]));
+      buf[0] = dc_filter(buf[0], sq * T(iN[0]), sq * T(iN[M]));
     } else {
       Cx<T> zk = buf[k], zm = buf[M - k];
-      pair_filter(zk, zm, a.wn(k), a.scale * T(iN[k]), a.scale * T(iN[M - k]));
+      pair_filter(zk, zm, a.wn(k), sq * T(iN[k]), sq * T(iN[M - k]));
       buf[k] = zk;
       if (k != M - k) buf[M - k] = zm;
     }
@@ -803,7 +807,7 @@ __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T, S> a) {
   FftShape sh{a.logM2, 1, 1, M2, false, a.logM2};
   lds_fft<T, kNT, E, false, kPad2, true>(buf, sh, stw);
   const float* iN = a.iNt + int64_t(g) * (M + 1);  // [k1][k2] order, then iN[M]
-  const T sc = a.scale;
+  const T sc = T(0.25) * a.scale;   // the filter's gains are iN/(4M)
   if (pr != 0) {
     const Cx<T> wa = a.wn(ra);
     const float* ia = iN + int64_t(ra) * M2;
@@ -871,15 +875,17 @@ __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T, S> a) {
 #define MM_PASS2W 1
 #endif
 
-// LDS slot of element i of a row: XOR of bits LOGE.. onto the low five bits.
-// A bank model of every access of the kernel (radix-E writes at stride E,
-// radix-8 reads and writes, the filter's forward and reversed walks) finds
-// this conflict-free or nearly so for 8-byte accesses on 32 or 64 banks,
-// where a one-slot-per-E padding costs up to 1.8x; it is a bijection on
-// [0, 64 E) and needs no padding.
+// LDS slot of element i of a row: one pad slot after every 32 elements.
+// Every access of the kernel (radix-E writes at stride E, radix-8 reads and
+// writes, the filter's forward and reversed walks) is then a per-lane base
+// plus a constant, so the compiler folds it into the LDS instruction's
+// offset; a bank model of those accesses (8-byte elements, 32 or 64 banks)
+// costs 1.125 of the conflict-free cycles at 1024-bin rows, 1.0 at 2048 and
+// at most 1.375 at 512.
+constexpr int kP2PadLog = 5;
 template <int LOGE>
 __device__ __forceinline__ int pad_e(int i) {
-  return i ^ ((i >> LOGE) & 31);
+  return i + (i >> kP2PadLog);
 }
 
 // MODE 0: forward FFT, 1/N(f) filter, inverse FFT.  MODE 1 (correlated
@@ -901,7 +907,7 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
   constexpr int LOGE = (E == 8) ? 3 : (E == 16) ? 4 : 5;
   constexpr int L = 64 * E;              // = M2
   constexpr int LOGL = LOGE + 6;
-  constexpr int RS = L;                  // LDS row (swizzled, unpadded)
+  constexpr int RS = L + (L >> kP2PadLog);   // padded LDS row
   constexpr int NB = E / 8;              // radix-8 butterflies per lane
   constexpr int NW = 2 * PB;             // waves (rows) per block
   constexpr int NT = 64 * NW;
@@ -943,7 +949,7 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
   auto twL = [&](int m) { return a.tw[m << tsh]; };   // W_L^m, from the cached table
   Cx<T>* R = rows + wave * RS;
   const Cx<T> tb = tB[wave * 64 + lane];
-  auto twE = [&](int m) { return twL(m << 6); };   // W_E^m = W_L^(64 m)
+  const ConstTw<T, (E < 16 ? 16 : E)> twE;   // W_E^m (unused at E = 8)
   // ---------------- forward: radix-E from global, then 2 x radix-8
   if constexpr (MODE != 2) {
 #pragma unroll
@@ -1073,8 +1079,8 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
     Cx<T>* Rb = Ra + RS;
     const int tp = threadIdx.x & 127;   // thread within the pair
     const float* iN = a.iNt + int64_t(g) * (M + 1);
-    const T sc = a.scale;
-    // the filter's gains (MODE 0 only reads 1/N(f))
+    const T sc = T(0.25) * a.scale;
+    // the filter's gains iN/(4M) (MODE 0 only reads 1/N(f))
     auto gain = [&](const float* p, int i) { return MODE == 0 ? sc * T(p[i]) : T(0); };
     if (pr != 0) {
       const Cx<T> wa = a.wn(ra);
@@ -1829,7 +1835,8 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       const dim3 g2(gd * (M1 / 2));
       // one row pair per block: two waves
       constexpr int PB = 1;
-      const size_t lds2w = size_t(2 * PB) * (M2 + M2 / 64 + 64) * sizeof(Cx<T>);
+      const size_t lds2w =
+          size_t(2 * PB) * (M2 + (M2 >> kP2PadLog) + M2 / 64 + 64) * sizeof(Cx<T>);
       const bool wave_rows = MM_PASS2W && lds2w <= 80 * 1024 && ((int64_t(gd) * M1 / 2) % PB) == 0;
       const dim3 g2w(unsigned(int64_t(gd) * M1 / 2 / PB)), b2w(128 * PB);
       if (pl.corr_rank > 0) {
