@@ -1015,23 +1015,33 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
     __syncthreads();
     const int Ns = 1 << logNs;
     const int sh = LOGL - logNs - 3;     // W_{8 Ns}^(r k) = W_L^(r k << sh)
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int j = lane + 64 * i;
-      const int k = j & (Ns - 1);
+    // the twiddles W_{8 Ns}^(r k), r = 1..7, of butterfly k: read W and W^4
+    // and form the other powers
+    auto twiddles = [&](int k, Cx<T> (&t)[8]) {
       Cx<T> t1 = twL(k << sh), t4 = twL((4 * k) << sh);
       if (inv) {
         t1.y = -t1.y;
         t4.y = -t4.y;
       }
-      const Cx<T> t2 = t1 * t1, t3 = t2 * t1;
-      u[i][1] = u[i][1] * t1;
-      u[i][2] = u[i][2] * t2;
-      u[i][3] = u[i][3] * t3;
-      u[i][4] = u[i][4] * t4;
-      u[i][5] = u[i][5] * (t4 * t1);
-      u[i][6] = u[i][6] * (t4 * t2);
-      u[i][7] = u[i][7] * (t4 * t3);
+      t[1] = t1;
+      t[2] = t1 * t1;
+      t[3] = t[2] * t1;
+      t[4] = t4;
+      t[5] = t4 * t1;
+      t[6] = t4 * t[2];
+      t[7] = t4 * t[3];
+    };
+    // with Ns <= 64 every butterfly of a lane has k = lane mod Ns: one set
+    Cx<T> ts[8];
+    if (Ns <= 64) twiddles(lane & (Ns - 1), ts);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int j = lane + 64 * i;
+      const int k = j & (Ns - 1);
+      Cx<T> tt[8];
+      if (Ns > 64) twiddles(k, tt);
+#pragma unroll
+      for (int r = 1; r < 8; ++r) u[i][r] = u[i][r] * (Ns <= 64 ? ts[r] : tt[r]);
       if (inv)
         dft_reg<T, 8, true>(u[i]);
       else
