@@ -92,8 +92,10 @@ def summarize(trace_dir, fetch_dir, write_dir, bench_log, out_dir):
     import glob
 
     def one(pattern):
+        # newest first, so a folder that also holds an older run's files
+        # yields this run's
         f = glob.glob(os.path.join(pattern, "**", "*.csv"), recursive=True)
-        return f
+        return sorted(f, key=os.path.getmtime, reverse=True)
 
     stats = [f for f in one(trace_dir) if f.endswith("kernel_stats.csv")]
     rows = list(csv.DictReader(open(stats[0]))) if stats else []

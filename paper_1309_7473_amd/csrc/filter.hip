@@ -1005,6 +1005,22 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
   }
   __syncthreads();
   auto radix8 = [&](int logNs, bool inv, bool to_lds) {
+    const int Ns = 1 << logNs;
+    const int sh = LOGL - logNs - 3;     // W_{8 Ns}^(r k) = W_L^(r k << sh)
+    // with Ns <= 64 every butterfly of a lane has k = lane mod Ns: one set
+    constexpr int NQ = NB;
+    const int nq = Ns <= 64 ? 1 : NQ;
+    // W and W^4 of each butterfly, read before the stage's LDS reads and
+    // barrier so their latency overlaps them
+    Cx<T> q1[NQ], q4[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      if (i < nq) {
+        const int k = (lane + 64 * i) & (Ns - 1);
+        q1[i] = twL(k << sh);
+        q4[i] = twL((4 * k) << sh);
+      }
+    }
     Cx<T> u[NB][8];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -1013,12 +1029,10 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
       for (int r = 0; r < 8; ++r) u[i][r] = R[pad_e<LOGE>(j + (L / 8) * r)];
     }
     __syncthreads();
-    const int Ns = 1 << logNs;
-    const int sh = LOGL - logNs - 3;     // W_{8 Ns}^(r k) = W_L^(r k << sh)
-    // the twiddles W_{8 Ns}^(r k), r = 1..7, of butterfly k: read W and W^4
-    // and form the other powers
-    auto twiddles = [&](int k, Cx<T> (&t)[8]) {
-      Cx<T> t1 = twL(k << sh), t4 = twL((4 * k) << sh);
+    // the twiddles W_{8 Ns}^(r k), r = 1..7, of butterfly i's k from W and
+    // W^4: the other powers by products
+    auto twiddles = [&](int i, Cx<T> (&t)[8]) {
+      Cx<T> t1 = q1[i], t4 = q4[i];
       if (inv) {
         t1.y = -t1.y;
         t4.y = -t4.y;
@@ -1031,15 +1045,14 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
       t[6] = t4 * t[2];
       t[7] = t4 * t[3];
     };
-    // with Ns <= 64 every butterfly of a lane has k = lane mod Ns: one set
     Cx<T> ts[8];
-    if (Ns <= 64) twiddles(lane & (Ns - 1), ts);
+    if (Ns <= 64) twiddles(0, ts);
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int j = lane + 64 * i;
       const int k = j & (Ns - 1);
       Cx<T> tt[8];
-      if (Ns > 64) twiddles(k, tt);
+      if (Ns > 64) twiddles(i, tt);
 #pragma unroll
       for (int r = 1; r < 8; ++r) u[i][r] = u[i][r] * (Ns <= 64 ? ts[r] : tt[r]);
       if (inv)
