@@ -866,7 +866,7 @@ __global__ void __launch_bounds__(kNT) k_pass2(PassArgs<T, S> a) {
 // A block holds PB row pairs (2 PB waves).  Per row the length-M2 FFT is a
 // radix-E stage in registers fed straight from global memory (lane l holds
 // elements l + 64 r), then two radix-8 Stockham stages through this wave's
-// swizzled LDS row; the spectrum ends in natural order.  Stage twiddles come
+// padded LDS row; the spectrum ends in natural order.  Stage twiddles come
 // from the global table (it stays in cache); keeping them out of LDS lets
 // more blocks share a CU.  The pair filter runs on the two rows of a pair,
 // the inverse FFT mirrors the forward one and its last stage stores straight
@@ -914,7 +914,6 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<T>* rows = reinterpret_cast<Cx<T>*>(smem);   // [NW][RS]
   Cx<T>* tA = rows + NW * RS;                      // [NW][E]
-  Cx<T>* tB = tA + NW * E;                         // [NW][64]
   const int M1 = a.M1i;
   const int M = a.Mi;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -934,8 +933,11 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
   const int rb = (pr == 0) ? (M1 >> 1) : (M1 - pr);
   const int myrow = row_of(wave);
   auto* w = a.work + int64_t(g) * M + int64_t(myrow) * L;
-  // the row's loads are issued before the twiddle tables are built, so the
-  // two latencies overlap
+  // the row's loads are issued before the twiddles are formed, so the two
+  // latencies overlap.  The four-step twiddle of element j2 = l + 64 r of
+  // the row is W_M^(row j2) = tA[r] * tb: tA[r] = W_M^(64 row r) from a
+  // small per-row LDS table, tb = W_M^(row l) in a register (the last
+  // inverse stage stores index j2 from lane j2 mod 64 too)
   Cx<T> v[E];
   if constexpr (MODE != 2) {
 #pragma unroll
@@ -943,12 +945,11 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
   }
   for (int t = threadIdx.x; t < NW * E; t += NT)
     tA[t] = a.wn(2 * int64_t(row_of(t / E)) * (int64_t(t % E) << 6));
-  for (int t = threadIdx.x; t < NW * 64; t += NT) tB[t] = a.wn(2 * int64_t(row_of(t >> 6)) * (t & 63));
+  const Cx<T> tb = a.wn(2 * int64_t(myrow) * lane);
   __syncthreads();
   const int tsh = a.logLmax - LOGL;
   auto twL = [&](int m) { return a.tw[m << tsh]; };   // W_L^m, from the cached table
   Cx<T>* R = rows + wave * RS;
-  const Cx<T> tb = tB[wave * 64 + lane];
   const ConstTw<T, (E < 16 ? 16 : E)> twE;   // W_E^m (unused at E = 8)
   // ---------------- forward: radix-E from global, then 2 x radix-8
   if constexpr (MODE != 2) {
@@ -1068,7 +1069,7 @@ k_pass2w(PassArgs<T, S> a, CorrArgs c) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           const int idx = out + r * Ns;
-          Sto<T, S>::st(w + idx, u[i][r] * conj(tA[wave * E + (idx >> 6)] * tB[wave * 64 + (idx & 63)]));
+          Sto<T, S>::st(w + idx, u[i][r] * conj(tA[wave * E + (idx >> 6)] * tb));
         }
       }
     }
@@ -1859,7 +1860,7 @@ static mm_status run_pipeline_t(ScanImpl* s, const void* tod, hipStream_t st) {
       // one row pair per block: two waves
       constexpr int PB = 1;
       const size_t lds2w =
-          size_t(2 * PB) * (M2 + (M2 >> kP2PadLog) + M2 / 64 + 64) * sizeof(Cx<T>);
+          size_t(2 * PB) * (M2 + (M2 >> kP2PadLog) + M2 / 64) * sizeof(Cx<T>);
       const bool wave_rows = MM_PASS2W && lds2w <= 80 * 1024 && ((int64_t(gd) * M1 / 2) % PB) == 0;
       const dim3 g2w(unsigned(int64_t(gd) * M1 / 2 / PB)), b2w(128 * PB);
       if (pl.corr_rank > 0) {
